@@ -1,0 +1,163 @@
+/*
+ * vbyte.h -- C ABI of libvbyte, VByte decoding of uint32 on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The operation is the one of Plaisance, Kurz, Lemire, "Vectorized VByte
+ * Decoding" (arXiv 1503.07387):
+ *   - byte format, section 1 and Table 1: an integer is written 7 bits per
+ *     byte, least-significant group first; the top bit of a byte is 1 on
+ *     every byte of a code except its last ("terminator", top bit 0); a
+ *     uint32 takes 1 to 5 bytes;
+ *   - decoding, Algorithm 1 (the conventional decoder): each terminator ends
+ *     one integer, the value is the sum of the 7-bit groups at weights
+ *     2^0, 2^7, 2^14, 2^21, 2^28, in uint32 arithmetic;
+ *   - differential coding, section 1 ("Differential coding") and section 4
+ *     ("Differential Coding"): the stream holds gaps; decoding adds each gap
+ *     to the last value decoded, carried in a 32-bit integer.
+ *
+ * Conventions shared by every call below.
+ *   Memory.  Every data pointer (bytes, out, offsets, prevs, status words)
+ *     is a DEVICE pointer on the current HIP device, allocated and owned by
+ *     the caller; the library never frees or retains it.  `bytes` may have
+ *     any alignment; `out` must be 4-byte aligned; inputs and outputs must
+ *     not overlap.  The library keeps its own device workspace per
+ *     (device, stream), grown on demand; it frees it at process exit.
+ *   Streams.  `stream` is a hipStream_t passed as void*; NULL means the null
+ *     stream.  Work is enqueued in stream order; calls on one stream are
+ *     ordered, calls on different streams are independent (each stream has
+ *     its own workspace).
+ *   Strict semantics (paper silent; readings R3-R6).  A stream is valid iff
+ *     bytes[0..nbytes) is exactly n codes ending at its last byte:
+ *       VBYTE_EMALFORMED  five or more consecutive bytes >= 0x80 anywhere;
+ *       VBYTE_ETRUNC      last byte >= 0x80, or fewer than n terminators;
+ *       VBYTE_ECOUNT      more than n terminators.
+ *     When several hold, the larger code wins (EMALFORMED > ETRUNC >
+ *     ECOUNT), the same classification as the CPU oracle.  A fifth byte in
+ *     [16,128) is accepted and wraps mod 2^32 (R4); over-long codes such as
+ *     80 00 are accepted (R5).
+ *   Errors.  Argument errors (VBYTE_EINVAL) are returned before anything is
+ *     enqueued.  Data errors of *_async calls land in the caller's device
+ *     status word, written once by the kernel (no zero-initialisation
+ *     needed) and valid after the stream reaches that point; synchronous
+ *     calls wait and return them.  On a data error out[0..n) is
+ *     unspecified, but no element outside out[0..n) is ever written and no
+ *     16-byte block that holds no byte of bytes[0..nbytes) is ever read;
+ *     bytes outside the stream never influence a result.
+ *   Limits.  nbytes < 2^36.
+ */
+#ifndef VBYTE_H
+#define VBYTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum vbyte_status {
+    VBYTE_OK = 0,
+    VBYTE_EINVAL = 1,      /* bad argument: NULL pointer, misaligned out, size limit, bad offsets */
+    VBYTE_ECOUNT = 2,      /* more terminators than n */
+    VBYTE_ETRUNC = 3,      /* last byte >= 0x80 or fewer terminators than n */
+    VBYTE_EMALFORMED = 4,  /* a run of >= 5 continuation bytes */
+    VBYTE_EHIP = 5,        /* a HIP runtime call failed */
+    VBYTE_ENOMEM = 6       /* workspace allocation failed */
+} vbyte_status;
+
+/* ------------------------------------------------------------ single stream */
+
+/* DEC (Algorithm 1): decode n uint32 from bytes[0..nbytes) into out[0..n).
+ * Synchronous on the null stream: returns the data status. */
+vbyte_status vbyte_decode(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n);
+
+/* DEC_DELTA (section 1 "Differential coding", section 4 "Differential
+ * Coding"): out[i] = prev + g_0 + ... + g_i mod 2^32, where g_i are the
+ * decoded gaps; prev is the value before the first gap (0 for a list coded
+ * from x_1 - 0), or the last value of a previous part of the same stream,
+ * which makes decoding resumable.  Synchronous on the null stream. */
+vbyte_status vbyte_decode_delta(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                uint32_t prev);
+
+/* Asynchronous forms of the two calls above, enqueued on `stream`.
+ * d_status: device int32 that receives the vbyte_status of the data. */
+vbyte_status vbyte_decode_async(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                int32_t *d_status, void *stream);
+vbyte_status vbyte_decode_delta_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
+                                      size_t n, uint32_t prev, int32_t *d_status, void *stream);
+
+/* Number of terminator bytes (top bit 0) in bytes[0..nbytes), i.e. the
+ * number of codes a valid stream holds (section 1: one terminator per
+ * integer).  Written to the device word *d_count. */
+vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count, void *stream);
+
+/* ------------------------------------------------------------ batched lists */
+
+/* Batched CSR decode of posting lists (section 1: each list of sorted
+ * document identifiers is coded independently, from x_1 - 0).  List i is
+ * bytes[byte_off[i], byte_off[i+1]) and decodes to out[out_off[i],
+ * out_off[i+1]) with n_i = out_off[i+1] - out_off[i] integers.
+ *   byte_off, out_off: device int64[nlists+1], non-decreasing (checked on
+ *     the device; a decreasing pair sets VBYTE_EINVAL on the lists around it).
+ *   prevs: device uint32[nlists] start values for delta lists, or NULL (0).
+ *   delta: 0 plain, 1 differential.
+ *   d_list_status: device int32[nlists], required; receives each list's
+ *     status under the strict semantics above.
+ * One persistent launch decodes every list: lists larger than one tile are
+ * split into tiles chained by a look-back scan, small lists take one
+ * wavefront each.  Asynchronous on `stream`. */
+vbyte_status vbyte_decode_batch(const uint8_t *bytes, const int64_t *byte_off, uint32_t *out,
+                                const int64_t *out_off, size_t nlists, const uint32_t *prevs,
+                                int delta, int32_t *d_list_status, void *stream);
+
+/* Gather form of the batch, for lists that are not adjacent in memory (the
+ * serving loop decodes the lists of a query out of a resident index).
+ * lists: device int64[nlists][4] rows (byte_begin, byte_end, out_begin, n);
+ * list i is bytes[byte_begin, byte_end) and decodes to out[out_begin,
+ * out_begin + n).  prevs, delta and d_list_status as in vbyte_decode_batch.
+ * `work` is an optional device int32 work table built on the host with
+ * vbyte_plan_lists (NULL: the library builds it on the device). */
+vbyte_status vbyte_decode_lists(const uint8_t *bytes, const int64_t *lists, uint32_t *out,
+                                size_t nlists, const uint32_t *prevs, int delta,
+                                int32_t *d_list_status, void *stream);
+
+/* ------------------------------------------------------------ encoder */
+
+/* ENC (section 1, Table 1) on the GPU: writes the concatenated canonical
+ * codes of values[0..n) to bytes[0..*d_nbytes).  capacity is the size of
+ * `bytes`; 5*n always suffices.  If the codes need more than capacity
+ * bytes, nothing past capacity is written and *d_nbytes receives the size
+ * that was needed.  d_nbytes: device uint64. */
+vbyte_status vbyte_encode_async(const uint32_t *values, size_t n, uint8_t *bytes, size_t capacity,
+                                uint64_t *d_nbytes, void *stream);
+
+/* Differential ENC (section 1): encodes the gaps x_i - x_{i-1} mod 2^32
+ * with x_{-1} = prev. */
+vbyte_status vbyte_encode_delta_async(const uint32_t *values, size_t n, uint32_t prev,
+                                      uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
+                                      void *stream);
+
+/* ------------------------------------------------------------ utilities */
+
+/* Bytes of device workspace a single-stream call on nbytes input uses. */
+size_t vbyte_workspace_size(size_t nbytes);
+
+/* Tuning knobs of the decode kernels (0 keeps a value unchanged):
+ * segs_per_wave: 1 KiB segments one wavefront decodes per tile (1..4);
+ * waves_per_block: wavefronts per workgroup (1..16);
+ * small_list_bytes: lists up to this size take one wavefront each in the
+ * batched forms.  Returns VBYTE_EINVAL for an unsupported value. */
+vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t small_list_bytes);
+void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_list_bytes);
+
+/* Static name of a status code. */
+const char *vbyte_status_str(vbyte_status st);
+
+/* Text of the last HIP error seen by this thread (after VBYTE_EHIP). */
+const char *vbyte_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VBYTE_H */

@@ -1,0 +1,179 @@
+"""ctypes wrapper over the plain C oracle (TEST INFRASTRUCTURE ONLY).
+
+Arguments and results are numpy arrays on the host.  ``build()`` compiles
+``vbyte_oracle.c`` with gcc into ``liborc.so`` next to this file.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+OK, EINVAL, ECOUNT, ETRUNC, EMALFORMED = 0, 1, 2, 3, 4
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ECOUNT: "ECOUNT",
+                ETRUNC: "ETRUNC", EMALFORMED: "EMALFORMED"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vbyte_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+
+def lib_path():
+    return _LIB
+
+
+def build(src=_SRC, out=_LIB, extra_flags=()):
+    """Compile the oracle (gcc -O2, no intrinsics, no vectorisation hints)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
+           *extra_flags, "-o", out + ".tmp", src]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def _u8p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _u32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _i64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _i32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def load(path=None):
+    """Load the oracle library (building it first when it is absent)."""
+    global _lib
+    if path is not None:
+        return _declare(ctypes.CDLL(path))
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = _declare(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _declare(lib):
+    c = ctypes
+    lib.orc_code_length.argtypes = [c.c_uint32]
+    lib.orc_code_length.restype = c.c_int
+    lib.orc_encode.argtypes = [c.POINTER(c.c_uint32), c.c_size_t, c.POINTER(c.c_uint8)]
+    lib.orc_encode.restype = c.c_size_t
+    lib.orc_encoded_size.argtypes = [c.POINTER(c.c_uint32), c.c_size_t]
+    lib.orc_encoded_size.restype = c.c_size_t
+    lib.orc_encode_delta.argtypes = [c.POINTER(c.c_uint32), c.c_size_t, c.c_uint32,
+                                     c.POINTER(c.c_uint8)]
+    lib.orc_encode_delta.restype = c.c_size_t
+    lib.orc_count.argtypes = [c.POINTER(c.c_uint8), c.c_size_t]
+    lib.orc_count.restype = c.c_uint64
+    lib.orc_validate.argtypes = [c.POINTER(c.c_uint8), c.c_size_t, c.c_size_t]
+    lib.orc_validate.restype = c.c_int
+    lib.orc_decode.argtypes = [c.POINTER(c.c_uint8), c.c_size_t, c.POINTER(c.c_uint32),
+                               c.c_size_t]
+    lib.orc_decode.restype = c.c_int
+    lib.orc_decode_delta.argtypes = [c.POINTER(c.c_uint8), c.c_size_t,
+                                     c.POINTER(c.c_uint32), c.c_size_t, c.c_uint32]
+    lib.orc_decode_delta.restype = c.c_int
+    lib.orc_decode_batch.argtypes = [c.POINTER(c.c_uint8), c.POINTER(c.c_int64),
+                                     c.POINTER(c.c_uint32), c.POINTER(c.c_int64),
+                                     c.c_size_t, c.POINTER(c.c_uint32), c.c_int,
+                                     c.POINTER(c.c_int32)]
+    lib.orc_decode_batch.restype = c.c_int
+    return lib
+
+
+def _as_u32(x):
+    return np.ascontiguousarray(x, dtype=np.uint32)
+
+
+def _as_u8(b):
+    if isinstance(b, (bytes, bytearray)):
+        return np.frombuffer(bytes(b), dtype=np.uint8).copy()
+    return np.ascontiguousarray(b, dtype=np.uint8)
+
+
+def code_length(x, lib=None):
+    """L(x), section 1."""
+    lib = lib or load()
+    return lib.orc_code_length(int(x) & 0xFFFFFFFF)
+
+
+def encoded_size(x, lib=None):
+    lib = lib or load()
+    x = _as_u32(x)
+    return int(lib.orc_encoded_size(_u32p(x), x.size))
+
+
+def encode(x, lib=None):
+    """ENC of a uint32 sequence -> uint8 array (section 1, Table 1)."""
+    lib = lib or load()
+    x = _as_u32(x)
+    out = np.empty(max(5 * x.size, 1), dtype=np.uint8)
+    nb = lib.orc_encode(_u32p(x), x.size, _u8p(out))
+    return out[:nb].copy()
+
+
+def encode_delta(x, prev=0, lib=None):
+    """ENC of the gaps x_i - x_{i-1} mod 2^32, x_0 = prev (section 1)."""
+    lib = lib or load()
+    x = _as_u32(x)
+    out = np.empty(max(5 * x.size, 1), dtype=np.uint8)
+    nb = lib.orc_encode_delta(_u32p(x), x.size, int(prev) & 0xFFFFFFFF, _u8p(out))
+    return out[:nb].copy()
+
+
+def count(b, lib=None):
+    """Number of terminator bytes (top bit 0)."""
+    lib = lib or load()
+    b = _as_u8(b)
+    return int(lib.orc_count(_u8p(b), b.size))
+
+
+def validate(b, n, lib=None):
+    lib = lib or load()
+    b = _as_u8(b)
+    return int(lib.orc_validate(_u8p(b), b.size, int(n)))
+
+
+def decode(b, n, lib=None):
+    """DEC (Algorithm 1 after validation).  Returns (status, uint32 array)."""
+    lib = lib or load()
+    b = _as_u8(b)
+    y = np.zeros(max(int(n), 1), dtype=np.uint32)
+    st = lib.orc_decode(_u8p(b), b.size, _u32p(y), int(n))
+    return int(st), y[:int(n)]
+
+
+def decode_delta(b, n, prev=0, lib=None):
+    """DEC then inclusive prefix sum from prev, mod 2^32."""
+    lib = lib or load()
+    b = _as_u8(b)
+    y = np.zeros(max(int(n), 1), dtype=np.uint32)
+    st = lib.orc_decode_delta(_u8p(b), b.size, _u32p(y), int(n), int(prev) & 0xFFFFFFFF)
+    return int(st), y[:int(n)]
+
+
+def decode_batch(b, byte_off, out_off, prevs=None, delta=False, lib=None):
+    """BATCH over CSR offsets.  Returns (status, out, per-list status)."""
+    lib = lib or load()
+    b = _as_u8(b)
+    byte_off = np.ascontiguousarray(byte_off, dtype=np.int64)
+    out_off = np.ascontiguousarray(out_off, dtype=np.int64)
+    nlists = byte_off.size - 1
+    total = int(out_off[-1]) if nlists >= 0 and out_off.size else 0
+    out = np.zeros(max(total, 1), dtype=np.uint32)
+    st_list = np.zeros(max(nlists, 1), dtype=np.int32)
+    pv = None
+    if prevs is not None:
+        pv = _as_u32(prevs)
+    st = lib.orc_decode_batch(_u8p(b), _i64p(byte_off), _u32p(out), _i64p(out_off),
+                              nlists, _u32p(pv) if pv is not None else None,
+                              1 if delta else 0, _i32p(st_list))
+    return int(st), out[:total], st_list[:nlists]

@@ -1,0 +1,210 @@
+/*
+ * vbyte_oracle.c -- plain scalar CPU oracle for VByte coding of uint32.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code, header, table or constant with the HIP library.
+ *
+ * Source: Plaisance, Kurz, Lemire, "Vectorized VByte Decoding"
+ * (arXiv 1503.07387).
+ *
+ *   - Byte format (section 1, Table 1): an integer is written 7 bits per
+ *     byte, least-significant group first; the top bit of a byte is 1 on
+ *     every byte of the code except the last, where it is 0.
+ *   - 32-bit scope (section 1): at most 5 bytes per uint32; the fifth byte
+ *     carries the top 4 bits (section 4, the 2-integer case).
+ *   - Decoder (Algorithm 1): read a byte, finish the integer when the byte
+ *     is below 128, otherwise accumulate its low 7 bits at weight 2^(7j).
+ *   - Differential coding (section 1, "Differential coding"; section 4,
+ *     "Differential Coding"): gaps are successive differences, decoding is
+ *     an inclusive prefix sum carried in a 32-bit integer.
+ *
+ * Readings where the paper is silent (all of them listed in the design doc):
+ *   R1  0 encodes as the single byte 00.
+ *   R3  five or more consecutive bytes with the top bit set anywhere in the
+ *       buffer -> EMALFORMED (a uint32 code is never longer than 5 bytes).
+ *   R4  a fifth byte in [16,128) is accepted; its weight 2^28 wraps mod 2^32
+ *       exactly as Algorithm 1 does in 32-bit arithmetic.
+ *   R5  over-long codes (e.g. 80 00) are accepted and decode to the sum of
+ *       their 7-bit groups.
+ *   R6  exact consumption: the buffer must hold exactly n codes ending at
+ *       its last byte; a last byte >= 0x80 or fewer than n terminators ->
+ *       ETRUNC, more than n terminators -> ECOUNT.  Precedence when several
+ *       apply: EMALFORMED, then ETRUNC, then ECOUNT.
+ *   R7  the differential sum wraps mod 2^32.
+ *   R8  y_i = y_{i-1} + g_i with y_0 = prev (default 0): inclusive scan.
+ *   R9  in a batch every list restarts from its own prev (default 0).
+ *
+ * Status numbering is fixed by the readings above (a larger data-error code
+ * takes precedence): OK 0, EINVAL 1, ECOUNT 2, ETRUNC 3, EMALFORMED 4.
+ */
+#include <stddef.h>
+#include <stdint.h>
+
+enum {
+    ORC_OK = 0,
+    ORC_EINVAL = 1,
+    ORC_ECOUNT = 2,
+    ORC_ETRUNC = 3,
+    ORC_EMALFORMED = 4
+};
+
+/* Code length L(x) from section 1: [0,2^7) -> 1 byte, [2^7,2^14) -> 2 bytes,
+ * and so on; a uint32 needs at most 5. */
+int orc_code_length(uint32_t x)
+{
+    if (x < (1u << 7)) return 1;
+    if (x < (1u << 14)) return 2;
+    if (x < (1u << 21)) return 3;
+    if (x < (1u << 28)) return 4;
+    return 5;
+}
+
+/* ENC(x) (section 1, Table 1): groups of 7 bits, least significant first,
+ * top bit set on every byte but the last.  Returns the number of bytes. */
+int orc_encode_one(uint32_t x, uint8_t *dst)
+{
+    int len = orc_code_length(x);
+    for (int j = 0; j < len; j++) {
+        uint8_t group = (uint8_t)((x >> (7 * j)) & 0x7Fu);
+        dst[j] = (j < len - 1) ? (uint8_t)(group | 0x80u) : group;
+    }
+    return len;
+}
+
+/* Concatenation of ENC(x_i) in sequence order.  dst must hold at least
+ * orc_encoded_size(x, n) bytes.  Returns the number of bytes written. */
+size_t orc_encode(const uint32_t *x, size_t n, uint8_t *dst)
+{
+    size_t pos = 0;
+    for (size_t i = 0; i < n; i++)
+        pos += (size_t)orc_encode_one(x[i], dst + pos);
+    return pos;
+}
+
+size_t orc_encoded_size(const uint32_t *x, size_t n)
+{
+    size_t total = 0;
+    for (size_t i = 0; i < n; i++)
+        total += (size_t)orc_code_length(x[i]);
+    return total;
+}
+
+/* Differential encoding (section 1): write the gaps x_i - x_{i-1} with
+ * x_0 = prev, computed mod 2^32 so any uint32 sequence round-trips. */
+size_t orc_encode_delta(const uint32_t *x, size_t n, uint32_t prev, uint8_t *dst)
+{
+    size_t pos = 0;
+    uint32_t last = prev;
+    for (size_t i = 0; i < n; i++) {
+        uint32_t gap = x[i] - last;  /* unsigned: wraps mod 2^32 */
+        pos += (size_t)orc_encode_one(gap, dst + pos);
+        last = x[i];
+    }
+    return pos;
+}
+
+/* Number of terminator bytes (top bit 0) in the buffer: one per code. */
+uint64_t orc_count(const uint8_t *b, size_t nbytes)
+{
+    uint64_t count = 0;
+    for (size_t i = 0; i < nbytes; i++)
+        if (b[i] < 128) count++;
+    return count;
+}
+
+/* Pass 1 of DEC: classify the buffer against n (readings R3, R6). */
+int orc_validate(const uint8_t *b, size_t nbytes, size_t n)
+{
+    int malformed = 0;
+    int run = 0;
+    uint64_t count = 0;
+    for (size_t i = 0; i < nbytes; i++) {
+        if (b[i] >= 128) {
+            run++;
+            if (run >= 5) malformed = 1;
+        } else {
+            run = 0;
+            count++;
+        }
+    }
+    if (malformed) return ORC_EMALFORMED;
+    if ((nbytes > 0 && b[nbytes - 1] >= 128) || count < (uint64_t)n)
+        return ORC_ETRUNC;
+    if (count > (uint64_t)n) return ORC_ECOUNT;
+    return ORC_OK;
+}
+
+/* Pass 2 of DEC: Algorithm 1, byte by byte, in uint32 arithmetic.  The
+ * caller has validated the buffer, so every code ends on a byte below 128
+ * within 5 bytes and the loop consumes the buffer exactly. */
+static void alg1_decode(const uint8_t *b, size_t n, uint32_t *y)
+{
+    size_t i = 0;
+    for (size_t k = 0; k < n; k++) {
+        uint32_t c = 0;
+        for (int j = 0; j < 5; j++) {
+            uint32_t byte = b[i++];
+            if (byte < 128) {
+                /* j = 4: weight 2^28, only the low 4 bits survive (R4). */
+                y[k] = c + (byte << (7 * j));
+                break;
+            }
+            c = c + ((byte & 0x7Fu) << (7 * j));
+        }
+    }
+}
+
+/* DEC: returns a status; y[0..n) holds the integers when the status is OK
+ * and is left untouched otherwise. */
+int orc_decode(const uint8_t *b, size_t nbytes, uint32_t *y, size_t n)
+{
+    int st = orc_validate(b, nbytes, n);
+    if (st != ORC_OK) return st;
+    alg1_decode(b, n, y);
+    return ORC_OK;
+}
+
+/* DEC_DELTA: DEC, then the inclusive prefix sum y_i = y_{i-1} + g_i with
+ * y_0 = prev, mod 2^32 (R7, R8). */
+int orc_decode_delta(const uint8_t *b, size_t nbytes, uint32_t *y, size_t n,
+                     uint32_t prev)
+{
+    int st = orc_decode(b, nbytes, y, n);
+    if (st != ORC_OK) return st;
+    uint32_t s = prev;
+    for (size_t k = 0; k < n; k++) {
+        s = s + y[k];
+        y[k] = s;
+    }
+    return ORC_OK;
+}
+
+/* BATCH (R9): list i is bytes[byte_off[i], byte_off[i+1]) and decodes to
+ * out[out_off[i], out_off[i+1]), independently of every other list.
+ * prevs may be NULL (all 0).  list_status[i] receives each list's status.
+ * Returns EINVAL for decreasing offsets (nothing decoded), else the largest
+ * per-list status. */
+int orc_decode_batch(const uint8_t *bytes, const int64_t *byte_off,
+                     uint32_t *out, const int64_t *out_off, size_t nlists,
+                     const uint32_t *prevs, int delta, int32_t *list_status)
+{
+    for (size_t i = 0; i < nlists; i++) {
+        if (byte_off[i + 1] < byte_off[i] || out_off[i + 1] < out_off[i])
+            return ORC_EINVAL;
+    }
+    int worst = ORC_OK;
+    for (size_t i = 0; i < nlists; i++) {
+        const uint8_t *b = bytes + byte_off[i];
+        size_t nb = (size_t)(byte_off[i + 1] - byte_off[i]);
+        size_t n = (size_t)(out_off[i + 1] - out_off[i]);
+        uint32_t *y = out + out_off[i];
+        uint32_t prev = prevs ? prevs[i] : 0u;
+        int st = delta ? orc_decode_delta(b, nb, y, n, prev)
+                       : orc_decode(b, nb, y, n);
+        list_status[i] = st;
+        if (st > worst) worst = st;
+    }
+    return worst;
+}

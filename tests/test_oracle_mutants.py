@@ -1,0 +1,72 @@
+"""Plant plausible mistakes in copies of the oracle (CPU only) and check that
+the pins catch every one of them.
+
+Each mutant is the oracle source with one textual change, compiled with gcc
+into a temporary directory and exercised in a child process, so a mutant that
+misbehaves cannot take the test run down.  The real oracle is never modified.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "vbyte_oracle.c")
+
+# (name, original text, mutated text); each original must occur exactly once.
+MUTANTS = [
+    ("enc_shift_8", "((x >> (7 * j)) & 0x7Fu)", "((x >> (8 * j)) & 0x7Fu)"),
+    ("enc_cont_on_last", "(j < len - 1) ? (uint8_t)(group | 0x80u)", "(j < len) ? (uint8_t)(group | 0x80u)"),
+    ("len_threshold_14", "if (x < (1u << 14)) return 2;", "if (x < (1u << 15)) return 2;"),
+    ("len_threshold_28", "if (x < (1u << 28)) return 4;", "if (x < (1u << 27)) return 4;"),
+    ("dec_shift_8", "c = c + ((byte & 0x7Fu) << (7 * j));", "c = c + ((byte & 0x7Fu) << (8 * j));"),
+    ("dec_drop_mask", "c = c + ((byte & 0x7Fu) << (7 * j));", "c = c + (byte << (7 * j));"),
+    ("dec_four_bytes", "for (int j = 0; j < 5; j++) {", "for (int j = 0; j < 4; j++) {"),
+    ("dec_terminator_le", "if (byte < 128) {\n                /*", "if (byte <= 128) {\n                /*"),
+    ("val_run6", "if (run >= 5) malformed = 1;", "if (run >= 6) malformed = 1;"),
+    ("val_no_lastbyte", "if ((nbytes > 0 && b[nbytes - 1] >= 128) || count < (uint64_t)n)",
+     "if (count < (uint64_t)n)"),
+    ("val_swap_trunc_count", "if (count > (uint64_t)n) return ORC_ECOUNT;", "if (count > (uint64_t)n) return ORC_ETRUNC;"),
+    ("count_le", "if (b[i] < 128) count++;", "if (b[i] <= 128) count++;"),
+    ("delta_no_prev", "uint32_t s = prev;", "uint32_t s = 0;"),
+    ("delta_exclusive", "s = s + y[k];\n        y[k] = s;", "uint32_t g = y[k];\n        y[k] = s;\n        s = s + g;"),
+    ("delta_sign", "s = s + y[k];", "s = s - y[k];"),
+    ("encdelta_sign", "uint32_t gap = x[i] - last;", "uint32_t gap = last - x[i];"),
+    ("batch_no_prev", "uint32_t prev = prevs ? prevs[i] : 0u;", "uint32_t prev = 0u;"),
+    ("batch_no_einval", "return ORC_EINVAL;\n    }\n    int worst", "(void)0;\n    }\n    int worst"),
+]
+
+RUNNER = r"""
+import sys
+sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+import oracle.oracle as oo
+import pins
+lib = oo.load({lib!r})
+for p in pins.ALL_PINS:
+    try:
+        p(lib)
+    except AssertionError:
+        print("CAUGHT", p.__name__)
+        sys.exit(0)
+print("SURVIVED")
+sys.exit(0)
+"""
+
+
+@pytest.mark.parametrize("name,orig,mut", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, orig, mut):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} not unique"
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(src.replace(orig, mut))
+    mlib = str(tmp_path / "libmutant.so")
+    oracle.build(src=str(msrc), out=mlib, extra_flags=("-w",))
+    code = RUNNER.format(root=ROOT, tests=os.path.join(ROOT, "tests"), lib=mlib)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    out = r.stdout + r.stderr
+    # a crash of the mutant also counts as caught, but say so
+    assert "SURVIVED" not in out, f"mutant {name} passed every pin"
+    assert r.returncode == 0 or r.returncode < 0 or "CAUGHT" in out
