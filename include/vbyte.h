@@ -97,29 +97,40 @@ vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count,
  * document identifiers is coded independently, from x_1 - 0).  List i is
  * bytes[byte_off[i], byte_off[i+1]) and decodes to out[out_off[i],
  * out_off[i+1]) with n_i = out_off[i+1] - out_off[i] integers.
- *   byte_off, out_off: device int64[nlists+1], non-decreasing (checked on
- *     the device; a decreasing pair sets VBYTE_EINVAL on the lists around it).
+ *   bytes, nbytes: the byte array that holds every list (device).
+ *   byte_off, out_off: device int64[nlists+1].  A list whose byte range
+ *     leaves [0, nbytes), whose output range leaves [0, nout), or whose
+ *     offsets decrease gets VBYTE_EINVAL and is not decoded (checked on the
+ *     device, so nothing outside the buffers is touched).
+ *   out, nout: output array of nout uint32 (device).
  *   prevs: device uint32[nlists] start values for delta lists, or NULL (0).
  *   delta: 0 plain, 1 differential.
  *   d_list_status: device int32[nlists], required; receives each list's
  *     status under the strict semantics above.
- * One persistent launch decodes every list: lists larger than one tile are
- * split into tiles chained by a look-back scan, small lists take one
+ * A small prep kernel classifies the lists and builds a work table; one
+ * persistent launch then decodes every list: lists larger than
+ * small_list_bytes (vbyte_set_tuning) are split into tiles chained by a
+ * per-list look-back scan and are queued first, smaller lists take one
  * wavefront each.  Asynchronous on `stream`. */
-vbyte_status vbyte_decode_batch(const uint8_t *bytes, const int64_t *byte_off, uint32_t *out,
-                                const int64_t *out_off, size_t nlists, const uint32_t *prevs,
-                                int delta, int32_t *d_list_status, void *stream);
+vbyte_status vbyte_decode_batch(const uint8_t *bytes, size_t nbytes, const int64_t *byte_off,
+                                uint32_t *out, size_t nout, const int64_t *out_off, size_t nlists,
+                                const uint32_t *prevs, int delta, int32_t *d_list_status,
+                                void *stream);
 
 /* Gather form of the batch, for lists that are not adjacent in memory (the
- * serving loop decodes the lists of a query out of a resident index).
- * lists: device int64[nlists][4] rows (byte_begin, byte_end, out_begin, n);
- * list i is bytes[byte_begin, byte_end) and decodes to out[out_begin,
- * out_begin + n).  prevs, delta and d_list_status as in vbyte_decode_batch.
- * `work` is an optional device int32 work table built on the host with
- * vbyte_plan_lists (NULL: the library builds it on the device). */
-vbyte_status vbyte_decode_lists(const uint8_t *bytes, const int64_t *lists, uint32_t *out,
-                                size_t nlists, const uint32_t *prevs, int delta,
-                                int32_t *d_list_status, void *stream);
+ * serving loop decodes the lists of several queries out of a resident
+ * index; a list may appear more than once).
+ *   lists: device int64[nlists][4] rows (byte_begin, byte_end, out_begin, n);
+ *     list i is bytes[byte_begin, byte_end) and decodes to
+ *     out[out_begin, out_begin + n).
+ *   list_bytes: an upper bound on the sum of byte_end - byte_begin over the
+ *     rows; it sizes the work table.  If the rows need more, every list
+ *     gets VBYTE_EINVAL.
+ * Everything else as in vbyte_decode_batch. */
+vbyte_status vbyte_decode_lists(const uint8_t *bytes, size_t nbytes, const int64_t *lists,
+                                size_t nlists, size_t list_bytes, uint32_t *out, size_t nout,
+                                const uint32_t *prevs, int delta, int32_t *d_list_status,
+                                void *stream);
 
 /* ------------------------------------------------------------ encoder */
 
@@ -144,7 +155,7 @@ size_t vbyte_workspace_size(size_t nbytes);
 
 /* Tuning knobs of the decode kernels (0 keeps a value unchanged):
  * segs_per_wave: 1 KiB segments one wavefront decodes per tile (1..4);
- * waves_per_block: wavefronts per workgroup (1..16);
+ * waves_per_block: wavefronts per workgroup (1..8);
  * small_list_bytes: lists up to this size take one wavefront each in the
  * batched forms.  Returns VBYTE_EINVAL for an unsupported value. */
 vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t small_list_bytes);

@@ -1,0 +1,380 @@
+// capi.cpp -- the C ABI of libvbyte (include/vbyte.h): argument checks,
+// the per-(device, stream) workspace cache, and kernel launches.
+//
+// Every call validates its arguments on the host and returns VBYTE_EINVAL
+// before enqueuing anything; data errors are produced by the kernels into a
+// device status word.  The library allocates only its own workspace
+// (look-back descriptors, ticket header, batch work tables).
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include <hip/hip_runtime.h>
+
+#include "vbyte.h"
+#include "vbyte_internal.h"
+
+namespace vb {
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+std::atomic<int> g_segs{4};
+std::atomic<int> g_wpb{4};
+std::atomic<int64_t> g_small{8192};
+
+vbyte_status hip_fail(hipError_t e, const char *what) {
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
+    return VBYTE_EHIP;
+}
+
+// Workspace layout (bytes):
+//   [0, 8)      ticket/epoch header word
+//   [64, 68)    status slot used by the synchronous calls
+//   [128, 152)  batch totals (3 x uint64)
+//   [256, ...)  descriptors, then batch tables
+constexpr size_t kStatusOff = 64;
+constexpr size_t kTotalsOff = 128;
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    uint64_t launches = 0;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+struct Cleanup {
+    ~Cleanup() {
+        // Process exit: the runtime may already be torn down; release quietly.
+        for (auto &kv : g_ws)
+            if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    }
+} g_cleanup;
+
+// Returns a workspace of at least `need` bytes for `stream`, zero-filled on
+// (re)allocation and re-zeroed before the epoch tag could wrap.  `launches`
+// is the number of ticketed launches the caller is about to enqueue.
+vbyte_status get_ws(hipStream_t stream, size_t need, int launches, Workspace **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace &w = g_ws[{dev, stream}];
+    need = std::max(need, kHeaderBytes);
+    if (w.bytes < need) {
+        if (w.ptr) {
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        size_t sz = std::max(need + need / 2, (size_t)1 << 20);
+        sz = (sz + 255) & ~(size_t)255;
+        e = hipMalloc(&w.ptr, sz);
+        if (e != hipSuccess) {
+            w.ptr = nullptr;
+            std::snprintf(g_last_error, sizeof g_last_error, "hipMalloc(%zu): %s", sz, hipGetErrorString(e));
+            return VBYTE_ENOMEM;
+        }
+        w.bytes = sz;
+        w.launches = 0;
+        e = launch_zero(w.ptr, sz, stream);
+        if (e != hipSuccess) return hip_fail(e, "zero workspace");
+    }
+    if (w.launches + (uint64_t)launches >= kEpochLaunchLimit) {
+        e = launch_zero(w.ptr, w.bytes, stream);
+        if (e != hipSuccess) return hip_fail(e, "re-zero workspace");
+        w.launches = 0;
+    }
+    w.launches += (uint64_t)launches;
+    *out = &w;
+    return VBYTE_OK;
+}
+
+uint8_t *ws_base(Workspace *w) { return (uint8_t *)w->ptr; }
+
+constexpr uint64_t kMaxBytes = 1ull << 36;
+
+// Enqueues a single-stream decode.  With d_status == nullptr the status goes
+// to the workspace's own slot, returned through *slot (synchronous calls).
+vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                           uint32_t prev, int delta, int32_t *d_status, hipStream_t s,
+                           int32_t **slot = nullptr) {
+    if (nbytes >= kMaxBytes) return VBYTE_EINVAL;
+    if (nbytes > 0 && !bytes) return VBYTE_EINVAL;
+    if (n > 0 && !out) return VBYTE_EINVAL;
+    if (((uintptr_t)out & 3u) != 0) return VBYTE_EINVAL;
+    if (((uintptr_t)d_status & 3u) != 0) return VBYTE_EINVAL;
+    if (!d_status && !slot) return VBYTE_EINVAL;
+    const int segs = g_segs.load(), wpb = g_wpb.load();
+    StreamArgs a{};
+    a.vstart = (uintptr_t)bytes & 15u;
+    a.base = bytes - a.vstart;
+    a.vend = a.vstart + nbytes;
+    a.out = out;
+    a.n = n;
+    a.prev = prev;
+    const uint64_t ntiles = nbytes ? stream_tiles(a.vstart, nbytes, segs) : 0;
+    if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
+    a.ntiles = (uint32_t)ntiles;
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, kHeaderBytes + ntiles * sizeof(Desc), ntiles ? 1 : 0, &w);
+    if (st != VBYTE_OK) return st;
+    if (!d_status) {
+        d_status = (int32_t *)(ws_base(w) + kStatusOff);
+        *slot = d_status;
+    }
+    if (nbytes == 0) {
+        hipError_t e = launch_set_status(d_status, n == 0 ? VBYTE_OK : VBYTE_ETRUNC, s);
+        return e == hipSuccess ? VBYTE_OK : hip_fail(e, "set status");
+    }
+    a.hdr = (uint64_t *)ws_base(w);
+    a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
+    a.d_status = d_status;
+    a.d_count = nullptr;
+    hipError_t e = launch_stream(a, delta, 0, segs, wpb, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode launch");
+}
+
+vbyte_status decode_sync(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n, uint32_t prev,
+                         int delta) {
+    hipStream_t s = nullptr;
+    int32_t *slot = nullptr;
+    vbyte_status st = decode_stream(bytes, nbytes, out, n, prev, delta, nullptr, s, &slot);
+    if (st != VBYTE_OK) return st;
+    int32_t h = -1;
+    hipError_t e = hipMemcpyAsync(&h, slot, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return (vbyte_status)h;
+}
+
+vbyte_status batch_common(ListArgs a, size_t list_bytes, hipStream_t s) {
+    if (a.nlists == 0) return VBYTE_OK;
+    if (!a.list_status || ((uintptr_t)a.list_status & 3u)) return VBYTE_EINVAL;
+    if (!a.bytes && a.nbytes) return VBYTE_EINVAL;
+    if (!a.out && a.nout) return VBYTE_EINVAL;
+    if (((uintptr_t)a.out & 3u) != 0) return VBYTE_EINVAL;
+    if (a.nlists >= (1ull << 31)) return VBYTE_EINVAL;
+    const int segs = g_segs.load(), wpb = g_wpb.load();
+    const uint64_t tb = (uint64_t)segs * kSegBytes;
+    a.small_bytes = (uint64_t)std::max<int64_t>(g_small.load(), 0);
+    // A large list holds more than small_bytes bytes and needs at most
+    // bytes/tb + 2 tiles; a small list needs one item.
+    const uint64_t nlarge_max = std::min<uint64_t>(a.nlists, list_bytes / (a.small_bytes + 1));
+    a.max_items = list_bytes / tb + 2 * nlarge_max + a.nlists + 2;
+    if (a.max_items >= (1ull << 31)) return VBYTE_EINVAL;
+    const uint32_t nblocks = (uint32_t)((a.nlists + kPrepBlock - 1) / kPrepBlock);
+    size_t off = kHeaderBytes;
+    const size_t desc_off = off;
+    off += a.max_items * sizeof(Desc);
+    const size_t prep_off = off;
+    off += (size_t)nblocks * sizeof(Desc);
+    const size_t items_off = off;
+    off += a.max_items * sizeof(int2);
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, off, 2, &w);
+    if (st != VBYTE_OK) return st;
+    uint8_t *b = ws_base(w);
+    a.hdr = (uint64_t *)b;
+    a.totals = (uint64_t *)(b + kTotalsOff);
+    a.desc = (Desc *)(b + desc_off);
+    a.prep_desc = (Desc *)(b + prep_off);
+    a.items = (int2 *)(b + items_off);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    const int grid = cus * std::max(1, 16 / wpb);
+    a.nwaves = (uint32_t)(grid * wpb);
+    hipError_t e = launch_batch(a, segs, wpb, grid, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "batch launch");
+}
+
+}  // namespace
+}  // namespace vb
+
+using namespace vb;
+
+extern "C" {
+
+vbyte_status vbyte_decode(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n) {
+    return decode_sync(bytes, nbytes, out, n, 0, 0);
+}
+
+vbyte_status vbyte_decode_delta(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                uint32_t prev) {
+    return decode_sync(bytes, nbytes, out, n, prev, 1);
+}
+
+vbyte_status vbyte_decode_async(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                int32_t *d_status, void *stream) {
+    return decode_stream(bytes, nbytes, out, n, 0, 0, d_status, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_decode_delta_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
+                                      size_t n, uint32_t prev, int32_t *d_status, void *stream) {
+    return decode_stream(bytes, nbytes, out, n, prev, 1, d_status, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (!d_count || ((uintptr_t)d_count & 7u)) return VBYTE_EINVAL;
+    if (nbytes >= kMaxBytes) return VBYTE_EINVAL;
+    if (nbytes > 0 && !bytes) return VBYTE_EINVAL;
+    if (nbytes == 0) {
+        hipError_t e = launch_set_u64(d_count, 0, s);
+        return e == hipSuccess ? VBYTE_OK : hip_fail(e, "set count");
+    }
+    const int segs = g_segs.load(), wpb = g_wpb.load();
+    StreamArgs a{};
+    a.vstart = (uintptr_t)bytes & 15u;
+    a.base = bytes - a.vstart;
+    a.vend = a.vstart + nbytes;
+    a.out = nullptr;
+    a.n = 0;
+    const uint64_t ntiles = stream_tiles(a.vstart, nbytes, segs);
+    if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
+    a.ntiles = (uint32_t)ntiles;
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, kHeaderBytes + ntiles * sizeof(Desc), 1, &w);
+    if (st != VBYTE_OK) return st;
+    a.hdr = (uint64_t *)ws_base(w);
+    a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
+    a.d_status = nullptr;
+    a.d_count = d_count;
+    hipError_t e = launch_stream(a, 0, 1, segs, wpb, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "count launch");
+}
+
+vbyte_status vbyte_decode_batch(const uint8_t *bytes, size_t nbytes, const int64_t *byte_off,
+                                uint32_t *out, size_t nout, const int64_t *out_off, size_t nlists,
+                                const uint32_t *prevs, int delta, int32_t *d_list_status,
+                                void *stream) {
+    if (nlists > 0 && (!byte_off || !out_off)) return VBYTE_EINVAL;
+    if (delta != 0 && delta != 1) return VBYTE_EINVAL;
+    ListArgs a{};
+    a.bytes = bytes;
+    a.nbytes = nbytes;
+    a.nout = nout;
+    a.byte_off = byte_off;
+    a.out_off = out_off;
+    a.rows = nullptr;
+    a.out = out;
+    a.prevs = prevs;
+    a.list_status = d_list_status;
+    a.nlists = nlists;
+    a.delta = delta;
+    return batch_common(a, nbytes, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_decode_lists(const uint8_t *bytes, size_t nbytes, const int64_t *lists,
+                                size_t nlists, size_t list_bytes, uint32_t *out, size_t nout,
+                                const uint32_t *prevs, int delta, int32_t *d_list_status,
+                                void *stream) {
+    if (nlists > 0 && !lists) return VBYTE_EINVAL;
+    if (delta != 0 && delta != 1) return VBYTE_EINVAL;
+    ListArgs a{};
+    a.bytes = bytes;
+    a.nbytes = nbytes;
+    a.nout = nout;
+    a.byte_off = nullptr;
+    a.out_off = nullptr;
+    a.rows = lists;
+    a.out = out;
+    a.prevs = prevs;
+    a.list_status = d_list_status;
+    a.nlists = nlists;
+    a.delta = delta;
+    return batch_common(a, list_bytes, (hipStream_t)stream);
+}
+
+static vbyte_status encode_common(const uint32_t *values, size_t n, uint32_t prev, int delta,
+                                  uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
+                                  hipStream_t s) {
+    if (!d_nbytes || ((uintptr_t)d_nbytes & 7u)) return VBYTE_EINVAL;
+    if (n > 0 && !values) return VBYTE_EINVAL;
+    if (((uintptr_t)values & 3u) != 0) return VBYTE_EINVAL;
+    if (capacity > 0 && !bytes) return VBYTE_EINVAL;
+    if (n == 0) {
+        hipError_t e = launch_set_u64(d_nbytes, 0, s);
+        return e == hipSuccess ? VBYTE_OK : hip_fail(e, "set nbytes");
+    }
+    const uint64_t ntiles = (n + kEncodeWaveValues - 1) / kEncodeWaveValues;
+    if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
+    EncodeArgs a{};
+    a.values = values;
+    a.n = n;
+    a.prev = prev;
+    a.delta = delta;
+    a.bytes = bytes;
+    a.capacity = capacity;
+    a.d_nbytes = d_nbytes;
+    a.ntiles = (uint32_t)ntiles;
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, kHeaderBytes + ntiles * sizeof(Desc), 1, &w);
+    if (st != VBYTE_OK) return st;
+    a.hdr = (uint64_t *)ws_base(w);
+    a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
+    hipError_t e = launch_encode(a, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "encode launch");
+}
+
+vbyte_status vbyte_encode_async(const uint32_t *values, size_t n, uint8_t *bytes, size_t capacity,
+                                uint64_t *d_nbytes, void *stream) {
+    return encode_common(values, n, 0, 0, bytes, capacity, d_nbytes, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_encode_delta_async(const uint32_t *values, size_t n, uint32_t prev,
+                                      uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
+                                      void *stream) {
+    return encode_common(values, n, prev, 1, bytes, capacity, d_nbytes, (hipStream_t)stream);
+}
+
+size_t vbyte_workspace_size(size_t nbytes) {
+    return kHeaderBytes + stream_tiles(15, nbytes, g_segs.load()) * sizeof(Desc);
+}
+
+vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t small_list_bytes) {
+    if (segs_per_wave != 0 && segs_per_wave != 1 && segs_per_wave != 2 && segs_per_wave != 4)
+        return VBYTE_EINVAL;
+    if (waves_per_block < 0 || waves_per_block > 8) return VBYTE_EINVAL;
+    if (small_list_bytes < 0) return VBYTE_EINVAL;
+    if (segs_per_wave) g_segs.store(segs_per_wave);
+    if (waves_per_block) g_wpb.store(waves_per_block);
+    if (small_list_bytes) g_small.store(small_list_bytes);
+    return VBYTE_OK;
+}
+
+void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_list_bytes) {
+    if (segs_per_wave) *segs_per_wave = g_segs.load();
+    if (waves_per_block) *waves_per_block = g_wpb.load();
+    if (small_list_bytes) *small_list_bytes = g_small.load();
+}
+
+const char *vbyte_status_str(vbyte_status st) {
+    switch (st) {
+        case VBYTE_OK: return "VBYTE_OK";
+        case VBYTE_EINVAL: return "VBYTE_EINVAL";
+        case VBYTE_ECOUNT: return "VBYTE_ECOUNT";
+        case VBYTE_ETRUNC: return "VBYTE_ETRUNC";
+        case VBYTE_EMALFORMED: return "VBYTE_EMALFORMED";
+        case VBYTE_EHIP: return "VBYTE_EHIP";
+        case VBYTE_ENOMEM: return "VBYTE_ENOMEM";
+    }
+    return "VBYTE_UNKNOWN";
+}
+
+const char *vbyte_last_error(void) { return g_last_error; }
+
+}  // extern "C"

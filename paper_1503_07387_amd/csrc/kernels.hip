@@ -1,0 +1,916 @@
+// kernels.hip -- gfx950 (MI355X) kernels of libvbyte: VByte decoding of
+// uint32 (plain and differential), terminator counting, encoding, and the
+// batched / persistent decode of many posting lists.
+//
+// Method: Plaisance, Kurz, Lemire, "Vectorized VByte Decoding".  The byte
+// format is that of section 1 / Table 1; a code ends at its terminator byte
+// (top bit 0) and its value is the sum of its 7-bit groups at weights
+// 2^(7j) in uint32 arithmetic (Algorithm 1).  Differential decoding is an
+// inclusive prefix sum of the gaps carried in 32 bits (section 1,
+// "Differential coding"; section 4, "Differential Coding").
+//
+// GPU design (the paper's x86 Masked VByte is prior art, not the design):
+//  * A wavefront owns tiles of SEGS x 1 KiB.  Each lane loads 16 bytes of a
+//    segment with one 128-bit load; the 4 bytes before a lane's 16 come from
+//    the lane below via DPP wave_shr (the "halo"), so a code that starts in
+//    one lane and ends in the next is resolved where its terminator lies.
+//    Codes are at most 5 bytes, so 4 halo bytes always reach a code's start
+//    (the paper's decoder likewise relies on a segment beginning with a
+//    whole code, section 4).
+//  * The terminator mask of a lane's 16 bytes plays the role of the paper's
+//    pmovmskb continuation mask (complemented); its popcount is the lane's
+//    number of integers, and a DPP wave scan of the counts gives every lane
+//    its output rank -- the GPU counterpart of the "bytes consumed" chain.
+//  * Ranks across tiles come from a single-pass decoupled look-back over
+//    per-tile descriptors (tile count, tile gap sum, malformed flag), so the
+//    stream is read once.
+//  * Each lane assembles its codes sequentially over its 20-byte window
+//    (7-bit groups shifted into place; the fifth group's shift of 28 wraps
+//    mod 2^32 like Algorithm 1), writes them compacted into LDS, and the
+//    wavefront stores them to HBM with aligned 128-bit stores.
+//  * The differential form adds a lane-local running sum, a wave scan of
+//    lane sums, the tile's exclusive prefix sum from the look-back, and the
+//    caller's start value, all mod 2^32 (the wave-level counterpart of the
+//    4-wide shift-and-add prefix sum of section 4).
+//  * Descriptor words are published and read with relaxed agent-scope 64-bit
+//    atomics that bypass the per-XCD L2, so no cache-flushing fence is
+//    needed between tiles on different XCDs.
+
+#include "vbyte_internal.h"
+#include "vbyte.h"
+
+namespace vb {
+namespace {
+
+typedef uint8_t u8;
+typedef uint32_t u32;
+typedef uint64_t u64;
+typedef int64_t i64;
+
+constexpr u64 kCountMask = (1ull << 37) - 1;
+
+// ------------------------------------------------------------------ atomics
+__device__ __forceinline__ u64 aload(const u64 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void astore(u64 *p, u64 v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 aadd(u64 *p, u64 v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ u32 lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ u32 first_lane(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ u64 first_lane64(u64 v) {
+    return ((u64)first_lane((u32)(v >> 32)) << 32) | first_lane((u32)v);
+}
+__device__ __forceinline__ u32 read_lane(u32 v, u32 l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ u64 ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ u32 dpp_zero(u32 x) {
+    return (u32)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, true);
+}
+
+// Inclusive wave64 prefix sum, mod 2^32: four row shifts inside each row of
+// 16 lanes, then row broadcasts of lanes 15 and 31.
+__device__ __forceinline__ u32 wave_scan(u32 x) {
+    x += dpp_zero<0x111>(x);        // row_shr:1
+    x += dpp_zero<0x112>(x);        // row_shr:2
+    x += dpp_zero<0x114>(x);        // row_shr:4
+    x += dpp_zero<0x118>(x);        // row_shr:8
+    x += dpp_zero<0x142, 0xA>(x);   // row_bcast:15 -> rows 1, 3
+    x += dpp_zero<0x143, 0xC>(x);   // row_bcast:31 -> rows 2, 3
+    return x;
+}
+__device__ __forceinline__ u32 wave_sum(u32 x) { return read_lane(wave_scan(x), 63); }
+
+// Value of lane-1 (wave_shr:1); lane 0 receives `lane0`.
+__device__ __forceinline__ u32 from_lane_below(u32 x, u32 lane0) {
+    return (u32)__builtin_amdgcn_update_dpp((int)lane0, (int)x, 0x138, 0xF, 0xF, false);
+}
+
+// LDS written by some lanes of a wavefront and read by others: LDS
+// instructions of one wavefront execute in order, so a compiler barrier at
+// wavefront scope is all that is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------ descriptors
+__device__ __forceinline__ u32 make_tag(u32 epoch) { return (1u << 25) | (epoch & 0x1FFFFFFu); }
+__device__ __forceinline__ u64 pack_c(u32 tag, bool mal, u64 c) {
+    return ((u64)tag << 38) | ((u64)(mal ? 1 : 0) << 37) | (c & kCountMask);
+}
+__device__ __forceinline__ u64 pack_s(u32 tag, u32 s) { return ((u64)tag << 32) | s; }
+
+struct Prefix {
+    u64 c;
+    u32 s;
+    bool mal;
+};
+
+// Decoupled look-back: exclusive prefix of descriptor `idx` over the chain
+// that starts at descriptor `first` (which always publishes an inclusive
+// value).  All 64 lanes read one predecessor each per round.
+template <bool SUM>
+__device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first, u32 tag) {
+    const u32 ln = lane_id();
+    u64 acc_c = 0;
+    u32 acc_s = 0;
+    bool acc_m = false;
+    i64 pos = idx - 1;
+    for (;;) {
+        const i64 p = pos - (i64)ln;
+        u32 state = 2;   // 0 not ready, 1 aggregate, 2 inclusive (or before the chain)
+        u64 cv = 0;
+        u32 sv = 0;
+        if (p >= first) {
+            const Desc *d = desc + p;
+            const u64 ci = aload(&d->c_inc), ca = aload(&d->c_agg);
+            const u64 si = SUM ? aload(&d->s_inc) : 0, sa = SUM ? aload(&d->s_agg) : 0;
+            const bool inc = (u32)(ci >> 38) == tag && (!SUM || (u32)(si >> 32) == tag);
+            const bool agg = (u32)(ca >> 38) == tag && (!SUM || (u32)(sa >> 32) == tag);
+            if (inc) {
+                cv = ci;
+                sv = (u32)si;
+            } else if (agg) {
+                state = 1;
+                cv = ca;
+                sv = (u32)sa;
+            } else {
+                state = 0;
+            }
+        }
+        const u64 m_inc = ballot(state == 2);
+        const u64 m_nr = ballot(state == 0);
+        const u32 fi = m_inc ? (u32)__builtin_ctzll(m_inc) : 64u;
+        const u32 fn = m_nr ? (u32)__builtin_ctzll(m_nr) : 64u;
+        const u32 lim = fi < fn ? fi : fn;
+        const bool take = ln < lim;
+        acc_c += wave_sum(take ? (u32)(cv & kCountMask) : 0u);
+        if (SUM) acc_s += wave_sum(take ? sv : 0u);
+        acc_m |= ballot(take && ((cv >> 37) & 1)) != 0;
+        if (fi < fn) {
+            const u64 c = ((u64)read_lane((u32)(cv >> 32), fi) << 32) | read_lane((u32)cv, fi);
+            acc_c += c & kCountMask;
+            acc_m |= ((c >> 37) & 1) != 0;
+            if (SUM) acc_s += read_lane(sv, fi);
+            break;
+        }
+        pos -= lim;
+        if (lim == 0) __builtin_amdgcn_s_sleep(1);
+    }
+    return Prefix{acc_c, acc_s, acc_m};
+}
+
+// ------------------------------------------------------------ byte loads
+__device__ __forceinline__ void load16(const u8 *p, u32 (&w)[4]) {
+    const uint4 q = *(const uint4 *)p;
+    w[0] = q.x;
+    w[1] = q.y;
+    w[2] = q.z;
+    w[3] = q.w;
+}
+
+// Bytes [v, v+16) of the aligned base; only bytes in [lo, hi) are read, the
+// others are zero and marked invalid.
+__device__ __forceinline__ void load16_guarded(const u8 *base, u64 v, u64 lo, u64 hi, u32 (&w)[4],
+                                               u32 &valid) {
+    w[0] = w[1] = w[2] = w[3] = 0;
+    valid = 0;
+    if (v >= lo && v + 16 <= hi) {
+        load16(base + v, w);
+        valid = 0xFFFFu;
+        return;
+    }
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const u64 p = v + b;
+        if (p >= lo && p < hi) {
+            w[b >> 2] |= (u32)base[p] << (8 * (b & 3));
+            valid |= 1u << b;
+        }
+    }
+}
+
+// 4 bytes [v, v+4) (v a multiple of 4) with validity bits at 12..15, the
+// position a lane's last dword has in its 16-bit validity mask.
+__device__ __forceinline__ void load4_guarded(const u8 *base, i64 v, u64 lo, u64 hi, u32 &w,
+                                              u32 &valid_hi) {
+    w = 0;
+    valid_hi = 0;
+    if (v >= (i64)lo && (u64)v + 4 <= hi) {
+        w = *(const u32 *)(base + v);
+        valid_hi = 0xF000u;
+        return;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const i64 p = v + b;
+        if (p >= (i64)lo && (u64)p < hi) {
+            w |= (u32)base[p] << (8 * b);
+            valid_hi |= 1u << (12 + b);
+        }
+    }
+}
+
+// Top bit of each byte of w (bit 7 of byte k -> bit k).
+__device__ __forceinline__ u32 top4(u32 w) {
+    u32 t = w & 0x80808080u;
+    t |= t << 7;    // bytes 0,1 -> bits 14,15; bytes 2,3 -> bits 30,31
+    t |= t << 14;   // bits 14,15 -> 28,29
+    return t >> 28;
+}
+__device__ __forceinline__ u32 top16(const u32 (&w)[4]) {
+    return top4(w[0]) | (top4(w[1]) << 4) | (top4(w[2]) << 8) | (top4(w[3]) << 12);
+}
+
+// Per-lane segment summary: terminator mask (valid bytes < 0x80), count and
+// whether a run of 5 continuation bytes ends in the lane's 16 bytes.
+struct SegMask {
+    u32 term;
+    u32 cnt;
+    bool mal;
+};
+__device__ __forceinline__ SegMask seg_mask(const u32 (&w)[4], u32 valid, u32 h, u32 hvalid_hi) {
+    const u32 top = top16(w);
+    const u32 cont = top & valid;
+    const u32 term = ~top & valid;
+    // 20-bit continuation window: halo bytes at bits 0..3, own at 4..19
+    const u32 c20 = (cont << 4) | ((top4(h) & (hvalid_hi >> 12)) & 0xFu);
+    const u32 run5 = c20 & (c20 >> 1) & (c20 >> 2) & (c20 >> 3) & (c20 >> 4);
+    SegMask m;
+    m.term = term;
+    m.cnt = __builtin_popcount(term);
+    m.mal = (run5 & 0xFFFFu) != 0;
+    return m;
+}
+
+// Sequential assembly over the lane's window: 4 halo bytes (no output) then
+// its 16 bytes.  r[j] receives, for a terminator at byte j, the integer it
+// ends (DELTA: the lane-local inclusive sum of integers up to j).  Returns
+// the lane sum of integers.  Invalid bytes reset the state and end nothing.
+template <bool DELTA, bool EDGE>
+__device__ __forceinline__ u32 assemble(const u32 (&w)[4], u32 valid, u32 h, u32 hvalid_hi,
+                                        u32 (&r)[16]) {
+    u32 acc = 0, sh = 0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const u32 g = __builtin_amdgcn_ubfe(h, 8 * p, 7);
+        const u32 v = acc | (g << (sh & 31));
+        u32 km = (u32)__builtin_amdgcn_sbfe(h, 8 * p + 7, 1);
+        if (EDGE) km &= 0u - ((hvalid_hi >> (12 + p)) & 1u);
+        acc = v & km;
+        sh = (sh + 7) & km;
+    }
+    u32 s = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const u32 dw = w[j >> 2];
+        const int o = 8 * (j & 3);
+        const u32 g = __builtin_amdgcn_ubfe(dw, o, 7);
+        const u32 v = acc | (g << (sh & 31));
+        u32 km = (u32)__builtin_amdgcn_sbfe(dw, o + 7, 1);
+        u32 tm = ~km;
+        if (EDGE) {
+            const u32 vb = 0u - ((valid >> j) & 1u);
+            km &= vb;
+            tm &= vb;
+        }
+        if (DELTA) {
+            s += v & tm;
+            r[j] = s;
+        } else {
+            r[j] = v;
+        }
+        acc = v & km;
+        sh = (sh + 7) & km;
+    }
+    return s;
+}
+
+// Write the lane's integers, compacted, to stage[amis + lex + k].
+template <bool DELTA>
+__device__ __forceinline__ void emit(u32 *stage, u32 start, u32 term, const u32 (&r)[16], u32 add) {
+    u32 k = start;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if ((term >> j) & 1u) {
+            stage[k] = DELTA ? r[j] + add : r[j];
+            ++k;
+        }
+    }
+}
+
+// Misalignment (in uint32 elements, 0..3) of out + gbase against 16 bytes.
+__device__ __forceinline__ u32 out_mis(const u32 *out, u64 gbase) {
+    return (u32)((((uintptr_t)out >> 2) + gbase) & 3u);
+}
+
+// Store `total` staged integers (stage[amis + e], e < total) to
+// out[gbase + e] for gbase + e < n, with 16-byte aligned stores.
+template <bool DELTA>
+__device__ __forceinline__ void store_stage(const u32 *stage, u32 amis, u32 total, u32 *out, u64 gbase,
+                                            u64 n, u32 add) {
+    const u32 ln = lane_id();
+    const u32 nq = (amis + total + 3) >> 2;
+    for (u32 q = ln; q < nq; q += kWave) {
+        const u32 i0 = q << 2;
+        const i64 e0 = (i64)i0 - (i64)amis;
+        if (e0 >= 0 && (u64)e0 + 4 <= total && gbase + (u64)e0 + 4 <= n) {
+            uint4 v = *(const uint4 *)(stage + i0);
+            if (DELTA) {
+                v.x += add;
+                v.y += add;
+                v.z += add;
+                v.w += add;
+            }
+            *(uint4 *)(out + gbase + e0) = v;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const i64 e = e0 + t;
+                if (e >= 0 && (u64)e < total && gbase + (u64)e < n)
+                    out[gbase + e] = stage[i0 + t] + (DELTA ? add : 0u);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ one tile
+// A tile of SEGS segments of one stream (or list).  `base` is 16-byte
+// aligned; valid bytes are [vstart, vend); the tile starts at tv.
+struct TileIn {
+    const u8 *base;
+    u64 vstart, vend, tv;
+    u32 *out;
+    u64 n;
+    u32 prev;
+    Desc *desc;
+    i64 didx, dfirst;
+    u32 tag;
+};
+
+struct TileOut {
+    u64 total;   // integers up to and including this tile
+    bool mal;
+};
+
+template <bool DELTA, bool COUNT, int SEGS, bool EDGE>
+__device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage) {
+    const u32 ln = lane_id();
+    u32 w[SEGS][4];
+    u32 valid[SEGS];
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u64 v = t.tv + (u64)s * kSegBytes + 16u * ln;
+        if (EDGE) {
+            load16_guarded(t.base, v, t.vstart, t.vend, w[s], valid[s]);
+        } else {
+            load16(t.base + v, w[s]);
+            valid[s] = 0xFFFFu;
+        }
+    }
+    u32 h0, hv0;
+    if (EDGE) {
+        load4_guarded(t.base, (i64)t.tv - 4, t.vstart, t.vend, h0, hv0);
+    } else {
+        h0 = *(const u32 *)(t.base + t.tv - 4);
+        hv0 = 0xF000u;
+    }
+
+    // Phase 1: masks, counts, ranks (and for DELTA the integers and sums).
+    u32 term[SEGS], lex[SEGS], segbase[SEGS], segcnt[SEGS];
+    u32 lsum[SEGS];
+    u32 r[DELTA ? SEGS : 1][16];
+    u32 ctot = 0, stot = 0;
+    bool mal = false;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 l0w = s == 0 ? h0 : read_lane(w[s - 1][3], 63);
+        const u32 l0v = s == 0 ? hv0 : read_lane(valid[s - 1], 63);
+        const u32 h = from_lane_below(w[s][3], l0w);
+        const u32 hv = EDGE ? from_lane_below(valid[s], l0v) : 0xF000u;
+        const SegMask m = seg_mask(w[s], valid[s], h, hv & 0xF000u);
+        term[s] = m.term;
+        mal |= m.mal;
+        const u32 ci = wave_scan(m.cnt);
+        lex[s] = ci - m.cnt;
+        segbase[s] = ctot;
+        segcnt[s] = read_lane(ci, 63);
+        ctot += segcnt[s];
+        if (DELTA) {
+            const u32 ls = assemble<true, EDGE>(w[s], valid[s], h, hv & 0xF000u, r[s]);
+            const u32 si = wave_scan(ls);
+            lsum[s] = stot + si - ls;
+            stot += read_lane(si, 63);
+        }
+    }
+    const bool tmal = ballot(mal) != 0;
+
+    // Publish the aggregate, look back, publish the inclusive prefix.
+    Prefix ex;
+    if (t.didx == t.dfirst) {
+        ex = Prefix{0, t.prev, false};
+    } else {
+        if (ln == 0) {
+            if (DELTA) astore(&t.desc[t.didx].s_agg, pack_s(t.tag, stot));
+            astore(&t.desc[t.didx].c_agg, pack_c(t.tag, tmal, ctot));
+        }
+        ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag);
+    }
+    const u64 total = ex.c + ctot;
+    const bool allmal = ex.mal || tmal;
+    if (ln == 0) {
+        if (DELTA) astore(&t.desc[t.didx].s_inc, pack_s(t.tag, ex.s + stot));
+        astore(&t.desc[t.didx].c_inc, pack_c(t.tag, allmal, total));
+    }
+    if (COUNT) return TileOut{total, allmal};
+
+    // Phase 2: compact each segment's integers through LDS and store them.
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u64 gbase = ex.c + segbase[s];
+        if (gbase >= t.n || segcnt[s] == 0) continue;
+        const u32 amis = out_mis(t.out, gbase);
+        if (DELTA) {
+            emit<true>(stage, amis + lex[s], term[s], r[s], lsum[s]);
+        } else {
+            const u32 l0w = s == 0 ? h0 : read_lane(w[s - 1][3], 63);
+            const u32 l0v = s == 0 ? hv0 : read_lane(valid[s - 1], 63);
+            const u32 h = from_lane_below(w[s][3], l0w);
+            const u32 hv = EDGE ? from_lane_below(valid[s], l0v) : 0xF000u;
+            u32 rp[16];
+            assemble<false, EDGE>(w[s], valid[s], h, hv & 0xF000u, rp);
+            emit<false>(stage, amis + lex[s], term[s], rp, 0u);
+        }
+        wave_lds_sync();
+        store_stage<DELTA>(stage, amis, segcnt[s], t.out, gbase, t.n, ex.s);
+        wave_lds_sync();
+    }
+    return TileOut{total, allmal};
+}
+
+// Status of a finished stream or list (readings R3-R6): malformed first,
+// then truncated (last byte continues, or too few integers), then count.
+__device__ __forceinline__ int32_t final_status(bool mal, u8 last_byte, u64 total, u64 n) {
+    if (mal) return VBYTE_EMALFORMED;
+    if (last_byte >= 0x80 || total < n) return VBYTE_ETRUNC;
+    if (total > n) return VBYTE_ECOUNT;
+    return VBYTE_OK;
+}
+
+// ------------------------------------------------------------ single stream
+template <bool DELTA, bool COUNT, int SEGS>
+__global__ __launch_bounds__(1024) void k_stream(StreamArgs a) {
+    extern __shared__ u32 lds[];
+    const u32 ln = lane_id();
+    const u32 wib = threadIdx.x >> 6;
+    const u64 wg = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
+    if (wg >= a.ntiles) return;   // exactly ntiles wavefronts take a ticket
+    u32 *stage = lds + wib * kStageWords;
+
+    u64 tw = 0;
+    if (ln == 0) tw = aadd(a.hdr, 1);
+    tw = first_lane64(tw);
+    const u32 tile = (u32)tw;
+    const u32 epoch = (u32)(tw >> 32);
+    if (tile == a.ntiles - 1 && ln == 0) astore(a.hdr, (u64)(epoch + 1) << 32);
+
+    TileIn t;
+    t.base = a.base;
+    t.vstart = a.vstart;
+    t.vend = a.vend;
+    t.tv = (u64)tile * (SEGS * kSegBytes);
+    t.out = a.out;
+    t.n = a.n;
+    t.prev = a.prev;
+    t.desc = a.desc;
+    t.didx = tile;
+    t.dfirst = 0;
+    t.tag = make_tag(epoch);
+    const bool interior = tile > 0 && t.tv + SEGS * kSegBytes <= a.vend;
+    TileOut r;
+    if (interior)
+        r = run_tile<DELTA, COUNT, SEGS, false>(t, stage);
+    else
+        r = run_tile<DELTA, COUNT, SEGS, true>(t, stage);
+
+    if (tile == a.ntiles - 1 && ln == 0) {
+        if (COUNT) {
+            *a.d_count = r.total;
+        } else {
+            const u8 last = a.base[a.vend - 1];
+            *a.d_status = final_status(r.mal, last, r.total, a.n);
+        }
+    }
+}
+
+// ------------------------------------------------------------ batched lists
+struct ListDesc {
+    i64 bb, be, ob, n;
+};
+
+__device__ __forceinline__ ListDesc list_desc(const ListArgs &a, u64 i) {
+    ListDesc d;
+    if (a.rows) {
+        const int64_t *r = a.rows + 4 * i;
+        d.bb = r[0];
+        d.be = r[1];
+        d.ob = r[2];
+        d.n = r[3];
+    } else {
+        d.bb = a.byte_off[i];
+        d.be = a.byte_off[i + 1];
+        d.ob = a.out_off[i];
+        d.n = a.out_off[i + 1] - d.ob;
+    }
+    return d;
+}
+
+__device__ __forceinline__ bool list_ok(const ListArgs &a, const ListDesc &d) {
+    return d.bb >= 0 && d.be >= d.bb && (u64)d.be <= a.nbytes && d.ob >= 0 && d.n >= 0 &&
+           (u64)d.ob + (u64)d.n <= a.nout && (d.be - d.bb) < (1ll << 36);
+}
+
+// Prep: classify every list (empty / small / large) and build the work
+// table with a decoupled look-back scan over blocks of kPrepBlock lists.
+// Large-list tiles take items [0, L); small lists take items counted down
+// from max_items - 1, so their slots need no knowledge of L.
+template <int SEGS>
+__global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks) {
+    __shared__ u32 sh_c[kPrepBlock / kWave], sh_s[kPrepBlock / kWave];
+    __shared__ u64 sh_tw;
+    __shared__ u64 sh_exc;
+    __shared__ u32 sh_exs;
+    const u32 tid = threadIdx.x;
+    const u32 ln = lane_id();
+    const u32 wib = tid >> 6;
+    if (tid == 0) sh_tw = aadd(a.hdr, 1);
+    __syncthreads();
+    const u64 tw = sh_tw;
+    const u32 blk = (u32)tw;
+    const u32 epoch = (u32)(tw >> 32);
+    if (blk == nblocks - 1 && tid == 0) astore(a.hdr, (u64)(epoch + 1) << 32);
+    const u32 tag = make_tag(epoch);
+    const u64 tb = (u64)SEGS * kSegBytes;
+
+    const u64 i = (u64)blk * kPrepBlock + tid;
+    u32 nlarge = 0, nsmall = 0;
+    ListDesc d{0, 0, 0, 0};
+    if (i < a.nlists) {
+        d = list_desc(a, i);
+        if (!list_ok(a, d)) {
+            a.list_status[i] = VBYTE_EINVAL;
+        } else if (d.be == d.bb) {
+            a.list_status[i] = d.n == 0 ? VBYTE_OK : VBYTE_ETRUNC;
+        } else if ((u64)(d.be - d.bb) <= a.small_bytes) {
+            nsmall = 1;
+        } else {
+            const u64 vs = (u64)(uintptr_t)(a.bytes + d.bb) & 15u;
+            nlarge = (u32)((vs + (u64)(d.be - d.bb) + tb - 1) / tb);
+        }
+    }
+    // block scan of (nlarge, nsmall)
+    const u32 cl = wave_scan(nlarge), cs = wave_scan(nsmall);
+    if (ln == 63) {
+        sh_c[wib] = cl;
+        sh_s[wib] = cs;
+    }
+    __syncthreads();
+    u32 wl = 0, ws = 0, bl = 0, bs = 0;
+    for (u32 k = 0; k < kPrepBlock / kWave; ++k) {
+        if (k < wib) {
+            wl += sh_c[k];
+            ws += sh_s[k];
+        }
+        bl += sh_c[k];
+        bs += sh_s[k];
+    }
+    if (wib == 0) {
+        Prefix ex;
+        if (blk == 0) {
+            ex = Prefix{0, 0, false};
+        } else {
+            if (ln == 0) {
+                astore(&a.prep_desc[blk].s_agg, pack_s(tag, bs));
+                astore(&a.prep_desc[blk].c_agg, pack_c(tag, false, bl));
+            }
+            ex = lookback<true>(a.prep_desc, blk, 0, tag);
+        }
+        if (ln == 0) {
+            astore(&a.prep_desc[blk].s_inc, pack_s(tag, ex.s + bs));
+            astore(&a.prep_desc[blk].c_inc, pack_c(tag, false, ex.c + bl));
+            sh_exc = ex.c;
+            sh_exs = ex.s;
+            if (blk == nblocks - 1) {
+                const u64 L = ex.c + bl, S = (u64)ex.s + bs;
+                const bool fits = L + S <= a.max_items;
+                astore(&a.totals[0], L);
+                astore(&a.totals[1], fits ? L + S : 0);
+                astore(&a.totals[2], fits ? 0 : 1);
+            }
+        }
+    }
+    __syncthreads();
+    const u64 lstart = sh_exc + wl + (cl - nlarge);
+    const u64 sslot = (u64)sh_exs + ws + (cs - nsmall);
+    for (u32 k = 0; k < nlarge; ++k) {
+        const u64 it = lstart + k;
+        if (it < a.max_items) a.items[it] = make_int2((int)i, (int)k);
+    }
+    if (nsmall) {
+        if (sslot < a.max_items) a.items[a.max_items - 1 - sslot] = make_int2((int)i, 0);
+    }
+}
+
+// Small list: one wavefront walks its segments in order, carrying the rank
+// and the running sum, with no look-back.
+template <bool DELTA>
+__device__ void run_small(const ListArgs &a, u64 li, const ListDesc &d, u32 *stage) {
+    const u32 ln = lane_id();
+    const u8 *p0 = a.bytes + d.bb;
+    const u8 *base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
+    const u64 vstart = (u64)(p0 - base);
+    const u64 vend = vstart + (u64)(d.be - d.bb);
+    u32 *out = a.out + d.ob;
+    const u64 n = (u64)d.n;
+    u64 rank = 0;
+    u32 run = a.prevs ? a.prevs[li] : 0u;
+    bool mal = false;
+    u32 pw = 0, pv = 0;   // lane 63's last dword and validity of the previous segment
+    for (u64 tv = 0; tv < vend; tv += kSegBytes) {
+        u32 w[4], valid;
+        load16_guarded(base, tv + 16u * ln, vstart, vend, w, valid);
+        const u32 h = from_lane_below(w[3], pw);
+        const u32 hv = from_lane_below(valid, pv) & 0xF000u;
+        const SegMask m = seg_mask(w, valid, h, hv);
+        mal |= m.mal;
+        const u32 ci = wave_scan(m.cnt);
+        const u32 segcnt = read_lane(ci, 63);
+        u32 r[16];
+        const u32 ls = assemble<DELTA, true>(w, valid, h, hv, r);
+        u32 lex_s = 0, segsum = 0;
+        if (DELTA) {
+            const u32 si = wave_scan(ls);
+            lex_s = si - ls;
+            segsum = read_lane(si, 63);
+        }
+        if (segcnt && rank < n) {
+            const u32 amis = out_mis(out, rank);
+            emit<DELTA>(stage, amis + ci - m.cnt, m.term, r, lex_s);
+            wave_lds_sync();
+            store_stage<DELTA>(stage, amis, segcnt, out, rank, n, run);
+            wave_lds_sync();
+        }
+        rank += segcnt;
+        run += segsum;
+        pw = read_lane(w[3], 63);
+        pv = read_lane(valid, 63);
+    }
+    const bool anymal = ballot(mal) != 0;
+    if (ln == 0) a.list_status[li] = final_status(anymal, base[vend - 1], rank, n);
+}
+
+template <bool DELTA, int SEGS>
+__global__ __launch_bounds__(1024) void k_batch(ListArgs a) {
+    extern __shared__ u32 lds[];
+    const u32 ln = lane_id();
+    const u32 wib = threadIdx.x >> 6;
+    u32 *stage = lds + wib * kStageWords;
+    const u64 L = aload(&a.totals[0]);
+    const u64 T = aload(&a.totals[1]);
+    const bool failed = aload(&a.totals[2]) != 0;
+    const u64 last_ticket = T + a.nwaves - 1;
+    const u64 gw = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
+    for (;;) {
+        u64 tw = 0;
+        if (ln == 0) tw = aadd(a.hdr, 1);
+        tw = first_lane64(tw);
+        const u64 it = (u32)tw;
+        const u32 epoch = (u32)(tw >> 32);
+        if (it == last_ticket && ln == 0) astore(a.hdr, (u64)(epoch + 1) << 32);
+        if (it >= T) break;
+        if (it < L) {
+            const int2 e = a.items[it];
+            const u64 li = (u64)e.x;
+            const u32 ti = (u32)e.y;
+            const ListDesc d = list_desc(a, li);
+            const u8 *p0 = a.bytes + d.bb;
+            TileIn t;
+            t.base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
+            t.vstart = (u64)(p0 - t.base);
+            t.vend = t.vstart + (u64)(d.be - d.bb);
+            t.tv = (u64)ti * (SEGS * kSegBytes);
+            t.out = a.out + d.ob;
+            t.n = (u64)d.n;
+            t.prev = a.prevs ? a.prevs[li] : 0u;
+            t.desc = a.desc;
+            t.didx = (i64)it;
+            t.dfirst = (i64)it - ti;
+            t.tag = make_tag(epoch);
+            const bool interior = ti > 0 && t.tv + SEGS * kSegBytes <= t.vend;
+            TileOut r;
+            if (DELTA) {
+                r = interior ? run_tile<true, false, SEGS, false>(t, stage)
+                             : run_tile<true, false, SEGS, true>(t, stage);
+            } else {
+                r = interior ? run_tile<false, false, SEGS, false>(t, stage)
+                             : run_tile<false, false, SEGS, true>(t, stage);
+            }
+            const bool last = t.tv + SEGS * kSegBytes >= t.vend;
+            if (last && ln == 0) a.list_status[li] = final_status(r.mal, t.base[t.vend - 1], r.total, t.n);
+        } else {
+            const int2 e = a.items[a.max_items - 1 - (it - L)];
+            const u64 li = (u64)e.x;
+            const ListDesc d = list_desc(a, li);
+            run_small<DELTA>(a, li, d, stage);
+        }
+    }
+    if (failed) {
+        for (u64 i = gw * kWave + ln; i < a.nlists; i += (u64)a.nwaves * kWave) a.list_status[i] = VBYTE_EINVAL;
+    }
+}
+
+// ------------------------------------------------------------ encoder
+// Canonical ENC (section 1): L(x) bytes, 7 bits each, least significant
+// first, top bit set on all but the last.  One wavefront encodes 1024
+// values per tile: lane lengths -> wave scan -> look-back for the tile's
+// byte offset -> bytes assembled in LDS -> stored to HBM.
+__device__ __forceinline__ u32 code_len(u32 x) {
+    const u32 bits = 32u - (u32)__builtin_clz(x | 1u);
+    return (bits + 6u) / 7u;
+}
+
+__global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
+    extern __shared__ u32 lds[];
+    const u32 ln = lane_id();
+    const u32 wib = threadIdx.x >> 6;
+    const u64 wg = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
+    if (wg >= a.ntiles) return;
+    u8 *stage = (u8 *)(lds + wib * (kEncodeWaveValues * 5 / 4 + 8));
+
+    u64 tw = 0;
+    if (ln == 0) tw = aadd(a.hdr, 1);
+    tw = first_lane64(tw);
+    const u32 tile = (u32)tw;
+    const u32 epoch = (u32)(tw >> 32);
+    if (tile == a.ntiles - 1 && ln == 0) astore(a.hdr, (u64)(epoch + 1) << 32);
+    const u32 tag = make_tag(epoch);
+
+    // lane owns values [v0, v0 + 16)
+    const u64 v0 = (u64)tile * kEncodeWaveValues + 16u * ln;
+    u32 x[16];
+    u32 lanebytes = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const u64 i = v0 + k;
+        u32 v = 0;
+        if (i < a.n) {
+            v = a.values[i];
+            if (a.delta) v -= (i == 0) ? a.prev : a.values[i - 1];
+        }
+        x[k] = v;
+        lanebytes += (i < a.n) ? code_len(v) : 0u;
+    }
+    const u32 bi = wave_scan(lanebytes);
+    const u32 tilebytes = read_lane(bi, 63);
+    Prefix ex;
+    if (tile == 0) {
+        ex = Prefix{0, 0, false};
+    } else {
+        if (ln == 0) astore(&a.desc[tile].c_agg, pack_c(tag, false, tilebytes));
+        ex = lookback<false>(a.desc, tile, 0, tag);
+    }
+    if (ln == 0) astore(&a.desc[tile].c_inc, pack_c(tag, false, ex.c + tilebytes));
+    const u64 gb = ex.c;   // byte offset of this tile
+    const u32 mis = (u32)(((uintptr_t)a.bytes + gb) & 3u);
+    // assemble into LDS at stage[mis + local offset]
+    u32 off = mis + bi - lanebytes;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (v0 + k < a.n) {
+            const u32 v = x[k];
+            const u32 len = code_len(v);
+            for (u32 j = 0; j < len; ++j) {
+                const u32 g = (v >> (7 * j)) & 0x7Fu;
+                stage[off + j] = (u8)(j + 1 < len ? (g | 0x80u) : g);
+            }
+            off += len;
+        }
+    }
+    wave_lds_sync();
+    // store: words covering [gb - mis, gb + tilebytes); edge words byte by byte
+    const u32 nwords = (mis + tilebytes + 3) >> 2;
+    const u32 *sw = (const u32 *)stage;
+    u8 *obase = a.bytes + gb - mis;
+    for (u32 q = ln; q < nwords; q += kWave) {
+        const u32 b0 = q << 2;
+        const u64 g0 = gb - mis + b0;
+        if (b0 >= mis && b0 + 4 <= mis + tilebytes && g0 + 4 <= a.capacity) {
+            *(u32 *)(obase + b0) = sw[q];
+        } else {
+            for (u32 t = 0; t < 4; ++t) {
+                const u32 b = b0 + t;
+                if (b >= mis && b < mis + tilebytes && g0 + t < a.capacity) obase[b] = stage[b];
+            }
+        }
+    }
+    if (tile == a.ntiles - 1 && ln == 0) *a.d_nbytes = ex.c + tilebytes;
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void k_set_status(int32_t *p, int32_t v) { *p = v; }
+__global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
+__global__ void k_zero(uint4 *p, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+template <bool DELTA, bool COUNT, int SEGS>
+hipError_t launch_stream_t(const StreamArgs &a, int wpb, hipStream_t s) {
+    const u32 blocks = (a.ntiles + wpb - 1) / wpb;
+    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
+    k_stream<DELTA, COUNT, SEGS><<<blocks, wpb * kWave, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int SEGS>
+hipError_t launch_stream_s(const StreamArgs &a, int delta, int count_only, int wpb, hipStream_t s) {
+    if (count_only) return launch_stream_t<false, true, SEGS>(a, wpb, s);
+    if (delta) return launch_stream_t<true, false, SEGS>(a, wpb, s);
+    return launch_stream_t<false, false, SEGS>(a, wpb, s);
+}
+
+template <int SEGS>
+hipError_t launch_batch_s(const ListArgs &a, int wpb, int grid_blocks, hipStream_t s) {
+    const u32 nblocks = (u32)((a.nlists + kPrepBlock - 1) / kPrepBlock);
+    if (nblocks) {
+        k_prep<SEGS><<<nblocks, kPrepBlock, 0, s>>>(a, nblocks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
+    if (a.delta)
+        k_batch<true, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
+    else
+        k_batch<false, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int segs, int wpb,
+                         hipStream_t s) {
+    switch (segs) {
+        case 1: return launch_stream_s<1>(a, delta, count_only, wpb, s);
+        case 2: return launch_stream_s<2>(a, delta, count_only, wpb, s);
+        case 4: return launch_stream_s<4>(a, delta, count_only, wpb, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch(const ListArgs &a, int segs, int wpb, int grid_blocks, hipStream_t s) {
+    switch (segs) {
+        case 1: return launch_batch_s<1>(a, wpb, grid_blocks, s);
+        case 2: return launch_batch_s<2>(a, wpb, grid_blocks, s);
+        case 4: return launch_batch_s<4>(a, wpb, grid_blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_encode(const EncodeArgs &a, hipStream_t s) {
+    const int wpb = 4;
+    const u32 blocks = (a.ntiles + wpb - 1) / wpb;
+    const size_t lds = (size_t)wpb * (kEncodeWaveValues * 5 / 4 + 8) * sizeof(u32);
+    k_encode<<<blocks, wpb * kWave, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_status(int32_t *d_status, int32_t value, hipStream_t s) {
+    k_set_status<<<1, 1, 0, s>>>(d_status, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s) {
+    k_set_u64<<<1, 1, 0, s>>>(p, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_zero<<<(unsigned)blocks, 256, 0, s>>>((uint4 *)p, n16);
+    return hipGetLastError();
+}
+
+}  // namespace vb

@@ -1,0 +1,227 @@
+"""Python binding of libvbyte (argument marshalling only).
+
+Every function forwards torch tensors that live on the GPU to the C ABI of
+``include/vbyte.h``; PyTorch only provides device memory and the current
+stream.  All decoding, counting and encoding runs in the HIP kernels of
+``csrc/``.  The library is loaded from this directory and must have been
+built (``python -m paper_1503_07387_amd.build``); there is no fallback.
+
+uint32 results are returned as ``torch.int32`` tensors holding the same bits.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvbyte.so")
+
+OK, EINVAL, ECOUNT, ETRUNC, EMALFORMED, EHIP, ENOMEM = range(7)
+STATUS_NAMES = {OK: "VBYTE_OK", EINVAL: "VBYTE_EINVAL", ECOUNT: "VBYTE_ECOUNT",
+                ETRUNC: "VBYTE_ETRUNC", EMALFORMED: "VBYTE_EMALFORMED",
+                EHIP: "VBYTE_EHIP", ENOMEM: "VBYTE_ENOMEM"}
+
+EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
+           "vbyte_decode_delta_async", "vbyte_count", "vbyte_decode_batch",
+           "vbyte_decode_lists", "vbyte_encode_async", "vbyte_encode_delta_async",
+           "vbyte_workspace_size", "vbyte_set_tuning", "vbyte_get_tuning",
+           "vbyte_status_str", "vbyte_last_error"]
+
+
+class VByteError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = int(status)
+        msg = STATUS_NAMES.get(self.status, str(status))
+        if what:
+            msg = f"{what}: {msg}"
+        if self.status == EHIP:
+            msg += " (" + _lib().vbyte_last_error().decode() + ")"
+        super().__init__(msg)
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libvbyte.so is not built ({LIB_PATH}); run "
+                               "python -m paper_1503_07387_amd.build")
+        _L = _declare(ctypes.CDLL(LIB_PATH))
+    return _L
+
+
+def load(path=LIB_PATH):
+    """Load a libvbyte build from `path` with its prototypes declared."""
+    return _declare(ctypes.CDLL(path))
+
+
+def _declare(lib):
+    c = ctypes
+    vp, sz, u32, i32, i64 = c.c_void_p, c.c_size_t, c.c_uint32, c.c_int, c.c_int64
+    sig = {
+        "vbyte_decode": [vp, sz, vp, sz],
+        "vbyte_decode_delta": [vp, sz, vp, sz, u32],
+        "vbyte_decode_async": [vp, sz, vp, sz, vp, vp],
+        "vbyte_decode_delta_async": [vp, sz, vp, sz, u32, vp, vp],
+        "vbyte_count": [vp, sz, vp, vp],
+        "vbyte_decode_batch": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, vp],
+        "vbyte_decode_lists": [vp, sz, vp, sz, sz, vp, sz, vp, i32, vp, vp],
+        "vbyte_encode_async": [vp, sz, vp, sz, vp, vp],
+        "vbyte_encode_delta_async": [vp, sz, u32, vp, sz, vp, vp],
+        "vbyte_set_tuning": [i32, i32, i64],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = c.c_int
+    lib.vbyte_workspace_size.argtypes = [sz]
+    lib.vbyte_workspace_size.restype = sz
+    lib.vbyte_get_tuning.argtypes = [c.POINTER(c.c_int), c.POINTER(c.c_int), c.POINTER(c.c_int64)]
+    lib.vbyte_get_tuning.restype = None
+    lib.vbyte_status_str.argtypes = [c.c_int]
+    lib.vbyte_status_str.restype = c.c_char_p
+    lib.vbyte_last_error.argtypes = []
+    lib.vbyte_last_error.restype = c.c_char_p
+    return lib
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _check_call(st, what):
+    if st != OK:
+        raise VByteError(st, what)
+
+
+def _dev_u8(data):
+    if data.dtype != torch.uint8 or not data.is_cuda or not data.is_contiguous():
+        raise ValueError("data must be a contiguous torch.uint8 CUDA tensor")
+    return data
+
+
+def decode(data, n, *, delta=False, prev=0, out=None, status=None, stream=None, check=True):
+    """Decode ``n`` uint32 from the VByte bytes ``data`` (uint8 CUDA tensor).
+
+    Returns the int32 tensor of results.  With ``check`` the call waits for
+    the kernel and raises VByteError on a data error; otherwise the status is
+    left in ``status`` (an int32 CUDA tensor of one element) for the caller.
+    """
+    _dev_u8(data)
+    n = int(n)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=data.device)
+    elif out.dtype != torch.int32 or out.numel() < n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of at least n elements")
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=data.device)
+    s = _stream(stream)
+    L = _lib()
+    if delta:
+        st = L.vbyte_decode_delta_async(_ptr(data), data.numel(), _ptr(out), n,
+                                        int(prev) & 0xFFFFFFFF, _ptr(status), s)
+    else:
+        st = L.vbyte_decode_async(_ptr(data), data.numel(), _ptr(out), n, _ptr(status), s)
+    _check_call(st, "decode")
+    if check:
+        v = int(status.item())
+        if v != OK:
+            raise VByteError(v, "decode")
+    return out[:n]
+
+
+def count(data, *, stream=None, result=None):
+    """Number of terminator bytes (codes) in ``data``; returns a Python int
+    (or fills the uint64 slot of ``result``, an int64 CUDA tensor, without
+    waiting when given)."""
+    _dev_u8(data)
+    res = result if result is not None else torch.empty(1, dtype=torch.int64, device=data.device)
+    _check_call(_lib().vbyte_count(_ptr(data), data.numel(), _ptr(res), _stream(stream)), "count")
+    if result is not None:
+        return result
+    return int(res.item())
+
+
+def decode_batch(data, byte_off, out_off, *, delta=False, prevs=None, out=None,
+                 list_status=None, stream=None):
+    """Batched CSR decode.  byte_off/out_off: int64 CUDA tensors of nlists+1.
+    Returns (out int32 tensor, per-list int32 status tensor); no wait."""
+    _dev_u8(data)
+    nlists = byte_off.numel() - 1
+    if out is None:
+        total = int(out_off[-1].item()) if nlists > 0 else 0
+        out = torch.empty(max(total, 0), dtype=torch.int32, device=data.device)
+    if list_status is None:
+        list_status = torch.empty(max(nlists, 0), dtype=torch.int32, device=data.device)
+    st = _lib().vbyte_decode_batch(_ptr(data), data.numel(), _ptr(byte_off), _ptr(out), out.numel(),
+                                   _ptr(out_off), max(nlists, 0), _ptr(prevs), 1 if delta else 0,
+                                   _ptr(list_status), _stream(stream))
+    _check_call(st, "decode_batch")
+    return out, list_status
+
+
+def decode_lists(data, rows, list_bytes, out, *, delta=False, prevs=None, list_status=None,
+                 stream=None):
+    """Gather-form batch: rows is an int64 CUDA tensor [nlists, 4] of
+    (byte_begin, byte_end, out_begin, n).  Returns the per-list status."""
+    _dev_u8(data)
+    nlists = rows.shape[0] if rows.numel() else 0
+    if list_status is None:
+        list_status = torch.empty(nlists, dtype=torch.int32, device=data.device)
+    st = _lib().vbyte_decode_lists(_ptr(data), data.numel(), _ptr(rows), nlists, int(list_bytes),
+                                   _ptr(out), out.numel(), _ptr(prevs), 1 if delta else 0,
+                                   _ptr(list_status), _stream(stream))
+    _check_call(st, "decode_lists")
+    return list_status
+
+
+def encode(values, *, delta=False, prev=0, out=None, nbytes=None, stream=None, trim=True):
+    """Canonical VByte encoding on the GPU of an int32/uint32-bits CUDA tensor.
+    Returns the uint8 tensor of codes (trimmed to the encoded size when
+    ``trim``, which waits for the kernel)."""
+    if values.dtype != torch.int32 or not values.is_cuda or not values.is_contiguous():
+        raise ValueError("values must be a contiguous int32 CUDA tensor (uint32 bits)")
+    n = values.numel()
+    if out is None:
+        out = torch.empty(max(5 * n, 1), dtype=torch.uint8, device=values.device)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=values.device)
+    s = _stream(stream)
+    L = _lib()
+    if delta:
+        st = L.vbyte_encode_delta_async(_ptr(values), n, int(prev) & 0xFFFFFFFF, _ptr(out),
+                                        out.numel(), _ptr(nbytes), s)
+    else:
+        st = L.vbyte_encode_async(_ptr(values), n, _ptr(out), out.numel(), _ptr(nbytes), s)
+    _check_call(st, "encode")
+    if trim:
+        return out[: int(nbytes.item())]
+    return out, nbytes
+
+
+def set_tuning(segs_per_wave=0, waves_per_block=0, small_list_bytes=0):
+    _check_call(_lib().vbyte_set_tuning(int(segs_per_wave), int(waves_per_block),
+                                        int(small_list_bytes)), "set_tuning")
+
+
+def get_tuning():
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+    _lib().vbyte_get_tuning(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return {"segs_per_wave": a.value, "waves_per_block": b.value, "small_list_bytes": c.value}
+
+
+def workspace_size(nbytes):
+    return int(_lib().vbyte_workspace_size(int(nbytes)))
+
+
+def as_u32_numpy(t):
+    """Host numpy uint32 view of an int32 result tensor."""
+    return t.detach().cpu().numpy().view("uint32")

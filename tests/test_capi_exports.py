@@ -1,0 +1,75 @@
+"""CPU checks of the boundary: libvbyte builds, loads, and exports every
+symbol that include/vbyte.h declares (no compute calls without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vbyte.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vbyte_[a-z0-9_]+)\s*\(", text)))
+
+
+def _lib_path():
+    from paper_1503_07387_amd import vbyte
+    if not os.path.exists(vbyte.LIB_PATH):
+        from paper_1503_07387_amd import build
+        build.build()
+    return vbyte.LIB_PATH
+
+
+def test_header_declares_expected_calls():
+    names = declared_functions()
+    for must in ("vbyte_decode", "vbyte_decode_delta", "vbyte_decode_batch", "vbyte_count"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_covers_header():
+    from paper_1503_07387_amd import vbyte
+    assert sorted(vbyte.EXPORTS) == declared_functions()
+
+
+def test_exported_symbols_are_c_linkage():
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib_path()], capture_output=True,
+                         text=True, check=True).stdout
+    syms = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    for n in declared_functions():
+        assert n in syms, n
+
+
+def test_status_strings_without_gpu():
+    from paper_1503_07387_amd import vbyte
+    lib = vbyte.load(_lib_path())
+    for code, name in vbyte.STATUS_NAMES.items():
+        assert lib.vbyte_status_str(code).decode() == name
+
+
+def test_tuning_argument_checks_without_gpu():
+    from paper_1503_07387_amd import vbyte
+    lib = vbyte.load(_lib_path())
+    assert lib.vbyte_set_tuning(3, 0, 0) == vbyte.EINVAL
+    assert lib.vbyte_set_tuning(0, 9, 0) == vbyte.EINVAL
+    assert lib.vbyte_set_tuning(0, 0, -1) == vbyte.EINVAL
+    assert lib.vbyte_set_tuning(0, 0, 0) == vbyte.OK
+
+
+def test_header_status_numbers_match_oracle_readings():
+    # the oracle defines its own numbers (it shares no header with the
+    # library); both follow the precedence EMALFORMED > ETRUNC > ECOUNT
+    import oracle
+    text = open(HEADER).read()
+    nums = dict((k, int(v)) for k, v in re.findall(r"VBYTE_(\w+)\s*=\s*(\d+)", text))
+    assert nums["OK"] == oracle.OK and nums["ECOUNT"] == oracle.ECOUNT
+    assert nums["ETRUNC"] == oracle.ETRUNC and nums["EMALFORMED"] == oracle.EMALFORMED
+    assert nums["EINVAL"] == oracle.EINVAL
