@@ -1,0 +1,202 @@
+"""Benchmark of the VByte decode hot path on one MI355X.
+
+A step is one pass of the whole hot path over the benchmark workload: the
+differential decode (VByte gaps -> uint32 document identifiers, wrapping
+prefix sum) of two synthetic single streams of 64Mi gaps each, one with
+geometric gaps of mean 8 (almost only 1-byte codes) and one of mean 300
+(a 35/65 mix of 1- and 2-byte codes).  The inputs are generated, VByte-encoded
+on the GPU by the library's encoder and resident in HBM before timing starts.
+
+Printed: one JSON line with throughput (Gints/s), the HBM roofline of the
+decode kernel (algorithmic bytes in + 4n out per launch over the launch's
+HIP-event time), and the scalar CPU oracle timed on the host as a baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gints/s + HBM GB/s (% peak), batched vs plain per-list; p50/p99 query latency"
+HBM_PEAK_GBPS = 8000.0
+N_STREAM = 1 << 26
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "decode_delta_64Mi_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1503_07387_amd", "csrc", "kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(bytes_per_launch_alg):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None
+    when the kernel source changed since the counters were taken."""
+    try:
+        with open(PROFILE_COUNTERS) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return prof.get("hbm_bytes_per_launch")
+
+
+def make_streams(torch, vbyte, workloads):
+    """The two gap streams, encoded on the GPU.  Returns a list of dicts."""
+    out = []
+    for mean in (8, 300):
+        t0 = time.time()
+        g = workloads.geometric_gaps(n=N_STREAM, mean=mean)
+        gd = torch.from_numpy(g.view("int32")).cuda()
+        enc = vbyte.encode(gd)
+        torch.cuda.synchronize()
+        log(f"stream mean {mean}: {N_STREAM} gaps -> {enc.numel()} bytes "
+            f"({enc.numel() / N_STREAM:.4f} B/int), prepared in {time.time() - t0:.1f}s")
+        out.append({"mean": mean, "gaps": g, "gaps_dev": gd, "bytes": enc,
+                    "out": torch.empty(N_STREAM, dtype=torch.int32, device="cuda"),
+                    "status": torch.empty(1, dtype=torch.int32, device="cuda")})
+    return out
+
+
+def verify(torch, streams):
+    for s in streams:
+        if int(s["status"].item()) != 0:
+            raise RuntimeError(f"decode status {int(s['status'].item())} on stream mean {s['mean']}")
+        ref = torch.cumsum(s["gaps_dev"].to(torch.int64) & 0xFFFFFFFF, 0) & 0xFFFFFFFF
+        got = s["out"].to(torch.int64) & 0xFFFFFFFF
+        if not torch.equal(ref, got):
+            raise RuntimeError(f"decoded identifiers differ from the gap prefix sum (mean {s['mean']})")
+
+
+def cpu_baseline(streams, budget_s=15.0):
+    """The scalar oracle (plain C, one thread) on the same workload: decode of
+    whole streams, repeated until about budget_s of CPU work is spent."""
+    import oracle
+    host = [(s["bytes"].cpu().numpy(), s["gaps"].size) for s in streams]
+    ints = 0
+    t0 = time.perf_counter()
+    passes = 0
+    while True:
+        for b, n in host:
+            st, _ = oracle.decode_delta(b, n, 0)
+            if st != oracle.OK:
+                raise RuntimeError("oracle failed on the benchmark stream")
+            ints += n
+        passes += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or passes >= 10:
+            break
+    return {"value": ints / el / 1e9, "unit": "Gints/s", "cores": 1, "kind": "oracle",
+            "sample": f"{passes} pass(es) over both 64Mi-gap streams (the full workload), "
+                      f"scalar C oracle (Algorithm 1 + wrapping prefix sum), 1 thread, "
+                      f"{el:.1f}s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the decode would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1503_07387_amd import vbyte, workloads
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    vbyte._lib()
+    streams = make_streams(torch, vbyte, workloads)
+    alg_bytes = [s["bytes"].numel() + 4 * N_STREAM for s in streams]
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        for i, s in enumerate(streams):
+            if events is not None:
+                events[i][0].record(stream)
+            vbyte.decode(s["bytes"], N_STREAM, delta=True, prev=0, out=s["out"],
+                         status=s["status"], check=False)
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    verify(torch, streams)
+
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in streams] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    verify(torch, streams)
+
+    kernel_ms = [[evs[k][i][0].elapsed_time(evs[k][i][1]) for k in range(args.steps)]
+                 for i in range(len(streams))]
+    avg_ms = [sum(v) / len(v) for v in kernel_ms]
+    ms_per_step = wall * 1e3 / args.steps
+    ints_per_step = N_STREAM * len(streams)
+    value = ints_per_step / (ms_per_step / 1e3) / 1e9
+    achieved = sum(alg_bytes) / (sum(avg_ms) / 1e3) / 1e9   # GB/s over both launches
+    per_stream = []
+    for i, s in enumerate(streams):
+        per_stream.append({
+            "gap_mean": s["mean"], "n": N_STREAM, "bytes_in": int(s["bytes"].numel()),
+            "kernel_ms": round(avg_ms[i], 4),
+            "gints_per_s": round(N_STREAM / (avg_ms[i] / 1e3) / 1e9, 2),
+            "alg_gbps": round(alg_bytes[i] / (avg_ms[i] / 1e3) / 1e9, 1),
+            "pct_hbm_peak": round(100 * alg_bytes[i] / (avg_ms[i] / 1e3) / 1e9 / HBM_PEAK_GBPS, 1),
+        })
+    traffic = measured_traffic(alg_bytes)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "differential VByte decode of two single streams of 64Mi uint32 "
+                               "gaps each (geometric gaps, mean 8 and mean 300), wrapping prefix sum",
+                   "n_per_stream": N_STREAM, "streams": 2, "gap_means": [8, 300],
+                   "tuning": vbyte.get_tuning()},
+        "hbm_gbps": round(achieved, 1),
+        "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBPS, 2),
+        "streams": per_stream,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_stream<delta> (vb::k_stream<true,false,SEGS>)",
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle ...")
+        res["cpu_baseline"] = cpu_baseline(streams, args.cpu_budget)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

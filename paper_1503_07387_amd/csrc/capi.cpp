@@ -25,8 +25,8 @@ namespace {
 thread_local char g_last_error[256] = "";
 
 std::atomic<int> g_segs{4};
-std::atomic<int> g_wpb{4};
-std::atomic<int64_t> g_small{8192};
+std::atomic<int> g_wpb{8};
+std::atomic<int64_t> g_small{16384};
 
 vbyte_status hip_fail(hipError_t e, const char *what) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
@@ -34,7 +34,7 @@ vbyte_status hip_fail(hipError_t e, const char *what) {
 }
 
 // Workspace layout (bytes):
-//   [0, 8)      ticket/epoch header word
+//   [0, 24)     epoch word and the two batched queue words
 //   [64, 68)    status slot used by the synchronous calls
 //   [128, 152)  batch totals (3 x uint64)
 //   [256, ...)  descriptors, then batch tables
@@ -122,7 +122,7 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
     a.out = out;
     a.n = n;
     a.prev = prev;
-    const uint64_t ntiles = nbytes ? stream_tiles(a.vstart, nbytes, segs) : 0;
+    const uint64_t ntiles = nbytes ? stream_tiles(a.vstart, nbytes, segs, wpb) : 0;
     if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
     a.ntiles = (uint32_t)ntiles;
     Workspace *w = nullptr;
@@ -166,7 +166,8 @@ vbyte_status batch_common(ListArgs a, size_t list_bytes, hipStream_t s) {
     if (((uintptr_t)a.out & 3u) != 0) return VBYTE_EINVAL;
     if (a.nlists >= (1ull << 31)) return VBYTE_EINVAL;
     const int segs = g_segs.load(), wpb = g_wpb.load();
-    const uint64_t tb = (uint64_t)segs * kSegBytes;
+    const uint64_t tb = (uint64_t)segs * wpb * kSegBytes;
+    a.wpb = (uint32_t)wpb;
     a.small_bytes = (uint64_t)std::max<int64_t>(g_small.load(), 0);
     // A large list holds more than small_bytes bytes and needs at most
     // bytes/tb + 2 tiles; a small list needs one item.
@@ -176,7 +177,7 @@ vbyte_status batch_common(ListArgs a, size_t list_bytes, hipStream_t s) {
     const uint32_t nblocks = (uint32_t)((a.nlists + kPrepBlock - 1) / kPrepBlock);
     size_t off = kHeaderBytes;
     const size_t desc_off = off;
-    off += a.max_items * sizeof(Desc);
+    off += a.max_items * kSpanTiles * sizeof(Desc);
     const size_t prep_off = off;
     off += (size_t)nblocks * sizeof(Desc);
     const size_t items_off = off;
@@ -196,7 +197,6 @@ vbyte_status batch_common(ListArgs a, size_t list_bytes, hipStream_t s) {
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
     const int grid = cus * std::max(1, 16 / wpb);
-    a.nwaves = (uint32_t)(grid * wpb);
     hipError_t e = launch_batch(a, segs, wpb, grid, s);
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "batch launch");
 }
@@ -243,7 +243,7 @@ vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count,
     a.vend = a.vstart + nbytes;
     a.out = nullptr;
     a.n = 0;
-    const uint64_t ntiles = stream_tiles(a.vstart, nbytes, segs);
+    const uint64_t ntiles = stream_tiles(a.vstart, nbytes, segs, wpb);
     if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
     a.ntiles = (uint32_t)ntiles;
     Workspace *w = nullptr;
@@ -342,7 +342,7 @@ vbyte_status vbyte_encode_delta_async(const uint32_t *values, size_t n, uint32_t
 }
 
 size_t vbyte_workspace_size(size_t nbytes) {
-    return kHeaderBytes + stream_tiles(15, nbytes, g_segs.load()) * sizeof(Desc);
+    return kHeaderBytes + stream_tiles(15, nbytes, g_segs.load(), 1) * sizeof(Desc);
 }
 
 vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t small_list_bytes) {

@@ -47,7 +47,8 @@ typedef uint32_t u32;
 typedef uint64_t u64;
 typedef int64_t i64;
 
-constexpr u64 kCountMask = (1ull << 37) - 1;
+constexpr u64 kCountMask = (1ull << 36) - 1;
+constexpr int kLookbackWindows = 4;   // 64-descriptor windows read per round trip
 
 // ------------------------------------------------------------------ atomics
 __device__ __forceinline__ u64 aload(const u64 *p) {
@@ -65,9 +66,6 @@ __device__ __forceinline__ u32 lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 __device__ __forceinline__ u32 first_lane(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ u64 first_lane64(u64 v) {
-    return ((u64)first_lane((u32)(v >> 32)) << 32) | first_lane((u32)v);
-}
 __device__ __forceinline__ u32 read_lane(u32 v, u32 l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ u64 ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
@@ -104,11 +102,23 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // ------------------------------------------------------------ descriptors
+// c word: [63:38] tag, [37] malformed seen, [36] inclusive flag, [35:0] count
+// s word: [63:38] tag, [32] inclusive flag, [31:0] wrapping sum
 __device__ __forceinline__ u32 make_tag(u32 epoch) { return (1u << 25) | (epoch & 0x1FFFFFFu); }
-__device__ __forceinline__ u64 pack_c(u32 tag, bool mal, u64 c) {
-    return ((u64)tag << 38) | ((u64)(mal ? 1 : 0) << 37) | (c & kCountMask);
+__device__ __forceinline__ u64 pack_c(u32 tag, bool inc, bool mal, u64 c) {
+    return ((u64)tag << 38) | ((u64)(mal ? 1 : 0) << 37) | ((u64)(inc ? 1 : 0) << 36) | (c & kCountMask);
 }
-__device__ __forceinline__ u64 pack_s(u32 tag, u32 s) { return ((u64)tag << 32) | s; }
+__device__ __forceinline__ u64 pack_s(u32 tag, bool inc, u32 s) {
+    return ((u64)tag << 38) | ((u64)(inc ? 1 : 0) << 32) | s;
+}
+
+// Publish a tile's aggregate (inc = false) or inclusive prefix (inc = true):
+// the sum word first, the count word last.
+template <bool SUM>
+__device__ __forceinline__ void publish(Desc *d, u32 tag, bool inc, bool mal, u64 c, u32 s) {
+    if (SUM) astore(&d->s, pack_s(tag, inc, s));
+    astore(&d->c, pack_c(tag, inc, mal, c));
+}
 
 struct Prefix {
     u64 c;
@@ -118,7 +128,11 @@ struct Prefix {
 
 // Decoupled look-back: exclusive prefix of descriptor `idx` over the chain
 // that starts at descriptor `first` (which always publishes an inclusive
-// value).  All 64 lanes read one predecessor each per round.
+// value).  Each round trip reads kLookbackWindows x 64 predecessors (one per
+// lane per window, two 64-bit atomic loads each), then walks them nearest
+// first: aggregates are summed until an inclusive prefix ends the walk; a
+// predecessor that has published nothing yet (or is between its two
+// stores) stops the walk and the remaining ones are read again.
 template <bool SUM>
 __device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first, u32 tag) {
     const u32 ln = lane_id();
@@ -127,45 +141,56 @@ __device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first,
     bool acc_m = false;
     i64 pos = idx - 1;
     for (;;) {
-        const i64 p = pos - (i64)ln;
-        u32 state = 2;   // 0 not ready, 1 aggregate, 2 inclusive (or before the chain)
-        u64 cv = 0;
-        u32 sv = 0;
-        if (p >= first) {
-            const Desc *d = desc + p;
-            const u64 ci = aload(&d->c_inc), ca = aload(&d->c_agg);
-            const u64 si = SUM ? aload(&d->s_inc) : 0, sa = SUM ? aload(&d->s_agg) : 0;
-            const bool inc = (u32)(ci >> 38) == tag && (!SUM || (u32)(si >> 32) == tag);
-            const bool agg = (u32)(ca >> 38) == tag && (!SUM || (u32)(sa >> 32) == tag);
-            if (inc) {
-                cv = ci;
-                sv = (u32)si;
-            } else if (agg) {
-                state = 1;
-                cv = ca;
-                sv = (u32)sa;
-            } else {
-                state = 0;
+        u64 cw[kLookbackWindows], sw[kLookbackWindows];
+#pragma unroll
+        for (int k = 0; k < kLookbackWindows; ++k) {
+            const i64 p = pos - (i64)ln - 64 * k;
+            cw[k] = 0;
+            sw[k] = 0;
+            if (p >= first) {
+                cw[k] = aload(&desc[p].c);
+                if (SUM) sw[k] = aload(&desc[p].s);
             }
         }
-        const u64 m_inc = ballot(state == 2);
-        const u64 m_nr = ballot(state == 0);
-        const u32 fi = m_inc ? (u32)__builtin_ctzll(m_inc) : 64u;
-        const u32 fn = m_nr ? (u32)__builtin_ctzll(m_nr) : 64u;
-        const u32 lim = fi < fn ? fi : fn;
-        const bool take = ln < lim;
-        acc_c += wave_sum(take ? (u32)(cv & kCountMask) : 0u);
-        if (SUM) acc_s += wave_sum(take ? sv : 0u);
-        acc_m |= ballot(take && ((cv >> 37) & 1)) != 0;
-        if (fi < fn) {
-            const u64 c = ((u64)read_lane((u32)(cv >> 32), fi) << 32) | read_lane((u32)cv, fi);
-            acc_c += c & kCountMask;
-            acc_m |= ((c >> 37) & 1) != 0;
-            if (SUM) acc_s += read_lane(sv, fi);
-            break;
+        i64 consumed = 0;
+        bool done = false;
+#pragma unroll
+        for (int k = 0; k < kLookbackWindows; ++k) {
+            const i64 p = pos - (i64)ln - 64 * k;
+            const u64 c = cw[k];
+            const bool vc = (u32)(c >> 38) == tag;
+            const bool ic = (c >> 36) & 1;
+            bool ok = vc;
+            if (SUM) {
+                const bool vs = (u32)(sw[k] >> 38) == tag;
+                const bool is = (sw[k] >> 32) & 1;
+                ok = vc && vs && ic == is;
+            }
+            // 0 not ready, 1 aggregate, 2 inclusive (or before the chain)
+            const u32 state = p < first ? 2u : (ok ? (ic ? 2u : 1u) : 0u);
+            const u64 m_inc = ballot(state == 2);
+            const u64 m_nr = ballot(state == 0);
+            const u32 fi = m_inc ? (u32)__builtin_ctzll(m_inc) : 64u;
+            const u32 fn = m_nr ? (u32)__builtin_ctzll(m_nr) : 64u;
+            const u32 lim = fi < fn ? fi : fn;
+            const bool take = ln < lim;
+            acc_c += wave_sum(take ? (u32)(c & kCountMask) : 0u);
+            if (SUM) acc_s += wave_sum(take ? (u32)sw[k] : 0u);
+            acc_m |= ballot(take && ((c >> 37) & 1)) != 0;
+            consumed += lim;
+            if (fi < fn) {
+                const u64 ci = ((u64)read_lane((u32)(c >> 32), fi) << 32) | read_lane((u32)c, fi);
+                acc_c += ci & kCountMask;
+                acc_m |= ((ci >> 37) & 1) != 0;
+                if (SUM) acc_s += read_lane((u32)sw[k], fi);
+                done = true;
+                break;
+            }
+            if (fn < 64) break;
         }
-        pos -= lim;
-        if (lim == 0) __builtin_amdgcn_s_sleep(1);
+        if (done) break;
+        pos -= consumed;
+        if (consumed == 0) __builtin_amdgcn_s_sleep(1);
     }
     return Prefix{acc_c, acc_s, acc_m};
 }
@@ -345,8 +370,10 @@ __device__ __forceinline__ void store_stage(const u32 *stage, u32 amis, u32 tota
 }
 
 // ------------------------------------------------------------ one tile
-// A tile of SEGS segments of one stream (or list).  `base` is 16-byte
-// aligned; valid bytes are [vstart, vend); the tile starts at tv.
+// A tile is the run of wpb x SEGS segments that one workgroup decodes;
+// wavefront w owns segments [w*SEGS, (w+1)*SEGS) of it.  `base` is 16-byte
+// aligned; valid bytes are [vstart, vend); the tile starts at tv.  One
+// ticket and one look-back descriptor per tile.
 struct TileIn {
     const u8 *base;
     u64 vstart, vend, tv;
@@ -363,14 +390,30 @@ struct TileOut {
     bool mal;
 };
 
+constexpr int kMaxWaves = 16;
+
+// Workgroup-shared scratch of the tile protocol.
+struct WgShared {
+    u32 wcnt[kMaxWaves];
+    u32 wsum[kMaxWaves];
+    u32 wmal[kMaxWaves];
+    u64 excl_c;
+    u32 excl_s;
+    u32 excl_mal;
+    u32 epoch;
+    u64 item;
+};
+
 template <bool DELTA, bool COUNT, int SEGS, bool EDGE>
-__device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage) {
+__device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage, WgShared &sh, u32 wib,
+                                            u32 wpb) {
     const u32 ln = lane_id();
+    const u64 wv = t.tv + (u64)wib * (SEGS * kSegBytes);   // this wavefront's first byte
     u32 w[SEGS][4];
     u32 valid[SEGS];
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
-        const u64 v = t.tv + (u64)s * kSegBytes + 16u * ln;
+        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
         if (EDGE) {
             load16_guarded(t.base, v, t.vstart, t.vend, w[s], valid[s]);
         } else {
@@ -380,9 +423,9 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage) {
     }
     u32 h0, hv0;
     if (EDGE) {
-        load4_guarded(t.base, (i64)t.tv - 4, t.vstart, t.vend, h0, hv0);
+        load4_guarded(t.base, (i64)wv - 4, t.vstart, t.vend, h0, hv0);
     } else {
-        h0 = *(const u32 *)(t.base + t.tv - 4);
+        h0 = *(const u32 *)(t.base + wv - 4);
         hv0 = 0xF000u;
     }
 
@@ -413,31 +456,52 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage) {
             stot += read_lane(si, 63);
         }
     }
-    const bool tmal = ballot(mal) != 0;
-
-    // Publish the aggregate, look back, publish the inclusive prefix.
-    Prefix ex;
-    if (t.didx == t.dfirst) {
-        ex = Prefix{0, t.prev, false};
-    } else {
-        if (ln == 0) {
-            if (DELTA) astore(&t.desc[t.didx].s_agg, pack_s(t.tag, stot));
-            astore(&t.desc[t.didx].c_agg, pack_c(t.tag, tmal, ctot));
-        }
-        ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag);
-    }
-    const u64 total = ex.c + ctot;
-    const bool allmal = ex.mal || tmal;
+    const bool wmal = ballot(mal) != 0;
     if (ln == 0) {
-        if (DELTA) astore(&t.desc[t.didx].s_inc, pack_s(t.tag, ex.s + stot));
-        astore(&t.desc[t.didx].c_inc, pack_c(t.tag, allmal, total));
+        sh.wcnt[wib] = ctot;
+        sh.wsum[wib] = stot;
+        sh.wmal[wib] = wmal ? 1u : 0u;
     }
-    if (COUNT) return TileOut{total, allmal};
+    __syncthreads();
+    u32 wex_c = 0, wex_s = 0, tc = 0, ts = 0, tm = 0;
+    for (u32 k = 0; k < wpb; ++k) {
+        const u32 c = sh.wcnt[k], s = sh.wsum[k];
+        if (k < wib) {
+            wex_c += c;
+            wex_s += s;
+        }
+        tc += c;
+        ts += s;
+        tm |= sh.wmal[k];
+    }
+
+    // Wavefront 0 publishes the aggregate, looks back, publishes the
+    // inclusive prefix and hands the exclusive prefix to the others.
+    if (wib == 0) {
+        Prefix ex;
+        if (t.didx == t.dfirst) {
+            ex = Prefix{0, t.prev, false};
+        } else {
+            if (ln == 0) publish<DELTA>(&t.desc[t.didx], t.tag, false, tm != 0, tc, ts);
+            ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag);
+        }
+        if (ln == 0) {
+            publish<DELTA>(&t.desc[t.didx], t.tag, true, ex.mal || tm != 0, ex.c + tc, ex.s + ts);
+            sh.excl_c = ex.c;
+            sh.excl_s = ex.s;
+            sh.excl_mal = ex.mal ? 1u : 0u;
+        }
+    }
+    __syncthreads();
+    const u64 exc = sh.excl_c;
+    const u32 exs = sh.excl_s;
+    const TileOut res{exc + tc, sh.excl_mal != 0 || tm != 0};
+    if (COUNT) return res;
 
     // Phase 2: compact each segment's integers through LDS and store them.
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
-        const u64 gbase = ex.c + segbase[s];
+        const u64 gbase = exc + wex_c + segbase[s];
         if (gbase >= t.n || segcnt[s] == 0) continue;
         const u32 amis = out_mis(t.out, gbase);
         if (DELTA) {
@@ -452,10 +516,10 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage) {
             emit<false>(stage, amis + lex[s], term[s], rp, 0u);
         }
         wave_lds_sync();
-        store_stage<DELTA>(stage, amis, segcnt[s], t.out, gbase, t.n, ex.s);
+        store_stage<DELTA>(stage, amis, segcnt[s], t.out, gbase, t.n, exs + wex_s);
         wave_lds_sync();
     }
-    return TileOut{total, allmal};
+    return res;
 }
 
 // Status of a finished stream or list (readings R3-R6): malformed first,
@@ -470,25 +534,26 @@ __device__ __forceinline__ int32_t final_status(bool mal, u8 last_byte, u64 tota
 // ------------------------------------------------------------ single stream
 template <bool DELTA, bool COUNT, int SEGS>
 __global__ __launch_bounds__(1024) void k_stream(StreamArgs a) {
-    extern __shared__ u32 lds[];
-    const u32 ln = lane_id();
-    const u32 wib = threadIdx.x >> 6;
-    const u64 wg = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
-    if (wg >= a.ntiles) return;   // exactly ntiles wavefronts take a ticket
+    extern __shared__ __align__(16) u32 lds[];
+    __shared__ WgShared sh;
+    const u32 tid = threadIdx.x;
+    const u32 wib = tid >> 6;
+    const u32 wpb = blockDim.x >> 6;
     u32 *stage = lds + wib * kStageWords;
 
-    u64 tw = 0;
-    if (ln == 0) tw = aadd(a.hdr, 1);
-    tw = first_lane64(tw);
-    const u32 tile = (u32)tw;
-    const u32 epoch = (u32)(tw >> 32);
-    if (tile == a.ntiles - 1 && ln == 0) astore(a.hdr, (u64)(epoch + 1) << 32);
+    // Tile = workgroup index: workgroups are dispatched in index order, so
+    // every tile a look-back waits for is already running.
+    const u32 tile = blockIdx.x;
+    if (tid == 0) sh.epoch = (u32)aload(a.hdr);
+    __syncthreads();
+    const u32 epoch = sh.epoch;
 
+    const u64 tb = (u64)wpb * SEGS * kSegBytes;
     TileIn t;
     t.base = a.base;
     t.vstart = a.vstart;
     t.vend = a.vend;
-    t.tv = (u64)tile * (SEGS * kSegBytes);
+    t.tv = (u64)tile * tb;
     t.out = a.out;
     t.n = a.n;
     t.prev = a.prev;
@@ -496,20 +561,23 @@ __global__ __launch_bounds__(1024) void k_stream(StreamArgs a) {
     t.didx = tile;
     t.dfirst = 0;
     t.tag = make_tag(epoch);
-    const bool interior = tile > 0 && t.tv + SEGS * kSegBytes <= a.vend;
+    const bool interior = tile > 0 && t.tv + tb <= a.vend;
     TileOut r;
     if (interior)
-        r = run_tile<DELTA, COUNT, SEGS, false>(t, stage);
+        r = run_tile<DELTA, COUNT, SEGS, false>(t, stage, sh, wib, wpb);
     else
-        r = run_tile<DELTA, COUNT, SEGS, true>(t, stage);
+        r = run_tile<DELTA, COUNT, SEGS, true>(t, stage, sh, wib, wpb);
 
-    if (tile == a.ntiles - 1 && ln == 0) {
+    if (tile == a.ntiles - 1 && tid == 0) {
         if (COUNT) {
             *a.d_count = r.total;
         } else {
             const u8 last = a.base[a.vend - 1];
             *a.d_status = final_status(r.mal, last, r.total, a.n);
         }
+        // The last tile's look-back has ended, so every tile has published
+        // and therefore read the epoch: retire this launch's descriptors.
+        astore(a.hdr, (u64)epoch + 1);
     }
 }
 
@@ -542,31 +610,27 @@ __device__ __forceinline__ bool list_ok(const ListArgs &a, const ListDesc &d) {
 
 // Prep: classify every list (empty / small / large) and build the work
 // table with a decoupled look-back scan over blocks of kPrepBlock lists.
-// Large-list tiles take items [0, L); small lists take items counted down
-// from max_items - 1, so their slots need no knowledge of L.
-template <int SEGS>
-__global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks) {
+// Large lists get one item per span of up to kSpanTiles workgroup tiles, at
+// [0, L); small lists get one slot each, counted down from max_items - 1 (so
+// a slot needs no knowledge of L).
+__global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u64 tb) {
     __shared__ u32 sh_c[kPrepBlock / kWave], sh_s[kPrepBlock / kWave];
-    __shared__ u64 sh_tw;
+    __shared__ u32 sh_epoch;
     __shared__ u64 sh_exc;
     __shared__ u32 sh_exs;
     const u32 tid = threadIdx.x;
     const u32 ln = lane_id();
     const u32 wib = tid >> 6;
-    if (tid == 0) sh_tw = aadd(a.hdr, 1);
+    const u32 blk = blockIdx.x;
+    if (tid == 0) sh_epoch = (u32)aload(a.hdr);
     __syncthreads();
-    const u64 tw = sh_tw;
-    const u32 blk = (u32)tw;
-    const u32 epoch = (u32)(tw >> 32);
-    if (blk == nblocks - 1 && tid == 0) astore(a.hdr, (u64)(epoch + 1) << 32);
+    const u32 epoch = sh_epoch;
     const u32 tag = make_tag(epoch);
-    const u64 tb = (u64)SEGS * kSegBytes;
 
     const u64 i = (u64)blk * kPrepBlock + tid;
     u32 nlarge = 0, nsmall = 0;
-    ListDesc d{0, 0, 0, 0};
     if (i < a.nlists) {
-        d = list_desc(a, i);
+        const ListDesc d = list_desc(a, i);
         if (!list_ok(a, d)) {
             a.list_status[i] = VBYTE_EINVAL;
         } else if (d.be == d.bb) {
@@ -575,10 +639,10 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks) {
             nsmall = 1;
         } else {
             const u64 vs = (u64)(uintptr_t)(a.bytes + d.bb) & 15u;
-            nlarge = (u32)((vs + (u64)(d.be - d.bb) + tb - 1) / tb);
+            const u64 tiles = (vs + (u64)(d.be - d.bb) + tb - 1) / tb;
+            nlarge = (u32)((tiles + kSpanTiles - 1) / kSpanTiles);
         }
     }
-    // block scan of (nlarge, nsmall)
     const u32 cl = wave_scan(nlarge), cs = wave_scan(nsmall);
     if (ln == 63) {
         sh_c[wib] = cl;
@@ -599,23 +663,20 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks) {
         if (blk == 0) {
             ex = Prefix{0, 0, false};
         } else {
-            if (ln == 0) {
-                astore(&a.prep_desc[blk].s_agg, pack_s(tag, bs));
-                astore(&a.prep_desc[blk].c_agg, pack_c(tag, false, bl));
-            }
+            if (ln == 0) publish<true>(&a.prep_desc[blk], tag, false, false, bl, bs);
             ex = lookback<true>(a.prep_desc, blk, 0, tag);
         }
         if (ln == 0) {
-            astore(&a.prep_desc[blk].s_inc, pack_s(tag, ex.s + bs));
-            astore(&a.prep_desc[blk].c_inc, pack_c(tag, false, ex.c + bl));
+            publish<true>(&a.prep_desc[blk], tag, true, false, ex.c + bl, ex.s + bs);
             sh_exc = ex.c;
             sh_exs = ex.s;
             if (blk == nblocks - 1) {
                 const u64 L = ex.c + bl, S = (u64)ex.s + bs;
                 const bool fits = L + S <= a.max_items;
-                astore(&a.totals[0], L);
-                astore(&a.totals[1], fits ? L + S : 0);
+                astore(&a.totals[0], fits ? L : 0);
+                astore(&a.totals[1], fits ? S : 0);
                 astore(&a.totals[2], fits ? 0 : 1);
+                astore(a.hdr, (u64)epoch + 1);   // every block has published
             }
         }
     }
@@ -676,66 +737,119 @@ __device__ void run_small(const ListArgs &a, u64 li, const ListDesc &d, u32 *sta
         pv = read_lane(valid, 63);
     }
     const bool anymal = ballot(mal) != 0;
-    if (ln == 0) a.list_status[li] = final_status(anymal, base[vend - 1], rank, n);
+    // every lane stores the same (uniform) status word
+    a.list_status[li] = final_status(anymal, base[vend - 1], rank, n);
 }
 
+// Wavefront-uniform fetch-and-increment of an LDS counter: lane 0 performs
+// the atomic and leaves the old value in the wavefront's LDS slot, which all
+// lanes then read (through memory, so the result is uniform by construction).
+__device__ __forceinline__ u32 pick_next(u32 *counter, u32 *slot) {
+    if (lane_id() == 0) *slot = atomicAdd(counter, 1u);
+    wave_lds_sync();
+    return first_lane(*slot);
+}
+
+// Persistent batched decode.  Workgroups first take spans of large-list
+// tiles from one queue (in list order, so a tile's predecessors were taken
+// earlier by running workgroups), then chunks of small lists from a second
+// queue (each wavefront pulls lists of the chunk through an LDS counter).
+// Both queue words are reset by their last taker; each queue costs one
+// device-wide atomic per span or chunk, not per tile or list.
 template <bool DELTA, int SEGS>
 __global__ __launch_bounds__(1024) void k_batch(ListArgs a) {
-    extern __shared__ u32 lds[];
+    extern __shared__ __align__(16) u32 lds[];
+    __shared__ WgShared sh;
+    __shared__ u32 sh_next;
+    __shared__ u32 sh_pick[kMaxWaves];
+    const u32 tid = threadIdx.x;
     const u32 ln = lane_id();
-    const u32 wib = threadIdx.x >> 6;
+    const u32 wib = tid >> 6;
+    const u32 wpb = blockDim.x >> 6;
     u32 *stage = lds + wib * kStageWords;
+    if (tid == 0) sh.epoch = (u32)aload(a.hdr);
+    __syncthreads();
+    const u32 epoch = sh.epoch;
     const u64 L = aload(&a.totals[0]);
-    const u64 T = aload(&a.totals[1]);
+    const u64 S = aload(&a.totals[1]);
     const bool failed = aload(&a.totals[2]) != 0;
-    const u64 last_ticket = T + a.nwaves - 1;
-    const u64 gw = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
+    const u64 G = gridDim.x;
+    const u64 tb = (u64)wpb * SEGS * kSegBytes;
+    u64 *qlarge = a.hdr + 1;
+    u64 *qsmall = a.hdr + 2;
+
     for (;;) {
-        u64 tw = 0;
-        if (ln == 0) tw = aadd(a.hdr, 1);
-        tw = first_lane64(tw);
-        const u64 it = (u32)tw;
-        const u32 epoch = (u32)(tw >> 32);
-        if (it == last_ticket && ln == 0) astore(a.hdr, (u64)(epoch + 1) << 32);
-        if (it >= T) break;
-        if (it < L) {
-            const int2 e = a.items[it];
-            const u64 li = (u64)e.x;
-            const u32 ti = (u32)e.y;
-            const ListDesc d = list_desc(a, li);
-            const u8 *p0 = a.bytes + d.bb;
-            TileIn t;
-            t.base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
-            t.vstart = (u64)(p0 - t.base);
-            t.vend = t.vstart + (u64)(d.be - d.bb);
-            t.tv = (u64)ti * (SEGS * kSegBytes);
-            t.out = a.out + d.ob;
-            t.n = (u64)d.n;
-            t.prev = a.prevs ? a.prevs[li] : 0u;
-            t.desc = a.desc;
-            t.didx = (i64)it;
-            t.dfirst = (i64)it - ti;
-            t.tag = make_tag(epoch);
-            const bool interior = ti > 0 && t.tv + SEGS * kSegBytes <= t.vend;
-            TileOut r;
-            if (DELTA) {
-                r = interior ? run_tile<true, false, SEGS, false>(t, stage)
-                             : run_tile<true, false, SEGS, true>(t, stage);
-            } else {
-                r = interior ? run_tile<false, false, SEGS, false>(t, stage)
-                             : run_tile<false, false, SEGS, true>(t, stage);
+        if (tid == 0) {
+            const u64 k = aadd(qlarge, 1);
+            if (k == L + G - 1) {      // last taker: every workgroup has read the epoch
+                astore(qlarge, 0);
+                astore(a.hdr, (u64)epoch + 1);
             }
-            const bool last = t.tv + SEGS * kSegBytes >= t.vend;
-            if (last && ln == 0) a.list_status[li] = final_status(r.mal, t.base[t.vend - 1], r.total, t.n);
-        } else {
-            const int2 e = a.items[a.max_items - 1 - (it - L)];
-            const u64 li = (u64)e.x;
-            const ListDesc d = list_desc(a, li);
-            run_small<DELTA>(a, li, d, stage);
+            sh.item = k;
+        }
+        __syncthreads();
+        const u64 k = sh.item;
+        __syncthreads();
+        if (k >= L) break;
+        const int2 e = a.items[k];
+        const u64 li = (u64)e.x;
+        const u32 sp = (u32)e.y;
+        const ListDesc d = list_desc(a, li);
+        const u8 *p0 = a.bytes + d.bb;
+        TileIn t;
+        t.base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
+        t.vstart = (u64)(p0 - t.base);
+        t.vend = t.vstart + (u64)(d.be - d.bb);
+        t.out = a.out + d.ob;
+        t.n = (u64)d.n;
+        t.prev = a.prevs ? a.prevs[li] : 0u;
+        t.desc = a.desc;
+        t.dfirst = (i64)(k - sp) * kSpanTiles;
+        t.tag = make_tag(epoch);
+        const u64 tiles = (t.vend + tb - 1) / tb;
+        const u64 t0 = (u64)sp * kSpanTiles;
+        const u64 t1 = t0 + kSpanTiles < tiles ? t0 + kSpanTiles : tiles;
+        for (u64 ti = t0; ti < t1; ++ti) {
+            t.tv = ti * tb;
+            t.didx = t.dfirst + (i64)ti;
+            const bool interior = ti > 0 && t.tv + tb <= t.vend;
+            const TileOut r = interior ? run_tile<DELTA, false, SEGS, false>(t, stage, sh, wib, wpb)
+                                       : run_tile<DELTA, false, SEGS, true>(t, stage, sh, wib, wpb);
+            if (ti == tiles - 1 && tid == 0)
+                a.list_status[li] = final_status(r.mal, t.base[t.vend - 1], r.total, t.n);
         }
     }
+
+    const u64 chunk = (u64)kSmallChunk;
+    const u64 nchunks = (S + chunk - 1) / chunk;
+    for (;;) {
+        if (tid == 0) {
+            const u64 c = aadd(qsmall, 1);
+            if (c == nchunks + G - 1) astore(qsmall, 0);
+            sh.item = c;
+            sh_next = 0;
+        }
+        __syncthreads();
+        const u64 c = sh.item;
+        __syncthreads();
+        if (c >= nchunks) break;
+        const u64 lo = c * chunk;
+        const u64 hi = lo + chunk < S ? lo + chunk : S;
+        // each wavefront pulls lists of the chunk through the LDS counter
+        u32 j = pick_next(&sh_next, &sh_pick[wib]);
+        while (lo + j < hi) {
+            const u64 slot = lo + j;
+            const int2 e = a.items[a.max_items - 1 - slot];
+            const u64 li = (u64)e.x;
+            run_small<DELTA>(a, li, list_desc(a, li), stage);
+            j = pick_next(&sh_next, &sh_pick[wib]);
+        }
+        __syncthreads();
+    }
     if (failed) {
-        for (u64 i = gw * kWave + ln; i < a.nlists; i += (u64)a.nwaves * kWave) a.list_status[i] = VBYTE_EINVAL;
+        const u64 nthreads = (u64)gridDim.x * blockDim.x;
+        for (u64 i = (u64)blockIdx.x * blockDim.x + tid; i < a.nlists; i += nthreads)
+            a.list_status[i] = VBYTE_EINVAL;
     }
 }
 
@@ -750,19 +864,15 @@ __device__ __forceinline__ u32 code_len(u32 x) {
 }
 
 __global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
-    extern __shared__ u32 lds[];
+    extern __shared__ __align__(16) u32 lds[];
     const u32 ln = lane_id();
     const u32 wib = threadIdx.x >> 6;
     const u64 wg = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
     if (wg >= a.ntiles) return;
     u8 *stage = (u8 *)(lds + wib * (kEncodeWaveValues * 5 / 4 + 8));
-
-    u64 tw = 0;
-    if (ln == 0) tw = aadd(a.hdr, 1);
-    tw = first_lane64(tw);
-    const u32 tile = (u32)tw;
-    const u32 epoch = (u32)(tw >> 32);
-    if (tile == a.ntiles - 1 && ln == 0) astore(a.hdr, (u64)(epoch + 1) << 32);
+    // tile = wavefront index in dispatch order; see k_stream for the epoch
+    const u32 tile = (u32)wg;
+    const u32 epoch = first_lane((u32)aload(a.hdr));
     const u32 tag = make_tag(epoch);
 
     // lane owns values [v0, v0 + 16)
@@ -786,10 +896,10 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
     if (tile == 0) {
         ex = Prefix{0, 0, false};
     } else {
-        if (ln == 0) astore(&a.desc[tile].c_agg, pack_c(tag, false, tilebytes));
+        if (ln == 0) publish<false>(&a.desc[tile], tag, false, false, tilebytes, 0);
         ex = lookback<false>(a.desc, tile, 0, tag);
     }
-    if (ln == 0) astore(&a.desc[tile].c_inc, pack_c(tag, false, ex.c + tilebytes));
+    if (ln == 0) publish<false>(&a.desc[tile], tag, true, false, ex.c + tilebytes, 0);
     const u64 gb = ex.c;   // byte offset of this tile
     const u32 mis = (u32)(((uintptr_t)a.bytes + gb) & 3u);
     // assemble into LDS at stage[mis + local offset]
@@ -823,7 +933,10 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
             }
         }
     }
-    if (tile == a.ntiles - 1 && ln == 0) *a.d_nbytes = ex.c + tilebytes;
+    if (tile == a.ntiles - 1 && ln == 0) {
+        *a.d_nbytes = ex.c + tilebytes;
+        astore(a.hdr, (u64)epoch + 1);
+    }
 }
 
 // ------------------------------------------------------------ small kernels
@@ -836,9 +949,8 @@ __global__ void k_zero(uint4 *p, size_t n16) {
 
 template <bool DELTA, bool COUNT, int SEGS>
 hipError_t launch_stream_t(const StreamArgs &a, int wpb, hipStream_t s) {
-    const u32 blocks = (a.ntiles + wpb - 1) / wpb;
     const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
-    k_stream<DELTA, COUNT, SEGS><<<blocks, wpb * kWave, lds, s>>>(a);
+    k_stream<DELTA, COUNT, SEGS><<<a.ntiles, wpb * kWave, lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -853,7 +965,7 @@ template <int SEGS>
 hipError_t launch_batch_s(const ListArgs &a, int wpb, int grid_blocks, hipStream_t s) {
     const u32 nblocks = (u32)((a.nlists + kPrepBlock - 1) / kPrepBlock);
     if (nblocks) {
-        k_prep<SEGS><<<nblocks, kPrepBlock, 0, s>>>(a, nblocks);
+        k_prep<<<nblocks, kPrepBlock, 0, s>>>(a, nblocks, (u64)wpb * SEGS * kSegBytes);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

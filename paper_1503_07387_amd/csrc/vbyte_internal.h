@@ -10,7 +10,9 @@
 namespace vb {
 
 // One wavefront segment: 64 lanes x 16 bytes, loaded with one 128-bit load
-// per lane.  A tile is SEGS consecutive segments decoded by one wavefront.
+// per lane.  A tile is wpb x SEGS consecutive segments decoded by one
+// workgroup of wpb wavefronts (SEGS each); it takes one ticket and owns one
+// look-back descriptor.
 constexpr int kWave = 64;
 constexpr int kSegBytes = 1024;
 // Per-wavefront LDS staging for one segment's outputs: at most one integer
@@ -21,27 +23,28 @@ constexpr int kStageWords = 1040;
 // tile (or per work item of a batched launch), then batch work tables.
 constexpr size_t kHeaderBytes = 256;
 
-// Look-back descriptor of one tile.  Each word is self-contained (a tag that
-// names the launch, a flag and a payload), published with one 64-bit atomic
-// store and read with one 64-bit atomic load, so no fence orders a payload
-// against a flag.
-//   c_*: [63:38] tag (26 bits), [37] malformed seen, [36:0] count
-//   s_*: [57:32] tag, [31:0] wrapping uint32 sum
-// *_agg hold the tile's own aggregate, *_inc the inclusive prefix up to and
-// including the tile.
+// Look-back descriptor of one tile: two self-contained 64-bit words, each
+// holding a tag that names the launch, an "inclusive" flag and a payload.
+// A tile first publishes its own aggregate (flag 0), later its inclusive
+// prefix (flag 1), each time with one 64-bit atomic store per word; a reader
+// accepts a descriptor only when both words carry this launch's tag and the
+// same flag, so no fence is needed to order a payload against a flag.
+//   c: [63:38] tag (26 bits), [37] malformed seen, [36] flag, [35:0] count
+//   s: [63:38] tag, [32] flag, [31:0] wrapping uint32 sum
 struct Desc {
-    uint64_t c_agg;
-    uint64_t s_agg;
-    uint64_t c_inc;
-    uint64_t s_inc;
+    uint64_t c;
+    uint64_t s;
 };
-static_assert(sizeof(Desc) == 32, "descriptor is 32 bytes");
+static_assert(sizeof(Desc) == 16, "descriptor is 16 bytes");
 
-// The header word holds (epoch << 32) | ticket.  Every launch takes exactly
-// a known number of tickets; the wavefront that takes the last one stores
-// ((epoch + 1) << 32), which both resets the ticket counter and retires the
-// descriptors of this launch for the next one.  Descriptors carry the low 25
-// bits of the epoch, so the host re-zeroes a workspace before 2^24 launches.
+// Header words: [0] launch epoch, [1] batched large-span queue, [2] batched
+// small-chunk queue.  Tiles of a single-stream launch are workgroup indices
+// (workgroups are dispatched in index order, so a tile's predecessors are
+// running when it looks back); each launch reads the epoch, tags its
+// descriptors with it, and the tile that finishes the chain stores epoch+1,
+// which retires the launch's descriptors for the next one.  Descriptors carry
+// the low 25 bits of the epoch, so the host re-zeroes a workspace before 2^24
+// launches.
 constexpr uint64_t kEpochLaunchLimit = (1ull << 24);
 
 struct StreamArgs {
@@ -75,11 +78,12 @@ struct ListArgs {
     uint64_t small_bytes;      // lists of at most this many bytes take one wavefront
     uint64_t max_items;        // capacity of the work table / descriptor array
     uint64_t *hdr;             // persistent-queue header (ticket word)
-    Desc *desc;                // one per work item
+    Desc *desc;                // kSpanTiles per large span
     Desc *prep_desc;           // one per prep block
     int2 *items;               // work table: (list, tile) per item
-    uint64_t *totals;          // [0] large items, [1] all items, [2] 1 if the table overflowed
-    uint32_t nwaves;           // wavefronts of the persistent launch
+    uint64_t *totals;          // [0] large spans L, [1] small lists S, [2] 1 if the table
+                               // overflowed (written by the prep kernel)
+    uint32_t wpb;              // wavefronts per workgroup (small lists per work item)
 };
 
 struct EncodeArgs {
@@ -105,12 +109,14 @@ hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 
 // Tiles of a single-stream decode of nbytes starting at misalignment vstart.
-inline uint64_t stream_tiles(uint64_t vstart, uint64_t nbytes, int segs) {
-    uint64_t tb = (uint64_t)segs * kSegBytes;
+inline uint64_t stream_tiles(uint64_t vstart, uint64_t nbytes, int segs, int wpb) {
+    uint64_t tb = (uint64_t)segs * wpb * kSegBytes;
     return (vstart + nbytes + tb - 1) / tb;
 }
 
 constexpr int kEncodeWaveValues = 1024;   // values per encoder tile (one wavefront)
 constexpr int kPrepBlock = 256;           // lists per prep workgroup
+constexpr int kSpanTiles = 4;             // large-list tiles per batched work item
+constexpr int kSmallChunk = 64;           // small lists per batched work item
 
 }  // namespace vb
