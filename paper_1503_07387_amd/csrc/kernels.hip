@@ -48,7 +48,7 @@ typedef uint64_t u64;
 typedef int64_t i64;
 
 constexpr u64 kCountMask = (1ull << 36) - 1;
-constexpr int kLookbackWindows = 4;   // 64-descriptor windows read per round trip
+constexpr int kLookbackWindows = 1;   // 64-descriptor windows read per round trip
 
 // ------------------------------------------------------------------ atomics
 __device__ __forceinline__ u64 aload(const u64 *p) {
@@ -321,14 +321,23 @@ __device__ __forceinline__ u32 assemble(const u32 (&w)[4], u32 valid, u32 h, u32
     return s;
 }
 
-// Write the lane's integers, compacted, to stage[amis + lex + k].
+// LDS staging layout.  Logical slot i lives at i ^ ((i >> 5) & 15): within
+// each row of 32 slots the low 4 bits are XOR-ed with the row number.  When
+// every lane holds the same number of integers (all 1-byte codes: 16 per
+// lane, all 2-byte codes: 8) the compacting writes below hit the same few
+// banks on every lane without it; with it they spread over all banks, while
+// 64 consecutive slots (the store phase) stay conflict-free and every aligned
+// group of 4 slots stays one aligned 16-byte group (permuted inside).
+__device__ __forceinline__ u32 swz(u32 i) { return i ^ ((i >> 5) & 15u); }
+
+// Write the lane's integers, compacted, to logical slots start + k.
 template <bool DELTA>
 __device__ __forceinline__ void emit(u32 *stage, u32 start, u32 term, const u32 (&r)[16], u32 add) {
     u32 k = start;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         if ((term >> j) & 1u) {
-            stage[k] = DELTA ? r[j] + add : r[j];
+            stage[swz(k)] = DELTA ? r[j] + add : r[j];
             ++k;
         }
     }
@@ -350,7 +359,23 @@ __device__ __forceinline__ void store_stage(const u32 *stage, u32 amis, u32 tota
         const u32 i0 = q << 2;
         const i64 e0 = (i64)i0 - (i64)amis;
         if (e0 >= 0 && (u64)e0 + 4 <= total && gbase + (u64)e0 + 4 <= n) {
-            uint4 v = *(const uint4 *)(stage + i0);
+            const u32 key = (i0 >> 5) & 15u;
+            const uint4 g = *(const uint4 *)(stage + (i0 ^ (key & 12u)));
+            // logical element t of the group sits at position t ^ (key & 3)
+            uint4 v = g;
+            if (key & 1u) {
+                v.x = g.y;
+                v.y = g.x;
+                v.z = g.w;
+                v.w = g.z;
+            }
+            if (key & 2u) {
+                const uint4 h = v;
+                v.x = h.z;
+                v.y = h.w;
+                v.z = h.x;
+                v.w = h.y;
+            }
             if (DELTA) {
                 v.x += add;
                 v.y += add;
@@ -363,7 +388,70 @@ __device__ __forceinline__ void store_stage(const u32 *stage, u32 amis, u32 tota
             for (int t = 0; t < 4; ++t) {
                 const i64 e = e0 + t;
                 if (e >= 0 && (u64)e < total && gbase + (u64)e < n)
-                    out[gbase + e] = stage[i0 + t] + (DELTA ? add : 0u);
+                    out[gbase + e] = stage[swz(i0 + t)] + (DELTA ? add : 0u);
+            }
+        }
+    }
+}
+
+// Store phase of a dense segment: 1024 one-byte codes, whose integers are
+// the bytes themselves.  The segment's bytes sit in stage (as bytes, in
+// order); lane q of each row expands the 4 bytes of elements 4q - amis ..
+// 4q - amis + 3 and stores them with one aligned 16-byte store.  DELTA: the
+// integers are the running sums, from a 4-wide local scan plus a wave scan of
+// the lane sums, carried across rows (the 4-wide shift-and-add prefix sum of
+// the paper's section 4, widened to the wavefront).
+template <bool DELTA>
+__device__ __forceinline__ void store_dense(const u32 *stage, u32 amis, u32 *out, u64 gbase, u64 n,
+                                            u32 add) {
+    const u32 ln = lane_id();
+    const u8 *sb = (const u8 *)stage;
+    u32 carry = add;
+    const u32 nq = (amis + kSegBytes + 3) >> 2;
+    for (u32 q0 = 0; q0 < nq; q0 += kWave) {
+        const u32 q = q0 + ln;
+        const int e0 = (int)(q << 2) - (int)amis;
+        u32 b4;
+        const bool inner = e0 >= 0 && e0 + 4 <= kSegBytes;
+        if (inner) {
+            const u32 lo = stage[e0 >> 2];
+            const u32 hi = (e0 & 3) ? stage[(e0 >> 2) + 1] : 0u;
+            b4 = __builtin_amdgcn_alignbyte(hi, lo, (u32)(e0 & 3));   // byte shift
+        } else {
+            b4 = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int e = e0 + t;
+                if (e >= 0 && e < kSegBytes) b4 |= (u32)sb[e] << (8 * t);
+            }
+        }
+        uint4 v;
+        v.x = b4 & 0xFFu;
+        v.y = (b4 >> 8) & 0xFFu;
+        v.z = (b4 >> 16) & 0xFFu;
+        v.w = b4 >> 24;
+        if (DELTA) {
+            v.y += v.x;
+            v.z += v.y;
+            v.w += v.z;
+            const u32 incl = wave_scan(v.w);
+            const u32 base = carry + incl - v.w;
+            carry += read_lane(incl, 63);
+            v.x += base;
+            v.y += base;
+            v.z += base;
+            v.w += base;
+        }
+        if (q < nq) {
+            if (inner && gbase + (u64)e0 + 4 <= n) {
+                *(uint4 *)(out + gbase + e0) = v;
+            } else {
+                const u32 vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int e = e0 + t;
+                    if (e >= 0 && e < kSegBytes && gbase + (u64)e < n) out[gbase + e] = vv[t];
+                }
             }
         }
     }
@@ -433,7 +521,8 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage, WgShare
     u32 term[SEGS], lex[SEGS], segbase[SEGS], segcnt[SEGS];
     u32 lsum[SEGS];
     u32 r[DELTA ? SEGS : 1][16];
-    u32 ctot = 0, stot = 0;
+    u32 sbase[SEGS];
+    u32 ctot = 0, stot = 0, dmask = 0;
     bool mal = false;
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
@@ -444,15 +533,27 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage, WgShare
         const SegMask m = seg_mask(w[s], valid[s], h, hv & 0xF000u);
         term[s] = m.term;
         mal |= m.mal;
+        // dense: all 1024 bytes are terminators and no code enters from below
+        const bool dense = !EDGE && ballot(m.term == 0xFFFFu) == ~0ull && (l0w >> 31) == 0;
+        dmask |= dense ? (1u << s) : 0u;
         const u32 ci = wave_scan(m.cnt);
         lex[s] = ci - m.cnt;
         segbase[s] = ctot;
         segcnt[s] = read_lane(ci, 63);
         ctot += segcnt[s];
         if (DELTA) {
-            const u32 ls = assemble<true, EDGE>(w[s], valid[s], h, hv & 0xF000u, r[s]);
+            u32 ls;
+            if (dense) {
+                ls = __builtin_amdgcn_sad_u8(w[s][0], 0u, 0u);
+                ls = __builtin_amdgcn_sad_u8(w[s][1], 0u, ls);
+                ls = __builtin_amdgcn_sad_u8(w[s][2], 0u, ls);
+                ls = __builtin_amdgcn_sad_u8(w[s][3], 0u, ls);
+            } else {
+                ls = assemble<true, EDGE>(w[s], valid[s], h, hv & 0xF000u, r[s]);
+            }
             const u32 si = wave_scan(ls);
             lsum[s] = stot + si - ls;
+            sbase[s] = stot;
             stot += read_lane(si, 63);
         }
     }
@@ -504,6 +605,13 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage, WgShare
         const u64 gbase = exc + wex_c + segbase[s];
         if (gbase >= t.n || segcnt[s] == 0) continue;
         const u32 amis = out_mis(t.out, gbase);
+        if (dmask & (1u << s)) {
+            *(uint4 *)(stage + 4 * ln) = make_uint4(w[s][0], w[s][1], w[s][2], w[s][3]);
+            wave_lds_sync();
+            store_dense<DELTA>(stage, amis, t.out, gbase, t.n, DELTA ? exs + wex_s + sbase[s] : 0u);
+            wave_lds_sync();
+            continue;
+        }
         if (DELTA) {
             emit<true>(stage, amis + lex[s], term[s], r[s], lsum[s]);
         } else {
@@ -763,7 +871,6 @@ __global__ __launch_bounds__(1024) void k_batch(ListArgs a) {
     __shared__ u32 sh_next;
     __shared__ u32 sh_pick[kMaxWaves];
     const u32 tid = threadIdx.x;
-    const u32 ln = lane_id();
     const u32 wib = tid >> 6;
     const u32 wpb = blockDim.x >> 6;
     u32 *stage = lds + wib * kStageWords;

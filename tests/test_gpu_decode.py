@@ -250,3 +250,34 @@ def test_gpu_encode_then_decode_roundtrip():
     enc = vbyte.encode(xt)
     y = vbyte.decode(enc, x.size)
     assert np.array_equal(u32(y), x)
+
+
+@pytest.mark.parametrize("segs,wpb", [(4, 8), (2, 4), (1, 1)])
+def test_dense_one_byte_segments(segs, wpb):
+    """Segments made only of 1-byte codes take the dense path; rare 2-byte
+    codes (some straddling a segment start), every output misalignment and a
+    truncated count check that it joins the general path seamlessly."""
+    vbyte.set_tuning(segs, wpb, 0)
+    rng = np.random.default_rng(segs + 10 * wpb)
+    n = 300_000
+    x = rng.integers(0, 128, n).astype(np.uint32)
+    # 2-byte codes at a few random positions and right before segment starts
+    b = oracle.encode(x)
+    pos = list(rng.integers(0, n - 1, 20))
+    for k in range(1, 40):
+        pos.append(1024 * k - 1)          # code bytes k*1024-1 and k*1024 straddle
+    for p in pos:
+        x[p] = 200
+    b = oracle.encode(x)
+    for ooff in range(4):
+        for boff in (0, 7):
+            st, y = check_against_oracle(b, n, boff=boff, ooff=ooff)
+            assert np.array_equal(y, x)
+            check_against_oracle(b, n, delta=True, prev=0xFFFFFFF0, boff=boff, ooff=ooff)
+    # fewer outputs than codes: the dense store respects n
+    st, _ = check_against_oracle(b, n - 777)
+    assert st == vbyte.ECOUNT
+    pure = rng.integers(0, 128, 70_000).astype(np.uint8)
+    for ooff in range(4):
+        check_against_oracle(pure, pure.size, ooff=ooff)
+        check_against_oracle(pure, pure.size, delta=True, prev=3, ooff=ooff)
