@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Gints/s + HBM GB/s (% peak), batched vs plain per-list; p50/p99 query latency"
 HBM_PEAK_GBPS = 8000.0
 N_STREAM = 1 << 26
+COPY_ELEMS = 1 << 26          # calibration copy: 256 MiB read + 256 MiB written
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "decode_delta_64Mi_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1503_07387_amd", "csrc", "kernels.hip")
 
@@ -103,13 +104,80 @@ def cpu_baseline(streams, budget_s=15.0):
                       f"{el:.1f}s wall"}
 
 
+DECODE_KERNEL = "k_stream<true, false"
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
+    """Turn two rocprofv3 --pmc runs of `bench.py --calibrate-copy` (one with
+    FETCH_SIZE, one with WRITE_SIZE; values in KiB per dispatch) into HBM
+    bytes per decode launch.  Each counter is scaled by what it reads for the
+    256 MiB calibration copy (known bytes / counted bytes)."""
+    import csv
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+
+    known = COPY_ELEMS * 4
+    res = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = load(path, name)
+        copies = [float(r["Counter_Value"]) * 1024 for r in rows if COPY_KERNEL in r["Kernel_Name"]]
+        copy = max(copies)
+        factor = known / copy
+        dec = [float(r["Counter_Value"]) * 1024 * factor for r in rows if DECODE_KERNEL in r["Kernel_Name"]]
+        res[name] = {"copy_counted_bytes": copy, "factor": factor, "decode_bytes": dec}
+    # dispatches alternate: gap-mean-8 stream, gap-mean-300 stream
+    f, w = res["FETCH_SIZE"]["decode_bytes"], res["WRITE_SIZE"]["decode_bytes"]
+    per = []
+    for k in range(2):
+        fk = f[k::2]
+        wk = w[k::2]
+        per.append({"fetch_bytes": sum(fk) / len(fk), "write_bytes": sum(wk) / len(wk),
+                    "hbm_bytes": sum(fk) / len(fk) + sum(wk) / len(wk)})
+    out = {"kernel": DECODE_KERNEL, "kernel_source_sha256_16": kernel_source_hash(),
+           "fetch_factor": res["FETCH_SIZE"]["factor"], "write_factor": res["WRITE_SIZE"]["factor"],
+           "copy_counted_bytes": {"FETCH_SIZE": res["FETCH_SIZE"]["copy_counted_bytes"],
+                                  "WRITE_SIZE": res["WRITE_SIZE"]["copy_counted_bytes"]},
+           "per_stream": per,
+           "hbm_bytes_per_launch": sum(p["hbm_bytes"] for p in per) / len(per),
+           "commands": command_lines}
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+    with open(out_md, "w") as fh:
+        fh.write("# HBM traffic of the differential decode kernel, 2 x 64Mi-gap streams\n\n")
+        fh.write("Counters from two rocprofv3 runs (one counter each), scaled by the same counter\n"
+                 "read for a plain 256 MiB device copy in the same process.\n\n")
+        for c in command_lines:
+            fh.write(f"    {c}\n")
+        fh.write(f"\nFETCH_SIZE factor {out['fetch_factor']:.4f}, WRITE_SIZE factor {out['write_factor']:.4f}\n\n")
+        fh.write("| stream | fetch MB | write MB | HBM MB |\n|---|---|---|---|\n")
+        for name, p in zip(("gap mean 8", "gap mean 300"), per):
+            fh.write(f"| {name} | {p['fetch_bytes'] / 1e6:.1f} | {p['write_bytes'] / 1e6:.1f} | "
+                     f"{p['hbm_bytes'] / 1e6:.1f} |\n")
+        fh.write(f"\nkernel source sha256[:16] = {out['kernel_source_sha256_16']}\n")
+    return out
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
+        fetch_csv, write_csv = sys.argv[2], sys.argv[3]
+        cmds = sys.argv[4:]
+        o = summarize_pmc(fetch_csv, write_csv, PROFILE_COUNTERS,
+                          PROFILE_COUNTERS.replace(".json", ".md"), cmds)
+        print(json.dumps(o))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain device copy of 256 MiB (int32 tensor copy) before the "
+                         "steps, as the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -124,6 +192,14 @@ def main():
     streams = make_streams(torch, vbyte, workloads)
     alg_bytes = [s["bytes"].numel() + 4 * N_STREAM for s in streams]
     stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy:
+        a = torch.arange(COPY_ELEMS, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     def step(events=None):
         for i, s in enumerate(streams):
@@ -166,6 +242,8 @@ def main():
             "pct_hbm_peak": round(100 * alg_bytes[i] / (avg_ms[i] / 1e3) / 1e9 / HBM_PEAK_GBPS, 1),
         })
     traffic = measured_traffic(alg_bytes)
+    if traffic is not None:
+        traffic = round(traffic)
     res = {
         "metric": METRIC,
         "value": round(value, 3),
