@@ -161,6 +161,134 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
     return out
 
 
+def build_index(torch, vbyte, workloads):
+    """Config 3: 100,000 Zipf-length lists of gaps, VByte-encoded on the GPU
+    with per-list byte offsets."""
+    t0 = time.time()
+    d = workloads.zipf_lists()
+    gaps = torch.from_numpy(d["gaps"].view("int32")).cuda()
+    vals_off = torch.from_numpy(d["out_off"]).cuda()
+    enc, byte_off = vbyte.encode_batch(gaps, vals_off)
+    torch.cuda.synchronize()
+    log(f"config 3: {d['lengths'].size} lists, {int(d['out_off'][-1])} integers, {enc.numel()} bytes "
+        f"({8 * enc.numel() / int(d['out_off'][-1]):.2f} bits/int), prepared in {time.time() - t0:.1f}s")
+    return {"lists": d, "gaps": gaps, "bytes": enc, "byte_off": byte_off, "out_off": vals_off}
+
+
+def bench_batched(torch, vbyte, serve, idx, reps=10):
+    """Batched CSR decode of config 3 in one persistent launch, against one
+    single-stream launch per list (both issued from native host loops)."""
+    d = idx["lists"]
+    nl = d["lengths"].size
+    total = int(d["out_off"][-1])
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    st = torch.empty(nl, dtype=torch.int32, device="cuda")
+
+    def once():
+        vbyte.decode_batch(idx["bytes"], idx["byte_off"], idx["out_off"], delta=True, out=out,
+                           list_status=st)
+
+    once()
+    torch.cuda.synchronize()
+    if int(st.max().item()) != 0:
+        raise RuntimeError("batched decode reported a bad list")
+    # spot-check a few lists against the gaps' prefix sums
+    for i in (0, 1, nl // 2, nl - 1, int(d["lengths"].argmax())):
+        a, b = int(d["out_off"][i]), int(d["out_off"][i + 1])
+        ref = torch.cumsum(idx["gaps"][a:b].to(torch.int64) & 0xFFFFFFFF, 0) & 0xFFFFFFFF
+        if not torch.equal(ref, out[a:b].to(torch.int64) & 0xFFFFFFFF):
+            raise RuntimeError(f"batched decode differs on list {i}")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / reps
+    in_bytes = idx["bytes"].numel()
+    # per-list launches and the server's single gather launch, same lists
+    bo = idx["byte_off"].cpu().numpy()
+    counts = d["lengths"].astype("int64")
+    import numpy as np
+    res = {}
+    for batching in (True, False):
+        srv = serve.Server(idx["bytes"], bo, counts, pool_bytes=(total + 1024) * 4, nstreams=1,
+                           max_batch_requests=1, batching=batching, delta=True)
+        lat, stt, _ = srv.run(np.zeros(1), [np.arange(nl, dtype=np.int64)])
+        lat, stt, _ = srv.run(np.zeros(1), [np.arange(nl, dtype=np.int64)])
+        srv.close()
+        if stt["worst_status"] != 0:
+            raise RuntimeError("server decode reported a bad list")
+        res[batching] = (float(lat[0]) * 1e3, int(stt["launches"]))
+    return {"workload": "100,000 differential lists, Zipf(1.2) lengths clipped to [1, 4Mi], 2^28 "
+                        "integers, gaps Geometric(len/2^25)",
+            "bytes_in": int(in_bytes), "integers": total,
+            "batched_csr_ms": round(batched_ms, 4),
+            "batched_gints_per_s": round(total / (batched_ms / 1e3) / 1e9, 2),
+            "batched_alg_gbps": round((in_bytes + 4 * total) / (batched_ms / 1e3) / 1e9, 1),
+            "gather_one_launch_ms": round(res[True][0], 3),
+            "per_list_launches_ms": round(res[False][0], 3),
+            "per_list_launches": res[False][1],
+            "speedup_batched_vs_per_list": round(res[False][0] / batched_ms, 1)}
+
+
+def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
+    """Config 4: Poisson queries of 2-8 Zipf(1.0) terms over the config-3
+    index; p50/p99 latency and throughput at fractions of saturation QPS."""
+    import numpy as np
+    d = idx["lists"]
+    pos_of_rank = np.argsort(d["rank_of"])
+    bo = idx["byte_off"].cpu().numpy()
+    counts = d["lengths"].astype("int64")
+    nl = counts.size
+
+    def make(qps, n, seed):
+        arr, ranks = workloads.query_stream(n, qps, nlists=nl, seed=seed)
+        return arr, [pos_of_rank[r] for r in ranks]
+
+    def run(srv, arr, terms):
+        lat, stt, _ = srv.run(arr, terms)
+        if stt["worst_status"] != 0 or stt["rejected"]:
+            raise RuntimeError("serving run reported a bad list or a rejected query")
+        lat = lat[warm:] if lat.size > warm else lat
+        return lat, stt
+
+    srv = serve.Server(idx["bytes"], bo, counts, pool_bytes=6 << 30, nstreams=4,
+                       max_batch_requests=64, batching=True, delta=True)
+    # saturation: every query queued at time 0 (closed loop)
+    arr, terms = make(1.0, nq, workloads.SEED_QUERIES)
+    _, stt = run(srv, np.zeros(nq), terms)
+    sat_qps = nq / stt["wall_s"]
+    ints_per_query = stt["integers"] / nq
+    points = []
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        qps = frac * sat_qps
+        arr, terms = make(qps, nq + warm, workloads.SEED_QUERIES + int(frac * 100))
+        lat, stt = run(srv, arr, terms)
+        points.append({"qps": round(qps, 1), "frac_of_saturation": frac,
+                       "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                       "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+                       "gints_per_s": round(stt["integers"] / stt["wall_s"] / 1e9, 2),
+                       "mean_batch_requests": round(stt["mean_batch_requests"], 2)})
+    srv.close()
+    # the same load at half saturation with one launch per list and no batching
+    srv = serve.Server(idx["bytes"], bo, counts, pool_bytes=6 << 30, nstreams=4,
+                       max_batch_requests=1, batching=False, delta=True)
+    arr, terms = make(0.5 * sat_qps, nq + warm, workloads.SEED_QUERIES + 50)
+    lat, stt = run(srv, arr, terms)
+    srv.close()
+    per_list = {"qps": round(0.5 * sat_qps, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+                "gints_per_s": round(stt["integers"] / stt["wall_s"] / 1e9, 2)}
+    return {"workload": "queries of 2-8 distinct Zipf(1.0) terms over the config-3 index (rank r = "
+                        "r-th longest list), Poisson arrivals, differential decode into a 6 GiB "
+                        "output pool, 4 streams",
+            "queries_per_point": nq, "warmup_queries": warm,
+            "saturation_qps": round(sat_qps, 1), "integers_per_query": round(ints_per_query, 1),
+            "points": points, "per_list_launches_at_half_saturation": per_list}
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
         fetch_csv, write_csv = sys.argv[2], sys.argv[3]
@@ -175,6 +303,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the config-3 batched comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the config-4 serving run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 256 MiB (int32 tensor copy) before the "
                          "steps, as the reference kernel for scaling HBM byte counters")
@@ -270,6 +400,16 @@ def main():
                      "kernel": "k_stream<delta> (vb::k_stream<true,false,SEGS>)",
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if not (args.no_batched and args.no_serving):
+        from paper_1503_07387_amd import serve
+        idx = build_index(torch, vbyte, workloads)
+        if not args.no_batched:
+            log("batched vs per-list launches (config 3) ...")
+            res["batched"] = bench_batched(torch, vbyte, serve, idx)
+        if not args.no_serving:
+            log("serving (config 4) ...")
+            res["serving"] = bench_serving(torch, vbyte, serve, workloads, idx)
+        del idx
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         res["cpu_baseline"] = cpu_baseline(streams, args.cpu_budget)

@@ -132,6 +132,58 @@ vbyte_status vbyte_decode_lists(const uint8_t *bytes, size_t nbytes, const int64
                                 const uint32_t *prevs, int delta, int32_t *d_list_status,
                                 void *stream);
 
+/* ------------------------------------------------------------ serving */
+
+/* Continuous-batching request loop over an index resident in HBM.  A
+ * request asks for the decoded posting lists of several terms; its result is
+ * the concatenation, in term order, of those lists, each decoded on its own
+ * (differential lists restart from 0: section 1).  The loop releases
+ * requests at their arrival times, admits them FIFO when the device output
+ * pool has room for their result, and launches every admitted request on an
+ * idle stream as one vbyte_decode_lists batch; batches on different streams
+ * overlap on the GPU.  With batching = 0 each list is one single-stream
+ * launch instead (the per-list baseline). */
+typedef struct vbyte_server vbyte_server;
+
+typedef struct vbyte_server_config {
+    size_t pool_bytes;       /* device output pool (admission budget) */
+    int nstreams;            /* 1..8 streams for overlapping batches */
+    int max_batch_requests;  /* requests per launch, at most */
+    int batching;            /* 1: one batched launch per batch; 0: one launch per list */
+    int delta;               /* 1: differential decode */
+} vbyte_server_config;
+
+typedef struct vbyte_serve_stats {
+    double wall_s;               /* first arrival origin to last completion */
+    uint64_t integers;           /* integers decoded for admitted requests */
+    uint64_t batches;
+    uint64_t launches;           /* decode launches issued */
+    double mean_batch_requests;
+    int32_t worst_status;        /* largest per-list status seen (VBYTE_OK if all good) */
+    uint64_t rejected;           /* requests larger than the whole pool */
+} vbyte_serve_stats;
+
+/* index_bytes: device pointer to the whole index (nbytes); byte_off: HOST
+ * int64[nlists+1] list boundaries; counts: HOST int64[nlists] integers per
+ * list.  The server copies the host metadata and allocates the pool, the
+ * streams and pinned staging; vbyte_server_destroy releases them. */
+vbyte_status vbyte_server_create(const uint8_t *index_bytes, size_t nbytes, const int64_t *byte_off,
+                                 const int64_t *counts, size_t nlists,
+                                 const vbyte_server_config *cfg, vbyte_server **out);
+void vbyte_server_destroy(vbyte_server *server);
+
+/* Open-loop run of nreq requests (HOST arrays): request r arrives
+ * arrival_s[r] seconds after the start (non-decreasing) and asks for lists
+ * terms[term_off[r] .. term_off[r+1]).  latency_s[r] (HOST) receives
+ * completion minus arrival on the host steady clock, or -1 if the request
+ * could never fit the pool.  If results (DEVICE uint32) is not NULL, request
+ * r's result is copied to results[result_off[r] ..] (result_off: HOST
+ * int64[nreq]).  Blocks until every request has completed. */
+vbyte_status vbyte_server_run(vbyte_server *server, size_t nreq, const double *arrival_s,
+                              const int64_t *term_off, const int64_t *terms, double *latency_s,
+                              uint32_t *results, const int64_t *result_off,
+                              vbyte_serve_stats *stats);
+
 /* ------------------------------------------------------------ encoder */
 
 /* ENC (section 1, Table 1) on the GPU: writes the concatenated canonical
@@ -147,6 +199,16 @@ vbyte_status vbyte_encode_async(const uint32_t *values, size_t n, uint8_t *bytes
 vbyte_status vbyte_encode_delta_async(const uint32_t *values, size_t n, uint32_t prev,
                                       uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
                                       void *stream);
+
+/* Batched ENC for CSR lists: encodes values[0..n) (all lists concatenated;
+ * list i is values[vals_off[i], vals_off[i+1])) in one pass and writes the
+ * byte offset of every list boundary to byte_off[0..nlists] (device int64),
+ * so that list i's codes are bytes[byte_off[i], byte_off[i+1]).  Plain
+ * encoding: for differential lists, pass the gaps.  vals_off: device int64,
+ * non-decreasing, values > n are clamped to n. */
+vbyte_status vbyte_encode_batch(const uint32_t *values, size_t n, const int64_t *vals_off,
+                                size_t nlists, uint8_t *bytes, size_t capacity, int64_t *byte_off,
+                                uint64_t *d_nbytes, void *stream);
 
 /* ------------------------------------------------------------ utilities */
 

@@ -301,7 +301,8 @@ vbyte_status vbyte_decode_lists(const uint8_t *bytes, size_t nbytes, const int64
 
 static vbyte_status encode_common(const uint32_t *values, size_t n, uint32_t prev, int delta,
                                   uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
-                                  hipStream_t s) {
+                                  hipStream_t s, const int64_t *vals_off = nullptr,
+                                  int64_t *byte_off = nullptr, size_t nbounds = 0) {
     if (!d_nbytes || ((uintptr_t)d_nbytes & 7u)) return VBYTE_EINVAL;
     if (n > 0 && !values) return VBYTE_EINVAL;
     if (((uintptr_t)values & 3u) != 0) return VBYTE_EINVAL;
@@ -327,7 +328,12 @@ static vbyte_status encode_common(const uint32_t *values, size_t n, uint32_t pre
     a.hdr = (uint64_t *)ws_base(w);
     a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
     hipError_t e = launch_encode(a, s);
-    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "encode launch");
+    if (e != hipSuccess) return hip_fail(e, "encode launch");
+    if (nbounds) {
+        e = launch_encode_bounds(a, vals_off, byte_off, nbounds, s);
+        if (e != hipSuccess) return hip_fail(e, "encode bounds launch");
+    }
+    return VBYTE_OK;
 }
 
 vbyte_status vbyte_encode_async(const uint32_t *values, size_t n, uint8_t *bytes, size_t capacity,
@@ -339,6 +345,23 @@ vbyte_status vbyte_encode_delta_async(const uint32_t *values, size_t n, uint32_t
                                       uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
                                       void *stream) {
     return encode_common(values, n, prev, 1, bytes, capacity, d_nbytes, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_encode_batch(const uint32_t *values, size_t n, const int64_t *vals_off,
+                                size_t nlists, uint8_t *bytes, size_t capacity, int64_t *byte_off,
+                                uint64_t *d_nbytes, void *stream) {
+    if (nlists > 0 && (!vals_off || !byte_off)) return VBYTE_EINVAL;
+    if (((uintptr_t)byte_off & 7u) || ((uintptr_t)vals_off & 7u)) return VBYTE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        if (nlists > 0) {
+            hipError_t e = launch_fill_i64(byte_off, nlists + 1, 0, s);
+            if (e != hipSuccess) return hip_fail(e, "zero byte offsets");
+        }
+        return encode_common(values, 0, 0, 0, bytes, capacity, d_nbytes, s);
+    }
+    return encode_common(values, n, 0, 0, bytes, capacity, d_nbytes, s, vals_off, byte_off,
+                         nlists ? nlists + 1 : 0);
 }
 
 size_t vbyte_workspace_size(size_t nbytes) {

@@ -1046,9 +1046,38 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
     }
 }
 
+// Byte offsets of CSR list boundaries after k_encode: boundary i of value
+// offset v = vals_off[i] starts at the inclusive byte count of the tiles
+// before v's tile plus the code lengths of the values of v's tile below v.
+// Reads the encoder's descriptors, which every tile published.
+__global__ void k_encode_bounds(EncodeArgs a, const int64_t *vals_off, int64_t *byte_off,
+                                uint64_t nb) {
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    u64 v = (u64)vals_off[i];
+    if (v > a.n) v = a.n;
+    const u64 tile = v / kEncodeWaveValues;
+    u64 off;
+    if (tile >= a.ntiles) {
+        off = aload(&a.desc[a.ntiles - 1].c) & kCountMask;
+    } else {
+        off = tile ? (aload(&a.desc[tile - 1].c) & kCountMask) : 0;
+        for (u64 j = tile * kEncodeWaveValues; j < v; ++j) {
+            u32 x = a.values[j];
+            if (a.delta) x -= (j == 0) ? a.prev : a.values[j - 1];
+            off += code_len(x);
+        }
+    }
+    byte_off[i] = (int64_t)off;
+}
+
 // ------------------------------------------------------------ small kernels
 __global__ void k_set_status(int32_t *p, int32_t v) { *p = v; }
 __global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
+__global__ void k_fill_i64(int64_t *p, uint64_t n, int64_t v) {
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+        p[i] = v;
+}
 __global__ void k_zero(uint4 *p, size_t n16) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
         p[i] = make_uint4(0, 0, 0, 0);
@@ -1113,6 +1142,13 @@ hipError_t launch_encode(const EncodeArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
+                                uint64_t nb, hipStream_t s) {
+    if (nb == 0) return hipSuccess;
+    k_encode_bounds<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(a, vals_off, byte_off, nb);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_status(int32_t *d_status, int32_t value, hipStream_t s) {
     k_set_status<<<1, 1, 0, s>>>(d_status, value);
     return hipGetLastError();
@@ -1120,6 +1156,14 @@ hipError_t launch_set_status(int32_t *d_status, int32_t value, hipStream_t s) {
 
 hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s) {
     k_set_u64<<<1, 1, 0, s>>>(p, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t value, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    u64 blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    k_fill_i64<<<(unsigned)blocks, 256, 0, s>>>(p, n, value);
     return hipGetLastError();
 }
 

@@ -104,9 +104,12 @@ hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int seg
                          hipStream_t s);
 hipError_t launch_batch(const ListArgs &a, int segs, int wpb, int grid_blocks, hipStream_t s);
 hipError_t launch_encode(const EncodeArgs &a, hipStream_t s);
+hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
+                                uint64_t nb, hipStream_t s);
 hipError_t launch_set_status(int32_t *d_status, int32_t value, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t value, hipStream_t s);
 
 // Tiles of a single-stream decode of nbytes starting at misalignment vstart.
 inline uint64_t stream_tiles(uint64_t vstart, uint64_t nbytes, int segs, int wpb) {
@@ -116,7 +119,7 @@ inline uint64_t stream_tiles(uint64_t vstart, uint64_t nbytes, int segs, int wpb
 
 constexpr int kEncodeWaveValues = 1024;   // values per encoder tile (one wavefront)
 constexpr int kPrepBlock = 256;           // lists per prep workgroup
-constexpr int kSpanTiles = 4;             // large-list tiles per batched work item
+constexpr int kSpanTiles = 1;             // large-list tiles per batched work item
 constexpr int kSmallChunk = 64;           // small lists per batched work item
 
 }  // namespace vb

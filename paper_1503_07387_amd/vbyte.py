@@ -24,6 +24,8 @@ STATUS_NAMES = {OK: "VBYTE_OK", EINVAL: "VBYTE_EINVAL", ECOUNT: "VBYTE_ECOUNT",
 EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_decode_delta_async", "vbyte_count", "vbyte_decode_batch",
            "vbyte_decode_lists", "vbyte_encode_async", "vbyte_encode_delta_async",
+           "vbyte_encode_batch", "vbyte_server_create", "vbyte_server_destroy",
+           "vbyte_server_run",
            "vbyte_workspace_size", "vbyte_set_tuning", "vbyte_get_tuning",
            "vbyte_status_str", "vbyte_last_error"]
 
@@ -70,6 +72,7 @@ def _declare(lib):
         "vbyte_decode_lists": [vp, sz, vp, sz, sz, vp, sz, vp, i32, vp, vp],
         "vbyte_encode_async": [vp, sz, vp, sz, vp, vp],
         "vbyte_encode_delta_async": [vp, sz, u32, vp, sz, vp, vp],
+        "vbyte_encode_batch": [vp, sz, vp, sz, vp, sz, vp, vp, vp],
         "vbyte_set_tuning": [i32, i32, i64],
     }
     for name, args in sig.items():
@@ -205,6 +208,24 @@ def encode(values, *, delta=False, prev=0, out=None, nbytes=None, stream=None, t
     if trim:
         return out[: int(nbytes.item())]
     return out, nbytes
+
+
+def encode_batch(values, vals_off, *, stream=None):
+    """Batched CSR encoding on the GPU.  values: int32 CUDA tensor (uint32
+    bits, all lists concatenated); vals_off: int64 CUDA tensor of nlists+1
+    value offsets.  Returns (bytes uint8 tensor, byte_off int64 tensor);
+    waits for the kernel to learn the encoded size."""
+    if values.dtype != torch.int32 or not values.is_cuda or not values.is_contiguous():
+        raise ValueError("values must be a contiguous int32 CUDA tensor (uint32 bits)")
+    n = values.numel()
+    nlists = vals_off.numel() - 1
+    out = torch.empty(max(5 * n, 1), dtype=torch.uint8, device=values.device)
+    byte_off = torch.empty(max(nlists + 1, 1), dtype=torch.int64, device=values.device)
+    nbytes = torch.empty(1, dtype=torch.int64, device=values.device)
+    st = _lib().vbyte_encode_batch(_ptr(values), n, _ptr(vals_off), max(nlists, 0), _ptr(out),
+                                   out.numel(), _ptr(byte_off), _ptr(nbytes), _stream(stream))
+    _check_call(st, "encode_batch")
+    return out[: int(nbytes.item())], byte_off[: nlists + 1]
 
 
 def set_tuning(segs_per_wave=0, waves_per_block=0, small_list_bytes=0):

@@ -281,3 +281,17 @@ def test_dense_one_byte_segments(segs, wpb):
     for ooff in range(4):
         check_against_oracle(pure, pure.size, ooff=ooff)
         check_against_oracle(pure, pure.size, delta=True, prev=3, ooff=ooff)
+
+
+@pytest.mark.parametrize("lens", [[0, 1, 1023, 1024, 1, 0, 3000, 5], [7], [0, 0], [2048, 2048]])
+def test_encode_batch_offsets(lens):
+    rng = np.random.default_rng(len(lens) + sum(lens))
+    x = mixed_values(rng, int(sum(lens)))
+    vals_off = np.zeros(len(lens) + 1, np.int64)
+    vals_off[1:] = np.cumsum(lens)
+    xt = torch.from_numpy(x.view(np.int32)).to(dev())
+    enc, byte_off = vbyte.encode_batch(xt, torch.from_numpy(vals_off).to(dev()))
+    torch.cuda.synchronize()
+    assert np.array_equal(enc.cpu().numpy(), oracle.encode(x))
+    ref = np.array([oracle.encoded_size(x[:v]) for v in vals_off], np.int64)
+    assert np.array_equal(byte_off.cpu().numpy(), ref)
