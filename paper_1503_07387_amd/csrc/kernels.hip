@@ -46,6 +46,10 @@ typedef uint8_t u8;
 typedef uint32_t u32;
 typedef uint64_t u64;
 typedef int64_t i64;
+// pointers into global memory (address space 1), for stores addressed as
+// scalar base + 32-bit offset
+typedef __attribute__((address_space(1))) u8 gbyte;
+typedef __attribute__((address_space(1))) u32 gword;
 
 constexpr u64 kCountMask = (1ull << 36) - 1;
 constexpr int kLookbackWindows = 1;   // 64-descriptor windows read per round trip
@@ -90,6 +94,10 @@ __device__ __forceinline__ u32 wave_sum(u32 x) { return read_lane(wave_scan(x), 
 // Value of lane-1 (wave_shr:1); lane 0 receives `lane0`.
 __device__ __forceinline__ u32 from_lane_below(u32 x, u32 lane0) {
     return (u32)__builtin_amdgcn_update_dpp((int)lane0, (int)x, 0x138, 0xF, 0xF, false);
+}
+// Value of lane+1 (wave_shl:1); lane 63 receives `lane63`.
+__device__ __forceinline__ u32 from_lane_above(u32 x, u32 lane63) {
+    return (u32)__builtin_amdgcn_update_dpp((int)lane63, (int)x, 0x130, 0xF, 0xF, false);
 }
 
 // LDS written by some lanes of a wavefront and read by others: LDS
@@ -225,15 +233,14 @@ __device__ __forceinline__ void load16_guarded(const u8 *base, u64 v, u64 lo, u6
     }
 }
 
-// 4 bytes [v, v+4) (v a multiple of 4) with validity bits at 12..15, the
-// position a lane's last dword has in its 16-bit validity mask.
+// 4 bytes [v, v+4) (v a multiple of 4) with validity bits at 0..3.
 __device__ __forceinline__ void load4_guarded(const u8 *base, i64 v, u64 lo, u64 hi, u32 &w,
-                                              u32 &valid_hi) {
+                                              u32 &valid4) {
     w = 0;
-    valid_hi = 0;
+    valid4 = 0;
     if (v >= (i64)lo && (u64)v + 4 <= hi) {
         w = *(const u32 *)(base + v);
-        valid_hi = 0xF000u;
+        valid4 = 0xFu;
         return;
     }
 #pragma unroll
@@ -241,159 +248,176 @@ __device__ __forceinline__ void load4_guarded(const u8 *base, i64 v, u64 lo, u64
         const i64 p = v + b;
         if (p >= (i64)lo && (u64)p < hi) {
             w |= (u32)base[p] << (8 * b);
-            valid_hi |= 1u << (12 + b);
+            valid4 |= 1u << b;
         }
     }
 }
 
-// Top bit of each byte of w (bit 7 of byte k -> bit k).
+// Top bit of each byte (bit 7 of byte k -> bit k), by dot products of the
+// isolated top bits (0 or 0x80 per byte) with byte weights 1, 2, 4, 8 and
+// 16, 32, 64, 128: each product sum is 128 times the mask.
 __device__ __forceinline__ u32 top4(u32 w) {
-    u32 t = w & 0x80808080u;
-    t |= t << 7;    // bytes 0,1 -> bits 14,15; bytes 2,3 -> bits 30,31
-    t |= t << 14;   // bits 14,15 -> 28,29
-    return t >> 28;
+    return __builtin_amdgcn_udot4(w & 0x80808080u, 0x08040201u, 0u, false) >> 7;
 }
 __device__ __forceinline__ u32 top16(const u32 (&w)[4]) {
-    return top4(w[0]) | (top4(w[1]) << 4) | (top4(w[2]) << 8) | (top4(w[3]) << 12);
+    u32 lo = __builtin_amdgcn_udot4(w[0] & 0x80808080u, 0x08040201u, 0u, false);
+    lo = __builtin_amdgcn_udot4(w[1] & 0x80808080u, 0x80402010u, lo, false);
+    u32 hi = __builtin_amdgcn_udot4(w[2] & 0x80808080u, 0x08040201u, 0u, false);
+    hi = __builtin_amdgcn_udot4(w[3] & 0x80808080u, 0x80402010u, hi, false);
+    return (lo >> 7) | (hi << 1);
 }
 
-// Per-lane segment summary: terminator mask (valid bytes < 0x80), count and
-// whether a run of 5 continuation bytes ends in the lane's 16 bytes.
+// a & sext(byte K of w): one VALU instruction with a sub-dword operand
+// select (SDWA) that sign-extends the selected byte, so a byte with its top
+// bit set acts as "all ones above bit 6" and a byte below 0x80 as itself.
+template <int K>
+__device__ __forceinline__ u32 and_sbyte(u32 a, u32 w);
+#define VB_AND_SBYTE(K)                                                                           \
+    template <>                                                                                   \
+    __device__ __forceinline__ u32 and_sbyte<K>(u32 a, u32 w) {                                   \
+        u32 r;                                                                                    \
+        asm("v_and_b32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD "                \
+            "src0_sel:DWORD src1_sel:BYTE_" #K                                                    \
+            : "=v"(r)                                                                             \
+            : "v"(a), "v"(w));                                                                    \
+        return r;                                                                                 \
+    }
+VB_AND_SBYTE(0)
+VB_AND_SBYTE(1)
+VB_AND_SBYTE(2)
+VB_AND_SBYTE(3)
+#undef VB_AND_SBYTE
+
+// Per-lane summary of the lane's 16 bytes, given the byte before them (top
+// byte of `below`, valid when `below_ok`) and the 4 bytes after them
+// (`above`, valid bytes flagged in bits 0..3 of `above_valid`).
+//  term:  valid bytes below 0x80 (terminators; their popcount is the number
+//         of integers the lane's bytes end).
+//  emit:  bytes that begin a code -- the byte before is a terminator or lies
+//         outside the stream -- whose terminator lies inside the stream.  A
+//         lane's integers are attributed to the lanes holding their first
+//         byte; every code has exactly one first byte and one terminator, so
+//         the counts agree over a whole stream.
+//  mal:   a run of 5 continuation bytes begins in the lane's bytes (a code of
+//         more than 5 bytes, which no uint32 has).
 struct SegMask {
     u32 term;
-    u32 cnt;
+    u32 emit;
     bool mal;
 };
-__device__ __forceinline__ SegMask seg_mask(const u32 (&w)[4], u32 valid, u32 h, u32 hvalid_hi) {
+template <bool EDGE>
+__device__ __forceinline__ SegMask seg_mask(const u32 (&w)[4], u32 valid, u32 below, bool below_ok,
+                                            u32 above, u32 above_valid) {
     const u32 top = top16(w);
-    const u32 cont = top & valid;
-    const u32 term = ~top & valid;
-    // 20-bit continuation window: halo bytes at bits 0..3, own at 4..19
-    const u32 c20 = (cont << 4) | ((top4(h) & (hvalid_hi >> 12)) & 0xFu);
-    const u32 run5 = c20 & (c20 >> 1) & (c20 >> 2) & (c20 >> 3) & (c20 >> 4);
+    const u32 topa = top4(above);
+    const u32 cont = EDGE ? top & valid : top;
+    const u32 term = EDGE ? ~top & valid : ~top & 0xFFFFu;
+    const u32 conta = EDGE ? topa & above_valid : topa;
+    // the byte before the lane ends a code, or is not part of the stream
+    const u32 tb = (EDGE && !below_ok) ? 1u : ((below >> 31) ^ 1u);
     SegMask m;
     m.term = term;
-    m.cnt = __builtin_popcount(term);
+    if (EDGE) {
+        const u32 start = ((((term | ~valid) << 1) | tb) & valid) & 0xFFFFu;
+        // a code beginning at byte j is terminated when some terminator
+        // lies at or after j within the lane's 20-byte window
+        const u32 t20 = term | ((~topa & above_valid & 0xFu) << 16);
+        const u32 hi = 31u - (u32)__builtin_clz(t20 | 1u);
+        m.emit = t20 ? start & ((2u << hi) - 1u) : 0u;
+    } else {
+        m.emit = ((term << 1) | tb) & 0xFFFFu;
+    }
+    const u32 c20 = cont | (conta << 16);
+    const u32 run5 = c20 & (c20 >> 1) & (c20 >> 2) & (c20 >> 3) & (c20 >> 4);
     m.mal = (run5 & 0xFFFFu) != 0;
     return m;
 }
 
-// Sequential assembly over the lane's window: 4 halo bytes (no output) then
-// its 16 bytes.  r[j] receives, for a terminator at byte j, the integer it
-// ends (DELTA: the lane-local inclusive sum of integers up to j).  Returns
-// the lane sum of integers.  Invalid bytes reset the state and end nothing.
-template <bool DELTA, bool EDGE>
-__device__ __forceinline__ u32 assemble(const u32 (&w)[4], u32 valid, u32 h, u32 hvalid_hi,
-                                        u32 (&r)[16]) {
-    u32 acc = 0, sh = 0;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const u32 g = __builtin_amdgcn_ubfe(h, 8 * p, 7);
-        const u32 v = acc | (g << (sh & 31));
-        u32 km = (u32)__builtin_amdgcn_sbfe(h, 8 * p + 7, 1);
-        if (EDGE) km &= 0u - ((hvalid_hi >> (12 + p)) & 1u);
-        acc = v & km;
-        sh = (sh + 7) & km;
+// Assembly of the lane's codes from the last byte down (Horner form of
+// Algorithm 1's sum): walking bytes j = 19 .. 0 of the window "own 16 bytes
+// then the 4 after", acc becomes the integer formed by the groups from byte
+// j up to the first terminator at or after j:
+//     acc = ((acc << 7) | 0x7F) & sext8(byte j)
+// which keeps (acc << 7) | group for a continuation byte and restarts at the
+// group for a terminator.  At a code's first byte acc is the code's integer,
+// with the fifth group's weight 2^28 wrapping mod 2^32 as in Algorithm 1.
+// Plain: r[j] = acc at byte j.  DELTA: r[j] = -(sum of the integers of codes
+// beginning after byte j), and the lane sum T is returned, so that T + r[j]
+// is the lane-local inclusive sum at a code beginning at j (bit j of emit).
+template <bool DELTA>
+__device__ __forceinline__ u32 horner(const u32 (&w)[4], u32 above, u32 emit, u32 (&r)[16]) {
+    u32 acc = and_sbyte<3>(0x7Fu, above);
+    acc = and_sbyte<2>((acc << 7) | 0x7Fu, above);
+    acc = and_sbyte<1>((acc << 7) | 0x7Fu, above);
+    acc = and_sbyte<0>((acc << 7) | 0x7Fu, above);
+    u32 nu = 0;
+#define VB_STEP(J)                                                               \
+    acc = and_sbyte<(J) & 3>((acc << 7) | 0x7Fu, w[(J) >> 2]);                   \
+    if (DELTA) {                                                                 \
+        r[J] = nu;                                                               \
+        nu -= acc & (u32)__builtin_amdgcn_sbfe(emit, (J), 1);                    \
+    } else {                                                                     \
+        r[J] = acc;                                                              \
     }
-    u32 s = 0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const u32 dw = w[j >> 2];
-        const int o = 8 * (j & 3);
-        const u32 g = __builtin_amdgcn_ubfe(dw, o, 7);
-        const u32 v = acc | (g << (sh & 31));
-        u32 km = (u32)__builtin_amdgcn_sbfe(dw, o + 7, 1);
-        u32 tm = ~km;
-        if (EDGE) {
-            const u32 vb = 0u - ((valid >> j) & 1u);
-            km &= vb;
-            tm &= vb;
-        }
-        if (DELTA) {
-            s += v & tm;
-            r[j] = s;
-        } else {
-            r[j] = v;
-        }
-        acc = v & km;
-        sh = (sh + 7) & km;
-    }
-    return s;
+    VB_STEP(15) VB_STEP(14) VB_STEP(13) VB_STEP(12)
+    VB_STEP(11) VB_STEP(10) VB_STEP(9) VB_STEP(8)
+    VB_STEP(7) VB_STEP(6) VB_STEP(5) VB_STEP(4)
+    VB_STEP(3) VB_STEP(2) VB_STEP(1) VB_STEP(0)
+#undef VB_STEP
+    return 0u - nu;
 }
 
-// LDS staging layout.  Logical slot i lives at i ^ ((i >> 5) & 15): within
-// each row of 32 slots the low 4 bits are XOR-ed with the row number.  When
-// every lane holds the same number of integers (all 1-byte codes: 16 per
-// lane, all 2-byte codes: 8) the compacting writes below hit the same few
-// banks on every lane without it; with it they spread over all banks, while
-// 64 consecutive slots (the store phase) stay conflict-free and every aligned
-// group of 4 slots stays one aligned 16-byte group (permuted inside).
-__device__ __forceinline__ u32 swz(u32 i) { return i ^ ((i >> 5) & 15u); }
+// Per-wavefront LDS rows: lane L's 16 candidate integers (one per byte) at
+// words kRowStride*L .. +15.  The stride of 20 words keeps the 16-byte
+// writes of 8 consecutive lanes on 32 distinct banks.
+constexpr u32 kRowStride = 20;
 
-// Write the lane's integers, compacted, to logical slots start + k.
-template <bool DELTA>
-__device__ __forceinline__ void emit(u32 *stage, u32 start, u32 term, const u32 (&r)[16], u32 add) {
-    u32 k = start;
+// Store the integers of the codes flagged in `emit` (one candidate u[j] per
+// byte j of the lane), compacted and in byte order, to out_seg[0 ..), with
+// slots below `lim` only when GUARD.  The segment's 1024 bytes are taken 64
+// at a time: row k covers bytes 64k .. 64k+63, i.e. the masks of lanes
+// 4k .. 4k+3; lane i of the wavefront handles byte 64k + i, and its output
+// slot is the row's base plus the number of flagged bytes below it in the
+// row (mbcnt of the row mask).  Each row is one masked store of consecutive
+// words.
+template <bool GUARD>
+__device__ __forceinline__ void store_rows(u32 *rows, const u32 (&u)[16], u32 emit, u32 *out_seg,
+                                           u32 lim) {
+    const u32 ln = lane_id();
+    uint4 *dst = (uint4 *)(rows + kRowStride * ln);
+    dst[0] = make_uint4(u[0], u[1], u[2], u[3]);
+    dst[1] = make_uint4(u[4], u[5], u[6], u[7]);
+    dst[2] = make_uint4(u[8], u[9], u[10], u[11]);
+    dst[3] = make_uint4(u[12], u[13], u[14], u[15]);
+    // even lanes: their mask in bits 0..15, the next lane's in bits 16..31
+    const u32 e2 = emit | (dpp_zero<0x101>(emit) << 16);   // row_shl:1
+    wave_lds_sync();
+    const u32 rd = kRowStride * (ln >> 4) + (ln & 15u);
+    u32 v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        if ((term >> j) & 1u) {
-            stage[swz(k)] = DELTA ? r[j] + add : r[j];
-            ++k;
+    for (int k = 0; k < 16; ++k) v[k] = rows[rd + 4 * kRowStride * k];
+    // out_seg is the same on every lane: keep it in scalar registers so each
+    // row's store takes a 32-bit byte offset from a scalar base
+    const u64 op = (u64)(uintptr_t)out_seg;
+    gbyte *ob = (gbyte *)(uintptr_t)(((u64)first_lane((u32)(op >> 32)) << 32) | first_lane((u32)op));
+    u32 base = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const u32 lo = read_lane(e2, 4 * k), hi = read_lane(e2, 4 * k + 2);
+        const u64 rm = ((u64)hi << 32) | lo;
+        if (__builtin_amdgcn_inverse_ballot_w64(rm)) {
+            const u32 slot = base + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            if (!GUARD || slot < lim) *(gword *)(ob + (slot << 2)) = v[k];
         }
+        base += (u32)__builtin_popcountll(rm);
     }
+    wave_lds_sync();
 }
 
 // Misalignment (in uint32 elements, 0..3) of out + gbase against 16 bytes.
 __device__ __forceinline__ u32 out_mis(const u32 *out, u64 gbase) {
     return (u32)((((uintptr_t)out >> 2) + gbase) & 3u);
 }
-
-// Store `total` staged integers (stage[amis + e], e < total) to
-// out[gbase + e] for gbase + e < n, with 16-byte aligned stores.
-template <bool DELTA>
-__device__ __forceinline__ void store_stage(const u32 *stage, u32 amis, u32 total, u32 *out, u64 gbase,
-                                            u64 n, u32 add) {
-    const u32 ln = lane_id();
-    const u32 nq = (amis + total + 3) >> 2;
-    for (u32 q = ln; q < nq; q += kWave) {
-        const u32 i0 = q << 2;
-        const i64 e0 = (i64)i0 - (i64)amis;
-        if (e0 >= 0 && (u64)e0 + 4 <= total && gbase + (u64)e0 + 4 <= n) {
-            const u32 key = (i0 >> 5) & 15u;
-            const uint4 g = *(const uint4 *)(stage + (i0 ^ (key & 12u)));
-            // logical element t of the group sits at position t ^ (key & 3)
-            uint4 v = g;
-            if (key & 1u) {
-                v.x = g.y;
-                v.y = g.x;
-                v.z = g.w;
-                v.w = g.z;
-            }
-            if (key & 2u) {
-                const uint4 h = v;
-                v.x = h.z;
-                v.y = h.w;
-                v.z = h.x;
-                v.w = h.y;
-            }
-            if (DELTA) {
-                v.x += add;
-                v.y += add;
-                v.z += add;
-                v.w += add;
-            }
-            *(uint4 *)(out + gbase + e0) = v;
-        } else {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const i64 e = e0 + t;
-                if (e >= 0 && (u64)e < total && gbase + (u64)e < n)
-                    out[gbase + e] = stage[swz(i0 + t)] + (DELTA ? add : 0u);
-            }
-        }
-    }
-}
-
 // Store phase of a dense segment: 1024 one-byte codes, whose integers are
 // the bytes themselves.  The segment's bytes sit in stage (as bytes, in
 // order); lane q of each row expands the 4 bytes of elements 4q - amis ..
@@ -493,7 +517,7 @@ struct WgShared {
 };
 
 template <bool DELTA, bool COUNT, int SEGS, bool EDGE>
-__device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage, WgShared &sh, u32 wib,
+__device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared &sh, u32 wib,
                                             u32 wpb) {
     const u32 ln = lane_id();
     const u64 wv = t.tv + (u64)wib * (SEGS * kSegBytes);   // this wavefront's first byte
@@ -509,37 +533,48 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage, WgShare
             valid[s] = 0xFFFFu;
         }
     }
-    u32 h0, hv0;
+    // the 4 bytes before the wavefront's bytes and the 4 after them
+    u32 hb, hbv, ha = 0, hav = 0;
     if (EDGE) {
-        load4_guarded(t.base, (i64)wv - 4, t.vstart, t.vend, h0, hv0);
+        load4_guarded(t.base, (i64)wv - 4, t.vstart, t.vend, hb, hbv);
+        if (!COUNT) load4_guarded(t.base, (i64)(wv + SEGS * kSegBytes), t.vstart, t.vend, ha, hav);
     } else {
-        h0 = *(const u32 *)(t.base + wv - 4);
-        hv0 = 0xF000u;
+        hb = *(const u32 *)(t.base + wv - 4);
+        hbv = 0xFu;
+        if (!COUNT) ha = *(const u32 *)(t.base + wv + SEGS * kSegBytes);
+        hav = 0xFu;
     }
 
-    // Phase 1: masks, counts, ranks (and for DELTA the integers and sums).
-    u32 term[SEGS], lex[SEGS], segbase[SEGS], segcnt[SEGS];
-    u32 lsum[SEGS];
+    // Phase 1: masks, counts (and for DELTA the integers and sums).
+    u32 emit[SEGS], above[SEGS], segbase[SEGS], segcnt[SEGS];
+    u32 lincl[SEGS], sbase[SEGS];
     u32 r[DELTA ? SEGS : 1][16];
-    u32 sbase[SEGS];
     u32 ctot = 0, stot = 0, dmask = 0;
     bool mal = false;
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
-        const u32 l0w = s == 0 ? h0 : read_lane(w[s - 1][3], 63);
-        const u32 l0v = s == 0 ? hv0 : read_lane(valid[s - 1], 63);
-        const u32 h = from_lane_below(w[s][3], l0w);
-        const u32 hv = EDGE ? from_lane_below(valid[s], l0v) : 0xF000u;
-        const SegMask m = seg_mask(w[s], valid[s], h, hv & 0xF000u);
-        term[s] = m.term;
+        const u32 l0w = s == 0 ? hb : read_lane(w[s - 1][3], 63);
+        const u32 below = from_lane_below(w[s][3], l0w);
+        bool below_ok = true;
+        if (EDGE) {
+            const u32 l0v = s == 0 ? (hbv << 12) : read_lane(valid[s - 1], 63);
+            below_ok = ((from_lane_below(valid[s], l0v) >> 15) & 1u) != 0;
+        }
+        u32 ab = 0, abv = 0;
+        if (!COUNT) {
+            ab = from_lane_above(w[s][0], s + 1 < SEGS ? read_lane(w[s + 1][0], 0) : ha);
+            abv = EDGE ? from_lane_above(valid[s], s + 1 < SEGS ? read_lane(valid[s + 1], 0) : hav) & 0xFu
+                       : 0xFu;
+        }
+        above[s] = ab;
+        const SegMask m = seg_mask<EDGE>(w[s], valid[s], below, below_ok, ab, abv);
+        emit[s] = m.emit;
         mal |= m.mal;
         // dense: all 1024 bytes are terminators and no code enters from below
-        const bool dense = !EDGE && ballot(m.term == 0xFFFFu) == ~0ull && (l0w >> 31) == 0;
+        const bool dense = !COUNT && !EDGE && ballot(m.term == 0xFFFFu) == ~0ull && (l0w >> 31) == 0;
         dmask |= dense ? (1u << s) : 0u;
-        const u32 ci = wave_scan(m.cnt);
-        lex[s] = ci - m.cnt;
+        segcnt[s] = wave_sum(__builtin_popcount(COUNT ? m.term : m.emit));
         segbase[s] = ctot;
-        segcnt[s] = read_lane(ci, 63);
         ctot += segcnt[s];
         if (DELTA) {
             u32 ls;
@@ -549,10 +584,10 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage, WgShare
                 ls = __builtin_amdgcn_sad_u8(w[s][2], 0u, ls);
                 ls = __builtin_amdgcn_sad_u8(w[s][3], 0u, ls);
             } else {
-                ls = assemble<true, EDGE>(w[s], valid[s], h, hv & 0xF000u, r[s]);
+                ls = horner<true>(w[s], ab, m.emit, r[s]);
             }
             const u32 si = wave_scan(ls);
-            lsum[s] = stot + si - ls;
+            lincl[s] = si;
             sbase[s] = stot;
             stot += read_lane(si, 63);
         }
@@ -599,33 +634,33 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *stage, WgShare
     const TileOut res{exc + tc, sh.excl_mal != 0 || tm != 0};
     if (COUNT) return res;
 
-    // Phase 2: compact each segment's integers through LDS and store them.
+    // Phase 2: store each segment's integers.
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
         const u64 gbase = exc + wex_c + segbase[s];
         if (gbase >= t.n || segcnt[s] == 0) continue;
-        const u32 amis = out_mis(t.out, gbase);
         if (dmask & (1u << s)) {
-            *(uint4 *)(stage + 4 * ln) = make_uint4(w[s][0], w[s][1], w[s][2], w[s][3]);
+            *(uint4 *)(rows + 4 * ln) = make_uint4(w[s][0], w[s][1], w[s][2], w[s][3]);
             wave_lds_sync();
-            store_dense<DELTA>(stage, amis, t.out, gbase, t.n, DELTA ? exs + wex_s + sbase[s] : 0u);
+            store_dense<DELTA>(rows, out_mis(t.out, gbase), t.out, gbase, t.n,
+                               DELTA ? exs + wex_s + sbase[s] : 0u);
             wave_lds_sync();
             continue;
         }
+        u32 u[16];
         if (DELTA) {
-            emit<true>(stage, amis + lex[s], term[s], r[s], lsum[s]);
+            // exclusive sum before the lane plus the lane's own sum T
+            const u32 add = exs + wex_s + sbase[s] + lincl[s];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) u[j] = r[s][j] + add;
         } else {
-            const u32 l0w = s == 0 ? h0 : read_lane(w[s - 1][3], 63);
-            const u32 l0v = s == 0 ? hv0 : read_lane(valid[s - 1], 63);
-            const u32 h = from_lane_below(w[s][3], l0w);
-            const u32 hv = EDGE ? from_lane_below(valid[s], l0v) : 0xF000u;
-            u32 rp[16];
-            assemble<false, EDGE>(w[s], valid[s], h, hv & 0xF000u, rp);
-            emit<false>(stage, amis + lex[s], term[s], rp, 0u);
+            horner<false>(w[s], above[s], emit[s], u);
         }
-        wave_lds_sync();
-        store_stage<DELTA>(stage, amis, segcnt[s], t.out, gbase, t.n, exs + wex_s);
-        wave_lds_sync();
+        u32 *out_seg = t.out + gbase;
+        if (gbase + segcnt[s] <= t.n)
+            store_rows<false>(rows, u, emit[s], out_seg, 0u);
+        else
+            store_rows<true>(rows, u, emit[s], out_seg, (u32)(t.n - gbase));
     }
     return res;
 }
@@ -641,7 +676,7 @@ __device__ __forceinline__ int32_t final_status(bool mal, u8 last_byte, u64 tota
 
 // ------------------------------------------------------------ single stream
 template <bool DELTA, bool COUNT, int SEGS>
-__global__ __launch_bounds__(1024) void k_stream(StreamArgs a) {
+__global__ __launch_bounds__(512) void k_stream(StreamArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;
     const u32 tid = threadIdx.x;
@@ -669,7 +704,7 @@ __global__ __launch_bounds__(1024) void k_stream(StreamArgs a) {
     t.didx = tile;
     t.dfirst = 0;
     t.tag = make_tag(epoch);
-    const bool interior = tile > 0 && t.tv + tb <= a.vend;
+    const bool interior = tile > 0 && t.tv + tb + 4 <= a.vend;
     TileOut r;
     if (interior)
         r = run_tile<DELTA, COUNT, SEGS, false>(t, stage, sh, wib, wpb);
@@ -803,7 +838,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
 // Small list: one wavefront walks its segments in order, carrying the rank
 // and the running sum, with no look-back.
 template <bool DELTA>
-__device__ void run_small(const ListArgs &a, u64 li, const ListDesc &d, u32 *stage) {
+__device__ __forceinline__ void run_small(const ListArgs &a, u64 li, const ListDesc &d, u32 *rows) {
     const u32 ln = lane_id();
     const u8 *p0 = a.bytes + d.bb;
     const u8 *base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
@@ -816,28 +851,31 @@ __device__ void run_small(const ListArgs &a, u64 li, const ListDesc &d, u32 *sta
     bool mal = false;
     u32 pw = 0, pv = 0;   // lane 63's last dword and validity of the previous segment
     for (u64 tv = 0; tv < vend; tv += kSegBytes) {
-        u32 w[4], valid;
+        u32 w[4], valid, nw, nv;
         load16_guarded(base, tv + 16u * ln, vstart, vend, w, valid);
-        const u32 h = from_lane_below(w[3], pw);
-        const u32 hv = from_lane_below(valid, pv) & 0xF000u;
-        const SegMask m = seg_mask(w, valid, h, hv);
+        load4_guarded(base, (i64)(tv + kSegBytes), vstart, vend, nw, nv);
+        const u32 below = from_lane_below(w[3], pw);
+        const bool below_ok = ((from_lane_below(valid, pv) >> 15) & 1u) != 0;
+        const u32 ab = from_lane_above(w[0], nw);
+        const u32 abv = from_lane_above(valid, nv) & 0xFu;
+        const SegMask m = seg_mask<true>(w, valid, below, below_ok, ab, abv);
         mal |= m.mal;
-        const u32 ci = wave_scan(m.cnt);
-        const u32 segcnt = read_lane(ci, 63);
+        const u32 segcnt = wave_sum(__builtin_popcount(m.emit));
         u32 r[16];
-        const u32 ls = assemble<DELTA, true>(w, valid, h, hv, r);
-        u32 lex_s = 0, segsum = 0;
+        const u32 ls = horner<DELTA>(w, ab, m.emit, r);
+        u32 segsum = 0;
         if (DELTA) {
             const u32 si = wave_scan(ls);
-            lex_s = si - ls;
             segsum = read_lane(si, 63);
+            const u32 add = run + si;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) r[j] += add;
         }
         if (segcnt && rank < n) {
-            const u32 amis = out_mis(out, rank);
-            emit<DELTA>(stage, amis + ci - m.cnt, m.term, r, lex_s);
-            wave_lds_sync();
-            store_stage<DELTA>(stage, amis, segcnt, out, rank, n, run);
-            wave_lds_sync();
+            if (rank + segcnt <= n)
+                store_rows<false>(rows, r, m.emit, out + rank, 0u);
+            else
+                store_rows<true>(rows, r, m.emit, out + rank, (u32)(n - rank));
         }
         rank += segcnt;
         run += segsum;
@@ -865,7 +903,7 @@ __device__ __forceinline__ u32 pick_next(u32 *counter, u32 *slot) {
 // Both queue words are reset by their last taker; each queue costs one
 // device-wide atomic per span or chunk, not per tile or list.
 template <bool DELTA, int SEGS>
-__global__ __launch_bounds__(1024) void k_batch(ListArgs a) {
+__global__ __launch_bounds__(512) void k_batch(ListArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;
     __shared__ u32 sh_next;
@@ -919,7 +957,7 @@ __global__ __launch_bounds__(1024) void k_batch(ListArgs a) {
         for (u64 ti = t0; ti < t1; ++ti) {
             t.tv = ti * tb;
             t.didx = t.dfirst + (i64)ti;
-            const bool interior = ti > 0 && t.tv + tb <= t.vend;
+            const bool interior = ti > 0 && t.tv + tb + 4 <= t.vend;
             const TileOut r = interior ? run_tile<DELTA, false, SEGS, false>(t, stage, sh, wib, wpb)
                                        : run_tile<DELTA, false, SEGS, true>(t, stage, sh, wib, wpb);
             if (ti == tiles - 1 && tid == 0)

@@ -15,9 +15,9 @@ namespace vb {
 // look-back descriptor.
 constexpr int kWave = 64;
 constexpr int kSegBytes = 1024;
-// Per-wavefront LDS staging for one segment's outputs: at most one integer
-// per input byte, plus up to 3 slots to align global stores to 16 bytes.
-constexpr int kStageWords = 1040;
+// Per-wavefront LDS rows of one segment: one candidate integer per input
+// byte, 16 per lane in rows of 20 words (padding against bank conflicts).
+constexpr int kStageWords = 64 * 20;
 
 // Workspace layout: a 256-byte header, then one look-back descriptor per
 // tile (or per work item of a batched launch), then batch work tables.
