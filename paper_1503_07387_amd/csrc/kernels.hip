@@ -52,7 +52,7 @@ typedef __attribute__((address_space(1))) u8 gbyte;
 typedef __attribute__((address_space(1))) u32 gword;
 
 constexpr u64 kCountMask = (1ull << 36) - 1;
-constexpr int kLookbackWindows = 1;   // 64-descriptor windows read per round trip
+constexpr int kLookbackWindows = 4;   // most 64-descriptor windows read per round trip
 
 // ------------------------------------------------------------------ atomics
 __device__ __forceinline__ u64 aload(const u64 *p) {
@@ -136,11 +136,15 @@ struct Prefix {
 
 // Decoupled look-back: exclusive prefix of descriptor `idx` over the chain
 // that starts at descriptor `first` (which always publishes an inclusive
-// value).  Each round trip reads kLookbackWindows x 64 predecessors (one per
-// lane per window, two 64-bit atomic loads each), then walks them nearest
-// first: aggregates are summed until an inclusive prefix ends the walk; a
-// predecessor that has published nothing yet (or is between its two
-// stores) stops the walk and the remaining ones are read again.
+// value).  Each round trip reads nw windows of 64 predecessors (one per lane
+// per window, two 64-bit atomic loads each), then walks them nearest first:
+// aggregates are summed until an inclusive prefix ends the walk; a
+// predecessor that has published nothing yet (or is between its two stores)
+// stops the walk and the remaining ones are read again.  A round that walks
+// a whole window without meeting an inclusive prefix widens the next round
+// to kLookbackWindows windows, so that a look-back far behind the chain of
+// inclusive prefixes catches up in one more round trip instead of one per 64
+// tiles.
 template <bool SUM>
 __device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first, u32 tag) {
     const u32 ln = lane_id();
@@ -148,6 +152,7 @@ __device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first,
     u32 acc_s = 0;
     bool acc_m = false;
     i64 pos = idx - 1;
+    u32 nw = 1;
     for (;;) {
         u64 cw[kLookbackWindows], sw[kLookbackWindows];
 #pragma unroll
@@ -155,15 +160,16 @@ __device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first,
             const i64 p = pos - (i64)ln - 64 * k;
             cw[k] = 0;
             sw[k] = 0;
-            if (p >= first) {
+            if ((u32)k < nw && p >= first) {
                 cw[k] = aload(&desc[p].c);
                 if (SUM) sw[k] = aload(&desc[p].s);
             }
         }
         i64 consumed = 0;
-        bool done = false;
+        bool done = false, stopped = false;
 #pragma unroll
         for (int k = 0; k < kLookbackWindows; ++k) {
+            if ((u32)k >= nw) break;
             const i64 p = pos - (i64)ln - 64 * k;
             const u64 c = cw[k];
             const bool vc = (u32)(c >> 38) == tag;
@@ -194,11 +200,15 @@ __device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first,
                 done = true;
                 break;
             }
-            if (fn < 64) break;
+            if (fn < 64) {
+                stopped = true;
+                break;
+            }
         }
         if (done) break;
         pos -= consumed;
         if (consumed == 0) __builtin_amdgcn_s_sleep(1);
+        nw = stopped ? 1u : (u32)kLookbackWindows;
     }
     return Prefix{acc_c, acc_s, acc_m};
 }
@@ -368,9 +378,10 @@ __device__ __forceinline__ u32 horner(const u32 (&w)[4], u32 above, u32 emit, u3
 }
 
 // Per-wavefront LDS rows: lane L's 16 candidate integers (one per byte) at
-// words kRowStride*L .. +15.  The stride of 20 words keeps the 16-byte
-// writes of 8 consecutive lanes on 32 distinct banks.
-constexpr u32 kRowStride = 20;
+// words kRowStride*L .. +15, written as 8-byte pairs.  The stride of 18
+// words puts the pairs of 16 consecutive lanes on 32 distinct banks.
+constexpr u32 kRowStride = 18;
+static_assert(kRowStride * kWave <= kStageWords, "row buffer exceeds the staging area");
 
 // Store the integers of the codes flagged in `emit` (one candidate u[j] per
 // byte j of the lane), compacted and in byte order, to out_seg[0 ..), with
@@ -384,11 +395,9 @@ template <bool GUARD>
 __device__ __forceinline__ void store_rows(u32 *rows, const u32 (&u)[16], u32 emit, u32 *out_seg,
                                            u32 lim) {
     const u32 ln = lane_id();
-    uint4 *dst = (uint4 *)(rows + kRowStride * ln);
-    dst[0] = make_uint4(u[0], u[1], u[2], u[3]);
-    dst[1] = make_uint4(u[4], u[5], u[6], u[7]);
-    dst[2] = make_uint4(u[8], u[9], u[10], u[11]);
-    dst[3] = make_uint4(u[12], u[13], u[14], u[15]);
+    uint2 *dst = (uint2 *)(rows + kRowStride * ln);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) dst[m] = make_uint2(u[2 * m], u[2 * m + 1]);
     // even lanes: their mask in bits 0..15, the next lane's in bits 16..31
     const u32 e2 = emit | (dpp_zero<0x101>(emit) << 16);   // row_shl:1
     wave_lds_sync();
@@ -485,7 +494,7 @@ __device__ __forceinline__ void store_dense(const u32 *stage, u32 amis, u32 *out
 // A tile is the run of wpb x SEGS segments that one workgroup decodes;
 // wavefront w owns segments [w*SEGS, (w+1)*SEGS) of it.  `base` is 16-byte
 // aligned; valid bytes are [vstart, vend); the tile starts at tv.  One
-// ticket and one look-back descriptor per tile.
+// look-back descriptor per tile.
 struct TileIn {
     const u8 *base;
     u64 vstart, vend, tv;
@@ -503,6 +512,7 @@ struct TileOut {
 };
 
 constexpr int kMaxWaves = 16;
+constexpr int kMaxBlock = 8 * kWave;   // at most 8 wavefronts per workgroup
 
 // Workgroup-shared scratch of the tile protocol.
 struct WgShared {
@@ -515,6 +525,21 @@ struct WgShared {
     u32 epoch;
     u64 item;
 };
+
+// Totals of the tile's wavefronts, read from `sh`.
+struct TileSum {
+    u32 c, s;
+    bool mal;
+};
+__device__ __forceinline__ TileSum tile_sum(const WgShared &sh, u32 wpb) {
+    TileSum r{0, 0, false};
+    for (u32 k = 0; k < wpb; ++k) {
+        r.c += sh.wcnt[k];
+        r.s += sh.wsum[k];
+        r.mal |= sh.wmal[k] != 0;
+    }
+    return r;
+}
 
 template <bool DELTA, bool COUNT, int SEGS, bool EDGE>
 __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared &sh, u32 wib,
@@ -599,30 +624,28 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
         sh.wmal[wib] = wmal ? 1u : 0u;
     }
     __syncthreads();
-    u32 wex_c = 0, wex_s = 0, tc = 0, ts = 0, tm = 0;
-    for (u32 k = 0; k < wpb; ++k) {
-        const u32 c = sh.wcnt[k], s = sh.wsum[k];
-        if (k < wib) {
-            wex_c += c;
-            wex_s += s;
-        }
-        tc += c;
-        ts += s;
-        tm |= sh.wmal[k];
+    u32 wex_c = 0, wex_s = 0;
+    for (u32 k = 0; k < wib; ++k) {
+        wex_c += sh.wcnt[k];
+        wex_s += sh.wsum[k];
     }
+    const TileSum tsum = tile_sum(sh, wpb);
 
     // Wavefront 0 publishes the aggregate, looks back, publishes the
-    // inclusive prefix and hands the exclusive prefix to the others.
+    // inclusive prefix and hands the exclusive prefix to the others; the
+    // aggregate and the inclusive prefix are stored by the same wavefront,
+    // in that order.
     if (wib == 0) {
         Prefix ex;
         if (t.didx == t.dfirst) {
             ex = Prefix{0, t.prev, false};
         } else {
-            if (ln == 0) publish<DELTA>(&t.desc[t.didx], t.tag, false, tm != 0, tc, ts);
+            if (ln == 0) publish<DELTA>(&t.desc[t.didx], t.tag, false, tsum.mal, tsum.c, tsum.s);
             ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag);
         }
         if (ln == 0) {
-            publish<DELTA>(&t.desc[t.didx], t.tag, true, ex.mal || tm != 0, ex.c + tc, ex.s + ts);
+            publish<DELTA>(&t.desc[t.didx], t.tag, true, ex.mal || tsum.mal, ex.c + tsum.c,
+                           ex.s + tsum.s);
             sh.excl_c = ex.c;
             sh.excl_s = ex.s;
             sh.excl_mal = ex.mal ? 1u : 0u;
@@ -631,7 +654,7 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
     __syncthreads();
     const u64 exc = sh.excl_c;
     const u32 exs = sh.excl_s;
-    const TileOut res{exc + tc, sh.excl_mal != 0 || tm != 0};
+    const TileOut res{exc + tsum.c, sh.excl_mal != 0 || tsum.mal};
     if (COUNT) return res;
 
     // Phase 2: store each segment's integers.
@@ -676,7 +699,7 @@ __device__ __forceinline__ int32_t final_status(bool mal, u8 last_byte, u64 tota
 
 // ------------------------------------------------------------ single stream
 template <bool DELTA, bool COUNT, int SEGS>
-__global__ __launch_bounds__(512) void k_stream(StreamArgs a) {
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(DELTA ? 4 : 8))) void k_stream(StreamArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;
     const u32 tid = threadIdx.x;
@@ -903,7 +926,7 @@ __device__ __forceinline__ u32 pick_next(u32 *counter, u32 *slot) {
 // Both queue words are reset by their last taker; each queue costs one
 // device-wide atomic per span or chunk, not per tile or list.
 template <bool DELTA, int SEGS>
-__global__ __launch_bounds__(512) void k_batch(ListArgs a) {
+__global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;
     __shared__ u32 sh_next;
@@ -1123,7 +1146,7 @@ __global__ void k_zero(uint4 *p, size_t n16) {
 
 template <bool DELTA, bool COUNT, int SEGS>
 hipError_t launch_stream_t(const StreamArgs &a, int wpb, hipStream_t s) {
-    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
+    const size_t lds = COUNT ? 0 : (size_t)wpb * kStageWords * sizeof(u32);
     k_stream<DELTA, COUNT, SEGS><<<a.ntiles, wpb * kWave, lds, s>>>(a);
     return hipGetLastError();
 }

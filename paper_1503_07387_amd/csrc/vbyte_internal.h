@@ -16,8 +16,8 @@ namespace vb {
 constexpr int kWave = 64;
 constexpr int kSegBytes = 1024;
 // Per-wavefront LDS rows of one segment: one candidate integer per input
-// byte, 16 per lane in rows of 20 words (padding against bank conflicts).
-constexpr int kStageWords = 64 * 20;
+// byte, 16 per lane in rows of 18 words (padding against bank conflicts).
+constexpr int kStageWords = 64 * 18;
 
 // Workspace layout: a 256-byte header, then one look-back descriptor per
 // tile (or per work item of a batched launch), then batch work tables.
