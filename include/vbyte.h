@@ -132,6 +132,28 @@ vbyte_status vbyte_decode_lists(const uint8_t *bytes, size_t nbytes, const int64
                                 const uint32_t *prevs, int delta, int32_t *d_list_status,
                                 void *stream);
 
+/* The batched decode captured once into a HIP graph and replayed: a replay
+ * enqueues the same two kernels as vbyte_decode_batch with the arguments
+ * given here, so callers that run the same batch shape repeatedly (a fixed
+ * index, new contents in the same buffers) pay one graph launch per batch.
+ *   Arguments as in vbyte_decode_batch; the pointers and sizes are fixed at
+ *   creation and their contents are read at each replay.
+ *   *graph receives the handle; the graph owns a workspace of its own,
+ *   allocated here (VBYTE_ENOMEM if that fails), so replays allocate
+ *   nothing.  The tuning in force at creation is baked in.
+ * vbyte_batch_graph_launch enqueues one replay on `stream` (asynchronous);
+ * replays of one graph must not overlap (enqueue them on one stream or
+ * order them).  vbyte_batch_graph_destroy frees the graph; the caller
+ * synchronizes first.  Errors: VBYTE_EINVAL for bad arguments, VBYTE_EHIP
+ * when capture or launch fails. */
+typedef struct vbyte_batch_graph vbyte_batch_graph;
+vbyte_status vbyte_batch_graph_create(const uint8_t *bytes, size_t nbytes, const int64_t *byte_off,
+                                      uint32_t *out, size_t nout, const int64_t *out_off,
+                                      size_t nlists, const uint32_t *prevs, int delta,
+                                      int32_t *d_list_status, vbyte_batch_graph **graph);
+vbyte_status vbyte_batch_graph_launch(vbyte_batch_graph *graph, void *stream);
+void vbyte_batch_graph_destroy(vbyte_batch_graph *graph);
+
 /* ------------------------------------------------------------ serving */
 
 /* Continuous-batching request loop over an index resident in HBM.  A
@@ -222,6 +244,38 @@ size_t vbyte_workspace_size(size_t nbytes);
  * batched forms.  Returns VBYTE_EINVAL for an unsupported value. */
 vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t small_list_bytes);
 void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_list_bytes);
+
+/* Autotuner of the tiling.  Times the caller's workload under each candidate
+ * tiling (reps calls each after one untimed call, HIP events on `stream`),
+ * then applies the fastest with vbyte_set_tuning and returns VBYTE_OK.
+ *   vbyte_autotune_decode: single-stream decode of bytes[0, nbytes) into
+ *     out[0, n) (plain or delta, prev 0); d_status is a device int32 the
+ *     calls write.  Candidates: segs_per_wave {1, 2, 4} x waves_per_block
+ *     {2, 4, 6, 8}.
+ *   vbyte_autotune_batch: vbyte_decode_batch of the given lists (prevs 0);
+ *     d_list_status is device int32[nlists].  Candidates: segs_per_wave
+ *     {2, 4} x waves_per_block {4, 8} x small_list_bytes {4, 16, 64, 256} KiB.
+ *   points, max_points: optional host array that receives each candidate
+ *     and its mean time; *npoints (optional) the number written.
+ * If the workload does not decode (a data status other than VBYTE_OK) that
+ * status is returned and the previous tuning is restored.  The tuning is
+ * process-wide: run no other decode meanwhile.  Synchronous. */
+typedef struct vbyte_tune_point {
+    int segs_per_wave;
+    int waves_per_block;
+    int64_t small_list_bytes;
+    double ms;        /* mean time of one call */
+    int32_t status;   /* worst data status the timed calls produced */
+} vbyte_tune_point;
+vbyte_status vbyte_autotune_decode(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                   int delta, int reps, int32_t *d_status,
+                                   vbyte_tune_point *points, size_t max_points, size_t *npoints,
+                                   void *stream);
+vbyte_status vbyte_autotune_batch(const uint8_t *bytes, size_t nbytes, const int64_t *byte_off,
+                                  uint32_t *out, size_t nout, const int64_t *out_off,
+                                  size_t nlists, int delta, int reps, int32_t *d_list_status,
+                                  vbyte_tune_point *points, size_t max_points, size_t *npoints,
+                                  void *stream);
 
 /* Static name of a status code. */
 const char *vbyte_status_str(vbyte_status st);

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libvbyte.so")
-SOURCES = ["kernels.hip", "capi.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "capi.cpp", "serve.cpp", "graph.cpp", "tune.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

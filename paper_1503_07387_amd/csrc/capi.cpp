@@ -158,8 +158,9 @@ vbyte_status decode_sync(const uint8_t *bytes, size_t nbytes, uint32_t *out, siz
     return (vbyte_status)h;
 }
 
-vbyte_status batch_common(ListArgs a, size_t list_bytes, hipStream_t s) {
-    if (a.nlists == 0) return VBYTE_OK;
+}  // namespace
+
+vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan) {
     if (!a.list_status || ((uintptr_t)a.list_status & 3u)) return VBYTE_EINVAL;
     if (!a.bytes && a.nbytes) return VBYTE_EINVAL;
     if (!a.out && a.nout) return VBYTE_EINVAL;
@@ -176,28 +177,46 @@ vbyte_status batch_common(ListArgs a, size_t list_bytes, hipStream_t s) {
     if (a.max_items >= (1ull << 31)) return VBYTE_EINVAL;
     const uint32_t nblocks = (uint32_t)((a.nlists + kPrepBlock - 1) / kPrepBlock);
     size_t off = kHeaderBytes;
-    const size_t desc_off = off;
+    plan->desc_off = off;
     off += a.max_items * kSpanTiles * sizeof(Desc);
-    const size_t prep_off = off;
+    plan->prep_off = off;
     off += (size_t)nblocks * sizeof(Desc);
-    const size_t items_off = off;
+    plan->items_off = off;
     off += a.max_items * sizeof(int2);
-    Workspace *w = nullptr;
-    vbyte_status st = get_ws(s, off, 2, &w);
-    if (st != VBYTE_OK) return st;
-    uint8_t *b = ws_base(w);
-    a.hdr = (uint64_t *)b;
-    a.totals = (uint64_t *)(b + kTotalsOff);
-    a.desc = (Desc *)(b + desc_off);
-    a.prep_desc = (Desc *)(b + prep_off);
-    a.items = (int2 *)(b + items_off);
+    plan->bytes = off;
+    plan->segs = segs;
+    plan->wpb = wpb;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
-    const int grid = cus * std::max(1, 16 / wpb);
-    hipError_t e = launch_batch(a, segs, wpb, grid, s);
+    plan->grid = cus * std::max(1, 16 / wpb);
+    return VBYTE_OK;
+}
+
+void batch_bind(ListArgs &a, const BatchPlan &plan, uint8_t *ws) {
+    a.hdr = (uint64_t *)ws;
+    a.totals = (uint64_t *)(ws + kTotalsOff);
+    a.desc = (Desc *)(ws + plan.desc_off);
+    a.prep_desc = (Desc *)(ws + plan.prep_off);
+    a.items = (int2 *)(ws + plan.items_off);
+}
+
+vbyte_status hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+
+namespace {
+
+vbyte_status batch_common(ListArgs a, size_t list_bytes, hipStream_t s) {
+    if (a.nlists == 0) return VBYTE_OK;
+    BatchPlan plan;
+    vbyte_status st = batch_plan(a, list_bytes, &plan);
+    if (st != VBYTE_OK) return st;
+    Workspace *w = nullptr;
+    st = get_ws(s, plan.bytes, 2, &w);
+    if (st != VBYTE_OK) return st;
+    batch_bind(a, plan, ws_base(w));
+    hipError_t e = launch_batch(a, plan.segs, plan.wpb, plan.grid, s);
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "batch launch");
 }
 

@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "vbyte.h"
+
 namespace vb {
 
 // One wavefront segment: 64 lanes x 16 bytes, loaded with one 128-bit load
@@ -110,6 +112,19 @@ hipError_t launch_set_status(int32_t *d_status, int32_t value, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t value, hipStream_t s);
+
+// Host side of the batched decode (capi.cpp), shared with the graph form.
+// batch_plan checks the arguments, fills the work-table sizing fields of
+// `a` from the current tuning and lays out the workspace; batch_bind points
+// `a` into a workspace of plan.bytes (zero-filled before its first use).
+struct BatchPlan {
+    size_t bytes, desc_off, prep_off, items_off;
+    int segs, wpb, grid;
+};
+vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan);
+void batch_bind(ListArgs &a, const BatchPlan &plan, uint8_t *ws);
+// Records a HIP failure for vbyte_last_error and returns VBYTE_EHIP.
+vbyte_status hip_error(hipError_t e, const char *what);
 
 // Tiles of a single-stream decode of nbytes starting at misalignment vstart.
 inline uint64_t stream_tiles(uint64_t vstart, uint64_t nbytes, int segs, int wpb) {

@@ -25,9 +25,16 @@ EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_decode_delta_async", "vbyte_count", "vbyte_decode_batch",
            "vbyte_decode_lists", "vbyte_encode_async", "vbyte_encode_delta_async",
            "vbyte_encode_batch", "vbyte_server_create", "vbyte_server_destroy",
-           "vbyte_server_run",
+           "vbyte_server_run", "vbyte_batch_graph_create", "vbyte_batch_graph_launch",
+           "vbyte_batch_graph_destroy", "vbyte_autotune_decode", "vbyte_autotune_batch",
            "vbyte_workspace_size", "vbyte_set_tuning", "vbyte_get_tuning",
            "vbyte_status_str", "vbyte_last_error"]
+
+
+class TunePoint(ctypes.Structure):
+    _fields_ = [("segs_per_wave", ctypes.c_int), ("waves_per_block", ctypes.c_int),
+                ("small_list_bytes", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("status", ctypes.c_int32)]
 
 
 class VByteError(RuntimeError):
@@ -74,11 +81,19 @@ def _declare(lib):
         "vbyte_encode_delta_async": [vp, sz, u32, vp, sz, vp, vp],
         "vbyte_encode_batch": [vp, sz, vp, sz, vp, sz, vp, vp, vp],
         "vbyte_set_tuning": [i32, i32, i64],
+        "vbyte_batch_graph_create": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, c.POINTER(vp)],
+        "vbyte_batch_graph_launch": [vp, vp],
+        "vbyte_autotune_decode": [vp, sz, vp, sz, i32, i32, vp, c.POINTER(TunePoint), sz,
+                                  c.POINTER(sz), vp],
+        "vbyte_autotune_batch": [vp, sz, vp, vp, sz, vp, sz, i32, i32, vp, c.POINTER(TunePoint),
+                                 sz, c.POINTER(sz), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = c.c_int
+    lib.vbyte_batch_graph_destroy.argtypes = [vp]
+    lib.vbyte_batch_graph_destroy.restype = None
     lib.vbyte_workspace_size.argtypes = [sz]
     lib.vbyte_workspace_size.restype = sz
     lib.vbyte_get_tuning.argtypes = [c.POINTER(c.c_int), c.POINTER(c.c_int), c.POINTER(c.c_int64)]
@@ -184,6 +199,81 @@ def decode_lists(data, rows, list_bytes, out, *, delta=False, prevs=None, list_s
                                    _ptr(list_status), _stream(stream))
     _check_call(st, "decode_lists")
     return list_status
+
+
+class BatchGraph:
+    """A batched decode captured into a HIP graph (vbyte_batch_graph_*):
+    the buffers are fixed at creation, their contents are read at each
+    replay.  Replays of one graph must be ordered."""
+
+    def __init__(self, data, byte_off, out_off, out, list_status, *, delta=False, prevs=None):
+        _dev_u8(data)
+        nlists = byte_off.numel() - 1
+        self._keep = (data, byte_off, out_off, out, list_status, prevs)
+        h = ctypes.c_void_p()
+        st = _lib().vbyte_batch_graph_create(_ptr(data), data.numel(), _ptr(byte_off), _ptr(out),
+                                             out.numel(), _ptr(out_off), max(nlists, 0),
+                                             _ptr(prevs), 1 if delta else 0, _ptr(list_status),
+                                             ctypes.byref(h))
+        _check_call(st, "batch_graph_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check_call(_lib().vbyte_batch_graph_launch(self.handle, _stream(stream)), "batch_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize()
+            _lib().vbyte_batch_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _points(arr, n):
+    return [{"segs_per_wave": p.segs_per_wave, "waves_per_block": p.waves_per_block,
+             "small_list_bytes": p.small_list_bytes, "ms": p.ms, "status": p.status}
+            for p in arr[:n]]
+
+
+def autotune_decode(data, n, *, delta=False, out=None, reps=5, stream=None):
+    """Run the library's autotuner on a single-stream decode of `data` and
+    apply the fastest tiling; returns the timed candidates."""
+    _dev_u8(data)
+    n = int(n)
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=data.device)
+    status = torch.empty(1, dtype=torch.int32, device=data.device)
+    arr = (TunePoint * 32)()
+    cnt = ctypes.c_size_t()
+    st = _lib().vbyte_autotune_decode(_ptr(data), data.numel(), _ptr(out), n, 1 if delta else 0,
+                                      int(reps), _ptr(status), arr, 32, ctypes.byref(cnt),
+                                      _stream(stream))
+    _check_call(st, "autotune_decode")
+    return _points(arr, cnt.value)
+
+
+def autotune_batch(data, byte_off, out_off, *, delta=False, out=None, reps=3, stream=None):
+    """Run the library's autotuner on a batched CSR decode and apply the
+    fastest tiling and small-list threshold; returns the timed candidates."""
+    _dev_u8(data)
+    nlists = byte_off.numel() - 1
+    if out is None:
+        total = int(out_off[-1].item()) if nlists > 0 else 0
+        out = torch.empty(max(total, 1), dtype=torch.int32, device=data.device)
+    status = torch.empty(max(nlists, 1), dtype=torch.int32, device=data.device)
+    arr = (TunePoint * 32)()
+    cnt = ctypes.c_size_t()
+    st = _lib().vbyte_autotune_batch(_ptr(data), data.numel(), _ptr(byte_off), _ptr(out),
+                                     out.numel(), _ptr(out_off), max(nlists, 0), 1 if delta else 0,
+                                     int(reps), _ptr(status), arr, 32, ctypes.byref(cnt),
+                                     _stream(stream))
+    _check_call(st, "autotune_batch")
+    return _points(arr, cnt.value)
 
 
 def encode(values, *, delta=False, prev=0, out=None, nbytes=None, stream=None, trim=True):
