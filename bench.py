@@ -28,6 +28,7 @@ HBM_PEAK_GBPS = 8000.0
 N_STREAM = 1 << 26
 COPY_ELEMS = 1 << 26          # calibration copy: 256 MiB read + 256 MiB written
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "decode_delta_64Mi_counters.json")
+PROFILE_TRACE = os.path.join(ROOT, "profiles", "decode_delta_64Mi_kernel_trace.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1503_07387_amd", "csrc", "kernels.hip")
 
 
@@ -36,8 +37,15 @@ def log(msg):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 prefix of the kernel source with comments and blank space
+    removed, so that only changes to the code itself retire the counters."""
+    import re
+    with open(KERNEL_SRC) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def measured_traffic(bytes_per_launch_alg):
@@ -157,7 +165,8 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
         for name, p in zip(("gap mean 8", "gap mean 300"), per):
             fh.write(f"| {name} | {p['fetch_bytes'] / 1e6:.1f} | {p['write_bytes'] / 1e6:.1f} | "
                      f"{p['hbm_bytes'] / 1e6:.1f} |\n")
-        fh.write(f"\nkernel source sha256[:16] = {out['kernel_source_sha256_16']}\n")
+        fh.write(f"\nkernel source sha256[:16] (comments and blank space removed) = "
+                 f"{out['kernel_source_sha256_16']}\n")
     return out
 
 
@@ -176,13 +185,20 @@ def build_index(torch, vbyte, workloads):
 
 
 def bench_batched(torch, vbyte, serve, idx, reps=10):
-    """Batched CSR decode of config 3 in one persistent launch, against one
-    single-stream launch per list (both issued from native host loops)."""
+    """Batched CSR decode of config 3 in one persistent launch (eager and as
+    a graph replay, with the autotuned tiling), against one single-stream
+    launch per list (both issued from native host loops); also the batched
+    rate per list-length group [2^K, 2^(K+1))."""
+    import numpy as np
     d = idx["lists"]
     nl = d["lengths"].size
     total = int(d["out_off"][-1])
     out = torch.empty(total, dtype=torch.int32, device="cuda")
     st = torch.empty(nl, dtype=torch.int32, device="cuda")
+    tune_points = vbyte.autotune_batch(idx["bytes"], idx["byte_off"], idx["out_off"], delta=True,
+                                       out=out, reps=2)
+    tuned = vbyte.get_tuning()
+    log(f"batch tuning: {tuned}")
 
     def once():
         vbyte.decode_batch(idx["bytes"], idx["byte_off"], idx["out_off"], delta=True, out=out,
@@ -206,10 +222,54 @@ def bench_batched(torch, vbyte, serve, idx, reps=10):
     torch.cuda.synchronize()
     batched_ms = e0.elapsed_time(e1) / reps
     in_bytes = idx["bytes"].numel()
+    # the same batch captured into a HIP graph and replayed
+    gout = torch.empty_like(out)
+    gst = torch.empty_like(st)
+    g = vbyte.BatchGraph(idx["bytes"], idx["byte_off"], idx["out_off"], gout, gst, delta=True)
+    g.launch()
+    torch.cuda.synchronize()
+    if not torch.equal(gout, out) or int(gst.max().item()) != 0:
+        raise RuntimeError("graph replay differs from the eager batch")
+    e0.record()
+    for _ in range(reps):
+        g.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / reps
+    g.close()
+    del gout, gst
+    # per list-length group: the group's lists as one gather batch
+    lens = d["lengths"]
+    bo_h = idx["byte_off"].cpu().numpy()
+    oo_h = d["out_off"]
+    groups = []
+    for k in range(int(np.log2(lens.max())) + 1):
+        sel = np.nonzero((lens >= (1 << k)) & (lens < (2 << k)))[0]
+        if sel.size == 0:
+            continue
+        rows = np.stack([bo_h[sel], bo_h[sel + 1], oo_h[sel], lens[sel]], axis=1).astype(np.int64)
+        rows_d = torch.from_numpy(np.ascontiguousarray(rows)).cuda()
+        gbytes = int((bo_h[sel + 1] - bo_h[sel]).sum())
+        gints = int(lens[sel].sum())
+        gs = torch.empty(sel.size, dtype=torch.int32, device="cuda")
+        vbyte.decode_lists(idx["bytes"], rows_d, gbytes, out, delta=True, list_status=gs)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            vbyte.decode_lists(idx["bytes"], rows_d, gbytes, out, delta=True, list_status=gs)
+        e1.record()
+        torch.cuda.synchronize()
+        if int(gs.max().item()) != 0:
+            raise RuntimeError(f"length group 2^{k} reported a bad list")
+        ms = e0.elapsed_time(e1) / reps
+        groups.append({"len_lo": 1 << k, "len_hi": (2 << k) - 1, "lists": int(sel.size),
+                       "integers": gints, "bytes_in": gbytes, "ms": round(ms, 4),
+                       "gints_per_s": round(gints / (ms / 1e3) / 1e9, 2),
+                       "alg_gbps": round((gbytes + 4 * gints) / (ms / 1e3) / 1e9, 1)})
+    # the batch tuning stays in force for the server runs below
     # per-list launches and the server's single gather launch, same lists
     bo = idx["byte_off"].cpu().numpy()
     counts = d["lengths"].astype("int64")
-    import numpy as np
     res = {}
     for batching in (True, False):
         srv = serve.Server(idx["bytes"], bo, counts, pool_bytes=(total + 1024) * 4, nstreams=1,
@@ -223,13 +283,18 @@ def bench_batched(torch, vbyte, serve, idx, reps=10):
     return {"workload": "100,000 differential lists, Zipf(1.2) lengths clipped to [1, 4Mi], 2^28 "
                         "integers, gaps Geometric(len/2^25)",
             "bytes_in": int(in_bytes), "integers": total,
+            "tuning": tuned, "tuned_candidates": len(tune_points),
             "batched_csr_ms": round(batched_ms, 4),
             "batched_gints_per_s": round(total / (batched_ms / 1e3) / 1e9, 2),
             "batched_alg_gbps": round((in_bytes + 4 * total) / (batched_ms / 1e3) / 1e9, 1),
+            "graph_replay_ms": round(graph_ms, 4),
+            "graph_replay_gints_per_s": round(total / (graph_ms / 1e3) / 1e9, 2),
+            "per_length_group": groups,
             "gather_one_launch_ms": round(res[True][0], 3),
             "per_list_launches_ms": round(res[False][0], 3),
             "per_list_launches": res[False][1],
-            "speedup_batched_vs_per_list": round(res[False][0] / batched_ms, 1)}
+            "speedup_batched_vs_per_list": round(res[False][0] / batched_ms, 1),
+            "speedup_graph_vs_per_list": round(res[False][0] / graph_ms, 1)}
 
 
 def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
@@ -289,7 +354,42 @@ def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
             "points": points, "per_list_launches_at_half_saturation": per_list}
 
 
+def summarize_trace(trace_csv, stats_csv, out_md, command_line):
+    """Turn a rocprofv3 --kernel-trace --stats run of bench.py (with
+    --no-autotune, so that every decode dispatch uses one tiling) into the
+    per-stream duration table of profiles/decode_delta_64Mi_kernel_trace.md."""
+    import csv
+    rows = [r for r in csv.DictReader(open(trace_csv)) if DECODE_KERNEL in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    names = sorted({r["Kernel_Name"] for r in rows})
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+    with open(out_md, "w") as fh:
+        fh.write("# Kernel trace: differential decode, 2 x 64Mi-gap streams (bench.py workload)\n\n")
+        fh.write("Command (run from the repository root on one MI355X):\n\n")
+        fh.write(f"    {command_line}\n\n")
+        fh.write("Decode kernel instance(s): " + ", ".join(f"`{n}`" for n in names) + ".\n")
+        fh.write("Dispatches alternate between the gap-mean-8 stream and the gap-mean-300 stream "
+                 "(first the warm-up steps, then the timed ones).\n\n")
+        fh.write("| stream | dispatches | avg us | min us | max us |\n|---|---|---|---|---|\n")
+        for k, name in enumerate(("gap mean 8", "gap mean 300")):
+            d = dur[k::2]
+            if d:
+                fh.write(f"| {name} | {len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |\n")
+        fh.write("\nrocprofv3 --stats summary (the ten kernels with the most total time):\n\n")
+        st = list(csv.DictReader(open(stats_csv)))
+        st.sort(key=lambda r: -float(r.get("TotalDurationNs", 0) or 0))
+        fh.write("| kernel | calls | avg ns | min ns | max ns |\n|---|---|---|---|---|\n")
+        for r in st[:10]:
+            fh.write(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | "
+                     f"{float(r['MinNs']):.0f} | {float(r['MaxNs']):.0f} |\n")
+    return {"dispatches": len(dur), "names": names}
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
+        o = summarize_trace(sys.argv[2], sys.argv[3], PROFILE_TRACE, sys.argv[4])
+        print(json.dumps(o))
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
         fetch_csv, write_csv = sys.argv[2], sys.argv[3]
         cmds = sys.argv[4:]
@@ -305,6 +405,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the config-3 batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the config-4 serving run")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's current tiling instead of autotuning each stream "
+                         "(profiling runs: every decode dispatch then uses one tiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 256 MiB (int32 tensor copy) before the "
                          "steps, as the reference kernel for scaling HBM byte counters")
@@ -331,8 +434,18 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # the tiling of each stream picked by the library's autotuner (untimed)
+    tunings = []
+    for s in streams:
+        if not args.no_autotune:
+            vbyte.autotune_decode(s["bytes"], N_STREAM, delta=True, out=s["out"], reps=3)
+        tunings.append(vbyte.get_tuning())
+        log(f"stream mean {s['mean']}: tuning {tunings[-1]}")
+
     def step(events=None):
         for i, s in enumerate(streams):
+            t = tunings[i]
+            vbyte.set_tuning(t["segs_per_wave"], t["waves_per_block"], t["small_list_bytes"])
             if events is not None:
                 events[i][0].record(stream)
             vbyte.decode(s["bytes"], N_STREAM, delta=True, prev=0, out=s["out"],
@@ -366,6 +479,7 @@ def main():
     for i, s in enumerate(streams):
         per_stream.append({
             "gap_mean": s["mean"], "n": N_STREAM, "bytes_in": int(s["bytes"].numel()),
+            "tuning": tunings[i],
             "kernel_ms": round(avg_ms[i], 4),
             "gints_per_s": round(N_STREAM / (avg_ms[i] / 1e3) / 1e9, 2),
             "alg_gbps": round(alg_bytes[i] / (avg_ms[i] / 1e3) / 1e9, 1),
@@ -390,7 +504,7 @@ def main():
         "config": {"workload": "differential VByte decode of two single streams of 64Mi uint32 "
                                "gaps each (geometric gaps, mean 8 and mean 300), wrapping prefix sum",
                    "n_per_stream": N_STREAM, "streams": 2, "gap_means": [8, 300],
-                   "tuning": vbyte.get_tuning()},
+                   "tuning": tunings},
         "hbm_gbps": round(achieved, 1),
         "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBPS, 2),
         "streams": per_stream,

@@ -11,27 +11,29 @@
 //
 // GPU design (the paper's x86 Masked VByte is prior art, not the design):
 //  * A wavefront owns tiles of SEGS x 1 KiB.  Each lane loads 16 bytes of a
-//    segment with one 128-bit load; the 4 bytes before a lane's 16 come from
-//    the lane below via DPP wave_shr (the "halo"), so a code that starts in
-//    one lane and ends in the next is resolved where its terminator lies.
-//    Codes are at most 5 bytes, so 4 halo bytes always reach a code's start
-//    (the paper's decoder likewise relies on a segment beginning with a
-//    whole code, section 4).
+//    segment with one 128-bit load; the dword before a lane's 16 bytes and
+//    the dword after them come from the neighbouring lanes by DPP (at the
+//    wavefront's ends from 4-byte halo loads).  Codes are at most 5 bytes,
+//    so the 4 bytes after a lane complete any code that begins in it (the
+//    paper's decoder likewise relies on a segment beginning with a whole
+//    code, section 4).
 //  * The terminator mask of a lane's 16 bytes plays the role of the paper's
-//    pmovmskb continuation mask (complemented); its popcount is the lane's
-//    number of integers, and a DPP wave scan of the counts gives every lane
-//    its output rank -- the GPU counterpart of the "bytes consumed" chain.
+//    pmovmskb continuation mask (complemented).  A lane owns the integers
+//    whose code begins in its bytes (the byte before is a terminator); their
+//    count is a popcount and the wave sum gives the segment's count.
 //  * Ranks across tiles come from a single-pass decoupled look-back over
 //    per-tile descriptors (tile count, tile gap sum, malformed flag), so the
 //    stream is read once.
-//  * Each lane assembles its codes sequentially over its 20-byte window
-//    (7-bit groups shifted into place; the fifth group's shift of 28 wraps
-//    mod 2^32 like Algorithm 1), writes them compacted into LDS, and the
-//    wavefront stores them to HBM with aligned 128-bit stores.
-//  * The differential form adds a lane-local running sum, a wave scan of
-//    lane sums, the tile's exclusive prefix sum from the look-back, and the
-//    caller's start value, all mod 2^32 (the wave-level counterpart of the
-//    4-wide shift-and-add prefix sum of section 4).
+//  * Each lane evaluates Algorithm 1's sum for every byte position at once,
+//    in Horner form from its last byte down, so that each code's integer is
+//    left at the code's first byte (the fifth group's weight 2^28 wraps mod
+//    2^32 like Algorithm 1).  The wavefront writes one candidate per byte to
+//    LDS and stores each 64-byte row of the segment with one masked store of
+//    consecutive words, the slots given by mbcnt over the row's mask.
+//  * The differential form keeps lane-local suffix sums during assembly and
+//    adds a wave scan of lane sums, the tile's exclusive prefix sum from the
+//    look-back and the caller's start value, all mod 2^32 (the wave-level
+//    counterpart of the 4-wide shift-and-add prefix sum of section 4).
 //  * Descriptor words are published and read with relaxed agent-scope 64-bit
 //    atomics that bypass the per-XCD L2, so no cache-flushing fence is
 //    needed between tiles on different XCDs.
@@ -988,7 +990,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
         }
     }
 
-    const u64 chunk = (u64)kSmallChunk;
+    // Chunks of up to kSmallChunk lists, smaller when there are few small
+    // lists, so that there are about 2 chunks per workgroup and every
+    // workgroup gets some; one device-wide atomic (about 12 ns, serialised
+    // on the queue word) per chunk.
+    u64 chunk = S / (G * 2);
+    chunk = chunk < 1 ? 1 : (chunk > (u64)kSmallChunk ? (u64)kSmallChunk : chunk);
     const u64 nchunks = (S + chunk - 1) / chunk;
     for (;;) {
         if (tid == 0) {
