@@ -413,8 +413,9 @@ def main():
                          "steps, as the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the decode would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (a stream "
+              "would shard by byte ranges with one exchange of per-range counts and sums)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -81,6 +81,12 @@ def _declare(lib):
     lib.orc_decode_delta.argtypes = [c.POINTER(c.c_uint8), c.c_size_t,
                                      c.POINTER(c.c_uint32), c.c_size_t, c.c_uint32]
     lib.orc_decode_delta.restype = c.c_int
+    lib.orc_decode_delta_m1.argtypes = [c.POINTER(c.c_uint8), c.c_size_t,
+                                        c.POINTER(c.c_uint32), c.c_size_t, c.c_uint32]
+    lib.orc_decode_delta_m1.restype = c.c_int
+    lib.orc_encode_delta_m1.argtypes = [c.POINTER(c.c_uint32), c.c_size_t, c.c_uint32,
+                                        c.POINTER(c.c_uint8)]
+    lib.orc_encode_delta_m1.restype = c.c_size_t
     lib.orc_decode_batch.argtypes = [c.POINTER(c.c_uint8), c.POINTER(c.c_int64),
                                      c.POINTER(c.c_uint32), c.POINTER(c.c_int64),
                                      c.c_size_t, c.POINTER(c.c_uint32), c.c_int,
@@ -160,8 +166,27 @@ def decode_delta(b, n, prev=0, lib=None):
     return int(st), y[:int(n)]
 
 
+def decode_delta_m1(b, n, prev=0, lib=None):
+    """DEC then differences minus one: y_0 = prev + g_0, y_k = y_(k-1) + g_k + 1."""
+    lib = lib or load()
+    b = _as_u8(b)
+    y = np.zeros(max(int(n), 1), dtype=np.uint32)
+    st = lib.orc_decode_delta_m1(_u8p(b), b.size, _u32p(y), int(n), int(prev) & 0xFFFFFFFF)
+    return int(st), y[:int(n)]
+
+
+def encode_delta_m1(x, prev=0, lib=None):
+    """ENC of the differences minus one (the first difference is x_0 - prev)."""
+    lib = lib or load()
+    x = _as_u32(x)
+    out = np.zeros(max(5 * x.size, 1), dtype=np.uint8)
+    m = lib.orc_encode_delta_m1(_u32p(x), x.size, int(prev) & 0xFFFFFFFF, _u8p(out))
+    return out[:m].copy()
+
+
 def decode_batch(b, byte_off, out_off, prevs=None, delta=False, lib=None):
-    """BATCH over CSR offsets.  Returns (status, out, per-list status)."""
+    """BATCH over CSR offsets (delta: 0/False plain, 1/True differences,
+    2 differences minus one).  Returns (status, out, per-list status)."""
     lib = lib or load()
     b = _as_u8(b)
     byte_off = np.ascontiguousarray(byte_off, dtype=np.int64)
@@ -175,5 +200,5 @@ def decode_batch(b, byte_off, out_off, prevs=None, delta=False, lib=None):
         pv = _as_u32(prevs)
     st = lib.orc_decode_batch(_u8p(b), _i64p(byte_off), _u32p(out), _i64p(out_off),
                               nlists, _u32p(pv) if pv is not None else None,
-                              1 if delta else 0, _i32p(st_list))
+                              int(delta), _i32p(st_list))
     return int(st), out[:total], st_list[:nlists]

@@ -20,7 +20,7 @@
  *     "Differential Coding"): gaps are successive differences, decoding is
  *     an inclusive prefix sum carried in a 32-bit integer.
  *
- * Readings where the paper is silent (all of them listed in the design doc):
+ * Readings where the paper is silent:
  *   R1  0 encodes as the single byte 00.
  *   R3  five or more consecutive bytes with the top bit set anywhere in the
  *       buffer -> EMALFORMED (a uint32 code is never longer than 5 bytes).
@@ -28,6 +28,9 @@
  *       exactly as Algorithm 1 does in 32-bit arithmetic.
  *   R5  over-long codes (e.g. 80 00) are accepted and decode to the sum of
  *       their 7-bit groups.
+ *   R11 differences minus one: only differences after the first are
+ *       reduced, as in the section's example x_1 - 0, x_2 - x_1 - 1; a
+ *       stream continued from an earlier piece passes prev + 1.
  *   R6  exact consumption: the buffer must hold exactly n codes ending at
  *       its last byte; a last byte >= 0x80 or fewer than n terminators ->
  *       ETRUNC, more than n terminators -> ECOUNT.  Precedence when several
@@ -181,9 +184,41 @@ int orc_decode_delta(const uint8_t *b, size_t nbytes, uint32_t *y, size_t n,
     return ORC_OK;
 }
 
+/* Differences minus one (section 1, "Differential coding": for lists with
+ * no repeated value, every difference after the first is reduced by one,
+ * x_1 - 0, x_2 - x_1 - 1, x_3 - x_2 - 1, ...; reading R11).  Decoding adds
+ * the one back: y_0 = prev + g_0 and y_k = y_(k-1) + g_k + 1, mod 2^32. */
+int orc_decode_delta_m1(const uint8_t *b, size_t nbytes, uint32_t *y, size_t n,
+                        uint32_t prev)
+{
+    int status = orc_decode(b, nbytes, y, n);
+    if (status != ORC_OK) return status;
+    uint32_t id = prev;
+    for (size_t k = 0; k < n; k++) {
+        uint32_t step = y[k] + (k > 0 ? 1u : 0u);
+        id = id + step;
+        y[k] = id;
+    }
+    return ORC_OK;
+}
+
+/* The matching encoder: gap_0 = x_0 - prev, gap_k = x_k - x_(k-1) - 1. */
+size_t orc_encode_delta_m1(const uint32_t *x, size_t n, uint32_t prev, uint8_t *dst)
+{
+    size_t pos = 0;
+    uint32_t last = prev;
+    for (size_t i = 0; i < n; i++) {
+        uint32_t gap = x[i] - last - (i > 0 ? 1u : 0u);   /* wraps mod 2^32 */
+        pos += (size_t)orc_encode_one(gap, dst + pos);
+        last = x[i];
+    }
+    return pos;
+}
+
 /* BATCH (R9): list i is bytes[byte_off[i], byte_off[i+1]) and decodes to
  * out[out_off[i], out_off[i+1]), independently of every other list.
- * prevs may be NULL (all 0).  list_status[i] receives each list's status.
+ * prevs may be NULL (all 0).  delta: 0 plain, 1 differences, 2 differences
+ * minus one.  list_status[i] receives each list's status.
  * Returns EINVAL for decreasing offsets (nothing decoded), else the largest
  * per-list status. */
 int orc_decode_batch(const uint8_t *bytes, const int64_t *byte_off,
@@ -201,7 +236,8 @@ int orc_decode_batch(const uint8_t *bytes, const int64_t *byte_off,
         size_t n = (size_t)(out_off[i + 1] - out_off[i]);
         uint32_t *y = out + out_off[i];
         uint32_t prev = prevs ? prevs[i] : 0u;
-        int st = delta ? orc_decode_delta(b, nb, y, n, prev)
+        int st = delta == 2 ? orc_decode_delta_m1(b, nb, y, n, prev)
+               : delta ? orc_decode_delta(b, nb, y, n, prev)
                        : orc_decode(b, nb, y, n);
         list_status[i] = st;
         if (st > worst) worst = st;

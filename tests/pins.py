@@ -249,6 +249,45 @@ def pin_resumable(lib):
     assert np.array_equal(np.concatenate([y1, y2]), full)
 
 
+def pin_delta_m1_closed_form(lib):
+    # Reading R11: y_k = prev + sum_{j<=k} g_j + k (mod 2^32), in Python
+    # integers; all-zero gaps give consecutive identifiers.
+    rng = np.random.default_rng(21)
+    for prev in (0, 9, M32):
+        g = rng.integers(0, 1 << 32, 3000, dtype=np.uint64).astype(np.uint32)
+        g[:500] = rng.integers(0, 40, 500)
+        b = oracle.encode(g, lib=lib)
+        st, y = oracle.decode_delta_m1(b, g.size, prev, lib=lib)
+        assert st == OK
+        tot, ref = prev, []
+        for k, v in enumerate(g.tolist()):
+            tot += v
+            ref.append((tot + k) % (1 << 32))
+        assert y.tolist() == ref
+        z = oracle.encode(np.zeros(50, np.uint32), lib=lib)
+        st, y = oracle.decode_delta_m1(z, 50, prev, lib=lib)
+        assert st == OK and y.tolist() == [(prev + k) % (1 << 32) for k in range(50)]
+        # against the plain differential decode of the same bytes: + k
+        st2, yd = oracle.decode_delta(b, g.size, prev, lib=lib)
+        st, y = oracle.decode_delta_m1(b, g.size, prev, lib=lib)
+        assert st2 == OK and np.array_equal(y - yd, np.arange(g.size, dtype=np.uint32))
+
+
+def pin_delta_m1_encode_roundtrip(lib):
+    rng = np.random.default_rng(22)
+    ids = np.unique(rng.integers(0, 1 << 32, 5000, dtype=np.uint64)).astype(np.uint32)
+    for prev in (0, int(ids[0]) // 2):
+        b = oracle.encode_delta_m1(ids, prev, lib=lib)
+        gaps = np.diff(ids.astype(np.int64), prepend=prev) - (np.arange(ids.size) > 0)
+        assert (gaps >= 0).all()
+        assert np.array_equal(b, oracle.encode(gaps.astype(np.uint32), lib=lib))
+        st, y = oracle.decode_delta_m1(b, ids.size, prev, lib=lib)
+        assert st == OK and np.array_equal(y, ids)
+    # consecutive identifiers cost one byte each
+    run = np.arange(1000, 3000, dtype=np.uint32)
+    assert oracle.encode_delta_m1(run, 1000, lib=lib).tolist() == [0] * run.size
+
+
 # ---------------------------------------------------------------- status readings
 # (bytes, n, expected status); the expectations follow readings R3-R6.
 STATUS_CASES = [
@@ -326,6 +365,12 @@ def pin_batch(lib):
     st, out, sts = oracle.decode_batch(bts, byte_off, bad_out, None, False, lib=lib)
     assert sts[4] == ETRUNC and st == ETRUNC
     assert all(sts[i] == OK for i in range(len(lens)) if i != 4)
+    st, out, sts = oracle.decode_batch(bts, byte_off, out_off, prevs, 2, lib=lib)
+    assert st == OK
+    for i, x in enumerate(lists):
+        a, b = out_off[i], out_off[i + 1]
+        ref = (np.cumsum(x, dtype=np.uint32) + prevs[i] + np.arange(len(x), dtype=np.uint32)).astype(np.uint32)
+        assert np.array_equal(out[a:b], ref)
     dec = byte_off.copy()
     dec[2] = dec[3] + 1                   # byte offsets decrease from list 2 to 3
     st, _, _ = oracle.decode_batch(bts, dec, out_off, None, False, lib=lib)
@@ -339,5 +384,6 @@ def pin_batch(lib):
 ALL_PINS = [pin_table1, pin_fig1, pin_closed_form_boundaries, pin_length_closed_form,
             pin_five_byte_algebra, pin_protobuf_exhaustive_21, pin_protobuf_random_wide,
             pin_canonical_bijection, pin_random_wide_roundtrip, pin_delta_cumsum,
-            pin_delta_encode_roundtrip, pin_resumable, pin_status_readings,
+            pin_delta_encode_roundtrip, pin_resumable, pin_delta_m1_closed_form,
+            pin_delta_m1_encode_roundtrip, pin_status_readings,
             pin_fifth_byte_wrap, pin_overlong, pin_batch]

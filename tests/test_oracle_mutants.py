@@ -36,6 +36,11 @@ MUTANTS = [
     ("delta_sign", "s = s + y[k];", "s = s - y[k];"),
     ("encdelta_sign", "uint32_t gap = x[i] - last;", "uint32_t gap = last - x[i];"),
     ("batch_no_prev", "uint32_t prev = prevs ? prevs[i] : 0u;", "uint32_t prev = 0u;"),
+    ("m1_first_too", "uint32_t step = y[k] + (k > 0 ? 1u : 0u);", "uint32_t step = y[k] + 1u;"),
+    ("m1_no_one", "uint32_t step = y[k] + (k > 0 ? 1u : 0u);", "uint32_t step = y[k];"),
+    ("encm1_first_too", "uint32_t gap = x[i] - last - (i > 0 ? 1u : 0u);", "uint32_t gap = x[i] - last - 1u;"),
+    ("batch_m1_as_delta", "int st = delta == 2 ? orc_decode_delta_m1(b, nb, y, n, prev)",
+     "int st = delta == 3 ? orc_decode_delta_m1(b, nb, y, n, prev)"),
     ("batch_no_einval", "return ORC_EINVAL;\n    }\n    int worst", "(void)0;\n    }\n    int worst"),
 ]
 
