@@ -86,6 +86,18 @@ vbyte_status vbyte_decode_async(const uint8_t *bytes, size_t nbytes, uint32_t *o
 vbyte_status vbyte_decode_delta_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
                                       size_t n, uint32_t prev, int32_t *d_status, void *stream);
 
+/* Differences minus one (section 1, "Differential coding": with no repeated
+ * value, every difference after the first is coded less one, x_1 - 0,
+ * x_2 - x_1 - 1, ...): out[0] = prev + g_0 and out[i] = out[i-1] + g_i + 1
+ * mod 2^32, i.e. out[i] = prev + g_0 + ... + g_i + i.  To continue a stream
+ * decoded in parts, pass the previous part's last value plus one as prev.
+ * Arguments and errors as in vbyte_decode_delta(_async). */
+vbyte_status vbyte_decode_delta_m1(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                   uint32_t prev);
+vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
+                                         size_t n, uint32_t prev, int32_t *d_status,
+                                         void *stream);
+
 /* Number of terminator bytes (top bit 0) in bytes[0..nbytes), i.e. the
  * number of codes a valid stream holds (section 1: one terminator per
  * integer).  Written to the device word *d_count. */
@@ -104,7 +116,8 @@ vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count,
  *     device, so nothing outside the buffers is touched).
  *   out, nout: output array of nout uint32 (device).
  *   prevs: device uint32[nlists] start values for delta lists, or NULL (0).
- *   delta: 0 plain, 1 differential.
+ *   delta: 0 plain, 1 differential, 2 differences minus one (each list as
+ *     in vbyte_decode_delta_m1 with its own prev).
  *   d_list_status: device int32[nlists], required; receives each list's
  *     status under the strict semantics above.
  * A small prep kernel classifies the lists and builds a work table; one
@@ -221,6 +234,12 @@ vbyte_status vbyte_encode_async(const uint32_t *values, size_t n, uint8_t *bytes
 vbyte_status vbyte_encode_delta_async(const uint32_t *values, size_t n, uint32_t prev,
                                       uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
                                       void *stream);
+
+/* ENC of differences minus one: x_0 - prev, then x_i - x_{i-1} - 1, mod
+ * 2^32 (the inverse of vbyte_decode_delta_m1). */
+vbyte_status vbyte_encode_delta_m1_async(const uint32_t *values, size_t n, uint32_t prev,
+                                         uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
+                                         void *stream);
 
 /* Batched ENC for CSR lists: encodes values[0..n) (all lists concatenated;
  * list i is values[vals_off[i], vals_off[i+1])) in one pass and writes the

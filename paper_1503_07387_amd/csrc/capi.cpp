@@ -246,6 +246,17 @@ vbyte_status vbyte_decode_delta_async(const uint8_t *bytes, size_t nbytes, uint3
     return decode_stream(bytes, nbytes, out, n, prev, 1, d_status, (hipStream_t)stream);
 }
 
+vbyte_status vbyte_decode_delta_m1(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                   uint32_t prev) {
+    return decode_sync(bytes, nbytes, out, n, prev, 2);
+}
+
+vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
+                                         size_t n, uint32_t prev, int32_t *d_status,
+                                         void *stream) {
+    return decode_stream(bytes, nbytes, out, n, prev, 2, d_status, (hipStream_t)stream);
+}
+
 vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (!d_count || ((uintptr_t)d_count & 7u)) return VBYTE_EINVAL;
@@ -281,7 +292,7 @@ vbyte_status vbyte_decode_batch(const uint8_t *bytes, size_t nbytes, const int64
                                 const uint32_t *prevs, int delta, int32_t *d_list_status,
                                 void *stream) {
     if (nlists > 0 && (!byte_off || !out_off)) return VBYTE_EINVAL;
-    if (delta != 0 && delta != 1) return VBYTE_EINVAL;
+    if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     ListArgs a{};
     a.bytes = bytes;
     a.nbytes = nbytes;
@@ -302,7 +313,7 @@ vbyte_status vbyte_decode_lists(const uint8_t *bytes, size_t nbytes, const int64
                                 const uint32_t *prevs, int delta, int32_t *d_list_status,
                                 void *stream) {
     if (nlists > 0 && !lists) return VBYTE_EINVAL;
-    if (delta != 0 && delta != 1) return VBYTE_EINVAL;
+    if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     ListArgs a{};
     a.bytes = bytes;
     a.nbytes = nbytes;
@@ -364,6 +375,12 @@ vbyte_status vbyte_encode_delta_async(const uint32_t *values, size_t n, uint32_t
                                       uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
                                       void *stream) {
     return encode_common(values, n, prev, 1, bytes, capacity, d_nbytes, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_encode_delta_m1_async(const uint32_t *values, size_t n, uint32_t prev,
+                                         uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
+                                         void *stream) {
+    return encode_common(values, n, prev, 2, bytes, capacity, d_nbytes, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_encode_batch(const uint32_t *values, size_t n, const int64_t *vals_off,

@@ -47,7 +47,7 @@ vbyte_status vbyte_batch_graph_create(const uint8_t *bytes, size_t nbytes, const
     if (!graph) return VBYTE_EINVAL;
     *graph = nullptr;
     if (nlists == 0 || !byte_off || !out_off) return VBYTE_EINVAL;
-    if (delta != 0 && delta != 1) return VBYTE_EINVAL;
+    if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     ListArgs a{};
     a.bytes = bytes;
     a.nbytes = nbytes;

@@ -387,15 +387,16 @@ static_assert(kRowStride * kWave <= kStageWords, "row buffer exceeds the staging
 
 // Store the integers of the codes flagged in `emit` (one candidate u[j] per
 // byte j of the lane), compacted and in byte order, to out_seg[0 ..), with
-// slots below `lim` only when GUARD.  The segment's 1024 bytes are taken 64
+// slots below `lim` only when GUARD; RANK adds rbase + slot to each (the
+// rank term of differences minus one).  The segment's 1024 bytes are taken 64
 // at a time: row k covers bytes 64k .. 64k+63, i.e. the masks of lanes
 // 4k .. 4k+3; lane i of the wavefront handles byte 64k + i, and its output
 // slot is the row's base plus the number of flagged bytes below it in the
 // row (mbcnt of the row mask).  Each row is one masked store of consecutive
 // words.
-template <bool GUARD>
+template <bool GUARD, bool RANK>
 __device__ __forceinline__ void store_rows(u32 *rows, const u32 (&u)[16], u32 emit, u32 *out_seg,
-                                           u32 lim) {
+                                           u32 lim, u32 rbase) {
     const u32 ln = lane_id();
     uint2 *dst = (uint2 *)(rows + kRowStride * ln);
 #pragma unroll
@@ -418,7 +419,7 @@ __device__ __forceinline__ void store_rows(u32 *rows, const u32 (&u)[16], u32 em
         const u64 rm = ((u64)hi << 32) | lo;
         if (__builtin_amdgcn_inverse_ballot_w64(rm)) {
             const u32 slot = base + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-            if (!GUARD || slot < lim) *(gword *)(ob + (slot << 2)) = v[k];
+            if (!GUARD || slot < lim) *(gword *)(ob + (slot << 2)) = RANK ? v[k] + rbase + slot : v[k];
         }
         base += (u32)__builtin_popcountll(rm);
     }
@@ -436,7 +437,7 @@ __device__ __forceinline__ u32 out_mis(const u32 *out, u64 gbase) {
 // integers are the running sums, from a 4-wide local scan plus a wave scan of
 // the lane sums, carried across rows (the 4-wide shift-and-add prefix sum of
 // the paper's section 4, widened to the wavefront).
-template <bool DELTA>
+template <bool DELTA, bool RANK>
 __device__ __forceinline__ void store_dense(const u32 *stage, u32 amis, u32 *out, u64 gbase, u64 n,
                                             u32 add) {
     const u32 ln = lane_id();
@@ -476,6 +477,13 @@ __device__ __forceinline__ void store_dense(const u32 *stage, u32 amis, u32 *out
             v.y += base;
             v.z += base;
             v.w += base;
+        }
+        if (RANK) {
+            const u32 rk = (u32)gbase + (u32)e0;
+            v.x += rk;
+            v.y += rk + 1u;
+            v.z += rk + 2u;
+            v.w += rk + 3u;
         }
         if (q < nq) {
             if (inner && gbase + (u64)e0 + 4 <= n) {
@@ -543,9 +551,12 @@ __device__ __forceinline__ TileSum tile_sum(const WgShared &sh, u32 wpb) {
     return r;
 }
 
-template <bool DELTA, bool COUNT, int SEGS, bool EDGE>
+// D: 0 plain, 1 differences (inclusive prefix sum), 2 differences minus one
+// (the prefix sum plus each integer's rank).
+template <int D, bool COUNT, int SEGS, bool EDGE>
 __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared &sh, u32 wib,
                                             u32 wpb) {
+    constexpr bool DELTA = D != 0, RANK = D == 2;
     const u32 ln = lane_id();
     const u64 wv = t.tv + (u64)wib * (SEGS * kSegBytes);   // this wavefront's first byte
     u32 w[SEGS][4];
@@ -667,8 +678,8 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
         if (dmask & (1u << s)) {
             *(uint4 *)(rows + 4 * ln) = make_uint4(w[s][0], w[s][1], w[s][2], w[s][3]);
             wave_lds_sync();
-            store_dense<DELTA>(rows, out_mis(t.out, gbase), t.out, gbase, t.n,
-                               DELTA ? exs + wex_s + sbase[s] : 0u);
+            store_dense<DELTA, RANK>(rows, out_mis(t.out, gbase), t.out, gbase, t.n,
+                                     DELTA ? exs + wex_s + sbase[s] : 0u);
             wave_lds_sync();
             continue;
         }
@@ -683,9 +694,9 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
         }
         u32 *out_seg = t.out + gbase;
         if (gbase + segcnt[s] <= t.n)
-            store_rows<false>(rows, u, emit[s], out_seg, 0u);
+            store_rows<false, RANK>(rows, u, emit[s], out_seg, 0u, (u32)gbase);
         else
-            store_rows<true>(rows, u, emit[s], out_seg, (u32)(t.n - gbase));
+            store_rows<true, RANK>(rows, u, emit[s], out_seg, (u32)(t.n - gbase), (u32)gbase);
     }
     return res;
 }
@@ -700,8 +711,8 @@ __device__ __forceinline__ int32_t final_status(bool mal, u8 last_byte, u64 tota
 }
 
 // ------------------------------------------------------------ single stream
-template <bool DELTA, bool COUNT, int SEGS>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(DELTA ? 4 : 8))) void k_stream(StreamArgs a) {
+template <int D, bool COUNT, int SEGS>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4 : 8))) void k_stream(StreamArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;
     const u32 tid = threadIdx.x;
@@ -732,9 +743,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(DELTA
     const bool interior = tile > 0 && t.tv + tb + 4 <= a.vend;
     TileOut r;
     if (interior)
-        r = run_tile<DELTA, COUNT, SEGS, false>(t, stage, sh, wib, wpb);
+        r = run_tile<D, COUNT, SEGS, false>(t, stage, sh, wib, wpb);
     else
-        r = run_tile<DELTA, COUNT, SEGS, true>(t, stage, sh, wib, wpb);
+        r = run_tile<D, COUNT, SEGS, true>(t, stage, sh, wib, wpb);
 
     if (tile == a.ntiles - 1 && tid == 0) {
         if (COUNT) {
@@ -862,8 +873,9 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
 
 // Small list: one wavefront walks its segments in order, carrying the rank
 // and the running sum, with no look-back.
-template <bool DELTA>
+template <int D>
 __device__ __forceinline__ void run_small(const ListArgs &a, u64 li, const ListDesc &d, u32 *rows) {
+    constexpr bool DELTA = D != 0, RANK = D == 2;
     const u32 ln = lane_id();
     const u8 *p0 = a.bytes + d.bb;
     const u8 *base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
@@ -898,9 +910,9 @@ __device__ __forceinline__ void run_small(const ListArgs &a, u64 li, const ListD
         }
         if (segcnt && rank < n) {
             if (rank + segcnt <= n)
-                store_rows<false>(rows, r, m.emit, out + rank, 0u);
+                store_rows<false, RANK>(rows, r, m.emit, out + rank, 0u, (u32)rank);
             else
-                store_rows<true>(rows, r, m.emit, out + rank, (u32)(n - rank));
+                store_rows<true, RANK>(rows, r, m.emit, out + rank, (u32)(n - rank), (u32)rank);
         }
         rank += segcnt;
         run += segsum;
@@ -927,7 +939,7 @@ __device__ __forceinline__ u32 pick_next(u32 *counter, u32 *slot) {
 // queue (each wavefront pulls lists of the chunk through an LDS counter).
 // Both queue words are reset by their last taker; each queue costs one
 // device-wide atomic per span or chunk, not per tile or list.
-template <bool DELTA, int SEGS>
+template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;
@@ -983,8 +995,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
             t.tv = ti * tb;
             t.didx = t.dfirst + (i64)ti;
             const bool interior = ti > 0 && t.tv + tb + 4 <= t.vend;
-            const TileOut r = interior ? run_tile<DELTA, false, SEGS, false>(t, stage, sh, wib, wpb)
-                                       : run_tile<DELTA, false, SEGS, true>(t, stage, sh, wib, wpb);
+            const TileOut r = interior ? run_tile<D, false, SEGS, false>(t, stage, sh, wib, wpb)
+                                       : run_tile<D, false, SEGS, true>(t, stage, sh, wib, wpb);
             if (ti == tiles - 1 && tid == 0)
                 a.list_status[li] = final_status(r.mal, t.base[t.vend - 1], r.total, t.n);
         }
@@ -1016,7 +1028,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
             const u64 slot = lo + j;
             const int2 e = a.items[a.max_items - 1 - slot];
             const u64 li = (u64)e.x;
-            run_small<DELTA>(a, li, list_desc(a, li), stage);
+            run_small<D>(a, li, list_desc(a, li), stage);
             j = pick_next(&sh_next, &sh_pick[wib]);
         }
         __syncthreads();
@@ -1030,7 +1042,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
 
 // ------------------------------------------------------------ encoder
 // Canonical ENC (section 1): L(x) bytes, 7 bits each, least significant
-// first, top bit set on all but the last.  One wavefront encodes 1024
+// first, top bit set on all but the last.  delta: 1 codes x_i - x_(i-1),
+// 2 codes x_i - x_(i-1) - 1 after the first (x_(-1) = prev).  One wavefront encodes 1024
 // values per tile: lane lengths -> wave scan -> look-back for the tile's
 // byte offset -> bytes assembled in LDS -> stored to HBM.
 __device__ __forceinline__ u32 code_len(u32 x) {
@@ -1060,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
         u32 v = 0;
         if (i < a.n) {
             v = a.values[i];
-            if (a.delta) v -= (i == 0) ? a.prev : a.values[i - 1];
+            if (a.delta) v -= (i == 0) ? a.prev : a.values[i - 1] + (a.delta == 2 ? 1u : 0u);
         }
         x[k] = v;
         lanebytes += (i < a.n) ? code_len(v) : 0u;
@@ -1132,7 +1145,7 @@ __global__ void k_encode_bounds(EncodeArgs a, const int64_t *vals_off, int64_t *
         off = tile ? (aload(&a.desc[tile - 1].c) & kCountMask) : 0;
         for (u64 j = tile * kEncodeWaveValues; j < v; ++j) {
             u32 x = a.values[j];
-            if (a.delta) x -= (j == 0) ? a.prev : a.values[j - 1];
+            if (a.delta) x -= (j == 0) ? a.prev : a.values[j - 1] + (a.delta == 2 ? 1u : 0u);
             off += code_len(x);
         }
     }
@@ -1151,18 +1164,19 @@ __global__ void k_zero(uint4 *p, size_t n16) {
         p[i] = make_uint4(0, 0, 0, 0);
 }
 
-template <bool DELTA, bool COUNT, int SEGS>
+template <int D, bool COUNT, int SEGS>
 hipError_t launch_stream_t(const StreamArgs &a, int wpb, hipStream_t s) {
     const size_t lds = COUNT ? 0 : (size_t)wpb * kStageWords * sizeof(u32);
-    k_stream<DELTA, COUNT, SEGS><<<a.ntiles, wpb * kWave, lds, s>>>(a);
+    k_stream<D, COUNT, SEGS><<<a.ntiles, wpb * kWave, lds, s>>>(a);
     return hipGetLastError();
 }
 
 template <int SEGS>
 hipError_t launch_stream_s(const StreamArgs &a, int delta, int count_only, int wpb, hipStream_t s) {
-    if (count_only) return launch_stream_t<false, true, SEGS>(a, wpb, s);
-    if (delta) return launch_stream_t<true, false, SEGS>(a, wpb, s);
-    return launch_stream_t<false, false, SEGS>(a, wpb, s);
+    if (count_only) return launch_stream_t<0, true, SEGS>(a, wpb, s);
+    if (delta == 2) return launch_stream_t<2, false, SEGS>(a, wpb, s);
+    if (delta) return launch_stream_t<1, false, SEGS>(a, wpb, s);
+    return launch_stream_t<0, false, SEGS>(a, wpb, s);
 }
 
 template <int SEGS>
@@ -1174,10 +1188,12 @@ hipError_t launch_batch_s(const ListArgs &a, int wpb, int grid_blocks, hipStream
         if (e != hipSuccess) return e;
     }
     const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
-    if (a.delta)
-        k_batch<true, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
+    if (a.delta == 2)
+        k_batch<2, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
+    else if (a.delta)
+        k_batch<1, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
     else
-        k_batch<false, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
+        k_batch<0, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
     return hipGetLastError();
 }
 

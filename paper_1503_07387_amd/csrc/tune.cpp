@@ -126,7 +126,7 @@ vbyte_status vbyte_autotune_batch(const uint8_t *bytes, size_t nbytes, const int
                                   size_t nlists, int delta, int reps, int32_t *d_list_status,
                                   vbyte_tune_point *points, size_t max_points, size_t *npoints,
                                   void *stream) {
-    if (!d_list_status || nlists == 0 || (delta != 0 && delta != 1)) return VBYTE_EINVAL;
+    if (!d_list_status || nlists == 0 || delta < 0 || delta > 2) return VBYTE_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     Cand cands[16];
     int nc = 0;

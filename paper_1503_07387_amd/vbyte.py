@@ -22,7 +22,8 @@ STATUS_NAMES = {OK: "VBYTE_OK", EINVAL: "VBYTE_EINVAL", ECOUNT: "VBYTE_ECOUNT",
                 EHIP: "VBYTE_EHIP", ENOMEM: "VBYTE_ENOMEM"}
 
 EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
-           "vbyte_decode_delta_async", "vbyte_count", "vbyte_decode_batch",
+           "vbyte_decode_delta_async", "vbyte_decode_delta_m1", "vbyte_decode_delta_m1_async",
+           "vbyte_encode_delta_m1_async", "vbyte_count", "vbyte_decode_batch",
            "vbyte_decode_lists", "vbyte_encode_async", "vbyte_encode_delta_async",
            "vbyte_encode_batch", "vbyte_server_create", "vbyte_server_destroy",
            "vbyte_server_run", "vbyte_batch_graph_create", "vbyte_batch_graph_launch",
@@ -74,6 +75,9 @@ def _declare(lib):
         "vbyte_decode_delta": [vp, sz, vp, sz, u32],
         "vbyte_decode_async": [vp, sz, vp, sz, vp, vp],
         "vbyte_decode_delta_async": [vp, sz, vp, sz, u32, vp, vp],
+        "vbyte_decode_delta_m1": [vp, sz, vp, sz, u32],
+        "vbyte_decode_delta_m1_async": [vp, sz, vp, sz, u32, vp, vp],
+        "vbyte_encode_delta_m1_async": [vp, sz, u32, vp, sz, vp, vp],
         "vbyte_count": [vp, sz, vp, vp],
         "vbyte_decode_batch": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, vp],
         "vbyte_decode_lists": [vp, sz, vp, sz, sz, vp, sz, vp, i32, vp, vp],
@@ -126,8 +130,17 @@ def _dev_u8(data):
     return data
 
 
-def decode(data, n, *, delta=False, prev=0, out=None, status=None, stream=None, check=True):
+def _mode(delta, minus_one):
+    if minus_one:
+        return 2
+    return 1 if delta else 0
+
+
+def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=None, stream=None,
+           check=True):
     """Decode ``n`` uint32 from the VByte bytes ``data`` (uint8 CUDA tensor).
+    ``delta``: inclusive prefix sum of the gaps from ``prev``; ``minus_one``:
+    differences minus one (vbyte_decode_delta_m1).
 
     Returns the int32 tensor of results.  With ``check`` the call waits for
     the kernel and raises VByteError on a data error; otherwise the status is
@@ -143,7 +156,10 @@ def decode(data, n, *, delta=False, prev=0, out=None, status=None, stream=None, 
         status = torch.empty(1, dtype=torch.int32, device=data.device)
     s = _stream(stream)
     L = _lib()
-    if delta:
+    if minus_one:
+        st = L.vbyte_decode_delta_m1_async(_ptr(data), data.numel(), _ptr(out), n,
+                                           int(prev) & 0xFFFFFFFF, _ptr(status), s)
+    elif delta:
         st = L.vbyte_decode_delta_async(_ptr(data), data.numel(), _ptr(out), n,
                                         int(prev) & 0xFFFFFFFF, _ptr(status), s)
     else:
@@ -168,7 +184,7 @@ def count(data, *, stream=None, result=None):
     return int(res.item())
 
 
-def decode_batch(data, byte_off, out_off, *, delta=False, prevs=None, out=None,
+def decode_batch(data, byte_off, out_off, *, delta=False, minus_one=False, prevs=None, out=None,
                  list_status=None, stream=None):
     """Batched CSR decode.  byte_off/out_off: int64 CUDA tensors of nlists+1.
     Returns (out int32 tensor, per-list int32 status tensor); no wait."""
@@ -180,14 +196,14 @@ def decode_batch(data, byte_off, out_off, *, delta=False, prevs=None, out=None,
     if list_status is None:
         list_status = torch.empty(max(nlists, 0), dtype=torch.int32, device=data.device)
     st = _lib().vbyte_decode_batch(_ptr(data), data.numel(), _ptr(byte_off), _ptr(out), out.numel(),
-                                   _ptr(out_off), max(nlists, 0), _ptr(prevs), 1 if delta else 0,
-                                   _ptr(list_status), _stream(stream))
+                                   _ptr(out_off), max(nlists, 0), _ptr(prevs),
+                                   _mode(delta, minus_one), _ptr(list_status), _stream(stream))
     _check_call(st, "decode_batch")
     return out, list_status
 
 
-def decode_lists(data, rows, list_bytes, out, *, delta=False, prevs=None, list_status=None,
-                 stream=None):
+def decode_lists(data, rows, list_bytes, out, *, delta=False, minus_one=False, prevs=None,
+                 list_status=None, stream=None):
     """Gather-form batch: rows is an int64 CUDA tensor [nlists, 4] of
     (byte_begin, byte_end, out_begin, n).  Returns the per-list status."""
     _dev_u8(data)
@@ -195,7 +211,7 @@ def decode_lists(data, rows, list_bytes, out, *, delta=False, prevs=None, list_s
     if list_status is None:
         list_status = torch.empty(nlists, dtype=torch.int32, device=data.device)
     st = _lib().vbyte_decode_lists(_ptr(data), data.numel(), _ptr(rows), nlists, int(list_bytes),
-                                   _ptr(out), out.numel(), _ptr(prevs), 1 if delta else 0,
+                                   _ptr(out), out.numel(), _ptr(prevs), _mode(delta, minus_one),
                                    _ptr(list_status), _stream(stream))
     _check_call(st, "decode_lists")
     return list_status
@@ -206,15 +222,16 @@ class BatchGraph:
     the buffers are fixed at creation, their contents are read at each
     replay.  Replays of one graph must be ordered."""
 
-    def __init__(self, data, byte_off, out_off, out, list_status, *, delta=False, prevs=None):
+    def __init__(self, data, byte_off, out_off, out, list_status, *, delta=False, minus_one=False,
+                 prevs=None):
         _dev_u8(data)
         nlists = byte_off.numel() - 1
         self._keep = (data, byte_off, out_off, out, list_status, prevs)
         h = ctypes.c_void_p()
         st = _lib().vbyte_batch_graph_create(_ptr(data), data.numel(), _ptr(byte_off), _ptr(out),
                                              out.numel(), _ptr(out_off), max(nlists, 0),
-                                             _ptr(prevs), 1 if delta else 0, _ptr(list_status),
-                                             ctypes.byref(h))
+                                             _ptr(prevs), _mode(delta, minus_one),
+                                             _ptr(list_status), ctypes.byref(h))
         _check_call(st, "batch_graph_create")
         self.handle = h
 
@@ -276,7 +293,8 @@ def autotune_batch(data, byte_off, out_off, *, delta=False, out=None, reps=3, st
     return _points(arr, cnt.value)
 
 
-def encode(values, *, delta=False, prev=0, out=None, nbytes=None, stream=None, trim=True):
+def encode(values, *, delta=False, minus_one=False, prev=0, out=None, nbytes=None, stream=None,
+           trim=True):
     """Canonical VByte encoding on the GPU of an int32/uint32-bits CUDA tensor.
     Returns the uint8 tensor of codes (trimmed to the encoded size when
     ``trim``, which waits for the kernel)."""
@@ -289,7 +307,10 @@ def encode(values, *, delta=False, prev=0, out=None, nbytes=None, stream=None, t
         nbytes = torch.empty(1, dtype=torch.int64, device=values.device)
     s = _stream(stream)
     L = _lib()
-    if delta:
+    if minus_one:
+        st = L.vbyte_encode_delta_m1_async(_ptr(values), n, int(prev) & 0xFFFFFFFF, _ptr(out),
+                                           out.numel(), _ptr(nbytes), s)
+    elif delta:
         st = L.vbyte_encode_delta_async(_ptr(values), n, int(prev) & 0xFFFFFFFF, _ptr(out),
                                         out.numel(), _ptr(nbytes), s)
     else:
