@@ -264,13 +264,21 @@ size_t vbyte_workspace_size(size_t nbytes);
 vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t small_list_bytes);
 void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_list_bytes);
 
+/* Kernel of the single-stream decodes (vbyte_decode*, not the batched
+ * forms): 0 (the default) gives every tile its own look-back; k in 1..64
+ * gives each workgroup a chunk of k consecutive tiles, which it first reads
+ * for their counts and sums, then looks back once for the chunk, then reads
+ * again and decodes.  Returns VBYTE_EINVAL outside 0..64. */
+vbyte_status vbyte_set_chunk_tiles(int tiles_per_chunk);
+int vbyte_get_chunk_tiles(void);
+
 /* Autotuner of the tiling.  Times the caller's workload under each candidate
  * tiling (reps calls each after one untimed call, HIP events on `stream`),
  * then applies the fastest with vbyte_set_tuning and returns VBYTE_OK.
  *   vbyte_autotune_decode: single-stream decode of bytes[0, nbytes) into
  *     out[0, n) (plain or delta, prev 0); d_status is a device int32 the
- *     calls write.  Candidates: segs_per_wave {1, 2, 4} x waves_per_block
- *     {2, 4, 6, 8}.
+ *     calls write.  Candidates: segs_per_wave {2, 4} x waves_per_block
+ *     {4, 8} x tiles_per_chunk {0, 2, 4, 8, 16}.
  *   vbyte_autotune_batch: vbyte_decode_batch of the given lists (prevs 0);
  *     d_list_status is device int32[nlists].  Candidates: segs_per_wave
  *     {2, 4} x waves_per_block {4, 8} x small_list_bytes {4, 16, 64, 256} KiB.
@@ -283,6 +291,7 @@ typedef struct vbyte_tune_point {
     int segs_per_wave;
     int waves_per_block;
     int64_t small_list_bytes;
+    int tiles_per_chunk;
     double ms;        /* mean time of one call */
     int32_t status;   /* worst data status the timed calls produced */
 } vbyte_tune_point;

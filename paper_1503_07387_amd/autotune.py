@@ -9,6 +9,7 @@ without timing again:
     {"<device name>": {"<workload key>": {"segs_per_wave": 4,
                                           "waves_per_block": 8,
                                           "small_list_bytes": 16384,
+                                          "tiles_per_chunk": 4,
                                           "ms": 0.118}}}
 
 The default file is $VBYTE_TUNE_CACHE or ~/.cache/vbyte_tuning.json.
@@ -57,7 +58,8 @@ def batch_key(nbytes, nlists, delta):
 
 
 def _apply(entry):
-    vbyte.set_tuning(entry["segs_per_wave"], entry["waves_per_block"], entry["small_list_bytes"])
+    vbyte.set_tuning(entry["segs_per_wave"], entry["waves_per_block"], entry["small_list_bytes"],
+                     tiles_per_chunk=entry.get("tiles_per_chunk", 0))
 
 
 def _tuned(key, run, path, retune):
@@ -70,9 +72,7 @@ def _tuned(key, run, path, retune):
         return entry, None
     points = run()
     best = vbyte.get_tuning()
-    ms = min((p["ms"] for p in points if p["segs_per_wave"] == best["segs_per_wave"]
-              and p["waves_per_block"] == best["waves_per_block"]
-              and p["small_list_bytes"] == best["small_list_bytes"]), default=None)
+    ms = min((p["ms"] for p in points if all(p[k] == best[k] for k in best)), default=None)
     entry = dict(best, ms=ms)
     d.setdefault(dev, {})[key] = entry
     _store(path, d)

@@ -27,6 +27,7 @@ thread_local char g_last_error[256] = "";
 std::atomic<int> g_segs{4};
 std::atomic<int> g_wpb{8};
 std::atomic<int64_t> g_small{16384};
+std::atomic<int> g_chunk{0};   // single stream: 0 = per-tile look-back, k = chunks of k tiles
 
 vbyte_status hip_fail(hipError_t e, const char *what) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
@@ -125,8 +126,11 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
     const uint64_t ntiles = nbytes ? stream_tiles(a.vstart, nbytes, segs, wpb) : 0;
     if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
     a.ntiles = (uint32_t)ntiles;
+    const int chunk = g_chunk.load();
+    const uint64_t nchunks = chunk > 0 ? (ntiles + chunk - 1) / chunk : 0;
+    const uint64_t ndesc = chunk > 0 ? nchunks : ntiles;
     Workspace *w = nullptr;
-    vbyte_status st = get_ws(s, kHeaderBytes + ntiles * sizeof(Desc), ntiles ? 1 : 0, &w);
+    vbyte_status st = get_ws(s, kHeaderBytes + ndesc * sizeof(Desc), ntiles ? 1 : 0, &w);
     if (st != VBYTE_OK) return st;
     if (!d_status) {
         d_status = (int32_t *)(ws_base(w) + kStatusOff);
@@ -140,7 +144,8 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
     a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
     a.d_status = d_status;
     a.d_count = nullptr;
-    hipError_t e = launch_stream(a, delta, 0, segs, wpb, s);
+    hipError_t e = chunk > 0 ? launch_chunks(a, delta, segs, wpb, (uint32_t)nchunks, s)
+                             : launch_stream(a, delta, 0, segs, wpb, s);
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode launch");
 }
 
@@ -414,6 +419,14 @@ vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t sm
     if (small_list_bytes) g_small.store(small_list_bytes);
     return VBYTE_OK;
 }
+
+vbyte_status vbyte_set_chunk_tiles(int tiles_per_chunk) {
+    if (tiles_per_chunk < 0 || tiles_per_chunk > 64) return VBYTE_EINVAL;
+    g_chunk.store(tiles_per_chunk);
+    return VBYTE_OK;
+}
+
+int vbyte_get_chunk_tiles(void) { return g_chunk.load(); }
 
 void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_list_bytes) {
     if (segs_per_wave) *segs_per_wave = g_segs.load();

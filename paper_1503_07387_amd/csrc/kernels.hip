@@ -514,12 +514,23 @@ struct TileIn {
     Desc *desc;
     i64 didx, dfirst;
     u32 tag;
+    // kKnown: exclusive prefix of the tile (count, sum, malformed so far)
+    u64 known_c;
+    u32 known_s;
+    bool known_mal;
 };
 
 struct TileOut {
-    u64 total;   // integers up to and including this tile
+    u64 total;   // integers up to and including this tile (kAgg: of the wavefront)
     bool mal;
+    u32 sum;     // inclusive wrapping sum (kAgg: of the wavefront)
 };
+
+// What run_tile does with a tile.
+constexpr int kFull = 0;    // decode, prefix from the look-back
+constexpr int kCount = 1;   // count terminators only, prefix from the look-back
+constexpr int kAgg = 2;     // this wavefront's count and sum only; no synchronisation
+constexpr int kKnown = 3;   // decode with the exclusive prefix given in TileIn
 
 constexpr int kMaxWaves = 16;
 constexpr int kMaxBlock = 8 * kWave;   // at most 8 wavefronts per workgroup
@@ -553,10 +564,11 @@ __device__ __forceinline__ TileSum tile_sum(const WgShared &sh, u32 wpb) {
 
 // D: 0 plain, 1 differences (inclusive prefix sum), 2 differences minus one
 // (the prefix sum plus each integer's rank).
-template <int D, bool COUNT, int SEGS, bool EDGE>
+template <int D, int KIND, int SEGS, bool EDGE>
 __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared &sh, u32 wib,
                                             u32 wpb) {
     constexpr bool DELTA = D != 0, RANK = D == 2;
+    constexpr bool COUNT = KIND == kCount, AGG = KIND == kAgg, KNOWN = KIND == kKnown;
     const u32 ln = lane_id();
     const u64 wv = t.tv + (u64)wib * (SEGS * kSegBytes);   // this wavefront's first byte
     u32 w[SEGS][4];
@@ -631,6 +643,7 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
         }
     }
     const bool wmal = ballot(mal) != 0;
+    if (AGG) return TileOut{ctot, wmal, stot};
     if (ln == 0) {
         sh.wcnt[wib] = ctot;
         sh.wsum[wib] = stot;
@@ -650,15 +663,18 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
     // in that order.
     if (wib == 0) {
         Prefix ex;
-        if (t.didx == t.dfirst) {
+        if (KNOWN) {
+            ex = Prefix{t.known_c, t.known_s, t.known_mal};
+        } else if (t.didx == t.dfirst) {
             ex = Prefix{0, t.prev, false};
         } else {
             if (ln == 0) publish<DELTA>(&t.desc[t.didx], t.tag, false, tsum.mal, tsum.c, tsum.s);
             ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag);
         }
         if (ln == 0) {
-            publish<DELTA>(&t.desc[t.didx], t.tag, true, ex.mal || tsum.mal, ex.c + tsum.c,
-                           ex.s + tsum.s);
+            if (!KNOWN)
+                publish<DELTA>(&t.desc[t.didx], t.tag, true, ex.mal || tsum.mal, ex.c + tsum.c,
+                               ex.s + tsum.s);
             sh.excl_c = ex.c;
             sh.excl_s = ex.s;
             sh.excl_mal = ex.mal ? 1u : 0u;
@@ -667,7 +683,7 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
     __syncthreads();
     const u64 exc = sh.excl_c;
     const u32 exs = sh.excl_s;
-    const TileOut res{exc + tsum.c, sh.excl_mal != 0 || tsum.mal};
+    const TileOut res{exc + tsum.c, sh.excl_mal != 0 || tsum.mal, exs + tsum.s};
     if (COUNT) return res;
 
     // Phase 2: store each segment's integers.
@@ -743,9 +759,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     const bool interior = tile > 0 && t.tv + tb + 4 <= a.vend;
     TileOut r;
     if (interior)
-        r = run_tile<D, COUNT, SEGS, false>(t, stage, sh, wib, wpb);
+        r = run_tile<D, COUNT ? kCount : kFull, SEGS, false>(t, stage, sh, wib, wpb);
     else
-        r = run_tile<D, COUNT, SEGS, true>(t, stage, sh, wib, wpb);
+        r = run_tile<D, COUNT ? kCount : kFull, SEGS, true>(t, stage, sh, wib, wpb);
 
     if (tile == a.ntiles - 1 && tid == 0) {
         if (COUNT) {
@@ -756,6 +772,101 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
         }
         // The last tile's look-back has ended, so every tile has published
         // and therefore read the epoch: retire this launch's descriptors.
+        astore(a.hdr, (u64)epoch + 1);
+    }
+}
+
+// ------------------------------------------------------------ chunked stream
+// Single stream in chunks of whole tiles, one chunk per workgroup (chunk =
+// workgroup index, so a chunk only ever waits for chunks dispatched before
+// it).  Pass 1 reads the chunk's tiles for their counts and sums only; the
+// chunk then publishes one aggregate and looks back once over the chunks
+// before it; pass 2 decodes the chunk's tiles in order with the prefix
+// known, re-reading their bytes (mostly from cache).  One look-back per
+// chunk instead of one per tile, and none of pass 2 waits on other
+// workgroups.
+template <int D, int SEGS>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4 : 8))) void k_chunks(StreamArgs a) {
+    constexpr bool DELTA = D != 0;
+    extern __shared__ __align__(16) u32 lds[];
+    __shared__ WgShared sh;
+    const u32 tid = threadIdx.x;
+    const u32 ln = lane_id();
+    const u32 wib = tid >> 6;
+    const u32 wpb = blockDim.x >> 6;
+    u32 *stage = lds + wib * kStageWords;
+    const u32 chunk = blockIdx.x, nch = gridDim.x;
+    if (tid == 0) sh.epoch = (u32)aload(a.hdr);
+    __syncthreads();
+    const u32 epoch = sh.epoch;
+    const u64 tb = (u64)wpb * SEGS * kSegBytes;
+    const u64 t0 = (u64)chunk * a.ntiles / nch, t1 = (u64)(chunk + 1) * a.ntiles / nch;
+    TileIn t{};
+    t.base = a.base;
+    t.vstart = a.vstart;
+    t.vend = a.vend;
+    t.out = a.out;
+    t.n = a.n;
+    t.prev = a.prev;
+    t.desc = a.desc;
+    t.tag = make_tag(epoch);
+
+    // pass 1: this wavefront's count and sum over the chunk
+    u64 cc = 0;
+    u32 cs = 0;
+    bool cm = false;
+    for (u64 ti = t0; ti < t1; ++ti) {
+        t.tv = ti * tb;
+        const bool interior = ti > 0 && t.tv + tb + 4 <= a.vend;
+        const TileOut g = interior ? run_tile<D, kAgg, SEGS, false>(t, stage, sh, wib, wpb)
+                                   : run_tile<D, kAgg, SEGS, true>(t, stage, sh, wib, wpb);
+        cc += g.total;
+        cs += g.sum;
+        cm |= g.mal;
+    }
+    if (ln == 0) {
+        sh.wcnt[wib] = (u32)cc;
+        sh.wsum[wib] = cs;
+        sh.wmal[wib] = cm ? 1u : 0u;
+    }
+    __syncthreads();
+    const TileSum csum = tile_sum(sh, wpb);
+    if (wib == 0) {
+        Prefix ex;
+        if (chunk == 0) {
+            ex = Prefix{0, a.prev, false};
+        } else {
+            if (ln == 0) publish<DELTA>(&a.desc[chunk], t.tag, false, csum.mal, csum.c, csum.s);
+            ex = lookback<DELTA>(a.desc, chunk, 0, t.tag);
+        }
+        if (ln == 0) {
+            publish<DELTA>(&a.desc[chunk], t.tag, true, ex.mal || csum.mal, ex.c + csum.c,
+                           ex.s + csum.s);
+            sh.excl_c = ex.c;
+            sh.excl_s = ex.s;
+            sh.excl_mal = ex.mal ? 1u : 0u;
+        }
+    }
+    __syncthreads();
+    t.known_c = sh.excl_c;
+    t.known_s = sh.excl_s;
+    t.known_mal = sh.excl_mal != 0;
+
+    // pass 2: decode the chunk's tiles in order
+    TileOut r{t.known_c, t.known_mal, t.known_s};
+    for (u64 ti = t0; ti < t1; ++ti) {
+        t.tv = ti * tb;
+        const bool interior = ti > 0 && t.tv + tb + 4 <= a.vend;
+        r = interior ? run_tile<D, kKnown, SEGS, false>(t, stage, sh, wib, wpb)
+                     : run_tile<D, kKnown, SEGS, true>(t, stage, sh, wib, wpb);
+        t.known_c = r.total;
+        t.known_s = r.sum;
+        t.known_mal = r.mal;
+    }
+    if (chunk == nch - 1 && tid == 0) {
+        const u8 last = a.base[a.vend - 1];
+        *a.d_status = final_status(r.mal, last, r.total, a.n);
+        // the last chunk's look-back has ended: every chunk has read the epoch
         astore(a.hdr, (u64)epoch + 1);
     }
 }
@@ -995,8 +1106,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
             t.tv = ti * tb;
             t.didx = t.dfirst + (i64)ti;
             const bool interior = ti > 0 && t.tv + tb + 4 <= t.vend;
-            const TileOut r = interior ? run_tile<D, false, SEGS, false>(t, stage, sh, wib, wpb)
-                                       : run_tile<D, false, SEGS, true>(t, stage, sh, wib, wpb);
+            const TileOut r = interior ? run_tile<D, kFull, SEGS, false>(t, stage, sh, wib, wpb)
+                                       : run_tile<D, kFull, SEGS, true>(t, stage, sh, wib, wpb);
             if (ti == tiles - 1 && tid == 0)
                 a.list_status[li] = final_status(r.mal, t.base[t.vend - 1], r.total, t.n);
         }
@@ -1171,6 +1282,20 @@ hipError_t launch_stream_t(const StreamArgs &a, int wpb, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int D, int SEGS>
+hipError_t launch_chunks_t(const StreamArgs &a, int wpb, u32 nchunks, hipStream_t s) {
+    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
+    k_chunks<D, SEGS><<<nchunks, wpb * kWave, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int SEGS>
+hipError_t launch_chunks_s(const StreamArgs &a, int delta, int wpb, u32 nchunks, hipStream_t s) {
+    if (delta == 2) return launch_chunks_t<2, SEGS>(a, wpb, nchunks, s);
+    if (delta) return launch_chunks_t<1, SEGS>(a, wpb, nchunks, s);
+    return launch_chunks_t<0, SEGS>(a, wpb, nchunks, s);
+}
+
 template <int SEGS>
 hipError_t launch_stream_s(const StreamArgs &a, int delta, int count_only, int wpb, hipStream_t s) {
     if (count_only) return launch_stream_t<0, true, SEGS>(a, wpb, s);
@@ -1205,6 +1330,16 @@ hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int seg
         case 1: return launch_stream_s<1>(a, delta, count_only, wpb, s);
         case 2: return launch_stream_s<2>(a, delta, count_only, wpb, s);
         case 4: return launch_stream_s<4>(a, delta, count_only, wpb, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_chunks(const StreamArgs &a, int delta, int segs, int wpb, uint32_t nchunks,
+                         hipStream_t s) {
+    switch (segs) {
+        case 1: return launch_chunks_s<1>(a, delta, wpb, nchunks, s);
+        case 2: return launch_chunks_s<2>(a, delta, wpb, nchunks, s);
+        case 4: return launch_chunks_s<4>(a, delta, wpb, nchunks, s);
         default: return hipErrorInvalidValue;
     }
 }

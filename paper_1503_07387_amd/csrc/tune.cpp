@@ -3,9 +3,10 @@
 //
 // It times the caller's own workload under every candidate tiling with HIP
 // events on the caller's stream, keeps the fastest and applies it with
-// vbyte_set_tuning.  Candidates: 1 KiB segments per wavefront {1, 2, 4} x
-// wavefronts per workgroup {2, 4, 6, 8} for a single stream; for the batched
-// form {2, 4} x {4, 8} x small-list threshold {4, 16, 64, 256} KiB.  The
+// vbyte_set_tuning / vbyte_set_chunk_tiles.  Candidates: 1 KiB segments per
+// wavefront {2, 4} x wavefronts per workgroup {4, 8} x tiles per chunk
+// {0, 2, 4, 8, 16} for a single stream; for the batched form {2, 4} x
+// {4, 8} x small-list threshold {4, 16, 64, 256} KiB.  The
 // tuning is process-wide, so no other decode should run meanwhile.
 
 #include <hip/hip_runtime.h>
@@ -20,6 +21,7 @@ namespace {
 struct Cand {
     int segs, wpb;
     int64_t small;
+    int chunk;
 };
 
 // Times `reps` calls of fn() on stream s (after one untimed call); the mean
@@ -52,6 +54,7 @@ vbyte_status tune(const Cand *cands, int ncand, F call, C check, int reps, hipSt
     int segs0, wpb0;
     int64_t small0;
     vbyte_get_tuning(&segs0, &wpb0, &small0);
+    const int chunk0 = vbyte_get_chunk_tiles();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -65,13 +68,15 @@ vbyte_status tune(const Cand *cands, int ncand, F call, C check, int reps, hipSt
     size_t written = 0;
     for (int i = 0; i < ncand && st == VBYTE_OK; ++i) {
         st = vbyte_set_tuning(cands[i].segs, cands[i].wpb, cands[i].small);
+        if (st == VBYTE_OK) st = vbyte_set_chunk_tiles(cands[i].chunk);
         double ms = 0;
         if (st == VBYTE_OK) st = time_calls(call, reps, s, e0, e1, &ms);
         int32_t data = VBYTE_OK;
         if (st == VBYTE_OK) st = check(&data);
         if (st != VBYTE_OK) break;
         if (points && (size_t)i < max_points) {
-            points[i] = vbyte_tune_point{cands[i].segs, cands[i].wpb, cands[i].small, ms, data};
+            points[i] = vbyte_tune_point{cands[i].segs, cands[i].wpb, cands[i].small,
+                                         cands[i].chunk, ms, data};
             written = (size_t)i + 1;
         }
         if (data != VBYTE_OK) {
@@ -88,9 +93,11 @@ vbyte_status tune(const Cand *cands, int ncand, F call, C check, int reps, hipSt
     if (npoints) *npoints = written;
     if (st != VBYTE_OK || best < 0) {
         (void)vbyte_set_tuning(segs0, wpb0, small0);
+        (void)vbyte_set_chunk_tiles(chunk0);
         return st != VBYTE_OK ? st : VBYTE_EINVAL;
     }
-    return vbyte_set_tuning(cands[best].segs, cands[best].wpb, cands[best].small);
+    const vbyte_status fin = vbyte_set_chunk_tiles(cands[best].chunk);
+    return fin != VBYTE_OK ? fin : vbyte_set_tuning(cands[best].segs, cands[best].wpb, cands[best].small);
 }
 
 }  // namespace
@@ -105,10 +112,11 @@ vbyte_status vbyte_autotune_decode(const uint8_t *bytes, size_t nbytes, uint32_t
     hipStream_t s = (hipStream_t)stream;
     int64_t small = 0;
     vbyte_get_tuning(nullptr, nullptr, &small);
-    Cand cands[12];
+    Cand cands[20];
     int nc = 0;
-    for (int segs : {1, 2, 4})
-        for (int wpb : {2, 4, 6, 8}) cands[nc++] = Cand{segs, wpb, small};
+    for (int segs : {2, 4})
+        for (int wpb : {4, 8})
+            for (int chunk : {0, 2, 4, 8, 16}) cands[nc++] = Cand{segs, wpb, small, chunk};
     auto call = [&]() {
         return delta ? vbyte_decode_delta_async(bytes, nbytes, out, n, 0, d_status, s)
                      : vbyte_decode_async(bytes, nbytes, out, n, d_status, s);
@@ -132,7 +140,8 @@ vbyte_status vbyte_autotune_batch(const uint8_t *bytes, size_t nbytes, const int
     int nc = 0;
     for (int segs : {2, 4})
         for (int wpb : {4, 8})
-            for (int64_t small : {4096, 16384, 65536, 262144}) cands[nc++] = Cand{segs, wpb, small};
+            for (int64_t small : {4096, 16384, 65536, 262144})
+                cands[nc++] = Cand{segs, wpb, small, vbyte_get_chunk_tiles()};
     auto call = [&]() {
         return vbyte_decode_batch(bytes, nbytes, byte_off, out, nout, out_off, nlists, nullptr,
                                   delta, d_list_status, s);

@@ -105,6 +105,10 @@ struct EncodeArgs {
 hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int segs, int wpb,
                          hipStream_t s);
 hipError_t launch_batch(const ListArgs &a, int segs, int wpb, int grid_blocks, hipStream_t s);
+// Chunked single-stream decode: a.ntiles tiles in nchunks chunks (one
+// descriptor per chunk).
+hipError_t launch_chunks(const StreamArgs &a, int delta, int segs, int wpb, uint32_t nchunks,
+                         hipStream_t s);
 hipError_t launch_encode(const EncodeArgs &a, hipStream_t s);
 hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
                                 uint64_t nb, hipStream_t s);

@@ -28,14 +28,15 @@ EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_encode_batch", "vbyte_server_create", "vbyte_server_destroy",
            "vbyte_server_run", "vbyte_batch_graph_create", "vbyte_batch_graph_launch",
            "vbyte_batch_graph_destroy", "vbyte_autotune_decode", "vbyte_autotune_batch",
+           "vbyte_set_chunk_tiles", "vbyte_get_chunk_tiles",
            "vbyte_workspace_size", "vbyte_set_tuning", "vbyte_get_tuning",
            "vbyte_status_str", "vbyte_last_error"]
 
 
 class TunePoint(ctypes.Structure):
     _fields_ = [("segs_per_wave", ctypes.c_int), ("waves_per_block", ctypes.c_int),
-                ("small_list_bytes", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("status", ctypes.c_int32)]
+                ("small_list_bytes", ctypes.c_int64), ("tiles_per_chunk", ctypes.c_int),
+                ("ms", ctypes.c_double), ("status", ctypes.c_int32)]
 
 
 class VByteError(RuntimeError):
@@ -85,6 +86,7 @@ def _declare(lib):
         "vbyte_encode_delta_async": [vp, sz, u32, vp, sz, vp, vp],
         "vbyte_encode_batch": [vp, sz, vp, sz, vp, sz, vp, vp, vp],
         "vbyte_set_tuning": [i32, i32, i64],
+        "vbyte_set_chunk_tiles": [i32],
         "vbyte_batch_graph_create": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, c.POINTER(vp)],
         "vbyte_batch_graph_launch": [vp, vp],
         "vbyte_autotune_decode": [vp, sz, vp, sz, i32, i32, vp, c.POINTER(TunePoint), sz,
@@ -96,6 +98,8 @@ def _declare(lib):
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = c.c_int
+    lib.vbyte_get_chunk_tiles.argtypes = []
+    lib.vbyte_get_chunk_tiles.restype = c.c_int
     lib.vbyte_batch_graph_destroy.argtypes = [vp]
     lib.vbyte_batch_graph_destroy.restype = None
     lib.vbyte_workspace_size.argtypes = [sz]
@@ -253,7 +257,8 @@ class BatchGraph:
 
 def _points(arr, n):
     return [{"segs_per_wave": p.segs_per_wave, "waves_per_block": p.waves_per_block,
-             "small_list_bytes": p.small_list_bytes, "ms": p.ms, "status": p.status}
+             "small_list_bytes": p.small_list_bytes, "tiles_per_chunk": p.tiles_per_chunk,
+             "ms": p.ms, "status": p.status}
             for p in arr[:n]]
 
 
@@ -339,15 +344,20 @@ def encode_batch(values, vals_off, *, stream=None):
     return out[: int(nbytes.item())], byte_off[: nlists + 1]
 
 
-def set_tuning(segs_per_wave=0, waves_per_block=0, small_list_bytes=0):
+def set_tuning(segs_per_wave=0, waves_per_block=0, small_list_bytes=0, tiles_per_chunk=None):
+    """Set the kernel tuning (0 keeps a value); tiles_per_chunk selects the
+    single-stream kernel (0: per-tile look-back, k: chunks of k tiles)."""
     _check_call(_lib().vbyte_set_tuning(int(segs_per_wave), int(waves_per_block),
                                         int(small_list_bytes)), "set_tuning")
+    if tiles_per_chunk is not None:
+        _check_call(_lib().vbyte_set_chunk_tiles(int(tiles_per_chunk)), "set_chunk_tiles")
 
 
 def get_tuning():
     a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
     _lib().vbyte_get_tuning(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
-    return {"segs_per_wave": a.value, "waves_per_block": b.value, "small_list_bytes": c.value}
+    return {"segs_per_wave": a.value, "waves_per_block": b.value, "small_list_bytes": c.value,
+            "tiles_per_chunk": int(_lib().vbyte_get_chunk_tiles())}
 
 
 def workspace_size(nbytes):

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 def restore_tuning():
     t = vbyte.get_tuning()
     yield
-    vbyte.set_tuning(t["segs_per_wave"], t["waves_per_block"], t["small_list_bytes"])
+    vbyte.set_tuning(**t)
 
 
 def make_lists(rng, lens, lengths=(1, 2, 3, 4, 5)):

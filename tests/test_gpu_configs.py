@@ -33,8 +33,17 @@ def test_config1_uniform_lengths():
     assert np.array_equal(y, yo) and np.array_equal(y, x)
 
 
+@pytest.fixture
+def chunked_tuning():
+    t = vbyte.get_tuning()
+    yield
+    vbyte.set_tuning(**t)
+
+
+@pytest.mark.parametrize("chunk", [0, 2, 8])
 @pytest.mark.parametrize("mean", [8, 300])
-def test_config2_differential_streams(mean):
+def test_config2_differential_streams(mean, chunk, chunked_tuning):
+    vbyte.set_tuning(tiles_per_chunk=chunk)
     g = workloads.geometric_gaps(mean=mean)
     b = oracle.encode(g)
     expect_bpi = {8: 1.0, 300: 1.6544}[mean]
@@ -76,7 +85,9 @@ def mix():
     return x, b
 
 
-def test_config5_plain(mix):
+@pytest.mark.parametrize("chunk", [0, 16])
+def test_config5_plain(mix, chunk, chunked_tuning):
+    vbyte.set_tuning(tiles_per_chunk=chunk)
     x, b = mix
     assert abs(b.size / x.size - 1.675) < 0.002
     st, y = _decode(b, x.size)

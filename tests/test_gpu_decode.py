@@ -14,11 +14,14 @@ pytestmark = pytest.mark.gpu
 DEFAULT_TUNING = None
 
 
-@pytest.fixture(autouse=True)
-def restore_tuning():
+@pytest.fixture(autouse=True, params=[0, 3], ids=["tile_lookback", "chunks_of_3"])
+def restore_tuning(request):
+    """Every test runs with both single-stream kernels: one look-back per
+    tile, and chunks of 3 tiles per workgroup."""
     t = vbyte.get_tuning()
+    vbyte.set_tuning(tiles_per_chunk=request.param)
     yield
-    vbyte.set_tuning(t["segs_per_wave"], t["waves_per_block"], t["small_list_bytes"])
+    vbyte.set_tuning(**t)
 
 
 def test_table1_and_fig1():

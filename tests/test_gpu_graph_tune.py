@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 def restore_tuning():
     t = vbyte.get_tuning()
     yield
-    vbyte.set_tuning(t["segs_per_wave"], t["waves_per_block"], t["small_list_bytes"])
+    vbyte.set_tuning(**t)
 
 
 def csr_lists(seed, nlists=400):
@@ -107,11 +107,13 @@ def test_autotune_decode_applies_fastest():
     b = oracle.encode(g)
     bd = torch.from_numpy(b).cuda()
     pts = vbyte.autotune_decode(bd, g.size, delta=True, reps=2)
-    assert len(pts) == 12
+    assert len(pts) == 20
+    assert {p["tiles_per_chunk"] for p in pts} == {0, 2, 4, 8, 16}
     assert all(p["status"] == vbyte.OK and p["ms"] > 0 for p in pts)
     best = min(pts, key=lambda p: p["ms"])
     t = vbyte.get_tuning()
-    assert (t["segs_per_wave"], t["waves_per_block"]) == (best["segs_per_wave"], best["waves_per_block"])
+    keys = ("segs_per_wave", "waves_per_block", "tiles_per_chunk")
+    assert {k: t[k] for k in keys} == {k: best[k] for k in keys}
     out = vbyte.decode(bd, g.size, delta=True)
     st, yo = oracle.decode_delta(b, g.size, 0)
     assert st == oracle.OK and np.array_equal(u32(out), yo)
@@ -127,7 +129,8 @@ def test_autotune_batch_applies_fastest():
     assert all(p["status"] == vbyte.OK for p in pts)
     best = min(pts, key=lambda p: p["ms"])
     t = vbyte.get_tuning()
-    assert t == {k: best[k] for k in ("segs_per_wave", "waves_per_block", "small_list_bytes")}
+    keys = ("segs_per_wave", "waves_per_block", "small_list_bytes")
+    assert {k: t[k] for k in keys} == {k: best[k] for k in keys}
     out, st = vbyte.decode_batch(bd, bo, oo, delta=True)
     torch.cuda.synchronize()
     sto, yo, _ = oracle.decode_batch(b, byte_off, out_off, None, True)
@@ -150,9 +153,10 @@ def test_autotune_cache_roundtrip(tmp_path):
     bd = torch.from_numpy(oracle.encode(g)).cuda()
     path = str(tmp_path / "tune.json")
     e1, pts = autotune.tune_stream(bd, g.size, delta=True, path=path, reps=1)
-    assert pts is not None and len(pts) == 12
-    vbyte.set_tuning(1, 2, 4096)
+    assert pts is not None and len(pts) == 20
+    vbyte.set_tuning(1, 2, 4096, tiles_per_chunk=0)
     e2, pts2 = autotune.tune_stream(bd, g.size, delta=True, path=path)
     assert pts2 is None and e2 == e1
     t = vbyte.get_tuning()
-    assert (t["segs_per_wave"], t["waves_per_block"]) == (e1["segs_per_wave"], e1["waves_per_block"])
+    keys = ("segs_per_wave", "waves_per_block", "tiles_per_chunk")
+    assert {k: t[k] for k in keys} == {k: e1[k] for k in keys}

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 def restore_tuning():
     t = vbyte.get_tuning()
     yield
-    vbyte.set_tuning(t["segs_per_wave"], t["waves_per_block"], t["small_list_bytes"])
+    vbyte.set_tuning(**t)
 
 
 def decode_m1(b, n, prev=0, boff=0, ooff=0):
@@ -40,11 +40,11 @@ def check(b, n, prev=0, boff=0, ooff=0):
         assert np.array_equal(y, yo), f"first mismatch at {np.nonzero(y != yo)[0][:1]}"
 
 
-@pytest.mark.parametrize("tiling", [(4, 8), (1, 2), (2, 4)])
+@pytest.mark.parametrize("tiling", [(4, 8, 0), (1, 2, 0), (2, 4, 0), (4, 8, 4), (2, 4, 2)])
 @pytest.mark.parametrize("kind", ["mixed", "ones", "gaps300"])
 @pytest.mark.parametrize("n", [1, 777, 40_000, 300_001])
 def test_stream_m1(tiling, kind, n):
-    vbyte.set_tuning(tiling[0], tiling[1], 0)
+    vbyte.set_tuning(tiling[0], tiling[1], 0, tiles_per_chunk=tiling[2])
     rng = np.random.default_rng(n + len(kind))
     if kind == "mixed":
         g = mixed_values(rng, n)
@@ -131,8 +131,10 @@ def test_batch_and_graph_m1(small):
         g.close()
 
 
+@pytest.mark.parametrize("chunk", [0, 4])
 @pytest.mark.parametrize("mean", [8, 300])
-def test_full_size_stream_m1(mean):
+def test_full_size_stream_m1(mean, chunk):
+    vbyte.set_tuning(tiles_per_chunk=chunk)
     g = workloads.geometric_gaps(mean=mean)
     b = oracle.encode(g)
     d = torch.from_numpy(b).cuda()
