@@ -87,6 +87,11 @@ def _declare(lib):
     lib.orc_encode_delta_m1.argtypes = [c.POINTER(c.c_uint32), c.c_size_t, c.c_uint32,
                                         c.POINTER(c.c_uint8)]
     lib.orc_encode_delta_m1.restype = c.c_size_t
+    lib.orc_decode_next.argtypes = [c.POINTER(c.c_uint8), c.c_size_t, c.c_size_t, c.c_size_t,
+                                    c.c_uint32, c.c_int, c.POINTER(c.c_uint32),
+                                    c.POINTER(c.c_size_t), c.POINTER(c.c_size_t),
+                                    c.POINTER(c.c_uint32)]
+    lib.orc_decode_next.restype = c.c_int
     lib.orc_decode_batch.argtypes = [c.POINTER(c.c_uint8), c.POINTER(c.c_int64),
                                      c.POINTER(c.c_uint32), c.POINTER(c.c_int64),
                                      c.c_size_t, c.POINTER(c.c_uint32), c.c_int,
@@ -182,6 +187,18 @@ def encode_delta_m1(x, prev=0, lib=None):
     out = np.zeros(max(5 * x.size, 1), dtype=np.uint8)
     m = lib.orc_encode_delta_m1(_u32p(x), x.size, int(prev) & 0xFFFFFFFF, _u8p(out))
     return out[:m].copy()
+
+
+def decode_next(b, off, k, prev=0, delta=0, lib=None):
+    """One resumable piece of at most k integers from byte off (reading R12).
+    Returns (status, values, next_off, next_prev)."""
+    lib = lib or load()
+    b = _as_u8(b)
+    y = np.zeros(max(int(k), 1), dtype=np.uint32)
+    no, m, npv = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_uint32(0)
+    st = lib.orc_decode_next(_u8p(b), b.size, int(off), int(k), int(prev) & 0xFFFFFFFF, int(delta),
+                             _u32p(y), ctypes.byref(no), ctypes.byref(m), ctypes.byref(npv))
+    return int(st), y[:m.value].copy(), int(no.value), int(npv.value)
 
 
 def decode_batch(b, byte_off, out_off, prevs=None, delta=False, lib=None):

@@ -31,6 +31,9 @@
  *   R11 differences minus one: only differences after the first are
  *       reduced, as in the section's example x_1 - 0, x_2 - x_1 - 1; a
  *       stream continued from an earlier piece passes prev + 1.
+ *   R12 a resumable piece of k integers is validated over its window of
+ *       5k bytes (or the rest of the buffer); its cursor moves only on
+ *       success.
  *   R6  exact consumption: the buffer must hold exactly n codes ending at
  *       its last byte; a last byte >= 0x80 or fewer than n terminators ->
  *       ETRUNC, more than n terminators -> ECOUNT.  Precedence when several
@@ -213,6 +216,65 @@ size_t orc_encode_delta_m1(const uint32_t *x, size_t n, uint32_t prev, uint8_t *
         last = x[i];
     }
     return pos;
+}
+
+/* Resumable decode in pieces of at most k integers (section 5 decodes long
+ * lists piece by piece into a buffer that stays in cache; reading R12).
+ * The piece starts at byte off and looks at the window
+ * b[off, off + min(nbytes - off, 5k)), which holds k whole codes whenever
+ * the data is well formed (a code has at most 5 bytes):
+ *   a run of 5 continuation bytes in the window   -> EMALFORMED
+ *   fewer than k codes and the window's last byte continues -> ETRUNC
+ *   otherwise the first m = min(k, codes in window) integers are decoded,
+ *   *next_off is the byte after the m-th code, *m_out = m, and *next_prev
+ *   is the value to pass as prev for the next piece: the last integer
+ *   (plus one for differences minus one), or prev if m = 0.
+ * delta: 0 plain, 1 differences from prev, 2 differences minus one (the
+ * first integer of the piece is prev + g_0).  On an error nothing is
+ * written to the outputs. */
+int orc_decode_next(const uint8_t *b, size_t nbytes, size_t off, size_t k, uint32_t prev,
+                    int delta, uint32_t *y, size_t *next_off, size_t *m_out,
+                    uint32_t *next_prev)
+{
+    if (k == 0 || off > nbytes) return ORC_EINVAL;
+    const uint8_t *p = b + off;
+    size_t w = nbytes - off;
+    if (w / 5 >= k) w = 5 * k;
+    int run = 0;
+    size_t codes = 0;
+    for (size_t i = 0; i < w; i++) {
+        if (p[i] >= 128) {
+            if (++run >= 5) return ORC_EMALFORMED;
+        } else {
+            run = 0;
+            codes++;
+        }
+    }
+    size_t m = codes < k ? codes : k;
+    if (m < k && w > 0 && p[w - 1] >= 128) return ORC_ETRUNC;
+    alg1_decode(p, m, y);
+    size_t used = 0, seen = 0;
+    while (seen < m) {
+        if (p[used] < 128) seen++;
+        used++;
+    }
+    uint32_t id = prev;
+    for (size_t i = 0; i < m; i++) {
+        if (delta == 1) {
+            id = id + y[i];
+            y[i] = id;
+        } else if (delta == 2) {
+            id = id + y[i] + (i > 0 ? 1u : 0u);
+            y[i] = id;
+        }
+    }
+    *next_off = off + used;
+    *m_out = m;
+    if (m == 0)
+        *next_prev = prev;
+    else
+        *next_prev = y[m - 1] + (delta == 2 ? 1u : 0u);
+    return ORC_OK;
 }
 
 /* BATCH (R9): list i is bytes[byte_off[i], byte_off[i+1]) and decodes to

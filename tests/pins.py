@@ -288,6 +288,56 @@ def pin_delta_m1_encode_roundtrip(lib):
     assert oracle.encode_delta_m1(run, 1000, lib=lib).tolist() == [0] * run.size
 
 
+def pin_resumable_pieces(lib):
+    # Reading R12: pieces of k integers, each resumed from the previous
+    # piece's cursor and prev, reproduce the whole-stream decodes, and each
+    # cursor is the canonical size of the values decoded so far.
+    rng = np.random.default_rng(23)
+    x = rng.integers(0, 1 << 32, 3000, dtype=np.uint64).astype(np.uint32)
+    x[rng.random(3000) < 0.5] %= 200
+    b = oracle.encode(x, lib=lib)
+    whole = {0: oracle.decode(b, x.size, lib=lib)[1],
+             1: oracle.decode_delta(b, x.size, 11, lib=lib)[1],
+             2: oracle.decode_delta_m1(b, x.size, 11, lib=lib)[1]}
+    for delta in (0, 1, 2):
+        for k in (1, 7, 1000, 2999, 3000, 5000):
+            off, prev, got = 0, 11, []
+            while True:
+                st, y, nxt, prev = oracle.decode_next(b, off, k, prev, delta, lib=lib)
+                assert st == OK
+                got.append(y)
+                assert nxt == oracle.encoded_size(x[:sum(len(g) for g in got)], lib=lib)
+                if y.size < k:
+                    break
+                off = nxt
+            assert nxt == b.size and y.size == (x.size % k if x.size % k else (0 if k <= x.size else x.size))
+            assert np.array_equal(np.concatenate(got), whole[delta])
+    # a prefix piece equals the head of the whole decode
+    for k in (1, 2, 5, 64):
+        st, y, nxt, _ = oracle.decode_next(b, 0, k, 0, 0, lib=lib)
+        assert st == OK and np.array_equal(y, whole[0][:k])
+
+
+def pin_resumable_errors(lib):
+    b = oracle.encode(np.array([1, 300, 70000, 5], np.uint32), lib=lib)
+    st, *_ = oracle.decode_next(b[:-1] if b[-1] < 128 else b, 0, 10, lib=lib)
+    assert st == OK                                  # the buffer ends on a terminator
+    cut = np.concatenate([b, [0x85, 0x81]]).astype(np.uint8)   # then an unfinished code
+    st, y, nxt, _ = oracle.decode_next(cut, 0, 4, lib=lib)
+    assert st == OK and y.size == 4 and nxt == b.size          # k codes found first
+    st, *_ = oracle.decode_next(cut, 0, 5, lib=lib)
+    assert st == ETRUNC
+    bad = np.concatenate([b, [0x80] * 5, [0x01]]).astype(np.uint8)
+    st, *_ = oracle.decode_next(bad, 0, 4, lib=lib)
+    assert st == EMALFORMED                          # the run lies in the 5k-byte window
+    st, y, nxt, _ = oracle.decode_next(bad, 0, 1, lib=lib)
+    assert st == OK and y.tolist() == [1]            # window of 5 bytes: no run inside
+    assert oracle.decode_next(b, 0, 0, lib=lib)[0] == EINVAL
+    assert oracle.decode_next(b, b.size + 1, 3, lib=lib)[0] == EINVAL
+    st, y, nxt, pv = oracle.decode_next(b, b.size, 3, 9, 1, lib=lib)
+    assert st == OK and y.size == 0 and nxt == b.size and pv == 9
+
+
 # ---------------------------------------------------------------- status readings
 # (bytes, n, expected status); the expectations follow readings R3-R6.
 STATUS_CASES = [
@@ -385,5 +435,6 @@ ALL_PINS = [pin_table1, pin_fig1, pin_closed_form_boundaries, pin_length_closed_
             pin_five_byte_algebra, pin_protobuf_exhaustive_21, pin_protobuf_random_wide,
             pin_canonical_bijection, pin_random_wide_roundtrip, pin_delta_cumsum,
             pin_delta_encode_roundtrip, pin_resumable, pin_delta_m1_closed_form,
-            pin_delta_m1_encode_roundtrip, pin_status_readings,
+            pin_delta_m1_encode_roundtrip, pin_resumable_pieces, pin_resumable_errors,
+            pin_status_readings,
             pin_fifth_byte_wrap, pin_overlong, pin_batch]

@@ -39,6 +39,11 @@ MUTANTS = [
     ("m1_first_too", "uint32_t step = y[k] + (k > 0 ? 1u : 0u);", "uint32_t step = y[k] + 1u;"),
     ("m1_no_one", "uint32_t step = y[k] + (k > 0 ? 1u : 0u);", "uint32_t step = y[k];"),
     ("encm1_first_too", "uint32_t gap = x[i] - last - (i > 0 ? 1u : 0u);", "uint32_t gap = x[i] - last - 1u;"),
+    ("next_window_4k", "if (w / 5 >= k) w = 5 * k;", "if (w / 4 >= k) w = 4 * k;"),
+    ("next_cursor_plus1", "*next_off = off + used;", "*next_off = off + used + 1;"),
+    ("next_m1_first", "id = id + y[i] + (i > 0 ? 1u : 0u);", "id = id + y[i] + 1u;"),
+    ("next_prev_no_one", "*next_prev = y[m - 1] + (delta == 2 ? 1u : 0u);", "*next_prev = y[m - 1];"),
+    ("next_trunc_ignored", "if (m < k && w > 0 && p[w - 1] >= 128) return ORC_ETRUNC;", "(void)0;"),
     ("batch_m1_as_delta", "int st = delta == 2 ? orc_decode_delta_m1(b, nb, y, n, prev)",
      "int st = delta == 3 ? orc_decode_delta_m1(b, nb, y, n, prev)"),
     ("batch_no_einval", "return ORC_EINVAL;\n    }\n    int worst", "(void)0;\n    }\n    int worst"),
