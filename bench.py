@@ -446,7 +446,7 @@ def main():
     def step(events=None):
         for i, s in enumerate(streams):
             t = tunings[i]
-            vbyte.set_tuning(t["segs_per_wave"], t["waves_per_block"], t["small_list_bytes"])
+            vbyte.set_tuning(**t)
             if events is not None:
                 events[i][0].record(stream)
             vbyte.decode(s["bytes"], N_STREAM, delta=True, prev=0, out=s["out"],

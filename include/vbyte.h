@@ -98,6 +98,35 @@ vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, ui
                                          size_t n, uint32_t prev, int32_t *d_status,
                                          void *stream);
 
+/* Resumable decode in pieces (section 5 decodes long lists piece by piece
+ * into a buffer that stays in cache): each call decodes the next piece of at
+ * most k integers of bytes[0..nbytes) into out[0..k), starting where the
+ * cursor *d_in points, and writes the advanced cursor to *d_out.  Both
+ * cursors live in device memory and the call never synchronizes, so a
+ * caller can chain pieces (alternating two cursors) with a consumer of
+ * out[] between them.
+ *   vbyte_cursor: byte_offset = first byte of the piece; decoded = integers
+ *     decoded by all pieces so far; prev = the start value of the piece's
+ *     differences (low 32 bits; set it to the list's prev before the first
+ *     piece).  On success the piece's integers are out[0..m) with
+ *     m = d_out->decoded - d_in->decoded; m < k only at the end of the data.
+ *   delta: 0 plain, 1 differences, 2 differences minus one.
+ *   d_status: device int32: VBYTE_OK, or VBYTE_EMALFORMED for a run of 5
+ *     continuation bytes within the piece's window of 5k bytes,
+ *     VBYTE_ETRUNC when the data ends inside a code before k integers,
+ *     VBYTE_EINVAL when the cursor lies past nbytes; on an error *d_out is
+ *     a copy of *d_in.
+ * d_in and d_out must differ.  Pieces of one stream must run in order (one
+ * stream).  Always uses one look-back per tile. */
+typedef struct vbyte_cursor {
+    uint64_t byte_offset;
+    uint64_t decoded;
+    uint64_t prev;
+} vbyte_cursor;
+vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t k,
+                                     int delta, const vbyte_cursor *d_in, vbyte_cursor *d_out,
+                                     int32_t *d_status, void *stream);
+
 /* Number of terminator bytes (top bit 0) in bytes[0..nbytes), i.e. the
  * number of codes a valid stream holds (section 1: one terminator per
  * integer).  Written to the device word *d_count. */

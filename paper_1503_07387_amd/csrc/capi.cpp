@@ -38,9 +38,11 @@ vbyte_status hip_fail(hipError_t e, const char *what) {
 //   [0, 24)     epoch word and the two batched queue words
 //   [64, 68)    status slot used by the synchronous calls
 //   [128, 152)  batch totals (3 x uint64)
+//   [192, 208)  resumable piece: offset of the code of rank k, code count
 //   [256, ...)  descriptors, then batch tables
 constexpr size_t kStatusOff = 64;
 constexpr size_t kTotalsOff = 128;
+constexpr size_t kPieceOff = 192;   // resumable pieces: rank-n offset and code count
 
 struct Workspace {
     void *ptr = nullptr;
@@ -260,6 +262,48 @@ vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, ui
                                          size_t n, uint32_t prev, int32_t *d_status,
                                          void *stream) {
     return decode_stream(bytes, nbytes, out, n, prev, 2, d_status, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t k,
+                                     int delta, const vbyte_cursor *d_in, vbyte_cursor *d_out,
+                                     int32_t *d_status, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (k == 0 || k > (1ull << 40) || !out || ((uintptr_t)out & 3u)) return VBYTE_EINVAL;
+    if (!d_in || !d_out || d_in == d_out || ((uintptr_t)d_in & 7u) || ((uintptr_t)d_out & 7u))
+        return VBYTE_EINVAL;
+    if (!d_status || ((uintptr_t)d_status & 3u)) return VBYTE_EINVAL;
+    if (delta < 0 || delta > 2) return VBYTE_EINVAL;
+    if (nbytes >= kMaxBytes || (nbytes > 0 && !bytes)) return VBYTE_EINVAL;
+    const int segs = g_segs.load(), wpb = g_wpb.load();
+    const uint64_t window = 5ull * k;
+    const uint64_t span = nbytes < window ? nbytes : window;
+    // tiles for the widest piece at the worst misalignment of its start
+    const uint64_t ntiles = stream_tiles(15, span > 0 ? span : 1, segs, wpb);
+    if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, kHeaderBytes + ntiles * sizeof(Desc), 1, &w);
+    if (st != VBYTE_OK) return st;
+    uint64_t *scratch = (uint64_t *)(ws_base(w) + kPieceOff);
+    const uint64_t *cin = (const uint64_t *)d_in;
+    StreamArgs a{};
+    const uint8_t *p = nbytes ? bytes : (const uint8_t *)d_in;   // any readable address
+    a.vstart = (uintptr_t)p & 15u;
+    a.base = p - a.vstart;
+    a.vend = a.vstart + nbytes;
+    a.out = out;
+    a.n = k;
+    a.ntiles = (uint32_t)ntiles;
+    a.hdr = (uint64_t *)ws_base(w);
+    a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
+    a.d_status = d_status;
+    a.cursor_in = cin;
+    a.window = window;
+    a.scratch = scratch;
+    hipError_t e = launch_stream(a, delta, 0, segs, wpb, s);
+    if (e != hipSuccess) return hip_fail(e, "piece launch");
+    e = launch_resume_finish(bytes, cin, (uint64_t *)d_out, scratch, d_status, out, k, nbytes,
+                             window, delta, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "cursor update");
 }
 
 vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count, void *stream) {

@@ -518,6 +518,8 @@ struct TileIn {
     u64 known_c;
     u32 known_s;
     bool known_mal;
+    // resumable pieces: receives the offset (from vstart) of the code of rank n
+    u64 *pos_out;
 };
 
 struct TileOut {
@@ -545,6 +547,8 @@ struct WgShared {
     u32 excl_mal;
     u32 epoch;
     u64 item;
+    u64 cur;    // resumable pieces: the piece's first byte and its prev
+    u32 cprev;
 };
 
 // Totals of the tile's wavefronts, read from `sh`.
@@ -690,6 +694,19 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
         const u64 gbase = exc + wex_c + segbase[s];
+        if (t.pos_out && gbase <= t.n && t.n < gbase + segcnt[s]) {
+            // The code of rank n begins in this segment: where a resumed
+            // piece starts.  Its lane is found by a scan of the lanes'
+            // counts, its byte as the right set bit of the lane's mask.
+            const u32 kk = (u32)(t.n - gbase);
+            const u32 cnt = __builtin_popcount(emit[s]);
+            const u32 ci = wave_scan(cnt);
+            if (kk >= ci - cnt && kk < ci) {
+                u32 e = emit[s];
+                for (u32 q = kk - (ci - cnt); q > 0; --q) e &= e - 1u;
+                *t.pos_out = wv + (u64)s * kSegBytes + 16u * ln + (u32)__builtin_ctz(e) - t.vstart;
+            }
+        }
         if (gbase >= t.n || segcnt[s] == 0) continue;
         if (dmask & (1u << s)) {
             *(uint4 *)(rows + 4 * ln) = make_uint4(w[s][0], w[s][1], w[s][2], w[s][3]);
@@ -739,24 +756,45 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     // Tile = workgroup index: workgroups are dispatched in index order, so
     // every tile a look-back waits for is already running.
     const u32 tile = blockIdx.x;
-    if (tid == 0) sh.epoch = (u32)aload(a.hdr);
+    if (tid == 0) {
+        sh.epoch = (u32)aload(a.hdr);
+        if (a.cursor_in) {
+            sh.cur = a.cursor_in[0];
+            sh.cprev = (u32)a.cursor_in[2];
+        }
+    }
     __syncthreads();
     const u32 epoch = sh.epoch;
 
     const u64 tb = (u64)wpb * SEGS * kSegBytes;
-    TileIn t;
+    TileIn t{};
     t.base = a.base;
     t.vstart = a.vstart;
     t.vend = a.vend;
+    t.prev = a.prev;
+    bool bad_cursor = false;
+    if (a.cursor_in) {
+        // the piece: at most `window` bytes from the cursor
+        const u64 total_bytes = a.vend - a.vstart;
+        u64 cur = sh.cur;
+        bad_cursor = cur > total_bytes;
+        if (bad_cursor) cur = total_bytes;
+        const u8 *p0 = a.base + a.vstart + cur;
+        t.base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
+        t.vstart = (u64)(p0 - t.base);
+        const u64 remain = total_bytes - cur;
+        t.vend = t.vstart + (remain < a.window ? remain : a.window);
+        t.prev = sh.cprev;
+        t.pos_out = a.scratch;
+    }
     t.tv = (u64)tile * tb;
     t.out = a.out;
     t.n = a.n;
-    t.prev = a.prev;
     t.desc = a.desc;
     t.didx = tile;
     t.dfirst = 0;
     t.tag = make_tag(epoch);
-    const bool interior = tile > 0 && t.tv + tb + 4 <= a.vend;
+    const bool interior = tile > 0 && t.tv + tb + 4 <= t.vend;
     TileOut r;
     if (interior)
         r = run_tile<D, COUNT ? kCount : kFull, SEGS, false>(t, stage, sh, wib, wpb);
@@ -766,6 +804,15 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     if (tile == a.ntiles - 1 && tid == 0) {
         if (COUNT) {
             *a.d_count = r.total;
+        } else if (a.cursor_in) {
+            // a piece: more codes than n are fine; a short piece that ends
+            // inside a code is truncated
+            a.scratch[1] = r.total;
+            const bool cut = r.total < a.n && t.vend > t.vstart && t.base[t.vend - 1] >= 0x80;
+            *a.d_status = bad_cursor ? VBYTE_EINVAL
+                          : r.mal    ? VBYTE_EMALFORMED
+                          : cut      ? VBYTE_ETRUNC
+                                     : VBYTE_OK;
         } else {
             const u8 last = a.base[a.vend - 1];
             *a.d_status = final_status(r.mal, last, r.total, a.n);
@@ -1089,7 +1136,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
         const u32 sp = (u32)e.y;
         const ListDesc d = list_desc(a, li);
         const u8 *p0 = a.bytes + d.bb;
-        TileIn t;
+        TileIn t{};
         t.base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
         t.vstart = (u64)(p0 - t.base);
         t.vend = t.vstart + (u64)(d.be - d.bb);
@@ -1264,6 +1311,33 @@ __global__ void k_encode_bounds(EncodeArgs a, const int64_t *vals_off, int64_t *
 }
 
 // ------------------------------------------------------------ small kernels
+// Cursor after a resumable piece: on success the piece's first byte moves
+// past the last decoded code (to the code of rank k if there is one, else
+// to the end of the piece's window less an unfinished code at its end) and
+// prev becomes the last integer (plus one for differences minus one); on an
+// error the cursor stays.
+__global__ void k_resume_finish(const u8 *bytes, const u64 *cin, u64 *cout, const u64 *scratch,
+                                const int32_t *d_status, const u32 *out, u64 k, u64 nbytes,
+                                u64 window, int delta) {
+    const u64 cur = cin[0], done = cin[1], prev = cin[2];
+    if (*d_status != VBYTE_OK) {
+        cout[0] = cur;
+        cout[1] = done;
+        cout[2] = prev;
+        return;
+    }
+    const u64 total = scratch[1];
+    const u64 m = total < k ? total : k;
+    const u64 remain = nbytes - cur;
+    const u64 wlen = remain < window ? remain : window;
+    u64 tail = 0;   // continuation bytes that end the window (an unfinished code)
+    while (tail < wlen && tail < 5 && bytes[cur + wlen - 1 - tail] >= 0x80) ++tail;
+    cout[0] = cur + (total > k ? scratch[0] : wlen - tail);
+    cout[1] = done + m;
+    cout[2] = m ? (u64)(out[m - 1] + (delta == 2 ? 1u : 0u)) : prev;
+}
+
+
 __global__ void k_set_status(int32_t *p, int32_t v) { *p = v; }
 __global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
 __global__ void k_fill_i64(int64_t *p, uint64_t n, int64_t v) {
@@ -1365,6 +1439,15 @@ hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, in
                                 uint64_t nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
     k_encode_bounds<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(a, vals_off, byte_off, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_resume_finish(const uint8_t *bytes, const uint64_t *cursor_in, uint64_t *cursor_out,
+                                const uint64_t *scratch, const int32_t *d_status,
+                                const uint32_t *out, uint64_t k, uint64_t nbytes, uint64_t window,
+                                int delta, hipStream_t s) {
+    k_resume_finish<<<1, 1, 0, s>>>(bytes, cursor_in, cursor_out, scratch, d_status, out, k, nbytes,
+                                    window, delta);
     return hipGetLastError();
 }
 

@@ -61,6 +61,14 @@ struct StreamArgs {
     Desc *desc;
     int32_t *d_status;     // may be null (count mode)
     uint64_t *d_count;     // count mode only
+    // Resumable pieces (vbyte_decode_next_async): base/vstart/vend describe
+    // the whole buffer; the piece starts at cursor_in[0] (byte offset), its
+    // prev is cursor_in[2], it looks at most `window` bytes ahead, and the
+    // kernel leaves the byte offset of the code of rank n (relative to the
+    // piece) in scratch[0] and the piece's code count in scratch[1].
+    const uint64_t *cursor_in;
+    uint64_t window;
+    uint64_t *scratch;
 };
 
 // One list of a batched launch, resolved on the device from either CSR
@@ -105,6 +113,11 @@ struct EncodeArgs {
 hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int segs, int wpb,
                          hipStream_t s);
 hipError_t launch_batch(const ListArgs &a, int segs, int wpb, int grid_blocks, hipStream_t s);
+// Cursor update after a resumable piece (one thread).
+hipError_t launch_resume_finish(const uint8_t *bytes, const uint64_t *cursor_in, uint64_t *cursor_out,
+                                const uint64_t *scratch, const int32_t *d_status,
+                                const uint32_t *out, uint64_t k, uint64_t nbytes, uint64_t window,
+                                int delta, hipStream_t s);
 // Chunked single-stream decode: a.ntiles tiles in nchunks chunks (one
 // descriptor per chunk).
 hipError_t launch_chunks(const StreamArgs &a, int delta, int segs, int wpb, uint32_t nchunks,

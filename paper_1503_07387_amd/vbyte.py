@@ -23,7 +23,7 @@ STATUS_NAMES = {OK: "VBYTE_OK", EINVAL: "VBYTE_EINVAL", ECOUNT: "VBYTE_ECOUNT",
 
 EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_decode_delta_async", "vbyte_decode_delta_m1", "vbyte_decode_delta_m1_async",
-           "vbyte_encode_delta_m1_async", "vbyte_count", "vbyte_decode_batch",
+           "vbyte_encode_delta_m1_async", "vbyte_decode_next_async", "vbyte_count", "vbyte_decode_batch",
            "vbyte_decode_lists", "vbyte_encode_async", "vbyte_encode_delta_async",
            "vbyte_encode_batch", "vbyte_server_create", "vbyte_server_destroy",
            "vbyte_server_run", "vbyte_batch_graph_create", "vbyte_batch_graph_launch",
@@ -78,6 +78,7 @@ def _declare(lib):
         "vbyte_decode_delta_async": [vp, sz, vp, sz, u32, vp, vp],
         "vbyte_decode_delta_m1": [vp, sz, vp, sz, u32],
         "vbyte_decode_delta_m1_async": [vp, sz, vp, sz, u32, vp, vp],
+        "vbyte_decode_next_async": [vp, sz, vp, sz, i32, vp, vp, vp, vp],
         "vbyte_encode_delta_m1_async": [vp, sz, u32, vp, sz, vp, vp],
         "vbyte_count": [vp, sz, vp, vp],
         "vbyte_decode_batch": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, vp],
@@ -174,6 +175,34 @@ def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=No
         if v != OK:
             raise VByteError(v, "decode")
     return out[:n]
+
+
+def new_cursor(prev=0, device=None):
+    """A device cursor (int64 tensor of 3: byte offset, decoded, prev) at
+    the start of a stream."""
+    return torch.tensor([0, 0, int(prev) & 0xFFFFFFFF], dtype=torch.int64,
+                        device=device or torch.device("cuda"))
+
+
+def decode_next(data, k, out, cursor_in, cursor_out, *, delta=False, minus_one=False, status=None,
+                stream=None):
+    """Decode the next piece of at most k integers of ``data`` into out[0..k)
+    from ``cursor_in`` and write the advanced cursor to ``cursor_out`` (both
+    int64 CUDA tensors of 3, see new_cursor).  Does not wait; the data status
+    goes to ``status`` (int32 CUDA tensor of one element)."""
+    _dev_u8(data)
+    if out.dtype != torch.int32 or not out.is_contiguous() or out.numel() < int(k):
+        raise ValueError("out must be a contiguous int32 tensor of at least k elements")
+    for c in (cursor_in, cursor_out):
+        if c.dtype != torch.int64 or c.numel() != 3 or not c.is_cuda:
+            raise ValueError("cursors must be int64 CUDA tensors of 3 elements")
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=data.device)
+    st = _lib().vbyte_decode_next_async(_ptr(data), data.numel(), _ptr(out), int(k),
+                                        _mode(delta, minus_one), _ptr(cursor_in), _ptr(cursor_out),
+                                        _ptr(status), _stream(stream))
+    _check_call(st, "decode_next")
+    return status
 
 
 def count(data, *, stream=None, result=None):
