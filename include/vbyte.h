@@ -117,7 +117,8 @@ vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, ui
  *     VBYTE_EINVAL when the cursor lies past nbytes; on an error *d_out is
  *     a copy of *d_in.
  * d_in and d_out must differ.  Pieces of one stream must run in order (one
- * stream).  Always uses one look-back per tile. */
+ * stream).  Always uses one look-back per tile, and at most 2 segments per
+ * wavefront whatever vbyte_set_tuning chose. */
 typedef struct vbyte_cursor {
     uint64_t byte_offset;
     uint64_t decoded;
@@ -297,7 +298,10 @@ void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_l
  * forms): 0 (the default) gives every tile its own look-back; k in 1..64
  * gives each workgroup a chunk of k consecutive tiles, which it first reads
  * for their counts and sums, then looks back once for the chunk, then reads
- * again and decodes.  Returns VBYTE_EINVAL outside 0..64. */
+ * again and decodes; -1 decodes in three launches with no look-back: every
+ * tile's count and sum, a scan of them in one workgroup, then every tile
+ * with its prefix known (the input is read twice).  Returns VBYTE_EINVAL
+ * outside -1..64. */
 vbyte_status vbyte_set_chunk_tiles(int tiles_per_chunk);
 int vbyte_get_chunk_tiles(void);
 
@@ -307,7 +311,7 @@ int vbyte_get_chunk_tiles(void);
  *   vbyte_autotune_decode: single-stream decode of bytes[0, nbytes) into
  *     out[0, n) (plain or delta, prev 0); d_status is a device int32 the
  *     calls write.  Candidates: segs_per_wave {2, 4} x waves_per_block
- *     {4, 8} x tiles_per_chunk {0, 2, 4, 8, 16}.
+ *     {4, 8} x tiles_per_chunk {-1, 0, 2, 4, 8, 16}.
  *   vbyte_autotune_batch: vbyte_decode_batch of the given lists (prevs 0);
  *     d_list_status is device int32[nlists].  Candidates: segs_per_wave
  *     {2, 4} x waves_per_block {4, 8} x small_list_bytes {4, 16, 64, 256} KiB.

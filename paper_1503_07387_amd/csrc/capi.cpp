@@ -27,7 +27,8 @@ thread_local char g_last_error[256] = "";
 std::atomic<int> g_segs{4};
 std::atomic<int> g_wpb{8};
 std::atomic<int64_t> g_small{16384};
-std::atomic<int> g_chunk{0};   // single stream: 0 = per-tile look-back, k = chunks of k tiles
+std::atomic<int> g_chunk{0};   // single stream: 0 = per-tile look-back, k = chunks of k tiles,
+                               // -1 = three launches with no look-back
 
 vbyte_status hip_fail(hipError_t e, const char *what) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
@@ -146,8 +147,9 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
     a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
     a.d_status = d_status;
     a.d_count = nullptr;
-    hipError_t e = chunk > 0 ? launch_chunks(a, delta, segs, wpb, (uint32_t)nchunks, s)
-                             : launch_stream(a, delta, 0, segs, wpb, s);
+    hipError_t e = chunk > 0    ? launch_chunks(a, delta, segs, wpb, (uint32_t)nchunks, s)
+                   : chunk < 0 ? launch_two_pass(a, delta, segs, wpb, s)
+                               : launch_stream(a, delta, 0, segs, wpb, s);
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode launch");
 }
 
@@ -274,7 +276,9 @@ vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32
     if (!d_status || ((uintptr_t)d_status & 3u)) return VBYTE_EINVAL;
     if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     if (nbytes >= kMaxBytes || (nbytes > 0 && !bytes)) return VBYTE_EINVAL;
-    const int segs = g_segs.load(), wpb = g_wpb.load();
+    // at most 2 segments per wavefront: the piece kernel's extra position
+    // search does not fit the 4-segment register budget
+    const int segs = g_segs.load() > 2 ? 2 : g_segs.load(), wpb = g_wpb.load();
     const uint64_t window = 5ull * k;
     const uint64_t span = nbytes < window ? nbytes : window;
     // tiles for the widest piece at the worst misalignment of its start
@@ -465,7 +469,7 @@ vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t sm
 }
 
 vbyte_status vbyte_set_chunk_tiles(int tiles_per_chunk) {
-    if (tiles_per_chunk < 0 || tiles_per_chunk > 64) return VBYTE_EINVAL;
+    if (tiles_per_chunk < -1 || tiles_per_chunk > 64) return VBYTE_EINVAL;
     g_chunk.store(tiles_per_chunk);
     return VBYTE_OK;
 }

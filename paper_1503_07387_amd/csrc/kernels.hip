@@ -500,6 +500,91 @@ __device__ __forceinline__ void store_dense(const u32 *stage, u32 amis, u32 *out
     }
 }
 
+// ------------------------------------------------------------ byte sums
+// The sum of a run of integers in byte form.  Byte j of a code holds the
+// group of weight 2^(7 p), where p is the number of continuation bytes
+// right before it (0 for the code's first byte), so the integers of any
+// whole codes add up to the sum over their bytes of (byte & 0x7F) * 2^(7 p)
+// (mod 2^32; a fifth group's 2^28 wraps as in Algorithm 1).  Over a prefix
+// [start, x) of the stream, that byte sum counts every code that begins
+// before x except the bytes at or after x of the code that straddles x, and
+// the terminators before x count the codes that end before x.  k_tile_agg
+// produces both per tile, k_tile_scan adds them up, and the tile at x adds
+// the straddling code from its own first bytes (straddle()).
+//
+// seg_bytes adds a lane's 16 bytes w (with the 4 bytes before them in
+// `below`) to its running number of continuation bytes and byte sum, and
+// flags a run of 5 continuation bytes that ends in the lane.  The terms
+// 2^(7 p) = 1 + sum over q = 1..p of (2^(7q) - 2^(7(q-1))) are taken as
+// byte sums over the bytes with at least q continuation bytes before them,
+// each a dot product of the 7-bit groups with 0/1 byte marks; q >= 2 only
+// where the wavefront has such a byte at all.
+template <bool SUM>
+__device__ __forceinline__ void seg_bytes(const u32 (&w)[4], u32 below, u32 &cont, u32 &sum,
+                                          bool &mal) {
+    u32 c[5];   // 0x01 per continuation byte: c[0] the 4 bytes below, c[k + 1] dword k
+    c[0] = (below >> 7) & 0x01010101u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k + 1] = (w[k] >> 7) & 0x01010101u;
+        cont += __builtin_popcount(c[k + 1]);
+    }
+    u32 g[4], m1[4], m2[4], any2 = 0, t0 = 0, t1 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        g[k] = w[k] & 0x7F7F7F7Fu;
+        // byte i of alignbyte(c[k+1], c[k], 3 - d) is the mark d + 1 bytes back
+        m1[k] = __builtin_amdgcn_alignbyte(c[k + 1], c[k], 3);
+        m2[k] = m1[k] & __builtin_amdgcn_alignbyte(c[k + 1], c[k], 2);
+        any2 |= m2[k];
+        if (SUM) {
+            t0 = __builtin_amdgcn_sad_u8(g[k], 0u, t0);
+            t1 = __builtin_amdgcn_udot4(g[k], m1[k], t1, false);
+        }
+    }
+    u32 s = t0 + 127u * t1;
+    if (ballot(any2 != 0) != 0) {
+        u32 t2 = 0, t3 = 0, t4 = 0, run5 = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u32 m3 = m2[k] & __builtin_amdgcn_alignbyte(c[k + 1], c[k], 1);
+            const u32 m4 = m3 & c[k];
+            run5 |= m4 & c[k + 1];
+            if (SUM) {
+                t2 = __builtin_amdgcn_udot4(g[k], m2[k], t2, false);
+                t3 = __builtin_amdgcn_udot4(g[k], m3, t3, false);
+                t4 = __builtin_amdgcn_udot4(g[k], m4, t4, false);
+            }
+        }
+        s += 16256u * t2 + 2080768u * t3 + 266338304u * t4;
+        mal |= run5 != 0;
+    }
+    if (SUM) sum += s;
+}
+
+// The code that straddles the start of a tile: `below` holds the 4 bytes
+// before the tile (zero outside the stream), f0 and f1 its first 8 bytes.
+// code = 1 when a code begins before the tile and ends in it; rest = the
+// byte-sum terms of its bytes in the tile.
+struct Straddle {
+    u32 code, rest;
+};
+__device__ __forceinline__ Straddle straddle(u32 below, u32 f0, u32 f1) {
+    // continuation bytes right before the tile (at most 4 are seen)
+    const u32 p0 = (u32)__builtin_clz(~(top4(below) << 28));
+    Straddle r{p0 ? 1u : 0u, 0u};
+    if (p0) {
+        const u64 f = ((u64)f1 << 32) | f0;
+        for (u32 j = 0; j < 8; ++j) {
+            const u32 b = (u32)(f >> (8 * j)) & 0xFFu;
+            const u32 sh = 7u * (p0 + j);
+            if (sh < 32) r.rest += (b & 0x7Fu) << sh;
+            if (b < 0x80u) break;
+        }
+    }
+    return r;
+}
+
 // ------------------------------------------------------------ one tile
 // A tile is the run of wpb x SEGS segments that one workgroup decodes;
 // wavefront w owns segments [w*SEGS, (w+1)*SEGS) of it.  `base` is 16-byte
@@ -533,6 +618,8 @@ constexpr int kFull = 0;    // decode, prefix from the look-back
 constexpr int kCount = 1;   // count terminators only, prefix from the look-back
 constexpr int kAgg = 2;     // this wavefront's count and sum only; no synchronisation
 constexpr int kKnown = 3;   // decode with the exclusive prefix given in TileIn
+constexpr int kPiece = 4;   // kFull, and record where the code of rank n begins
+constexpr int kKnownB = 5;  // kKnown with the prefix in byte form (see k_tile_agg)
 
 constexpr int kMaxWaves = 16;
 constexpr int kMaxBlock = 8 * kWave;   // at most 8 wavefronts per workgroup
@@ -572,7 +659,9 @@ template <int D, int KIND, int SEGS, bool EDGE>
 __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared &sh, u32 wib,
                                             u32 wpb) {
     constexpr bool DELTA = D != 0, RANK = D == 2;
-    constexpr bool COUNT = KIND == kCount, AGG = KIND == kAgg, KNOWN = KIND == kKnown;
+    constexpr bool COUNT = KIND == kCount, AGG = KIND == kAgg;
+    constexpr bool KNOWN = KIND == kKnown || KIND == kKnownB;
+    constexpr bool PIECE = KIND == kPiece;
     const u32 ln = lane_id();
     const u64 wv = t.tv + (u64)wib * (SEGS * kSegBytes);   // this wavefront's first byte
     u32 w[SEGS][4];
@@ -669,6 +758,11 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
         Prefix ex;
         if (KNOWN) {
             ex = Prefix{t.known_c, t.known_s, t.known_mal};
+            if (KIND == kKnownB) {
+                const Straddle st = straddle(hb, read_lane(w[0][0], 0), read_lane(w[0][1], 0));
+                ex.c += st.code;
+                ex.s += st.rest;
+            }
         } else if (t.didx == t.dfirst) {
             ex = Prefix{0, t.prev, false};
         } else {
@@ -694,7 +788,7 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
         const u64 gbase = exc + wex_c + segbase[s];
-        if (t.pos_out && gbase <= t.n && t.n < gbase + segcnt[s]) {
+        if (PIECE && gbase <= t.n && t.n < gbase + segcnt[s]) {
             // The code of rank n begins in this segment: where a resumed
             // piece starts.  Its lane is found by a scan of the lanes'
             // counts, its byte as the right set bit of the lane's mask.
@@ -744,8 +838,11 @@ __device__ __forceinline__ int32_t final_status(bool mal, u8 last_byte, u64 tota
 }
 
 // ------------------------------------------------------------ single stream
-template <int D, bool COUNT, int SEGS>
+// PIECE: a resumable piece (the window and prev come from the cursor); its
+// own instantiation, so that the whole-stream kernels carry none of it.
+template <int D, bool COUNT, int SEGS, bool PIECE>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4 : 8))) void k_stream(StreamArgs a) {
+    constexpr int KIND = COUNT ? kCount : PIECE ? kPiece : kFull;
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;
     const u32 tid = threadIdx.x;
@@ -758,7 +855,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     const u32 tile = blockIdx.x;
     if (tid == 0) {
         sh.epoch = (u32)aload(a.hdr);
-        if (a.cursor_in) {
+        if (PIECE) {
             sh.cur = a.cursor_in[0];
             sh.cprev = (u32)a.cursor_in[2];
         }
@@ -773,7 +870,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     t.vend = a.vend;
     t.prev = a.prev;
     bool bad_cursor = false;
-    if (a.cursor_in) {
+    if (PIECE) {
         // the piece: at most `window` bytes from the cursor
         const u64 total_bytes = a.vend - a.vstart;
         u64 cur = sh.cur;
@@ -797,14 +894,14 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     const bool interior = tile > 0 && t.tv + tb + 4 <= t.vend;
     TileOut r;
     if (interior)
-        r = run_tile<D, COUNT ? kCount : kFull, SEGS, false>(t, stage, sh, wib, wpb);
+        r = run_tile<D, KIND, SEGS, false>(t, stage, sh, wib, wpb);
     else
-        r = run_tile<D, COUNT ? kCount : kFull, SEGS, true>(t, stage, sh, wib, wpb);
+        r = run_tile<D, KIND, SEGS, true>(t, stage, sh, wib, wpb);
 
     if (tile == a.ntiles - 1 && tid == 0) {
         if (COUNT) {
             *a.d_count = r.total;
-        } else if (a.cursor_in) {
+        } else if (PIECE) {
             // a piece: more codes than n are fine; a short piece that ends
             // inside a code is truncated
             a.scratch[1] = r.total;
@@ -916,6 +1013,175 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
         // the last chunk's look-back has ended: every chunk has read the epoch
         astore(a.hdr, (u64)epoch + 1);
     }
+}
+
+// ------------------------------------------------------------ two passes
+// Single stream in three launches with no look-back: k_tile_agg stores every
+// tile's number of terminators, byte sum (seg_bytes) and malformed flag in
+// its descriptor slot, k_tile_scan (one workgroup) turns them into
+// exclusive prefixes in place and writes the status (the number of integers
+// of a stream is its number of terminators), and k_known decodes every tile
+// with that prefix plus the code that straddles the tile's start.  The
+// slots hold plain values with bits 63:38 clear, which no tagged descriptor
+// has, so a later look-back launch on the same workspace never accepts
+// them.
+template <int D, int SEGS>
+__global__ __launch_bounds__(kMaxBlock) void k_tile_agg(StreamArgs a) {
+    __shared__ u32 wc[kMaxWaves], ws[kMaxWaves], wm[kMaxWaves];
+    const u32 tid = threadIdx.x;
+    const u32 wib = tid >> 6;
+    const u32 wpb = blockDim.x >> 6;
+    const u32 ln = lane_id();
+    const u32 tile = blockIdx.x;
+    const u64 tb = (u64)wpb * SEGS * kSegBytes;
+    const u64 tv = (u64)tile * tb;
+    const u64 wv = tv + (u64)wib * (SEGS * kSegBytes);
+    // interior: the tile and the 4 bytes before it lie inside the stream
+    const bool interior = tile > 0 && tv + tb <= a.vend;
+    u32 w[SEGS][4];
+    u32 hb, hbv, valid;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
+        if (interior)
+            load16(a.base + v, w[s]);
+        else
+            load16_guarded(a.base, v, a.vstart, a.vend, w[s], valid);
+    }
+    if (interior)
+        hb = *(const u32 *)(a.base + wv - 4);
+    else
+        load4_guarded(a.base, (i64)wv - 4, a.vstart, a.vend, hb, hbv);
+    u32 cont = 0, sum = 0;
+    bool mal = false;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 below = from_lane_below(w[s][3], s == 0 ? hb : read_lane(w[s - 1][3], 63));
+        seg_bytes<D != 0>(w[s], below, cont, sum, mal);
+    }
+    cont = wave_sum(cont);
+    if (D) sum = wave_sum(sum);
+    const bool wmal = ballot(mal) != 0;
+    if (ln == 0) {
+        wc[wib] = cont;
+        ws[wib] = sum;
+        wm[wib] = wmal ? 1u : 0u;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        u32 ct = 0, st = 0, mt = 0;
+        for (u32 k = 0; k < wpb; ++k) {
+            ct += wc[k];
+            st += ws[k];
+            mt |= wm[k];
+        }
+        const u64 lo = tv > a.vstart ? tv : a.vstart;
+        const u64 hi = tv + tb < a.vend ? tv + tb : a.vend;
+        const u64 terms = hi - lo - ct;   // bytes of the stream in the tile minus continuations
+        a.desc[tile].c = terms | ((u64)mt << 37);
+        a.desc[tile].s = st;
+    }
+}
+
+constexpr int kScanBlock = 1024;
+
+constexpr int kScanPer = 8;   // tiles per thread per round
+
+__global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
+    __shared__ u32 wc[kScanBlock / kWave], ws[kScanBlock / kWave], wm[kScanBlock / kWave];
+    __shared__ u64 carry_c;
+    __shared__ u32 carry_s, carry_m;
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    if (tid == 0) {
+        carry_c = 0;
+        carry_s = a.prev;
+        carry_m = 0;
+    }
+    __syncthreads();
+    for (u64 b0 = 0; b0 < a.ntiles; b0 += (u64)kScanBlock * kScanPer) {
+        const u64 i0 = b0 + (u64)tid * kScanPer;
+        u32 c[kScanPer], sm[kScanPer];
+        bool m = false;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            c[q] = sm[q] = 0;
+            if (i0 + q < a.ntiles) {
+                const Desc d = a.desc[i0 + q];
+                c[q] = (u32)(d.c & kCountMask);   // at most the tile's bytes
+                m |= ((d.c >> 37) & 1u) != 0;
+                sm[q] = (u32)d.s;
+            }
+        }
+        u32 lc = 0, ls = 0;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            lc += c[q];
+            ls += sm[q];
+        }
+        // 64 x 8 tiles' counts fit 32 bits
+        const u32 ci = wave_scan(lc), si = wave_scan(ls);
+        const bool anym = ballot(m) != 0;
+        if (ln == kWave - 1) {
+            wc[wib] = ci;
+            ws[wib] = si;
+            wm[wib] = anym ? 1u : 0u;
+        }
+        __syncthreads();
+        u64 pc = carry_c;
+        u32 ps = carry_s;
+        for (u32 k = 0; k < wib; ++k) {
+            pc += wc[k];
+            ps += ws[k];
+        }
+        pc += ci - lc;
+        ps += si - ls;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            if (i0 + q < a.ntiles) {
+                a.desc[i0 + q].c = pc;
+                a.desc[i0 + q].s = ps;
+            }
+            pc += c[q];
+            ps += sm[q];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (u32 k = 0; k < kScanBlock / kWave; ++k) {
+                carry_c += wc[k];
+                carry_s += ws[k];
+                carry_m |= wm[k];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *a.d_status = final_status(carry_m != 0, a.base[a.vend - 1], carry_c, a.n);
+}
+
+template <int D, int SEGS>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4 : 8))) void k_known(StreamArgs a) {
+    extern __shared__ __align__(16) u32 lds[];
+    __shared__ WgShared sh;
+    const u32 tid = threadIdx.x;
+    const u32 wib = tid >> 6;
+    const u32 wpb = blockDim.x >> 6;
+    u32 *stage = lds + wib * kStageWords;
+    const u32 tile = blockIdx.x;
+    const u64 tb = (u64)wpb * SEGS * kSegBytes;
+    TileIn t{};
+    t.base = a.base;
+    t.vstart = a.vstart;
+    t.vend = a.vend;
+    t.tv = (u64)tile * tb;
+    t.out = a.out;
+    t.n = a.n;
+    t.known_c = a.desc[tile].c & kCountMask;
+    t.known_s = (u32)a.desc[tile].s;
+    t.known_mal = false;
+    const bool interior = tile > 0 && t.tv + tb + 4 <= t.vend;
+    if (interior)
+        (void)run_tile<D, kKnownB, SEGS, false>(t, stage, sh, wib, wpb);
+    else
+        (void)run_tile<D, kKnownB, SEGS, true>(t, stage, sh, wib, wpb);
 }
 
 // ------------------------------------------------------------ batched lists
@@ -1352,7 +1618,16 @@ __global__ void k_zero(uint4 *p, size_t n16) {
 template <int D, bool COUNT, int SEGS>
 hipError_t launch_stream_t(const StreamArgs &a, int wpb, hipStream_t s) {
     const size_t lds = COUNT ? 0 : (size_t)wpb * kStageWords * sizeof(u32);
-    k_stream<D, COUNT, SEGS><<<a.ntiles, wpb * kWave, lds, s>>>(a);
+    if (a.cursor_in) {
+        // pieces: decode only, at most 2 segments per wavefront
+        if constexpr (!COUNT && SEGS <= 2) {
+            k_stream<D, false, SEGS, true><<<a.ntiles, wpb * kWave, lds, s>>>(a);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    k_stream<D, COUNT, SEGS, false><<<a.ntiles, wpb * kWave, lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1368,6 +1643,26 @@ hipError_t launch_chunks_s(const StreamArgs &a, int delta, int wpb, u32 nchunks,
     if (delta == 2) return launch_chunks_t<2, SEGS>(a, wpb, nchunks, s);
     if (delta) return launch_chunks_t<1, SEGS>(a, wpb, nchunks, s);
     return launch_chunks_t<0, SEGS>(a, wpb, nchunks, s);
+}
+
+template <int D, int SEGS>
+hipError_t launch_two_pass_t(const StreamArgs &a, int wpb, hipStream_t s) {
+    k_tile_agg<D, SEGS><<<a.ntiles, wpb * kWave, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tile_scan<<<1, kScanBlock, 0, s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
+    k_known<D, SEGS><<<a.ntiles, wpb * kWave, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int SEGS>
+hipError_t launch_two_pass_s(const StreamArgs &a, int delta, int wpb, hipStream_t s) {
+    if (delta == 2) return launch_two_pass_t<2, SEGS>(a, wpb, s);
+    if (delta) return launch_two_pass_t<1, SEGS>(a, wpb, s);
+    return launch_two_pass_t<0, SEGS>(a, wpb, s);
 }
 
 template <int SEGS>
@@ -1404,6 +1699,15 @@ hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int seg
         case 1: return launch_stream_s<1>(a, delta, count_only, wpb, s);
         case 2: return launch_stream_s<2>(a, delta, count_only, wpb, s);
         case 4: return launch_stream_s<4>(a, delta, count_only, wpb, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_two_pass(const StreamArgs &a, int delta, int segs, int wpb, hipStream_t s) {
+    switch (segs) {
+        case 1: return launch_two_pass_s<1>(a, delta, wpb, s);
+        case 2: return launch_two_pass_s<2>(a, delta, wpb, s);
+        case 4: return launch_two_pass_s<4>(a, delta, wpb, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -4,8 +4,9 @@
 // It times the caller's own workload under every candidate tiling with HIP
 // events on the caller's stream, keeps the fastest and applies it with
 // vbyte_set_tuning / vbyte_set_chunk_tiles.  Candidates: 1 KiB segments per
-// wavefront {2, 4} x wavefronts per workgroup {4, 8} x tiles per chunk
-// {0, 2, 4, 8, 16} for a single stream; for the batched form {2, 4} x
+// wavefront {2, 4} x wavefronts per workgroup {4, 8} x single-stream kernel
+// {-1 (three launches), 0 (look-back per tile), chunks of 2, 4, 8, 16
+// tiles} for a single stream; for the batched form {2, 4} x
 // {4, 8} x small-list threshold {4, 16, 64, 256} KiB.  The
 // tuning is process-wide, so no other decode should run meanwhile.
 
@@ -112,11 +113,11 @@ vbyte_status vbyte_autotune_decode(const uint8_t *bytes, size_t nbytes, uint32_t
     hipStream_t s = (hipStream_t)stream;
     int64_t small = 0;
     vbyte_get_tuning(nullptr, nullptr, &small);
-    Cand cands[20];
+    Cand cands[24];
     int nc = 0;
     for (int segs : {2, 4})
         for (int wpb : {4, 8})
-            for (int chunk : {0, 2, 4, 8, 16}) cands[nc++] = Cand{segs, wpb, small, chunk};
+            for (int chunk : {-1, 0, 2, 4, 8, 16}) cands[nc++] = Cand{segs, wpb, small, chunk};
     auto call = [&]() {
         return delta ? vbyte_decode_delta_async(bytes, nbytes, out, n, 0, d_status, s)
                      : vbyte_decode_async(bytes, nbytes, out, n, d_status, s);

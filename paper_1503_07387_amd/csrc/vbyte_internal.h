@@ -122,6 +122,10 @@ hipError_t launch_resume_finish(const uint8_t *bytes, const uint64_t *cursor_in,
 // descriptor per chunk).
 hipError_t launch_chunks(const StreamArgs &a, int delta, int segs, int wpb, uint32_t nchunks,
                          hipStream_t s);
+// Single-stream decode in three launches with no look-back (tile aggregates,
+// a one-workgroup scan that also writes the status, decode with the prefix
+// known); one descriptor slot per tile.
+hipError_t launch_two_pass(const StreamArgs &a, int delta, int segs, int wpb, hipStream_t s);
 hipError_t launch_encode(const EncodeArgs &a, hipStream_t s);
 hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
                                 uint64_t nb, hipStream_t s);

@@ -14,10 +14,11 @@ pytestmark = pytest.mark.gpu
 DEFAULT_TUNING = None
 
 
-@pytest.fixture(autouse=True, params=[0, 3], ids=["tile_lookback", "chunks_of_3"])
+@pytest.fixture(autouse=True, params=[0, 3, -1], ids=["tile_lookback", "chunks_of_3", "two_pass"])
 def restore_tuning(request):
-    """Every test runs with both single-stream kernels: one look-back per
-    tile, and chunks of 3 tiles per workgroup."""
+    """Every test runs with the three single-stream kernels: one look-back
+    per tile, chunks of 3 tiles per workgroup, and the three launches with
+    no look-back (tile byte sums, scan, decode)."""
     t = vbyte.get_tuning()
     vbyte.set_tuning(tiles_per_chunk=request.param)
     yield

@@ -107,8 +107,8 @@ def test_autotune_decode_applies_fastest():
     b = oracle.encode(g)
     bd = torch.from_numpy(b).cuda()
     pts = vbyte.autotune_decode(bd, g.size, delta=True, reps=2)
-    assert len(pts) == 20
-    assert {p["tiles_per_chunk"] for p in pts} == {0, 2, 4, 8, 16}
+    assert len(pts) == 24
+    assert {p["tiles_per_chunk"] for p in pts} == {-1, 0, 2, 4, 8, 16}
     assert all(p["status"] == vbyte.OK and p["ms"] > 0 for p in pts)
     best = min(pts, key=lambda p: p["ms"])
     t = vbyte.get_tuning()
@@ -153,7 +153,7 @@ def test_autotune_cache_roundtrip(tmp_path):
     bd = torch.from_numpy(oracle.encode(g)).cuda()
     path = str(tmp_path / "tune.json")
     e1, pts = autotune.tune_stream(bd, g.size, delta=True, path=path, reps=1)
-    assert pts is not None and len(pts) == 20
+    assert pts is not None and len(pts) == 24
     vbyte.set_tuning(1, 2, 4096, tiles_per_chunk=0)
     e2, pts2 = autotune.tune_stream(bd, g.size, delta=True, path=path)
     assert pts2 is None and e2 == e1
