@@ -112,8 +112,38 @@ def cpu_baseline(streams, budget_s=15.0):
                       f"{el:.1f}s wall"}
 
 
-DECODE_KERNEL = "k_stream<true, false"
+# Kernels of one single-stream decode call: the look-back kernel alone, the
+# chunked kernel alone, or the two-pass sequence (tile sums, scan, decode);
+# a call ends with its last kernel.
+DECODE_KERNELS = ("k_stream<", "k_chunks<", "k_tile_agg<", "k_tile_scan", "k_known<")
+CALL_END_KERNELS = ("k_stream<", "k_chunks<", "k_known<")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def short_kernel(name):
+    return name.replace("vb::(anonymous namespace)::", "").split("(")[0]
+
+
+def group_calls(rows, value):
+    """Decode-call totals of value(row) over dispatch-ordered rows: every
+    decode kernel adds to the current call, a call-ending kernel closes it."""
+    calls, cur = [], 0.0
+    for r in rows:
+        name = r["Kernel_Name"]
+        if not any(k in name for k in DECODE_KERNELS):
+            continue
+        cur += value(r)
+        if any(k in name for k in CALL_END_KERNELS):
+            calls.append(cur)
+            cur = 0.0
+    return calls
+
+
+def describe_tuning(t):
+    c = t.get("tiles_per_chunk", 0)
+    mode = ("two-pass: k_tile_agg + k_tile_scan + k_known" if c < 0 else
+            "look-back: k_stream" if c == 0 else f"chunks of {c} tiles: k_chunks")
+    return f"{mode} (segs {t['segs_per_wave']}, waves {t['waves_per_block']})"
 
 
 def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
@@ -135,7 +165,7 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
         copies = [float(r["Counter_Value"]) * 1024 for r in rows if COPY_KERNEL in r["Kernel_Name"]]
         copy = max(copies)
         factor = known / copy
-        dec = [float(r["Counter_Value"]) * 1024 * factor for r in rows if DECODE_KERNEL in r["Kernel_Name"]]
+        dec = group_calls(rows, lambda r: float(r["Counter_Value"]) * 1024 * factor)
         res[name] = {"copy_counted_bytes": copy, "factor": factor, "decode_bytes": dec}
     # dispatches alternate: gap-mean-8 stream, gap-mean-300 stream
     f, w = res["FETCH_SIZE"]["decode_bytes"], res["WRITE_SIZE"]["decode_bytes"]
@@ -145,7 +175,8 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
         wk = w[k::2]
         per.append({"fetch_bytes": sum(fk) / len(fk), "write_bytes": sum(wk) / len(wk),
                     "hbm_bytes": sum(fk) / len(fk) + sum(wk) / len(wk)})
-    out = {"kernel": DECODE_KERNEL, "kernel_source_sha256_16": kernel_source_hash(),
+    out = {"kernels": "all kernels of one decode call (" + ", ".join(DECODE_KERNELS) + ")",
+           "kernel_source_sha256_16": kernel_source_hash(),
            "fetch_factor": res["FETCH_SIZE"]["factor"], "write_factor": res["WRITE_SIZE"]["factor"],
            "copy_counted_bytes": {"FETCH_SIZE": res["FETCH_SIZE"]["copy_counted_bytes"],
                                   "WRITE_SIZE": res["WRITE_SIZE"]["copy_counted_bytes"]},
@@ -155,9 +186,10 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
     with open(out_json, "w") as fh:
         json.dump(out, fh, indent=1)
     with open(out_md, "w") as fh:
-        fh.write("# HBM traffic of the differential decode kernel, 2 x 64Mi-gap streams\n\n")
+        fh.write("# HBM traffic of the differential decode, 2 x 64Mi-gap streams\n\n")
         fh.write("Counters from two rocprofv3 runs (one counter each), scaled by the same counter\n"
-                 "read for a plain 256 MiB device copy in the same process.\n\n")
+                 "read for a plain 256 MiB device copy in the same process, summed over the\n"
+                 "kernels of one decode call.\n\n")
         for c in command_lines:
             fh.write(f"    {c}\n")
         fh.write(f"\nFETCH_SIZE factor {out['fetch_factor']:.4f}, WRITE_SIZE factor {out['write_factor']:.4f}\n\n")
@@ -197,6 +229,9 @@ def bench_batched(torch, vbyte, serve, idx, reps=10):
     st = torch.empty(nl, dtype=torch.int32, device="cuda")
     tune_points = vbyte.autotune_batch(idx["bytes"], idx["byte_off"], idx["out_off"], delta=True,
                                        out=out, reps=2)
+    # per-list launches (below, and in the serving comparison) decode each
+    # list with the single-launch look-back kernel, the fewest launches per list
+    vbyte.set_tuning(tiles_per_chunk=0)
     tuned = vbyte.get_tuning()
     log(f"batch tuning: {tuned}")
 
@@ -355,26 +390,58 @@ def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
 
 
 def summarize_trace(trace_csv, stats_csv, out_md, command_line):
-    """Turn a rocprofv3 --kernel-trace --stats run of bench.py (with
-    --no-autotune, so that every decode dispatch uses one tiling) into the
-    per-stream duration table of profiles/decode_delta_64Mi_kernel_trace.md."""
+    """Turn a rocprofv3 --kernel-trace --stats run of bench.py (with a fixed
+    --tuning, so that every decode call runs the same kernels) into the
+    per-stream duration table of profiles/decode_delta_64Mi_kernel_trace.md:
+    per decode call, the sum of its kernels' durations and its span from
+    the first kernel's start to the last kernel's end (what the HIP events
+    around the call in bench.py measure), and per kernel."""
     import csv
-    rows = [r for r in csv.DictReader(open(trace_csv)) if DECODE_KERNEL in r["Kernel_Name"]]
+    rows = [r for r in csv.DictReader(open(trace_csv))
+            if any(k in r["Kernel_Name"] for k in DECODE_KERNELS)]
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-    names = sorted({r["Kernel_Name"] for r in rows})
-    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+    calls, cur = [], []
+    for r in rows:
+        cur.append(r)
+        if any(k in r["Kernel_Name"] for k in CALL_END_KERNELS):
+            calls.append(cur)
+            cur = []
+    names = []
+    for r in rows:
+        if short_kernel(r["Kernel_Name"]) not in names:
+            names.append(short_kernel(r["Kernel_Name"]))
+
+    def dur(r):
+        return (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+
     with open(out_md, "w") as fh:
         fh.write("# Kernel trace: differential decode, 2 x 64Mi-gap streams (bench.py workload)\n\n")
         fh.write("Command (run from the repository root on one MI355X):\n\n")
         fh.write(f"    {command_line}\n\n")
-        fh.write("Decode kernel instance(s): " + ", ".join(f"`{n}`" for n in names) + ".\n")
-        fh.write("Dispatches alternate between the gap-mean-8 stream and the gap-mean-300 stream "
+        fh.write("Kernels of one decode call: " + ", ".join(f"`{n}`" for n in names) + ".\n")
+        fh.write("Calls alternate between the gap-mean-8 stream and the gap-mean-300 stream "
                  "(first the warm-up steps, then the timed ones).\n\n")
-        fh.write("| stream | dispatches | avg us | min us | max us |\n|---|---|---|---|---|\n")
+        fh.write("| stream | calls | kernel sum avg us | span avg us | span min us | span max us |\n"
+                 "|---|---|---|---|---|---|\n")
         for k, name in enumerate(("gap mean 8", "gap mean 300")):
-            d = dur[k::2]
-            if d:
-                fh.write(f"| {name} | {len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |\n")
+            cs = calls[k::2]
+            if not cs:
+                continue
+            ksum = [sum(dur(r) for r in c) for c in cs]
+            span = [(int(c[-1]["End_Timestamp"]) - int(c[0]["Start_Timestamp"])) / 1e3 for c in cs]
+            fh.write(f"| {name} | {len(cs)} | {sum(ksum) / len(ksum):.1f} | {sum(span) / len(span):.1f} | "
+                     f"{min(span):.1f} | {max(span):.1f} |\n")
+        fh.write("\nPer kernel (average us per call):\n\n| stream | " + " | ".join(names) + " |\n|---|"
+                 + "---|" * len(names) + "\n")
+        for k, name in enumerate(("gap mean 8", "gap mean 300")):
+            cs = calls[k::2]
+            if not cs:
+                continue
+            cells = []
+            for n in names:
+                d = [dur(r) for c in cs for r in c if short_kernel(r["Kernel_Name"]) == n]
+                cells.append(f"{sum(d) / len(cs):.1f}")
+            fh.write(f"| {name} | " + " | ".join(cells) + " |\n")
         fh.write("\nrocprofv3 --stats summary (the ten kernels with the most total time):\n\n")
         st = list(csv.DictReader(open(stats_csv)))
         st.sort(key=lambda r: -float(r.get("TotalDurationNs", 0) or 0))
@@ -382,7 +449,7 @@ def summarize_trace(trace_csv, stats_csv, out_md, command_line):
         for r in st[:10]:
             fh.write(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['AverageNs']):.0f} | "
                      f"{float(r['MinNs']):.0f} | {float(r['MaxNs']):.0f} |\n")
-    return {"dispatches": len(dur), "names": names}
+    return {"calls": len(calls), "kernels": names}
 
 
 def main():
@@ -408,6 +475,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's current tiling instead of autotuning each stream "
                          "(profiling runs: every decode dispatch then uses one tiling)")
+    ap.add_argument("--tuning", default=None,
+                    help="SEGS,WAVES,CHUNK (both streams) or SEGS,WAVES,CHUNK/SEGS,WAVES,CHUNK "
+                         "(gap-mean-8 stream / gap-mean-300 stream): use this tiling and "
+                         "single-stream kernel instead of autotuning (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 256 MiB (int32 tensor copy) before the "
                          "steps, as the reference kernel for scaling HBM byte counters")
@@ -437,20 +508,27 @@ def main():
 
     # the tiling of each stream picked by the library's autotuner (untimed)
     tunings = []
-    for s in streams:
-        if not args.no_autotune:
+    fixed = args.tuning.split("/") if args.tuning else []
+    for i, s in enumerate(streams):
+        if fixed:
+            sg, wv, ch = (int(x) for x in fixed[min(i, len(fixed) - 1)].split(","))
+            vbyte.set_tuning(sg, wv, 0, tiles_per_chunk=ch)
+        elif not args.no_autotune:
             vbyte.autotune_decode(s["bytes"], N_STREAM, delta=True, out=s["out"], reps=3)
         tunings.append(vbyte.get_tuning())
         log(f"stream mean {s['mean']}: tuning {tunings[-1]}")
 
+    def decode_call(i):
+        s = streams[i]
+        vbyte.set_tuning(**tunings[i])
+        vbyte.decode(s["bytes"], N_STREAM, delta=True, prev=0, out=s["out"],
+                     status=s["status"], check=False)
+
     def step(events=None):
-        for i, s in enumerate(streams):
-            t = tunings[i]
-            vbyte.set_tuning(**t)
+        for i in range(len(streams)):
             if events is not None:
                 events[i][0].record(stream)
-            vbyte.decode(s["bytes"], N_STREAM, delta=True, prev=0, out=s["out"],
-                         status=s["status"], check=False)
+            decode_call(i)
             if events is not None:
                 events[i][1].record(stream)
 
@@ -512,7 +590,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic,
-                     "kernel": "k_stream<delta> (vb::k_stream<true,false,SEGS>)",
+                     "kernel": "the whole decode call of each stream, all its launches: "
+                               + "; ".join(f"mean {s['mean']}: {describe_tuning(t)}"
+                                           for s, t in zip(streams, tunings)),
                      "alg_bytes_per_launch": alg_bytes},
     }
     if not (args.no_batched and args.no_serving):
