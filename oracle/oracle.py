@@ -97,6 +97,22 @@ def _declare(lib):
                                      c.c_size_t, c.POINTER(c.c_uint32), c.c_int,
                                      c.POINTER(c.c_int32)]
     lib.orc_decode_batch.restype = c.c_int
+    u64p = c.POINTER(c.c_uint64)
+    lib.orc_code_length64.argtypes = [c.c_uint64]
+    lib.orc_code_length64.restype = c.c_int
+    lib.orc_encode64.argtypes = [u64p, c.c_size_t, c.POINTER(c.c_uint8)]
+    lib.orc_encode64.restype = c.c_size_t
+    lib.orc_encoded_size64.argtypes = [u64p, c.c_size_t]
+    lib.orc_encoded_size64.restype = c.c_size_t
+    lib.orc_encode_delta64.argtypes = [u64p, c.c_size_t, c.c_uint64, c.POINTER(c.c_uint8)]
+    lib.orc_encode_delta64.restype = c.c_size_t
+    lib.orc_validate64.argtypes = [c.POINTER(c.c_uint8), c.c_size_t, c.c_size_t]
+    lib.orc_validate64.restype = c.c_int
+    lib.orc_decode64.argtypes = [c.POINTER(c.c_uint8), c.c_size_t, u64p, c.c_size_t]
+    lib.orc_decode64.restype = c.c_int
+    lib.orc_decode64_delta.argtypes = [c.POINTER(c.c_uint8), c.c_size_t, u64p, c.c_size_t,
+                                       c.c_uint64]
+    lib.orc_decode64_delta.restype = c.c_int
     return lib
 
 
@@ -219,3 +235,66 @@ def decode_batch(b, byte_off, out_off, prevs=None, delta=False, lib=None):
                               nlists, _u32p(pv) if pv is not None else None,
                               int(delta), _i32p(st_list))
     return int(st), out[:total], st_list[:nlists]
+
+
+# ---------------------------------------------------------------- 64-bit (R13)
+def _u64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _as_u64(x):
+    return np.ascontiguousarray(x, dtype=np.uint64)
+
+
+def code_length64(x, lib=None):
+    lib = lib or load()
+    return int(lib.orc_code_length64(int(x) & 0xFFFFFFFFFFFFFFFF))
+
+
+def encoded_size64(x, lib=None):
+    lib = lib or load()
+    x = _as_u64(x)
+    return int(lib.orc_encoded_size64(_u64p(x), x.size))
+
+
+def encode64(x, lib=None):
+    """ENC of uint64 values: up to ten 7-bit groups each."""
+    lib = lib or load()
+    x = _as_u64(x)
+    out = np.zeros(max(10 * x.size, 1), dtype=np.uint8)
+    nb = lib.orc_encode64(_u64p(x), x.size, _u8p(out))
+    return out[:nb].copy()
+
+
+def encode_delta64(x, prev=0, lib=None):
+    """Gaps mod 2^64 from prev, then ENC."""
+    lib = lib or load()
+    x = _as_u64(x)
+    out = np.zeros(max(10 * x.size, 1), dtype=np.uint8)
+    nb = lib.orc_encode_delta64(_u64p(x), x.size, int(prev) & 0xFFFFFFFFFFFFFFFF, _u8p(out))
+    return out[:nb].copy()
+
+
+def validate64(b, n, lib=None):
+    lib = lib or load()
+    b = _as_u8(b)
+    return int(lib.orc_validate64(_u8p(b), b.size, int(n)))
+
+
+def decode64(b, n, lib=None):
+    """Algorithm 1 widened to uint64 after validation (R13).  Returns
+    (status, uint64 array)."""
+    lib = lib or load()
+    b = _as_u8(b)
+    y = np.zeros(max(int(n), 1), dtype=np.uint64)
+    st = lib.orc_decode64(_u8p(b), b.size, _u64p(y), int(n))
+    return int(st), y[:int(n)]
+
+
+def decode64_delta(b, n, prev=0, lib=None):
+    """decode64, then the inclusive prefix sum from prev, mod 2^64."""
+    lib = lib or load()
+    b = _as_u8(b)
+    y = np.zeros(max(int(n), 1), dtype=np.uint64)
+    st = lib.orc_decode64_delta(_u8p(b), b.size, _u64p(y), int(n), int(prev) & 0xFFFFFFFFFFFFFFFF)
+    return int(st), y[:int(n)]

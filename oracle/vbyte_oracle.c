@@ -34,6 +34,12 @@
  *   R12 a resumable piece of k integers is validated over its window of
  *       5k bytes (or the rest of the buffer); its cursor moves only on
  *       success.
+ *   R13 64-bit integers (section 1: the format applies to 64-bit integers
+ *       as well): at most 10 bytes per code, the tenth carrying bit 63; ten
+ *       or more consecutive continuation bytes -> EMALFORMED; a tenth byte
+ *       above 1 is accepted, its weight 2^63 wrapping mod 2^64 (only its
+ *       low bit counts); the differential sum wraps mod 2^64.  Truncation
+ *       and count statuses as in R6.
  *   R6  exact consumption: the buffer must hold exactly n codes ending at
  *       its last byte; a last byte >= 0x80 or fewer than n terminators ->
  *       ETRUNC, more than n terminators -> ECOUNT.  Precedence when several
@@ -305,4 +311,110 @@ int orc_decode_batch(const uint8_t *bytes, const int64_t *byte_off,
         if (st > worst) worst = st;
     }
     return worst;
+}
+
+/* ------------------------------------------------------------------------
+ * 64-bit integers (reading R13).  The same byte format with up to ten
+ * 7-bit groups; the code length, the encoder, the validation pass and the
+ * decoder are written out again for uint64 rather than shared with the
+ * 32-bit routines above, so that each can be read against the format on
+ * its own.
+ * ------------------------------------------------------------------------ */
+
+/* L(x) for uint64: the number of 7-bit groups up to the highest set bit, at
+ * least 1; 2^63 and above need 10. */
+int orc_code_length64(uint64_t x)
+{
+    int len = 1;
+    while (len < 10 && (x >> (7 * len)) != 0) len++;
+    return len;
+}
+
+size_t orc_encode64(const uint64_t *x, size_t n, uint8_t *dst)
+{
+    size_t pos = 0;
+    for (size_t i = 0; i < n; i++) {
+        int len = orc_code_length64(x[i]);
+        for (int j = 0; j < len; j++) {
+            uint8_t group = (uint8_t)((x[i] >> (7 * j)) & 0x7Fu);
+            dst[pos++] = (j < len - 1) ? (uint8_t)(group | 0x80u) : group;
+        }
+    }
+    return pos;
+}
+
+size_t orc_encoded_size64(const uint64_t *x, size_t n)
+{
+    size_t total = 0;
+    for (size_t i = 0; i < n; i++) total += (size_t)orc_code_length64(x[i]);
+    return total;
+}
+
+/* Gaps of a uint64 sequence, then ENC: g_0 = x_0 - prev, g_i = x_i - x_(i-1),
+ * mod 2^64. */
+size_t orc_encode_delta64(const uint64_t *x, size_t n, uint64_t prev, uint8_t *dst)
+{
+    size_t pos = 0;
+    uint64_t last = prev;
+    for (size_t i = 0; i < n; i++) {
+        uint64_t gap = x[i] - last;
+        last = x[i];
+        pos += orc_encode64(&gap, 1, dst + pos);
+    }
+    return pos;
+}
+
+/* Validation for 64-bit codes: a run of 10 continuation bytes is
+ * malformed; truncation and count as in R6. */
+int orc_validate64(const uint8_t *b, size_t nbytes, size_t n)
+{
+    int malformed = 0;
+    int run = 0;
+    uint64_t terminators = 0;
+    for (size_t i = 0; i < nbytes; i++) {
+        if (b[i] & 0x80u) {
+            run++;
+            if (run >= 10) malformed = 1;
+        } else {
+            run = 0;
+            terminators++;
+        }
+    }
+    if (malformed) return ORC_EMALFORMED;
+    if ((nbytes > 0 && (b[nbytes - 1] & 0x80u)) || terminators < (uint64_t)n) return ORC_ETRUNC;
+    if (terminators > (uint64_t)n) return ORC_ECOUNT;
+    return ORC_OK;
+}
+
+/* Algorithm 1 widened to uint64: up to ten groups, group j at weight
+ * 2^(7j) mod 2^64. */
+int orc_decode64(const uint8_t *b, size_t nbytes, uint64_t *y, size_t n)
+{
+    int st = orc_validate64(b, nbytes, n);
+    if (st != ORC_OK) return st;
+    size_t i = 0;
+    for (size_t k = 0; k < n; k++) {
+        uint64_t acc = 0;
+        for (int j = 0; j < 10; j++) {
+            uint64_t byte = b[i++];
+            acc += (byte & 0x7Fu) << (7 * j);
+            if (byte < 128) break;
+        }
+        y[k] = acc;
+    }
+    return ORC_OK;
+}
+
+/* Differential decode of uint64 gaps: inclusive prefix sum from prev,
+ * mod 2^64. */
+int orc_decode64_delta(const uint8_t *b, size_t nbytes, uint64_t *y, size_t n, uint64_t prev)
+{
+    int st = orc_decode64(b, nbytes, y, n);
+    if (st != ORC_OK) return st;
+    uint64_t run = prev;
+    for (size_t k = 0; k < n; k++) {
+        run += y[k];
+        y[k] = run;
+    }
+    return ORC_OK;
 }

@@ -431,10 +431,123 @@ def pin_batch(lib):
     assert st == EINVAL
 
 
+# ---------------------------------------------------------------- 64-bit (R13)
+M64 = (1 << 64) - 1
+
+
+def pb_decode64(buf, n):
+    from google.protobuf.internal import decoder
+    out, pos = [], 0
+    for _ in range(n):
+        v, pos = decoder._DecodeVarint(buf, pos)
+        out.append(v)
+    assert pos == len(buf)
+    return out
+
+
+def pin64_closed_form_boundaries(lib):
+    # 2^(7k)-1: k-1 bytes FF then 7F; 2^(7k): k bytes 80 then 01;
+    # 2^(7k)+1: 81, k-1 bytes 80, 01 -- for k up to 9 (section 1 byte ranges)
+    for k in range(1, 10):
+        cases = {
+            (1 << (7 * k)) - 1: bytes([0xFF] * (k - 1) + [0x7F]),
+            (1 << (7 * k)): bytes([0x80] * k + [0x01]),
+            (1 << (7 * k)) + 1: bytes([0x81] + [0x80] * (k - 1) + [0x01]),
+        }
+        for v, b in cases.items():
+            got = oracle.encode64(np.array([v], dtype=np.uint64), lib=lib).tobytes()
+            assert got == b, f"ENC64({v}) = {got.hex()} expected {b.hex()}"
+            assert oracle.code_length64(v, lib=lib) == len(b)
+            st, y = oracle.decode64(b, 1, lib=lib)
+            assert st == OK and int(y[0]) == v
+    # the top group of a 10-byte code holds bit 63 only
+    fixed = {0: b"\x00", M64: b"\xff" * 9 + b"\x01", 1 << 63: b"\x80" * 9 + b"\x01",
+             (1 << 63) - 1: b"\xff" * 8 + b"\x7f", M32: b"\xff\xff\xff\xff\x0f"}
+    for v, b in fixed.items():
+        assert oracle.encode64(np.array([v], dtype=np.uint64), lib=lib).tobytes() == b
+        st, y = oracle.decode64(b, 1, lib=lib)
+        assert st == OK and int(y[0]) == v
+
+
+def pin64_protobuf(lib):
+    # Protocol Buffers' varint is this format for 64-bit integers (section 1
+    # names it); its encoder and decoder are a codec written by others
+    rng = np.random.default_rng(64)
+    vals = [0, 1, M64, 1 << 63]
+    for L in range(1, 11):
+        lo = 0 if L == 1 else 1 << (7 * (L - 1))
+        hi = min(1 << (7 * L), 1 << 64)
+        vals += [lo + int(r) % (hi - lo) for r in rng.integers(0, 1 << 63, 300, dtype=np.uint64)]
+        vals += [hi - 1]
+    x = np.array(vals, dtype=np.uint64)
+    ours = oracle.encode64(x, lib=lib).tobytes()
+    assert ours == pb_encode(vals), "ENC64 differs from protobuf varint"
+    assert pb_decode64(ours, len(vals)) == vals
+    st, y = oracle.decode64(ours, len(vals), lib=lib)
+    assert st == OK and [int(t) for t in y] == vals
+
+
+def pin64_delta_bigint(lib):
+    # DEC64_DELTA against Python big integers reduced mod 2^64, and numpy's
+    # wrapping uint64 cumsum; the sum wraps many times
+    rng = np.random.default_rng(65)
+    g = rng.integers(0, 1 << 64, 5000, dtype=np.uint64)
+    g[rng.random(g.size) < 0.5] >>= np.uint64(40)
+    b = oracle.encode64(g, lib=lib)
+    prev = 0xFEDCBA9876543210
+    st, y = oracle.decode64_delta(b, g.size, prev, lib=lib)
+    acc, ref = prev, []
+    for v in g:
+        acc = (acc + int(v)) % (1 << 64)
+        ref.append(acc)
+    assert st == OK and [int(t) for t in y] == ref
+    with np.errstate(over="ignore"):
+        assert np.array_equal(y, np.cumsum(g, dtype=np.uint64) + np.uint64(prev))
+    # the encoder of differences round-trips any sequence
+    x = rng.integers(0, 1 << 64, 3000, dtype=np.uint64)
+    st, y = oracle.decode64_delta(oracle.encode_delta64(x, 77, lib=lib), x.size, 77, lib=lib)
+    assert st == OK and np.array_equal(y, x)
+
+
+def pin64_statuses(lib):
+    ten = bytes([0x80] * 9 + [0x01])
+    # a 10-byte code is whole; ten continuation bytes are malformed (R13)
+    assert oracle.validate64(ten, 1, lib=lib) == OK
+    assert oracle.validate64(bytes([0x80] * 10 + [0x01]), 1, lib=lib) == EMALFORMED
+    assert oracle.validate64(b"\x05" + bytes([0x81] * 10) + b"\x00", 2, lib=lib) == EMALFORMED
+    # a tenth byte above 1: only its low bit counts, 2^63 wraps (R13)
+    st, y = oracle.decode64(bytes([0x80] * 9 + [0x03]), 1, lib=lib)
+    assert st == OK and int(y[0]) == 1 << 63
+    st, y = oracle.decode64(bytes([0x80] * 9 + [0x7E]), 1, lib=lib)
+    assert st == OK and int(y[0]) == 0
+    # truncation, count, precedence (R6)
+    assert oracle.validate64(ten + b"\x81", 2, lib=lib) == ETRUNC
+    assert oracle.validate64(ten, 2, lib=lib) == ETRUNC
+    assert oracle.validate64(ten + b"\x01", 1, lib=lib) == ECOUNT
+    assert oracle.validate64(bytes([0x80] * 12), 0, lib=lib) == EMALFORMED
+    assert oracle.validate64(b"", 0, lib=lib) == OK
+    # codes of 5..9 bytes, valid for 64-bit, are malformed for 32-bit (R3)
+    b = oracle.encode64(np.array([1 << 40, 1 << 56], dtype=np.uint64), lib=lib)
+    assert oracle.validate64(b, 2, lib=lib) == OK and oracle.validate(b, 2, lib=lib) == EMALFORMED
+
+
+def pin64_agrees_with_32(lib):
+    # below 2^32 the two independently written codecs must agree byte for byte
+    rng = np.random.default_rng(66)
+    x = rng.integers(0, 1 << 32, 20000, dtype=np.uint64)
+    x[rng.random(x.size) < 0.5] >>= np.uint64(20)
+    b32 = oracle.encode(x.astype(np.uint32), lib=lib)
+    assert np.array_equal(oracle.encode64(x, lib=lib), b32)
+    st, y = oracle.decode64(b32, x.size, lib=lib)
+    assert st == OK and np.array_equal(y, x)
+
+
 ALL_PINS = [pin_table1, pin_fig1, pin_closed_form_boundaries, pin_length_closed_form,
             pin_five_byte_algebra, pin_protobuf_exhaustive_21, pin_protobuf_random_wide,
             pin_canonical_bijection, pin_random_wide_roundtrip, pin_delta_cumsum,
             pin_delta_encode_roundtrip, pin_resumable, pin_delta_m1_closed_form,
             pin_delta_m1_encode_roundtrip, pin_resumable_pieces, pin_resumable_errors,
             pin_status_readings,
-            pin_fifth_byte_wrap, pin_overlong, pin_batch]
+            pin_fifth_byte_wrap, pin_overlong, pin_batch,
+            pin64_closed_form_boundaries, pin64_protobuf, pin64_delta_bigint, pin64_statuses,
+            pin64_agrees_with_32]

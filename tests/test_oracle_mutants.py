@@ -47,6 +47,19 @@ MUTANTS = [
     ("batch_m1_as_delta", "int st = delta == 2 ? orc_decode_delta_m1(b, nb, y, n, prev)",
      "int st = delta == 3 ? orc_decode_delta_m1(b, nb, y, n, prev)"),
     ("batch_no_einval", "return ORC_EINVAL;\n    }\n    int worst", "(void)0;\n    }\n    int worst"),
+    ("len64_nine", "while (len < 10 && (x >> (7 * len)) != 0) len++;",
+     "while (len < 9 && (x >> (7 * len)) != 0) len++;"),
+    ("enc64_shift_8", "uint8_t group = (uint8_t)((x[i] >> (7 * j)) & 0x7Fu);",
+     "uint8_t group = (uint8_t)((x[i] >> (8 * j)) & 0x7Fu);"),
+    ("val64_run9", "if (run >= 10) malformed = 1;", "if (run >= 9) malformed = 1;"),
+    ("val64_run11", "if (run >= 10) malformed = 1;", "if (run >= 11) malformed = 1;"),
+    ("dec64_nine_groups", "for (int j = 0; j < 10; j++) {\n            uint64_t byte",
+     "for (int j = 0; j < 9; j++) {\n            uint64_t byte"),
+    ("dec64_keep_top", "acc += (byte & 0x7Fu) << (7 * j);", "acc += byte << (7 * j);"),
+    ("dec64_32bit_acc", "uint64_t acc = 0;\n        for (int j = 0; j < 10; j++)",
+     "uint32_t acc = 0;\n        for (int j = 0; j < 10; j++)"),
+    ("delta64_no_prev", "uint64_t run = prev;", "uint64_t run = 0;"),
+    ("encdelta64_sign", "uint64_t gap = x[i] - last;", "uint64_t gap = last - x[i];"),
 ]
 
 RUNNER = r"""
