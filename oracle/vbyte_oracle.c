@@ -337,7 +337,7 @@ size_t orc_encode64(const uint64_t *x, size_t n, uint8_t *dst)
         int len = orc_code_length64(x[i]);
         for (int j = 0; j < len; j++) {
             uint8_t group = (uint8_t)((x[i] >> (7 * j)) & 0x7Fu);
-            dst[pos++] = (j < len - 1) ? (uint8_t)(group | 0x80u) : group;
+            dst[pos++] = (j + 1 < len) ? (uint8_t)(group | 0x80u) : group;   /* last: top bit 0 */
         }
     }
     return pos;

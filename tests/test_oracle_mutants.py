@@ -59,6 +59,8 @@ MUTANTS = [
     ("dec64_32bit_acc", "uint64_t acc = 0;\n        for (int j = 0; j < 10; j++)",
      "uint32_t acc = 0;\n        for (int j = 0; j < 10; j++)"),
     ("delta64_no_prev", "uint64_t run = prev;", "uint64_t run = 0;"),
+    ("enc64_cont_on_last", "dst[pos++] = (j + 1 < len) ? (uint8_t)(group | 0x80u) : group;",
+     "dst[pos++] = (j < len) ? (uint8_t)(group | 0x80u) : group;"),
     ("encdelta64_sign", "uint64_t gap = x[i] - last;", "uint64_t gap = last - x[i];"),
 ]
 
