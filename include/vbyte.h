@@ -98,6 +98,24 @@ vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, ui
                                          size_t n, uint32_t prev, int32_t *d_status,
                                          void *stream);
 
+/* 64-bit integers (section 1: the format applies to 64-bit integers too).
+ * A code has at most 10 bytes, the tenth carrying bit 63; ten consecutive
+ * continuation bytes are VBYTE_EMALFORMED; a tenth byte above 1 is accepted
+ * and only its low bit counts (its weight 2^63 wraps mod 2^64); the
+ * differential form is out[i] = prev + g_0 + ... + g_i mod 2^64.
+ *   bytes: device, any alignment; out: device uint64[n], 8-byte aligned.
+ * Statuses, exact consumption, precedence and the synchronous/asynchronous
+ * split as in vbyte_decode(_async); nothing is written outside out[0..n)
+ * and no byte outside bytes[0..nbytes) is read.  Uses at most 2 segments
+ * per wavefront of the current tuning. */
+vbyte_status vbyte_decode64(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n);
+vbyte_status vbyte_decode64_delta(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
+                                  uint64_t prev);
+vbyte_status vbyte_decode64_async(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
+                                  int32_t *d_status, void *stream);
+vbyte_status vbyte_decode64_delta_async(const uint8_t *bytes, size_t nbytes, uint64_t *out,
+                                        size_t n, uint64_t prev, int32_t *d_status, void *stream);
+
 /* Resumable decode in pieces (section 5 decodes long lists piece by piece
  * into a buffer that stays in cache): each call decodes the next piece of at
  * most k integers of bytes[0..nbytes) into out[0..k), starting where the

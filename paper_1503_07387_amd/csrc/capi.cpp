@@ -167,6 +167,60 @@ vbyte_status decode_sync(const uint8_t *bytes, size_t nbytes, uint32_t *out, siz
     return (vbyte_status)h;
 }
 
+// Enqueues a 64-bit single-stream decode (reading R13); status as in
+// decode_stream.
+vbyte_status decode64_stream(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
+                             uint64_t prev, int delta, int32_t *d_status, hipStream_t s,
+                             int32_t **slot = nullptr) {
+    if (nbytes >= kMaxBytes) return VBYTE_EINVAL;
+    if (nbytes > 0 && !bytes) return VBYTE_EINVAL;
+    if (n > 0 && !out) return VBYTE_EINVAL;
+    if (((uintptr_t)out & 7u) != 0) return VBYTE_EINVAL;
+    if (((uintptr_t)d_status & 3u) != 0) return VBYTE_EINVAL;
+    if (!d_status && !slot) return VBYTE_EINVAL;
+    const int segs = std::min(g_segs.load(), 2), wpb = g_wpb.load();
+    Stream64Args a{};
+    a.vstart = (uintptr_t)bytes & 15u;
+    a.base = bytes - a.vstart;
+    a.vend = a.vstart + nbytes;
+    a.out = out;
+    a.n = n;
+    a.prev = prev;
+    const uint64_t unit = (uint64_t)segs * kSegBytes;
+    const uint64_t nunits = nbytes ? (a.vstart + nbytes + unit - 1) / unit : 0;
+    if (nunits >= (1ull << 31)) return VBYTE_EINVAL;
+    a.nunits = (uint32_t)nunits;
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, kHeaderBytes + nunits * 16, 0, &w);
+    if (st != VBYTE_OK) return st;
+    if (!d_status) {
+        d_status = (int32_t *)(ws_base(w) + kStatusOff);
+        *slot = d_status;
+    }
+    if (nbytes == 0) {
+        hipError_t e = launch_set_status(d_status, n == 0 ? VBYTE_OK : VBYTE_ETRUNC, s);
+        return e == hipSuccess ? VBYTE_OK : hip_fail(e, "set status");
+    }
+    a.slots = (uint4 *)(ws_base(w) + kHeaderBytes);
+    a.d_status = d_status;
+    hipError_t e = launch64(a, delta, segs, wpb, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode64 launch");
+}
+
+vbyte_status decode64_sync(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
+                           uint64_t prev, int delta) {
+    hipStream_t s = nullptr;
+    int32_t *slot = nullptr;
+    vbyte_status st = decode64_stream(bytes, nbytes, out, n, prev, delta, nullptr, s, &slot);
+    if (st != VBYTE_OK) return st;
+    int32_t h = -1;
+    hipError_t e = hipMemcpyAsync(&h, slot, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return (vbyte_status)h;
+}
+
 }  // namespace
 
 vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan) {
@@ -264,6 +318,25 @@ vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, ui
                                          size_t n, uint32_t prev, int32_t *d_status,
                                          void *stream) {
     return decode_stream(bytes, nbytes, out, n, prev, 2, d_status, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_decode64(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n) {
+    return decode64_sync(bytes, nbytes, out, n, 0, 0);
+}
+
+vbyte_status vbyte_decode64_delta(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
+                                  uint64_t prev) {
+    return decode64_sync(bytes, nbytes, out, n, prev, 1);
+}
+
+vbyte_status vbyte_decode64_async(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
+                                  int32_t *d_status, void *stream) {
+    return decode64_stream(bytes, nbytes, out, n, 0, 0, d_status, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_decode64_delta_async(const uint8_t *bytes, size_t nbytes, uint64_t *out,
+                                        size_t n, uint64_t prev, int32_t *d_status, void *stream) {
+    return decode64_stream(bytes, nbytes, out, n, prev, 1, d_status, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t k,

@@ -1184,6 +1184,339 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
         (void)run_tile<D, kKnownB, SEGS, true>(t, stage, sh, wib, wpb);
 }
 
+// ============================================================ 64-bit codes
+// The byte format for 64-bit integers (reading R13): up to ten 7-bit
+// groups, a run of ten continuation bytes is malformed, a tenth group
+// wraps mod 2^64, differences are summed mod 2^64.  Decoded in two passes
+// with no look-back, one unit of SEGS 1 KiB segments per wavefront:
+// k64_agg gives every unit its number of terminators, its byte sum (each
+// byte's group at weight 2^(7p), p the continuation bytes right before it,
+// capped at 9) and a malformed flag; k64_scan makes them exclusive prefixes
+// and writes the status; k64_known decodes every unit from its prefix plus
+// the code that straddles the unit's start (the same identity as the
+// 32-bit two-pass schedule).  A unit's wavefront needs no other wavefront.
+
+constexpr u32 kRow64Stride = 36;   // words per lane of u64 candidates (16-byte aligned rows)
+constexpr u32 kStage64Words = kWave * kRow64Stride;
+
+__device__ __forceinline__ int32_t sbyte(u32 w, u32 k) {   // byte k of w, sign-extended
+    return __builtin_amdgcn_sbfe((int32_t)w, 8 * k, 8);
+}
+
+// Continuation bytes right before a lane's byte 0 given the 12 bytes before
+// it (bytes -12..-1 in p1, p2, p3), capped at 9.
+__device__ __forceinline__ u32 run_before(u32 p1, u32 p2, u32 p3) {
+    const u32 cb = top4(p1) | (top4(p2) << 4) | (top4(p3) << 8);   // bit 11 = byte -1
+    const u32 r = (u32)__builtin_clz(~(cb << 20));
+    return r < 9 ? r : 9;
+}
+
+// A lane's 16 bytes into its running continuation count, byte sum and
+// malformed flag (a continuation byte with 9 continuation bytes before it).
+template <bool SUM>
+__device__ __forceinline__ void lane_bytes64(const u32 (&w)[4], u32 p1, u32 p2, u32 p3, u32 &cont,
+                                             u64 &sum, bool &mal) {
+    u32 pos = run_before(p1, p2, p3);
+    cont += __builtin_popcount(top16(w));
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const u32 b = (w[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        if (SUM) sum += (u64)(b & 0x7Fu) << (7 * pos);
+        const bool c = b >= 0x80u;
+        mal |= c && pos >= 9;
+        pos = c ? (pos < 9 ? pos + 1 : 9) : 0;
+    }
+}
+
+// 12 bytes from v (a multiple of 4), zero outside [lo, hi).
+__device__ __forceinline__ void load12(const u8 *base, i64 v, u64 lo, u64 hi, bool guarded,
+                                       u32 (&w)[3], u32 &valid) {
+    valid = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (guarded) {
+            u32 vk;
+            load4_guarded(base, v + 4 * k, lo, hi, w[k], vk);
+            valid |= vk << (4 * k);
+        } else {
+            w[k] = *(const u32 *)(base + v + 4 * k);
+            valid |= 0xFu << (4 * k);
+        }
+    }
+}
+
+// Wavefront sum of 64-bit values.
+__device__ __forceinline__ u64 wave_sum64(u64 x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, kWave);
+    return x;
+}
+
+template <int D, int SEGS>
+__global__ __launch_bounds__(kMaxBlock) void k64_agg(Stream64Args a) {
+    constexpr u32 W = SEGS * kSegBytes;
+    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
+    const u64 u = (u64)blockIdx.x * wpb + wib;
+    if (u >= a.nunits) return;   // whole wavefronts only: no workgroup barrier below
+    const u64 wv = u * W;
+    const bool interior = u > 0 && wv + W <= a.vend;   // the unit and 12 bytes before it are inside
+    u32 w[SEGS][4], valid, bl[3], blv;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
+        if (interior)
+            load16(a.base + v, w[s]);
+        else
+            load16_guarded(a.base, v, a.vstart, a.vend, w[s], valid);
+    }
+    load12(a.base, (i64)wv - 12, a.vstart, a.vend, !interior, bl, blv);
+    u32 cont = 0;
+    u64 sum = 0;
+    bool mal = false;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 p1 = from_lane_below(w[s][1], s == 0 ? bl[0] : read_lane(w[s - 1][1], 63));
+        const u32 p2 = from_lane_below(w[s][2], s == 0 ? bl[1] : read_lane(w[s - 1][2], 63));
+        const u32 p3 = from_lane_below(w[s][3], s == 0 ? bl[2] : read_lane(w[s - 1][3], 63));
+        lane_bytes64<D != 0>(w[s], p1, p2, p3, cont, sum, mal);
+    }
+    cont = wave_sum(cont);
+    if (D) sum = wave_sum64(sum);
+    const bool wmal = ballot(mal) != 0;
+    if (ln == 0) {
+        const u64 lo = wv > a.vstart ? wv : a.vstart;
+        const u64 hi = wv + W < a.vend ? wv + W : a.vend;
+        const u32 terms = (u32)(hi - lo) - cont;
+        a.slots[u] = make_uint4(terms, wmal ? 1u : 0u, (u32)sum, (u32)(sum >> 32));
+    }
+}
+
+// Inclusive wavefront scan of 64-bit values.
+__device__ __forceinline__ u64 wave_scan64(u64 x) {
+    const u32 ln = lane_id();
+#pragma unroll
+    for (u32 d = 1; d < kWave; d <<= 1) {
+        const u64 y = __shfl_up(x, d, kWave);
+        if (ln >= d) x += y;
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k64_scan(Stream64Args a) {
+    __shared__ u32 wc[kScanBlock / kWave], wm[kScanBlock / kWave];
+    __shared__ u64 ws[kScanBlock / kWave];
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u8 last = tid == 0 ? a.base[a.vend - 1] : 0;
+    u64 carry_c = 0, carry_s = a.prev;
+    bool carry_m = false;
+    for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScanBlock * kScanPer) {
+        const u64 i0 = b0 + (u64)tid * kScanPer;
+        uint4 q[kScanPer];
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k)
+            q[k] = i0 + k < a.nunits ? a.slots[i0 + k] : make_uint4(0, 0, 0, 0);
+        u32 lc = 0;
+        u64 ls = 0;
+        bool m = false;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            lc += q[k].x;
+            ls += q[k].z | ((u64)q[k].w << 32);
+            m |= q[k].y != 0;
+        }
+        // 64 x 8 units' counts fit 32 bits
+        const u32 ci = wave_scan(lc);
+        const u64 si = wave_scan64(ls);
+        const bool anym = ballot(m) != 0;
+        if (ln == kWave - 1) {
+            wc[wib] = ci;
+            ws[wib] = si;
+            wm[wib] = anym ? 1u : 0u;
+        }
+        __syncthreads();
+        u64 pc = carry_c, rc = carry_c, ps = carry_s, rs = carry_s;
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
+            if (k < wib) {
+                pc += wc[k];
+                ps += ws[k];
+            }
+            rc += wc[k];
+            rs += ws[k];
+            carry_m |= wm[k] != 0;
+        }
+        carry_c = rc;
+        carry_s = rs;
+        pc += ci - lc;
+        ps += si - ls;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (i0 + k < a.nunits)
+                a.slots[i0 + k] = make_uint4((u32)pc, (u32)(pc >> 32), (u32)ps, (u32)(ps >> 32));
+            pc += q[k].x;
+            ps += q[k].z | ((u64)q[k].w << 32);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *a.d_status = final_status(carry_m, last, carry_c, a.n);
+}
+
+// Assembly of a lane's 64-bit codes from byte 24 down to byte 0 of the
+// window "own 16 bytes, then the 9 after" (a0, a1 and byte 0 of a2): the
+// Horner form of the sum, acc = ((acc << 7) | 0x7F) & sext(byte), in 64
+// bits.  Plain: r[j] = acc at byte j; DELTA: r[j] = -(sum of the integers of
+// emitted codes beginning after byte j), and the lane sum is returned.
+template <bool DELTA>
+__device__ __forceinline__ u64 horner64(const u32 (&w)[4], u32 a0, u32 a1, u32 a2, u32 emit,
+                                        u64 (&r)[16]) {
+    u64 acc = (u64)(i64)sbyte(a2, 0) & 0x7Fu;
+#define VB64_STEP(WORD, K) acc = ((acc << 7) | 0x7Fu) & (u64)(i64)sbyte((WORD), (K));
+    VB64_STEP(a1, 3) VB64_STEP(a1, 2) VB64_STEP(a1, 1) VB64_STEP(a1, 0)
+    VB64_STEP(a0, 3) VB64_STEP(a0, 2) VB64_STEP(a0, 1) VB64_STEP(a0, 0)
+#undef VB64_STEP
+    u64 nu = 0;
+#pragma unroll
+    for (int j = 15; j >= 0; --j) {
+        acc = ((acc << 7) | 0x7Fu) & (u64)(i64)sbyte(w[j >> 2], j & 3);
+        if (DELTA) {
+            r[j] = nu;
+            if ((emit >> j) & 1u) nu -= acc;
+        } else {
+            r[j] = acc;
+        }
+    }
+    return 0 - nu;
+}
+
+template <int D, int SEGS>
+__global__ __launch_bounds__(kMaxBlock) void k64_known(Stream64Args a) {
+    constexpr bool DELTA = D != 0;
+    constexpr u32 W = SEGS * kSegBytes;
+    extern __shared__ __align__(16) u32 lds[];
+    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
+    const u64 u = (u64)blockIdx.x * wpb + wib;
+    if (u >= a.nunits) return;   // whole wavefronts only: no workgroup barrier below
+    u32 *rows = lds + wib * kStage64Words;
+    const u64 wv = u * W;
+    // interior: the unit, 12 bytes before and 12 after lie inside the stream
+    const bool interior = u > 0 && wv + W + 12 <= a.vend;
+    u32 w[SEGS][4], valid[SEGS], bl[3], blv, af[3], afv;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
+        if (interior) {
+            load16(a.base + v, w[s]);
+            valid[s] = 0xFFFFu;
+        } else {
+            load16_guarded(a.base, v, a.vstart, a.vend, w[s], valid[s]);
+        }
+    }
+    load12(a.base, (i64)wv - 12, a.vstart, a.vend, !interior, bl, blv);
+    load12(a.base, (i64)(wv + W), a.vstart, a.vend, !interior, af, afv);
+    const uint4 pre = a.slots[u];
+    u64 cnt = pre.x | ((u64)pre.y << 32);
+    u64 sum = pre.z | ((u64)pre.w << 32);   // the scan started from prev
+    {
+        // the code that begins before the unit and ends in it
+        const u32 p0 = run_before(bl[0], bl[1], bl[2]);
+        if (p0) {
+            cnt += 1;
+            const u32 f[3] = {read_lane(w[0][0], 0), read_lane(w[0][1], 0), read_lane(w[0][2], 0)};
+            u64 rest = 0;
+            for (u32 j = 0; j < 12; ++j) {
+                const u32 b = (f[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+                const u32 sh = 7u * (p0 + j);
+                if (sh < 64) rest += (u64)(b & 0x7Fu) << sh;
+                if (b < 0x80u) break;
+            }
+            sum += rest;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 lw = s == 0 ? bl[2] : read_lane(w[s - 1][3], 63);
+        const u32 below = from_lane_below(w[s][3], lw);
+        bool below_ok = true;
+        if (!interior) {
+            const u32 lv = s == 0 ? (blv >> 8) << 12 : read_lane(valid[s - 1], 63);
+            below_ok = ((from_lane_below(valid[s], lv) >> 15) & 1u) != 0;
+        }
+        const bool ls = s + 1 < SEGS;
+        const u32 a0 = from_lane_above(w[s][0], ls ? read_lane(w[s + 1][0], 0) : af[0]);
+        const u32 a1 = from_lane_above(w[s][1], ls ? read_lane(w[s + 1][1], 0) : af[1]);
+        const u32 a2 = from_lane_above(w[s][2], ls ? read_lane(w[s + 1][2], 0) : af[2]);
+        const u32 top = top16(w[s]);
+        const u32 term = ~top & valid[s] & 0xFFFFu;
+        const u32 tb = below_ok ? ((below >> 31) ^ 1u) : 1u;   // byte -1 ends a code or is outside
+        u32 emit;
+        if (interior) {
+            emit = ((term << 1) | tb) & 0xFFFFu;
+        } else {
+            // a code counts only if its terminator is in the stream: within
+            // the lane's 16 bytes or the 9 after them
+            u32 av = from_lane_above(valid[s], ls ? read_lane(valid[s + 1], 0) : afv) & 0x1FFu;
+            const u32 ta = ~(top4(a0) | (top4(a1) << 4) | (top4(a2) << 8)) & av;
+            const u32 t25 = term | (ta << 16);
+            const u32 start = ((((term | ~valid[s]) << 1) | tb) & valid[s]) & 0xFFFFu;
+            const u32 hi = 31u - (u32)__builtin_clz(t25 | 1u);
+            emit = t25 ? start & ((2u << hi) - 1u) : 0u;
+        }
+        u64 r[16];
+        const u64 tl = horner64<DELTA>(w[s], a0, a1, a2, emit, r);
+        const u32 cl = __builtin_popcount(emit);
+        const u32 ci = wave_scan(cl);
+        const u32 segcnt = read_lane(ci, 63);
+        if (DELTA) {
+            const u64 si = wave_scan64(tl);
+            const u64 add = sum + si;   // exclusive lane sum + the lane's own sum
+#pragma unroll
+            for (int j = 0; j < 16; ++j) r[j] += add;
+            sum += (u64)read_lane((u32)si, 63) | ((u64)read_lane((u32)(si >> 32), 63) << 32);
+        }
+        if (cnt < a.n && segcnt) {
+            // candidates to LDS rows, then one masked 8-byte store per lane
+            // for each 64-byte row of input bytes
+            u64 *row = (u64 *)(rows + ln * kRow64Stride);
+#pragma unroll
+            for (int j = 0; j < 16; j += 2)
+                *(uint4 *)(row + j) = make_uint4((u32)r[j], (u32)(r[j] >> 32), (u32)r[j + 1],
+                                                 (u32)(r[j + 1] >> 32));
+            wave_lds_sync();
+            const u64 lim = a.n - cnt;
+            u64 rowbase = 0;
+            for (u32 k = 0; k < 16; ++k) {
+                const u64 mask = (u64)read_lane(emit, 4 * k) | ((u64)read_lane(emit, 4 * k + 1) << 16) |
+                                 ((u64)read_lane(emit, 4 * k + 2) << 32) |
+                                 ((u64)read_lane(emit, 4 * k + 3) << 48);
+                if (!mask) continue;
+                const u32 below_in_row = __builtin_amdgcn_mbcnt_hi(
+                    (u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+                const u64 slot = rowbase + below_in_row;
+                if (((mask >> ln) & 1u) && slot < lim) {
+                    const u32 src = (4 * k + (ln >> 4)) * kRow64Stride + 2 * (ln & 15);
+                    const u64 v = *(const u64 *)(rows + src);
+                    a.out[cnt + slot] = v;
+                }
+                rowbase += __builtin_popcountll(mask);
+            }
+            wave_lds_sync();
+        }
+        cnt += segcnt;
+    }
+}
+
+template <int D, int SEGS>
+hipError_t launch64_t(const Stream64Args &a, int wpb, hipStream_t s) {
+    const u32 blocks = (a.nunits + wpb - 1) / wpb;
+    k64_agg<D, SEGS><<<blocks, wpb * kWave, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k64_scan<<<1, kScanBlock, 0, s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k64_known<D, SEGS><<<blocks, wpb * kWave, (size_t)wpb * kStage64Words * sizeof(u32), s>>>(a);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ batched lists
 struct ListDesc {
     i64 bb, be, ob, n;
@@ -1699,6 +2032,14 @@ hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int seg
         case 1: return launch_stream_s<1>(a, delta, count_only, wpb, s);
         case 2: return launch_stream_s<2>(a, delta, count_only, wpb, s);
         case 4: return launch_stream_s<4>(a, delta, count_only, wpb, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch64(const Stream64Args &a, int delta, int segs, int wpb, hipStream_t s) {
+    switch (segs) {
+        case 1: return delta ? launch64_t<1, 1>(a, wpb, s) : launch64_t<0, 1>(a, wpb, s);
+        case 2: return delta ? launch64_t<1, 2>(a, wpb, s) : launch64_t<0, 2>(a, wpb, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -71,6 +71,20 @@ struct StreamArgs {
     uint64_t *scratch;
 };
 
+// Single-stream decode of 64-bit codes (reading R13), in units of SEGS
+// segments per wavefront with one 16-byte slot per unit in `slots`.
+struct Stream64Args {
+    const uint8_t *base;   // 16-byte aligned, <= bytes
+    uint64_t vstart;       // bytes - base (0..15)
+    uint64_t vend;         // vstart + nbytes
+    uint64_t *out;
+    uint64_t n;
+    uint64_t prev;
+    uint32_t nunits;
+    uint4 *slots;
+    int32_t *d_status;
+};
+
 // One list of a batched launch, resolved on the device from either CSR
 // offsets or gather rows.
 struct ListArgs {
@@ -126,6 +140,9 @@ hipError_t launch_chunks(const StreamArgs &a, int delta, int segs, int wpb, uint
 // a one-workgroup scan that also writes the status, decode with the prefix
 // known); one descriptor slot per tile.
 hipError_t launch_two_pass(const StreamArgs &a, int delta, int segs, int wpb, hipStream_t s);
+// 64-bit decode: unit aggregates, a one-workgroup scan (status), decode;
+// segs 1 or 2.
+hipError_t launch64(const Stream64Args &a, int delta, int segs, int wpb, hipStream_t s);
 hipError_t launch_encode(const EncodeArgs &a, hipStream_t s);
 hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
                                 uint64_t nb, hipStream_t s);

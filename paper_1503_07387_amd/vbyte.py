@@ -23,7 +23,9 @@ STATUS_NAMES = {OK: "VBYTE_OK", EINVAL: "VBYTE_EINVAL", ECOUNT: "VBYTE_ECOUNT",
 
 EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_decode_delta_async", "vbyte_decode_delta_m1", "vbyte_decode_delta_m1_async",
-           "vbyte_encode_delta_m1_async", "vbyte_decode_next_async", "vbyte_count", "vbyte_decode_batch",
+           "vbyte_encode_delta_m1_async", "vbyte_decode_next_async", "vbyte_decode64",
+           "vbyte_decode64_delta", "vbyte_decode64_async", "vbyte_decode64_delta_async",
+           "vbyte_count", "vbyte_decode_batch",
            "vbyte_decode_lists", "vbyte_encode_async", "vbyte_encode_delta_async",
            "vbyte_encode_batch", "vbyte_server_create", "vbyte_server_destroy",
            "vbyte_server_run", "vbyte_batch_graph_create", "vbyte_batch_graph_launch",
@@ -79,6 +81,10 @@ def _declare(lib):
         "vbyte_decode_delta_m1": [vp, sz, vp, sz, u32],
         "vbyte_decode_delta_m1_async": [vp, sz, vp, sz, u32, vp, vp],
         "vbyte_decode_next_async": [vp, sz, vp, sz, i32, vp, vp, vp, vp],
+        "vbyte_decode64": [vp, sz, vp, sz],
+        "vbyte_decode64_delta": [vp, sz, vp, sz, c.c_uint64],
+        "vbyte_decode64_async": [vp, sz, vp, sz, vp, vp],
+        "vbyte_decode64_delta_async": [vp, sz, vp, sz, c.c_uint64, vp, vp],
         "vbyte_encode_delta_m1_async": [vp, sz, u32, vp, sz, vp, vp],
         "vbyte_count": [vp, sz, vp, vp],
         "vbyte_decode_batch": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, vp],
@@ -174,6 +180,34 @@ def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=No
         v = int(status.item())
         if v != OK:
             raise VByteError(v, "decode")
+    return out[:n]
+
+
+def decode64(data, n, *, delta=False, prev=0, out=None, status=None, stream=None, check=True):
+    """Decode ``n`` uint64 from the 64-bit VByte bytes ``data`` (uint8 CUDA
+    tensor; codes of up to 10 bytes).  ``delta``: inclusive prefix sum from
+    ``prev`` mod 2^64.  Returns an int64 tensor holding the uint64 bits;
+    ``check`` as in decode()."""
+    _dev_u8(data)
+    n = int(n)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=data.device)
+    elif out.dtype != torch.int64 or out.numel() < n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int64 tensor of at least n elements")
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=data.device)
+    s = _stream(stream)
+    L = _lib()
+    if delta:
+        st = L.vbyte_decode64_delta_async(_ptr(data), data.numel(), _ptr(out), n,
+                                          int(prev) & 0xFFFFFFFFFFFFFFFF, _ptr(status), s)
+    else:
+        st = L.vbyte_decode64_async(_ptr(data), data.numel(), _ptr(out), n, _ptr(status), s)
+    _check_call(st, "decode64")
+    if check:
+        v = int(status.item())
+        if v != OK:
+            raise VByteError(v, "decode64")
     return out[:n]
 
 
