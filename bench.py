@@ -202,6 +202,43 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
     return out
 
 
+def bench_decode64(torch, vbyte, streams, reps=10):
+    """64-bit differential decode (vbyte_decode64_delta, reading R13) of the
+    gap-mean-300 stream.  Codes of values below 2^32 are the same bytes in
+    both widths, so the stream is a valid 64-bit code stream; decoding it from
+    prev = 2^40 gives 64-bit identifiers.  Checked against a 64-bit cumsum."""
+    s = streams[1]
+    n = N_STREAM
+    prev = 1 << 40
+    vbyte.set_tuning(2, 8, 0)
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    vbyte.decode64(s["bytes"], n, delta=True, prev=prev, out=out, status=st, check=True)
+    ref = torch.cumsum(s["gaps_dev"].to(torch.int64) & 0xFFFFFFFF, 0) + prev
+    if not torch.equal(ref, out):
+        raise RuntimeError("64-bit decode differs from the 64-bit prefix sum")
+    del ref
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(reps):
+        e0.record()
+        vbyte.decode64(s["bytes"], n, delta=True, prev=prev, out=out, status=st, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    if int(st.item()) != 0:
+        raise RuntimeError("64-bit decode status")
+    avg = sum(ms) / len(ms)
+    alg = s["bytes"].numel() + 8 * n
+    return {"workload": "64-bit differential decode of the 64Mi-gap stream (gap mean 300) from "
+                        "prev 2^40: uint64 identifiers, 8-byte outputs",
+            "n": n, "bytes_in": int(s["bytes"].numel()), "tuning": "segs 2, waves 8",
+            "kernels": "k64_agg + k64_scan + k64_known", "ms": round(avg, 4),
+            "gints_per_s": round(n / (avg / 1e3) / 1e9, 2),
+            "alg_gbps": round(alg / (avg / 1e3) / 1e9, 1),
+            "pct_hbm_peak": round(100 * alg / (avg / 1e3) / 1e9 / HBM_PEAK_GBPS, 1)}
+
+
 def build_index(torch, vbyte, workloads):
     """Config 3: 100,000 Zipf-length lists of gaps, VByte-encoded on the GPU
     with per-list byte offsets."""
@@ -452,10 +489,55 @@ def summarize_trace(trace_csv, stats_csv, out_md, command_line):
     return {"calls": len(calls), "kernels": names}
 
 
+PROFILE_TRACE64 = os.path.join(ROOT, "profiles", "decode64_delta_64Mi_kernel_trace.md")
+DECODE64_KERNELS = ("k64_agg<", "k64_scan", "k64_known<")
+
+
+def summarize_trace64(trace_csv, out_md, command_line):
+    """Per-call durations of the 64-bit decode's kernels (the decode64 line of
+    bench.py) from a rocprofv3 --kernel-trace run."""
+    import csv
+    rows = [r for r in csv.DictReader(open(trace_csv))
+            if any(k in r["Kernel_Name"] for k in DECODE64_KERNELS)]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    calls, cur = [], []
+    for r in rows:
+        cur.append(r)
+        if "k64_known<" in r["Kernel_Name"]:
+            calls.append(cur)
+            cur = []
+
+    def dur(r):
+        return (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+
+    names = []
+    for r in rows:
+        if short_kernel(r["Kernel_Name"]) not in names:
+            names.append(short_kernel(r["Kernel_Name"]))
+    with open(out_md, "w") as fh:
+        fh.write("# Kernel trace: 64-bit differential decode of the 64Mi-gap stream (gap mean 300)\n\n")
+        fh.write("Command (run from the repository root on one MI355X):\n\n")
+        fh.write(f"    {command_line}\n\n")
+        span = [(int(c[-1]["End_Timestamp"]) - int(c[0]["Start_Timestamp"])) / 1e3 for c in calls]
+        ksum = [sum(dur(r) for r in c) for c in calls]
+        fh.write("| calls | kernel sum avg us | span avg us | span min us | span max us |\n"
+                 "|---|---|---|---|---|\n")
+        if calls:
+            fh.write(f"| {len(calls)} | {sum(ksum) / len(ksum):.1f} | {sum(span) / len(span):.1f} | "
+                     f"{min(span):.1f} | {max(span):.1f} |\n")
+        fh.write("\nPer kernel (average us per call): " + ", ".join(
+            f"`{n}` {sum(dur(r) for c in calls for r in c if short_kernel(r['Kernel_Name']) == n) / max(len(calls), 1):.1f}"
+            for n in names) + "\n")
+    return {"calls": len(calls), "kernels": names}
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
         o = summarize_trace(sys.argv[2], sys.argv[3], PROFILE_TRACE, sys.argv[4])
         print(json.dumps(o))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace64":
+        print(json.dumps(summarize_trace64(sys.argv[2], PROFILE_TRACE64, sys.argv[3])))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
         fetch_csv, write_csv = sys.argv[2], sys.argv[3]
@@ -472,6 +554,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the config-3 batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the config-4 serving run")
+    ap.add_argument("--no-decode64", action="store_true", help="skip the 64-bit decode line")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's current tiling instead of autotuning each stream "
                          "(profiling runs: every decode dispatch then uses one tiling)")
@@ -595,6 +678,9 @@ def main():
                                            for s, t in zip(streams, tunings)),
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if not args.no_decode64:
+        log("64-bit decode ...")
+        res["decode64"] = bench_decode64(torch, vbyte, streams)
     if not (args.no_batched and args.no_serving):
         from paper_1503_07387_amd import serve
         idx = build_index(torch, vbyte, workloads)

@@ -186,12 +186,12 @@ vbyte_status decode64_stream(const uint8_t *bytes, size_t nbytes, uint64_t *out,
     a.out = out;
     a.n = n;
     a.prev = prev;
-    const uint64_t unit = (uint64_t)segs * kSegBytes;
+    const uint64_t unit = (uint64_t)kUnit64Groups * segs * kSegBytes;
     const uint64_t nunits = nbytes ? (a.vstart + nbytes + unit - 1) / unit : 0;
     if (nunits >= (1ull << 31)) return VBYTE_EINVAL;
     a.nunits = (uint32_t)nunits;
     Workspace *w = nullptr;
-    vbyte_status st = get_ws(s, kHeaderBytes + nunits * 16, 0, &w);
+    vbyte_status st = get_ws(s, kHeaderBytes + nunits * 16 * (1 + kUnit64Groups), 0, &w);
     if (st != VBYTE_OK) return st;
     if (!d_status) {
         d_status = (int32_t *)(ws_base(w) + kStatusOff);
@@ -202,6 +202,7 @@ vbyte_status decode64_stream(const uint8_t *bytes, size_t nbytes, uint64_t *out,
         return e == hipSuccess ? VBYTE_OK : hip_fail(e, "set status");
     }
     a.slots = (uint4 *)(ws_base(w) + kHeaderBytes);
+    a.gslots = a.slots + nunits;
     a.d_status = d_status;
     hipError_t e = launch64(a, delta, segs, wpb, s);
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode64 launch");

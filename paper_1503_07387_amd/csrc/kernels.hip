@@ -1188,15 +1188,19 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
 // The byte format for 64-bit integers (reading R13): up to ten 7-bit
 // groups, a run of ten continuation bytes is malformed, a tenth group
 // wraps mod 2^64, differences are summed mod 2^64.  Decoded in two passes
-// with no look-back, one unit of SEGS 1 KiB segments per wavefront:
+// with no look-back, one unit of kUnitGroups x SEGS 1 KiB segments per
+// wavefront (taken a group of SEGS segments at a time):
 // k64_agg gives every unit its number of terminators, its byte sum (each
 // byte's group at weight 2^(7p), p the continuation bytes right before it,
-// capped at 9) and a malformed flag; k64_scan makes them exclusive prefixes
-// and writes the status; k64_known decodes every unit from its prefix plus
-// the code that straddles the unit's start (the same identity as the
-// 32-bit two-pass schedule).  A unit's wavefront needs no other wavefront.
+// capped at 9) and a malformed flag, and every group of it its own
+// terminators and byte sum; k64_scan makes the units' totals exclusive
+// prefixes and writes the status; k64_known decodes one group per
+// wavefront from its unit's prefix, the groups before it in the unit and
+// the code that straddles the group's start (the same identity as the
+// 32-bit two-pass schedule).  No wavefront waits for another.
 
 constexpr u32 kRow64Stride = 36;   // words per lane of u64 candidates (16-byte aligned rows)
+constexpr u32 kUnitGroups = kUnit64Groups;   // groups of SEGS segments per unit, in turn
 constexpr u32 kStage64Words = kWave * kRow64Stride;
 
 __device__ __forceinline__ int32_t sbyte(u32 w, u32 k) {   // byte k of w, sign-extended
@@ -1226,6 +1230,36 @@ __device__ __forceinline__ void lane_bytes64(const u32 (&w)[4], u32 p1, u32 p2, 
         mal |= c && pos >= 9;
         pos = c ? (pos < 9 ? pos + 1 : 9) : 0;
     }
+}
+
+// The same for a wavefront whose bytes have at most one continuation byte
+// before them (no code longer than 2 bytes, no malformed run): the byte sum
+// is the groups' sum plus 127 times the groups that follow a continuation
+// byte (dot products over 0/1 byte marks, as in seg_bytes).  Returns false,
+// having done nothing, when some lane of the wavefront has a deeper byte.
+template <bool SUM>
+__device__ __forceinline__ bool lane_bytes64_short(const u32 (&w)[4], u32 p3, u32 &cont, u64 &sum) {
+    u32 c[5];
+    c[0] = (p3 >> 7) & 0x01010101u;
+    u32 any2 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k + 1] = (w[k] >> 7) & 0x01010101u;
+        any2 |= __builtin_amdgcn_alignbyte(c[k + 1], c[k], 3) & __builtin_amdgcn_alignbyte(c[k + 1], c[k], 2);
+    }
+    if (ballot(any2 != 0) != 0) return false;
+    u32 t0 = 0, t1 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        cont += __builtin_popcount(c[k + 1]);
+        if (SUM) {
+            const u32 g = w[k] & 0x7F7F7F7Fu;
+            t0 = __builtin_amdgcn_sad_u8(g, 0u, t0);
+            t1 = __builtin_amdgcn_udot4(g, __builtin_amdgcn_alignbyte(c[k + 1], c[k], 3), t1, false);
+        }
+    }
+    if (SUM) sum += (u64)t0 + 127ull * t1;
+    return true;
 }
 
 // 12 bytes from v (a multiple of 4), zero outside [lo, hi).
@@ -1258,37 +1292,46 @@ __global__ __launch_bounds__(kMaxBlock) void k64_agg(Stream64Args a) {
     const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
     const u64 u = (u64)blockIdx.x * wpb + wib;
     if (u >= a.nunits) return;   // whole wavefronts only: no workgroup barrier below
-    const u64 wv = u * W;
-    const bool interior = u > 0 && wv + W <= a.vend;   // the unit and 12 bytes before it are inside
-    u32 w[SEGS][4], valid, bl[3], blv;
-#pragma unroll
-    for (int s = 0; s < SEGS; ++s) {
-        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
-        if (interior)
-            load16(a.base + v, w[s]);
-        else
-            load16_guarded(a.base, v, a.vstart, a.vend, w[s], valid);
-    }
-    load12(a.base, (i64)wv - 12, a.vstart, a.vend, !interior, bl, blv);
-    u32 cont = 0;
-    u64 sum = 0;
+    u32 ucont = 0;
+    u64 usum = 0;
     bool mal = false;
+    for (u32 g = 0; g < kUnitGroups; ++g) {
+        const u64 wv = (u * kUnitGroups + g) * W;
+        if (wv >= a.vend) break;
+        // interior: the group and the 12 bytes before it are inside the stream
+        const bool interior = wv >= 1024 && wv + W <= a.vend;
+        u32 w[SEGS][4], valid, bl[3], blv;
 #pragma unroll
-    for (int s = 0; s < SEGS; ++s) {
-        const u32 p1 = from_lane_below(w[s][1], s == 0 ? bl[0] : read_lane(w[s - 1][1], 63));
-        const u32 p2 = from_lane_below(w[s][2], s == 0 ? bl[1] : read_lane(w[s - 1][2], 63));
-        const u32 p3 = from_lane_below(w[s][3], s == 0 ? bl[2] : read_lane(w[s - 1][3], 63));
-        lane_bytes64<D != 0>(w[s], p1, p2, p3, cont, sum, mal);
-    }
-    cont = wave_sum(cont);
-    if (D) sum = wave_sum64(sum);
-    const bool wmal = ballot(mal) != 0;
-    if (ln == 0) {
+        for (int s = 0; s < SEGS; ++s) {
+            const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
+            if (interior)
+                load16(a.base + v, w[s]);
+            else
+                load16_guarded(a.base, v, a.vstart, a.vend, w[s], valid);
+        }
+        load12(a.base, (i64)wv - 12, a.vstart, a.vend, !interior, bl, blv);
+        u32 cont = 0;
+        u64 sum = 0;
+#pragma unroll
+        for (int s = 0; s < SEGS; ++s) {
+            const u32 p1 = from_lane_below(w[s][1], s == 0 ? bl[0] : read_lane(w[s - 1][1], 63));
+            const u32 p2 = from_lane_below(w[s][2], s == 0 ? bl[1] : read_lane(w[s - 1][2], 63));
+            const u32 p3 = from_lane_below(w[s][3], s == 0 ? bl[2] : read_lane(w[s - 1][3], 63));
+            if (!lane_bytes64_short<D != 0>(w[s], p3, cont, sum))
+                lane_bytes64<D != 0>(w[s], p1, p2, p3, cont, sum, mal);
+        }
+        // the group's own terminators and byte sum, for k64_known
+        cont = wave_sum(cont);
+        if (D) sum = wave_sum64(sum);
         const u64 lo = wv > a.vstart ? wv : a.vstart;
         const u64 hi = wv + W < a.vend ? wv + W : a.vend;
         const u32 terms = (u32)(hi - lo) - cont;
-        a.slots[u] = make_uint4(terms, wmal ? 1u : 0u, (u32)sum, (u32)(sum >> 32));
+        if (ln == 0) a.gslots[u * kUnitGroups + g] = make_uint4(terms, 0u, (u32)sum, (u32)(sum >> 32));
+        ucont += terms;
+        usum += sum;
     }
+    const bool wmal = ballot(mal) != 0;
+    if (ln == 0) a.slots[u] = make_uint4(ucont, wmal ? 1u : 0u, (u32)usum, (u32)(usum >> 32));
 }
 
 // Inclusive wavefront scan of 64-bit values.
@@ -1324,7 +1367,7 @@ __global__ __launch_bounds__(kScanBlock) void k64_scan(Stream64Args a) {
             ls += q[k].z | ((u64)q[k].w << 32);
             m |= q[k].y != 0;
         }
-        // 64 x 8 units' counts fit 32 bits
+        // 64 x 8 units of at most 16 KiB: the counts fit 32 bits
         const u32 ci = wave_scan(lc);
         const u64 si = wave_scan64(ls);
         const bool anym = ballot(m) != 0;
@@ -1393,12 +1436,29 @@ __global__ __launch_bounds__(kMaxBlock) void k64_known(Stream64Args a) {
     constexpr u32 W = SEGS * kSegBytes;
     extern __shared__ __align__(16) u32 lds[];
     const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
-    const u64 u = (u64)blockIdx.x * wpb + wib;
-    if (u >= a.nunits) return;   // whole wavefronts only: no workgroup barrier below
+    // one group of SEGS segments per wavefront: group gi = unit uu, group g of it
+    const u64 gi = (u64)blockIdx.x * wpb + wib;
+    const u64 wv = gi * W;
+    if (wv >= a.vend) return;   // whole wavefronts only: no workgroup barrier below
     u32 *rows = lds + wib * kStage64Words;
-    const u64 wv = u * W;
-    // interior: the unit, 12 bytes before and 12 after lie inside the stream
-    const bool interior = u > 0 && wv + W + 12 <= a.vend;
+    const u64 uu = gi / kUnitGroups;
+    const u32 g = (u32)(gi % kUnitGroups);
+    // prefix: the unit's (scanned from prev) plus the groups before g in it
+    const uint4 pre = a.slots[uu];
+    u64 cnt = pre.x | ((u64)pre.y << 32);
+    u64 sum = pre.z | ((u64)pre.w << 32);
+    {
+        u64 gc = 0, gs = 0;
+        if (ln < g) {
+            const uint4 q = a.gslots[uu * kUnitGroups + ln];
+            gc = q.x;
+            gs = q.z | ((u64)q.w << 32);
+        }
+        cnt += wave_sum64(gc);
+        sum += wave_sum64(gs);
+    }
+    // interior: the group, 12 bytes before and 12 after lie inside the stream
+    const bool interior = wv >= 1024 && wv + W + 12 <= a.vend;
     u32 w[SEGS][4], valid[SEGS], bl[3], blv, af[3], afv;
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
@@ -1412,11 +1472,8 @@ __global__ __launch_bounds__(kMaxBlock) void k64_known(Stream64Args a) {
     }
     load12(a.base, (i64)wv - 12, a.vstart, a.vend, !interior, bl, blv);
     load12(a.base, (i64)(wv + W), a.vstart, a.vend, !interior, af, afv);
-    const uint4 pre = a.slots[u];
-    u64 cnt = pre.x | ((u64)pre.y << 32);
-    u64 sum = pre.z | ((u64)pre.w << 32);   // the scan started from prev
     {
-        // the code that begins before the unit and ends in it
+        // the code that begins before the group and ends in it
         const u32 p0 = run_before(bl[0], bl[1], bl[2]);
         if (p0) {
             cnt += 1;
@@ -1513,7 +1570,9 @@ hipError_t launch64_t(const Stream64Args &a, int wpb, hipStream_t s) {
     k64_scan<<<1, kScanBlock, 0, s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k64_known<D, SEGS><<<blocks, wpb * kWave, (size_t)wpb * kStage64Words * sizeof(u32), s>>>(a);
+    const u64 ngroups = (a.vend + SEGS * kSegBytes - 1) / (SEGS * kSegBytes);
+    const u32 gblocks = (u32)((ngroups + wpb - 1) / wpb);
+    k64_known<D, SEGS><<<gblocks, wpb * kWave, (size_t)wpb * kStage64Words * sizeof(u32), s>>>(a);
     return hipGetLastError();
 }
 

@@ -71,8 +71,10 @@ struct StreamArgs {
     uint64_t *scratch;
 };
 
-// Single-stream decode of 64-bit codes (reading R13), in units of SEGS
-// segments per wavefront with one 16-byte slot per unit in `slots`.
+// Single-stream decode of 64-bit codes (reading R13), in units of
+// kUnit64Groups x SEGS segments per wavefront with one 16-byte slot per unit
+// in `slots`.
+constexpr int kUnit64Groups = 8;
 struct Stream64Args {
     const uint8_t *base;   // 16-byte aligned, <= bytes
     uint64_t vstart;       // bytes - base (0..15)
@@ -81,7 +83,8 @@ struct Stream64Args {
     uint64_t n;
     uint64_t prev;
     uint32_t nunits;
-    uint4 *slots;
+    uint4 *slots;    // per unit: its totals, then its exclusive prefix
+    uint4 *gslots;   // per group (kUnit64Groups per unit): its own totals
     int32_t *d_status;
 };
 

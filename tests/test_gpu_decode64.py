@@ -94,15 +94,16 @@ def test_fixed_length_mixes(lengths):
 @pytest.mark.parametrize("tiling", TILINGS)
 def test_unit_straddle(tiling):
     """A 10-byte (and a 6-byte) code at every phase across every lane,
-    segment and unit boundary."""
+    segment, group and unit boundary."""
     segs, wpb = tiling
     vbyte.set_tuning(segs, wpb, 0)
-    unit = segs * 1024
+    group = segs * 1024            # bytes a wavefront loads at once
+    unit = 8 * group               # bytes of one wavefront's unit (one slot)
     rng = np.random.default_rng(segs * 10 + wpb)
     for long_len in (10, 6):
         vals, pos = [], 0
         targets = sorted({k * 16 for k in range(1, 40)} | {k * 1024 for k in range(1, 6)} |
-                         {k * unit for k in range(1, 5)})
+                         {k * group for k in range(1, 5)} | {k * unit for k in range(1, 4)})
         for tgt in targets:
             for phase in range(long_len + 1):
                 start = tgt - phase
@@ -151,7 +152,7 @@ def test_statuses_match_oracle():
 @pytest.mark.parametrize("segs", [1, 2])
 def test_statuses_in_long_streams(segs):
     vbyte.set_tuning(segs, 4, 0)
-    unit = segs * 1024
+    unit = 8 * segs * 1024
     rng = np.random.default_rng(78)
     x = values64(rng, 40_000, (1, 2, 3, 9))
     b = oracle.encode64(x)
