@@ -97,6 +97,12 @@ def _declare(lib):
                                      c.c_size_t, c.POINTER(c.c_uint32), c.c_int,
                                      c.POINTER(c.c_int32)]
     lib.orc_decode_batch.restype = c.c_int
+    lib.orc_decode_delta4.argtypes = [c.POINTER(c.c_uint8), c.c_size_t, c.POINTER(c.c_uint32),
+                                      c.c_size_t, c.POINTER(c.c_uint32)]
+    lib.orc_decode_delta4.restype = c.c_int
+    lib.orc_encode_delta4.argtypes = [c.POINTER(c.c_uint32), c.c_size_t, c.POINTER(c.c_uint32),
+                                      c.POINTER(c.c_uint8)]
+    lib.orc_encode_delta4.restype = c.c_size_t
     u64p = c.POINTER(c.c_uint64)
     lib.orc_code_length64.argtypes = [c.c_uint64]
     lib.orc_code_length64.restype = c.c_int
@@ -235,6 +241,36 @@ def decode_batch(b, byte_off, out_off, prevs=None, delta=False, lib=None):
                               nlists, _u32p(pv) if pv is not None else None,
                               int(delta), _i32p(st_list))
     return int(st), out[:total], st_list[:nlists]
+
+
+# ---------------------------------------------------------------- blocks of four (R14)
+def _prev4(prev4):
+    if prev4 is None:
+        return None
+    p = np.ascontiguousarray(np.asarray(prev4, dtype=np.uint64).astype(np.uint32))
+    assert p.size == 4
+    return p
+
+
+def decode_delta4(b, n, prev4=None, lib=None):
+    """DEC then y_i = g_i + y_(i-4) mod 2^32 from the four values prev4
+    (zeros by default).  Returns (status, uint32 array)."""
+    lib = lib or load()
+    b = _as_u8(b)
+    p = _prev4(prev4)
+    y = np.zeros(max(int(n), 1), dtype=np.uint32)
+    st = lib.orc_decode_delta4(_u8p(b), b.size, _u32p(y), int(n), None if p is None else _u32p(p))
+    return int(st), y[:int(n)]
+
+
+def encode_delta4(x, prev4=None, lib=None):
+    """ENC of x_i - x_(i-4) mod 2^32 (x_(-4..-1) = prev4, zeros by default)."""
+    lib = lib or load()
+    x = _as_u32(x)
+    p = _prev4(prev4)
+    out = np.zeros(max(5 * x.size, 1), dtype=np.uint8)
+    nb = lib.orc_encode_delta4(_u32p(x), x.size, None if p is None else _u32p(p), _u8p(out))
+    return out[:nb].copy()
 
 
 # ---------------------------------------------------------------- 64-bit (R13)

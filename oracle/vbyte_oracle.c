@@ -34,6 +34,12 @@
  *   R12 a resumable piece of k integers is validated over its window of
  *       5k bytes (or the rest of the buffer); its cursor moves only on
  *       success.
+ *   R14 differences between blocks of four (section 1, "Differential
+ *       coding": x_1, ..., x_4, x_5 - x_1, x_6 - x_2, ...): y_i = g_i +
+ *       y_(i-4) mod 2^32, the four values before the stream given as prev4
+ *       (zero for a list coded from its start, which makes x_1..x_4 coded
+ *       as themselves); a stream continued from an earlier piece passes the
+ *       piece's last four values.
  *   R13 64-bit integers (section 1: the format applies to 64-bit integers
  *       as well): at most 10 bytes per code, the tenth carrying bit 63; ten
  *       or more consecutive continuation bytes -> EMALFORMED; a tenth byte
@@ -311,6 +317,36 @@ int orc_decode_batch(const uint8_t *bytes, const int64_t *byte_off,
         if (st > worst) worst = st;
     }
     return worst;
+}
+
+/* Differences between blocks of four (reading R14): y_i = g_i + y_(i-4)
+ * mod 2^32, with y_(-4..-1) = prev4[0..3] (all zero when prev4 is NULL). */
+int orc_decode_delta4(const uint8_t *b, size_t nbytes, uint32_t *y, size_t n,
+                      const uint32_t *prev4)
+{
+    int st = orc_decode(b, nbytes, y, n);
+    if (st != ORC_OK) return st;
+    uint32_t back[4] = {0, 0, 0, 0};   /* the value four positions earlier, by i mod 4 */
+    if (prev4)
+        for (int r = 0; r < 4; r++) back[r] = prev4[r];
+    for (size_t i = 0; i < n; i++) {
+        uint32_t v = y[i] + back[i % 4];
+        back[i % 4] = v;
+        y[i] = v;
+    }
+    return ORC_OK;
+}
+
+/* ENC of x_i - x_(i-4) (x_(-4..-1) = prev4, zero when NULL), mod 2^32. */
+size_t orc_encode_delta4(const uint32_t *x, size_t n, const uint32_t *prev4, uint8_t *dst)
+{
+    size_t pos = 0;
+    for (size_t i = 0; i < n; i++) {
+        uint32_t before = i >= 4 ? x[i - 4] : (prev4 ? prev4[i] : 0u);
+        uint32_t g = x[i] - before;
+        pos += orc_encode(&g, 1, dst + pos);
+    }
+    return pos;
 }
 
 /* ------------------------------------------------------------------------

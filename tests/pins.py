@@ -431,6 +431,52 @@ def pin_batch(lib):
     assert st == EINVAL
 
 
+# ---------------------------------------------------------------- blocks of four (R14)
+def pin_delta4_example_and_closed_form(lib):
+    # section 1's example: x_1..x_4 coded as themselves, then x_5 - x_1, ...
+    x = np.array([5, 9, 2, 7, 6, 11, 3, 9, 100, 12], np.uint32)
+    want = [5, 9, 2, 7, 1, 2, 1, 2, 94, 1]
+    assert oracle.encode_delta4(x, lib=lib).tobytes() == oracle.encode(np.array(want, np.uint32), lib=lib).tobytes()
+    st, y = oracle.decode_delta4(oracle.encode(np.array(want, np.uint32), lib=lib), len(want), lib=lib)
+    assert st == OK and np.array_equal(y, x)
+    # closed form: four interleaved wrapping prefix sums (numpy cumsum on a
+    # 4-column view) plus prev4, for ragged lengths too
+    rng = np.random.default_rng(44)
+    for n in (1, 3, 4, 5, 999, 4096, 10001):
+        g = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+        g[rng.random(n) < 0.5] >>= 20
+        prev4 = rng.integers(0, 1 << 32, 4, dtype=np.uint64).astype(np.uint32)
+        pad = np.zeros(-n % 4, np.uint32)
+        cols = np.concatenate([g, pad]).reshape(-1, 4)
+        ref = (np.cumsum(cols, axis=0, dtype=np.uint32) + prev4).reshape(-1)[:n]
+        st, y = oracle.decode_delta4(oracle.encode(g, lib=lib), n, prev4, lib=lib)
+        assert st == OK and np.array_equal(y, ref), n
+        # and Python integers mod 2^32
+        back = [int(v) for v in prev4]
+        for i in range(min(n, 300)):
+            back[i % 4] = (back[i % 4] + int(g[i])) % (1 << 32)
+            assert int(y[i]) == back[i % 4]
+
+
+def pin_delta4_roundtrip_and_resume(lib):
+    rng = np.random.default_rng(45)
+    x = rng.integers(0, 1 << 32, 20000, dtype=np.uint64).astype(np.uint32)
+    for prev4 in (None, [1, 2, 3, 0xFFFFFFFF]):
+        b = oracle.encode_delta4(x, prev4, lib=lib)
+        st, y = oracle.decode_delta4(b, x.size, prev4, lib=lib)
+        assert st == OK and np.array_equal(y, x)
+    # resuming after m values passes the last four of them
+    b = oracle.encode_delta4(x, lib=lib)
+    for m in (4, 5, 6, 7, 12345):
+        cut = oracle.encoded_size(np.concatenate([x[:4], x[4:m] - x[:m - 4]]).astype(np.uint32), lib=lib)
+        st1, y1 = oracle.decode_delta4(b[:cut], m, None, lib=lib)
+        st2, y2 = oracle.decode_delta4(b[cut:], x.size - m, x[m - 4:m], lib=lib)
+        assert st1 == st2 == OK and np.array_equal(np.concatenate([y1, y2]), x)
+    # statuses come from the byte stream alone
+    assert oracle.decode_delta4(b, x.size + 1, lib=lib)[0] == ETRUNC
+    assert oracle.decode_delta4(b, x.size - 1, lib=lib)[0] == ECOUNT
+
+
 # ---------------------------------------------------------------- 64-bit (R13)
 M64 = (1 << 64) - 1
 
@@ -550,4 +596,4 @@ ALL_PINS = [pin_table1, pin_fig1, pin_closed_form_boundaries, pin_length_closed_
             pin_status_readings,
             pin_fifth_byte_wrap, pin_overlong, pin_batch,
             pin64_closed_form_boundaries, pin64_protobuf, pin64_delta_bigint, pin64_statuses,
-            pin64_agrees_with_32]
+            pin64_agrees_with_32, pin_delta4_example_and_closed_form, pin_delta4_roundtrip_and_resume]

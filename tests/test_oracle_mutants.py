@@ -47,6 +47,13 @@ MUTANTS = [
     ("batch_m1_as_delta", "int st = delta == 2 ? orc_decode_delta_m1(b, nb, y, n, prev)",
      "int st = delta == 3 ? orc_decode_delta_m1(b, nb, y, n, prev)"),
     ("batch_no_einval", "return ORC_EINVAL;\n    }\n    int worst", "(void)0;\n    }\n    int worst"),
+    ("d4_stride2", "uint32_t v = y[i] + back[i % 4];\n        back[i % 4] = v;",
+     "uint32_t v = y[i] + back[i % 2];\n        back[i % 2] = v;"),
+    ("d4_no_prev", "for (int r = 0; r < 4; r++) back[r] = prev4[r];", "(void)0;"),
+    ("d4_prev_reversed", "for (int r = 0; r < 4; r++) back[r] = prev4[r];",
+     "for (int r = 0; r < 4; r++) back[r] = prev4[3 - r];"),
+    ("encd4_stride3", "uint32_t before = i >= 4 ? x[i - 4] : (prev4 ? prev4[i] : 0u);",
+     "uint32_t before = i >= 3 ? x[i - 3] : (prev4 ? prev4[i] : 0u);"),
     ("len64_nine", "while (len < 10 && (x >> (7 * len)) != 0) len++;",
      "while (len < 9 && (x >> (7 * len)) != 0) len++;"),
     ("enc64_shift_8", "uint8_t group = (uint8_t)((x[i] >> (7 * j)) & 0x7Fu);",
