@@ -98,6 +98,20 @@ vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, ui
                                          size_t n, uint32_t prev, int32_t *d_status,
                                          void *stream);
 
+/* Differences between blocks of four (section 1, "Differential coding":
+ * x_1, x_2, x_3, x_4, x_5 - x_1, x_6 - x_2, ...): out[i] = g_i + out[i-4]
+ * mod 2^32, the four values before the stream taken from prev4[0..3] (a
+ * host array; NULL means zeros, which decodes a list coded from its start).
+ * To continue a stream decoded in parts, pass the last four values of the
+ * previous part.  Arguments, statuses and the synchronous/asynchronous
+ * split otherwise as in vbyte_decode_delta(_async).  Uses at most 2
+ * segments per wavefront of the current tuning. */
+vbyte_status vbyte_decode_delta4(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                 const uint32_t *prev4);
+vbyte_status vbyte_decode_delta4_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
+                                       size_t n, const uint32_t *prev4, int32_t *d_status,
+                                       void *stream);
+
 /* 64-bit integers (section 1: the format applies to 64-bit integers too).
  * A code has at most 10 bytes, the tenth carrying bit 63; ten consecutive
  * continuation bytes are VBYTE_EMALFORMED; a tenth byte above 1 is accepted

@@ -208,6 +208,46 @@ vbyte_status decode64_stream(const uint8_t *bytes, size_t nbytes, uint64_t *out,
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode64 launch");
 }
 
+// Enqueues a blocks-of-four decode (reading R14); status as in decode_stream.
+vbyte_status decode4_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                            const uint32_t *prev4, int32_t *d_status, hipStream_t s,
+                            int32_t **slot = nullptr) {
+    if (nbytes >= kMaxBytes) return VBYTE_EINVAL;
+    if (nbytes > 0 && !bytes) return VBYTE_EINVAL;
+    if (n > 0 && !out) return VBYTE_EINVAL;
+    if (((uintptr_t)out & 3u) != 0) return VBYTE_EINVAL;
+    if (((uintptr_t)d_status & 3u) != 0) return VBYTE_EINVAL;
+    if (!d_status && !slot) return VBYTE_EINVAL;
+    const int segs = std::min(g_segs.load(), 2), wpb = g_wpb.load();
+    Stream4Args a{};
+    a.vstart = (uintptr_t)bytes & 15u;
+    a.base = bytes - a.vstart;
+    a.vend = a.vstart + nbytes;
+    a.out = out;
+    a.n = n;
+    for (int k = 0; k < 4; ++k) a.prev4[k] = prev4 ? prev4[k] : 0u;
+    const uint64_t unit = (uint64_t)kUnit64Groups * segs * kSegBytes;
+    const uint64_t nunits = nbytes ? (a.vstart + nbytes + unit - 1) / unit : 0;
+    if (nunits >= (1ull << 31)) return VBYTE_EINVAL;
+    a.nunits = (uint32_t)nunits;
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, kHeaderBytes + nunits * 32 * (1 + kUnit64Groups), 0, &w);
+    if (st != VBYTE_OK) return st;
+    if (!d_status) {
+        d_status = (int32_t *)(ws_base(w) + kStatusOff);
+        *slot = d_status;
+    }
+    if (nbytes == 0) {
+        hipError_t e = launch_set_status(d_status, n == 0 ? VBYTE_OK : VBYTE_ETRUNC, s);
+        return e == hipSuccess ? VBYTE_OK : hip_fail(e, "set status");
+    }
+    a.slots = (uint4 *)(ws_base(w) + kHeaderBytes);
+    a.gslots = a.slots + 2 * nunits;
+    a.d_status = d_status;
+    hipError_t e = launch4(a, segs, wpb, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode_delta4 launch");
+}
+
 vbyte_status decode64_sync(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
                            uint64_t prev, int delta) {
     hipStream_t s = nullptr;
@@ -319,6 +359,26 @@ vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, ui
                                          size_t n, uint32_t prev, int32_t *d_status,
                                          void *stream) {
     return decode_stream(bytes, nbytes, out, n, prev, 2, d_status, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_decode_delta4(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                 const uint32_t *prev4) {
+    hipStream_t s = nullptr;
+    int32_t *slot = nullptr;
+    vbyte_status st = decode4_stream(bytes, nbytes, out, n, prev4, nullptr, s, &slot);
+    if (st != VBYTE_OK) return st;
+    int32_t h = -1;
+    hipError_t e = hipMemcpyAsync(&h, slot, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "status copy");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return (vbyte_status)h;
+}
+
+vbyte_status vbyte_decode_delta4_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
+                                       size_t n, const uint32_t *prev4, int32_t *d_status,
+                                       void *stream) {
+    return decode4_stream(bytes, nbytes, out, n, prev4, d_status, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_decode64(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n) {

@@ -1576,6 +1576,289 @@ hipError_t launch64_t(const Stream64Args &a, int wpb, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ============================================================ blocks of four
+// Differences between blocks of four (reading R14): y_i = g_i + y_(i-4),
+// i.e. four interleaved prefix sums by rank mod 4, from the four values
+// prev4.  A code's class is its rank mod 4, known only once the count of
+// the codes before it is, so a run of codes is summarised by (count, S[4])
+// with S[c] the sum of its codes of rank = c mod 4 counted from the run's
+// first code; two runs combine as (cA + cB, SA[c] + SB[(c - cA) mod 4]).
+// Same layout as the 64-bit decode: units of kUnitGroups groups of SEGS
+// segments, one group per wavefront; k4_agg summarises every group and
+// unit, k4_scan turns the units into exclusive prefixes (absolute classes,
+// from prev4) and writes the status, k4_known decodes one group per
+// wavefront.  Codes are counted exactly (those that begin in the group and
+// end in the stream), so no straddle correction is needed.
+
+struct Run4 {
+    u64 c;
+    u32 s[4];
+};
+
+// s rotated by r: t[c] = s[(c - r) mod 4]
+__device__ __forceinline__ void rot4(const u32 (&s)[4], u32 r, u32 (&t)[4]) {
+    r &= 3u;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const u32 k = (c - r) & 3u;
+        t[c] = k == 0 ? s[0] : k == 1 ? s[1] : k == 2 ? s[2] : s[3];
+    }
+}
+
+__device__ __forceinline__ Run4 join4(const Run4 &a, const Run4 &b) {
+    u32 t[4];
+    rot4(b.s, (u32)a.c, t);
+    return Run4{a.c + b.c, {a.s[0] + t[0], a.s[1] + t[1], a.s[2] + t[2], a.s[3] + t[3]}};
+}
+
+__device__ __forceinline__ void put4(uint4 *slot, const Run4 &r) {
+    slot[0] = make_uint4((u32)r.c, (u32)(r.c >> 32), r.s[0], r.s[1]);
+    slot[1] = make_uint4(r.s[2], r.s[3], 0u, 0u);
+}
+__device__ __forceinline__ Run4 get4(const uint4 *slot) {
+    const uint4 a = slot[0], b = slot[1];
+    return Run4{a.x | ((u64)a.y << 32), {a.z, a.w, b.x, b.y}};
+}
+
+// Add the lane's codes (flagged in emit, values u) to s by class, the first
+// of them of class `cls`; returns the class after the last.
+__device__ __forceinline__ u32 add_by_class(const u32 (&u)[16], u32 emit, u32 cls, u32 (&s)[4]) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if ((emit >> j) & 1u) {
+            s[0] += cls == 0 ? u[j] : 0u;
+            s[1] += cls == 1 ? u[j] : 0u;
+            s[2] += cls == 2 ? u[j] : 0u;
+            s[3] += cls == 3 ? u[j] : 0u;
+            cls = (cls + 1) & 3u;
+        }
+    }
+    return cls;
+}
+
+// One group's segments: masks and values of every segment, and what the
+// caller does with them (summary or decode).  Returns the malformed flag.
+struct D4Seg {
+    u32 emit;
+    u32 u[16];
+};
+
+template <bool EDGE, int SEGS, class F>
+__device__ __forceinline__ bool d4_group(const Stream4Args &a, u64 wv, F &&f) {
+    const u32 ln = lane_id();
+    u32 w[SEGS][4], valid[SEGS];
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
+        if (EDGE) {
+            load16_guarded(a.base, v, a.vstart, a.vend, w[s], valid[s]);
+        } else {
+            load16(a.base + v, w[s]);
+            valid[s] = 0xFFFFu;
+        }
+    }
+    u32 hb, hbv, ha, hav;
+    if (EDGE) {
+        load4_guarded(a.base, (i64)wv - 4, a.vstart, a.vend, hb, hbv);
+        load4_guarded(a.base, (i64)(wv + SEGS * kSegBytes), a.vstart, a.vend, ha, hav);
+    } else {
+        hb = *(const u32 *)(a.base + wv - 4);
+        ha = *(const u32 *)(a.base + wv + SEGS * kSegBytes);
+        hbv = hav = 0xFu;
+    }
+    bool mal = false;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 l0w = s == 0 ? hb : read_lane(w[s - 1][3], 63);
+        const u32 below = from_lane_below(w[s][3], l0w);
+        bool below_ok = true;
+        if (EDGE) {
+            const u32 l0v = s == 0 ? (hbv << 12) : read_lane(valid[s - 1], 63);
+            below_ok = ((from_lane_below(valid[s], l0v) >> 15) & 1u) != 0;
+        }
+        const u32 ab = from_lane_above(w[s][0], s + 1 < SEGS ? read_lane(w[s + 1][0], 0) : ha);
+        const u32 abv = EDGE ? from_lane_above(valid[s], s + 1 < SEGS ? read_lane(valid[s + 1], 0) : hav) & 0xFu
+                             : 0xFu;
+        const SegMask m = seg_mask<EDGE>(w[s], valid[s], below, below_ok, ab, abv);
+        mal |= m.mal;
+        D4Seg g;
+        g.emit = m.emit;
+        horner<false>(w[s], ab, m.emit, g.u);
+        f(g);
+    }
+    return mal;
+}
+
+template <int SEGS>
+__global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
+    constexpr u32 W = SEGS * kSegBytes;
+    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
+    const u64 u = (u64)blockIdx.x * wpb + wib;
+    if (u >= a.nunits) return;   // whole wavefronts only: no workgroup barrier below
+    Run4 unit{0, {0, 0, 0, 0}};
+    bool mal = false;
+    for (u32 g = 0; g < kUnitGroups; ++g) {
+        const u64 wv = (u * kUnitGroups + g) * W;
+        if (wv >= a.vend) break;
+        Run4 grp{0, {0, 0, 0, 0}};
+        auto f = [&](const D4Seg &sg) {
+            const u32 cl = __builtin_popcount(sg.emit);
+            const u32 ci = wave_scan(cl);
+            u32 s[4] = {0, 0, 0, 0};
+            add_by_class(sg.u, sg.emit, (u32)(grp.c + ci - cl) & 3u, s);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) grp.s[c] += wave_sum(s[c]);
+            grp.c += read_lane(ci, 63);
+        };
+        const bool interior = wv >= 16 && wv + W + 4 <= a.vend;
+        mal |= interior ? d4_group<false, SEGS>(a, wv, f) : d4_group<true, SEGS>(a, wv, f);
+        if (ln == 0) put4(a.gslots + 2 * (u * kUnitGroups + g), grp);
+        unit = join4(unit, grp);
+    }
+    const bool wmal = ballot(mal) != 0;
+    if (ln == 0) {
+        put4(a.slots + 2 * u, unit);
+        a.slots[2 * u + 1].z = wmal ? 1u : 0u;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k4_scan(Stream4Args a) {
+    __shared__ Run4 wtot[kScanBlock / kWave];
+    __shared__ u32 wm[kScanBlock / kWave];
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u8 last = tid == 0 ? a.base[a.vend - 1] : 0;
+    Run4 carry{0, {a.prev4[0], a.prev4[1], a.prev4[2], a.prev4[3]}};
+    bool carry_m = false;
+    for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScanBlock * kScanPer) {
+        const u64 i0 = b0 + (u64)tid * kScanPer;
+        Run4 mine{0, {0, 0, 0, 0}};
+        bool m = false;
+        for (int k = 0; k < kScanPer; ++k) {
+            if (i0 + k < a.nunits) {
+                mine = join4(mine, get4(a.slots + 2 * (i0 + k)));
+                m |= a.slots[2 * (i0 + k) + 1].z != 0;
+            }
+        }
+        // inclusive scan over the wavefront's lanes (lane order = unit order)
+        Run4 inc = mine;
+#pragma unroll
+        for (u32 d = 1; d < kWave; d <<= 1) {
+            Run4 o;
+            o.c = __shfl_up(inc.c, d, kWave);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o.s[c] = __shfl_up(inc.s[c], d, kWave);
+            if (ln >= d) inc = join4(o, inc);
+        }
+        const bool anym = ballot(m) != 0;
+        if (ln == kWave - 1) {
+            wtot[wib] = inc;
+            wm[wib] = anym ? 1u : 0u;
+        }
+        __syncthreads();
+        Run4 pre = carry;
+        for (u32 k = 0; k < wib; ++k) pre = join4(pre, wtot[k]);
+        // exclusive within the wavefront: the lane below's inclusive value
+        Run4 below;
+        below.c = __shfl_up(inc.c, 1, kWave);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) below.s[c] = __shfl_up(inc.s[c], 1, kWave);
+        if (ln > 0) pre = join4(pre, below);
+        for (int k = 0; k < kScanPer; ++k) {
+            if (i0 + k < a.nunits) {
+                const Run4 r = get4(a.slots + 2 * (i0 + k));
+                put4(a.slots + 2 * (i0 + k), pre);
+                pre = join4(pre, r);
+            }
+        }
+        Run4 tot = carry;
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
+            tot = join4(tot, wtot[k]);
+            carry_m |= wm[k] != 0;
+        }
+        carry = tot;
+        __syncthreads();
+    }
+    if (tid == 0) *a.d_status = final_status(carry_m, last, carry.c, a.n);
+}
+
+template <int SEGS>
+__global__ __launch_bounds__(kMaxBlock) void k4_known(Stream4Args a) {
+    constexpr u32 W = SEGS * kSegBytes;
+    extern __shared__ __align__(16) u32 lds[];
+    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
+    const u64 gi = (u64)blockIdx.x * wpb + wib;
+    const u64 wv = gi * W;
+    if (wv >= a.vend) return;   // whole wavefronts only: no workgroup barrier below
+    u32 *rows = lds + wib * kStageWords;
+    const u64 uu = gi / kUnitGroups;
+    const u32 g = (u32)(gi % kUnitGroups);
+    // prefix: the unit's (absolute classes, from prev4), then the groups
+    // before g in it
+    Run4 run = get4(a.slots + 2 * uu);
+    for (u32 h = 0; h < g; ++h) run = join4(run, get4(a.gslots + 2 * (uu * kUnitGroups + h)));
+    auto f = [&](const D4Seg &sg) {
+        const u32 cl = __builtin_popcount(sg.emit);
+        const u32 ci = wave_scan(cl);
+        const u32 segcnt = read_lane(ci, 63);
+        // class sums of this lane's codes, classes from the global rank
+        const u32 cls0 = (u32)(run.c + ci - cl) & 3u;
+        u32 s[4] = {0, 0, 0, 0};
+        add_by_class(sg.u, sg.emit, cls0, s);
+        // running value per class before the lane: run.s + lanes below
+        u32 base[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const u32 inc = wave_scan(s[c]);
+            base[c] = run.s[c] + inc - s[c];
+            run.s[c] += read_lane(inc, 63);
+        }
+        u32 v[16];
+        u32 cls = cls0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const u32 b = cls == 0 ? base[0] : cls == 1 ? base[1] : cls == 2 ? base[2] : base[3];
+            const u32 y = b + sg.u[j];
+            v[j] = y;
+            if ((sg.emit >> j) & 1u) {
+                base[0] = cls == 0 ? y : base[0];
+                base[1] = cls == 1 ? y : base[1];
+                base[2] = cls == 2 ? y : base[2];
+                base[3] = cls == 3 ? y : base[3];
+                cls = (cls + 1) & 3u;
+            }
+        }
+        const u64 gbase = run.c;
+        if (gbase < a.n && segcnt) {
+            u32 *out_seg = a.out + gbase;
+            if (gbase + segcnt <= a.n)
+                store_rows<false, false>(rows, v, sg.emit, out_seg, 0u, 0u);
+            else
+                store_rows<true, false>(rows, v, sg.emit, out_seg, (u32)(a.n - gbase), 0u);
+        }
+        run.c += segcnt;
+    };
+    const bool interior = wv >= 16 && wv + W + 4 <= a.vend;
+    if (interior)
+        (void)d4_group<false, SEGS>(a, wv, f);
+    else
+        (void)d4_group<true, SEGS>(a, wv, f);
+}
+
+template <int SEGS>
+hipError_t launch4_t(const Stream4Args &a, int wpb, hipStream_t s) {
+    const u32 blocks = (a.nunits + wpb - 1) / wpb;
+    k4_agg<SEGS><<<blocks, wpb * kWave, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k4_scan<<<1, kScanBlock, 0, s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const u64 ngroups = (a.vend + SEGS * kSegBytes - 1) / (SEGS * kSegBytes);
+    const u32 gblocks = (u32)((ngroups + wpb - 1) / wpb);
+    k4_known<SEGS><<<gblocks, wpb * kWave, (size_t)wpb * kStageWords * sizeof(u32), s>>>(a);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ batched lists
 struct ListDesc {
     i64 bb, be, ob, n;
@@ -2091,6 +2374,14 @@ hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int seg
         case 1: return launch_stream_s<1>(a, delta, count_only, wpb, s);
         case 2: return launch_stream_s<2>(a, delta, count_only, wpb, s);
         case 4: return launch_stream_s<4>(a, delta, count_only, wpb, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch4(const Stream4Args &a, int segs, int wpb, hipStream_t s) {
+    switch (segs) {
+        case 1: return launch4_t<1>(a, wpb, s);
+        case 2: return launch4_t<2>(a, wpb, s);
         default: return hipErrorInvalidValue;
     }
 }

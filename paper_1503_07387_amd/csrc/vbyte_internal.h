@@ -88,6 +88,22 @@ struct Stream64Args {
     int32_t *d_status;
 };
 
+// Single-stream decode with differences between blocks of four (reading
+// R14), in the layout of Stream64Args; a slot is 32 bytes (count and the
+// four class sums).
+struct Stream4Args {
+    const uint8_t *base;   // 16-byte aligned, <= bytes
+    uint64_t vstart;       // bytes - base (0..15)
+    uint64_t vend;         // vstart + nbytes
+    uint32_t *out;
+    uint64_t n;
+    uint32_t prev4[4];
+    uint32_t nunits;
+    uint4 *slots;    // 2 per unit: its summary, then its exclusive prefix
+    uint4 *gslots;   // 2 per group (kUnit64Groups per unit): its summary
+    int32_t *d_status;
+};
+
 // One list of a batched launch, resolved on the device from either CSR
 // offsets or gather rows.
 struct ListArgs {
@@ -146,6 +162,9 @@ hipError_t launch_two_pass(const StreamArgs &a, int delta, int segs, int wpb, hi
 // 64-bit decode: unit aggregates, a one-workgroup scan (status), decode;
 // segs 1 or 2.
 hipError_t launch64(const Stream64Args &a, int delta, int segs, int wpb, hipStream_t s);
+// Blocks-of-four decode: group and unit summaries, a one-workgroup scan
+// (status), decode; segs 1 or 2.
+hipError_t launch4(const Stream4Args &a, int segs, int wpb, hipStream_t s);
 hipError_t launch_encode(const EncodeArgs &a, hipStream_t s);
 hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
                                 uint64_t nb, hipStream_t s);

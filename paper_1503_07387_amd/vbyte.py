@@ -23,7 +23,8 @@ STATUS_NAMES = {OK: "VBYTE_OK", EINVAL: "VBYTE_EINVAL", ECOUNT: "VBYTE_ECOUNT",
 
 EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_decode_delta_async", "vbyte_decode_delta_m1", "vbyte_decode_delta_m1_async",
-           "vbyte_encode_delta_m1_async", "vbyte_decode_next_async", "vbyte_decode64",
+           "vbyte_encode_delta_m1_async", "vbyte_decode_next_async", "vbyte_decode_delta4",
+           "vbyte_decode_delta4_async", "vbyte_decode64",
            "vbyte_decode64_delta", "vbyte_decode64_async", "vbyte_decode64_delta_async",
            "vbyte_count", "vbyte_decode_batch",
            "vbyte_decode_lists", "vbyte_encode_async", "vbyte_encode_delta_async",
@@ -81,6 +82,8 @@ def _declare(lib):
         "vbyte_decode_delta_m1": [vp, sz, vp, sz, u32],
         "vbyte_decode_delta_m1_async": [vp, sz, vp, sz, u32, vp, vp],
         "vbyte_decode_next_async": [vp, sz, vp, sz, i32, vp, vp, vp, vp],
+        "vbyte_decode_delta4": [vp, sz, vp, sz, c.POINTER(u32)],
+        "vbyte_decode_delta4_async": [vp, sz, vp, sz, c.POINTER(u32), vp, vp],
         "vbyte_decode64": [vp, sz, vp, sz],
         "vbyte_decode64_delta": [vp, sz, vp, sz, c.c_uint64],
         "vbyte_decode64_async": [vp, sz, vp, sz, vp, vp],
@@ -180,6 +183,34 @@ def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=No
         v = int(status.item())
         if v != OK:
             raise VByteError(v, "decode")
+    return out[:n]
+
+
+def decode_delta4(data, n, *, prev4=None, out=None, status=None, stream=None, check=True):
+    """Decode ``n`` uint32 coded as differences between blocks of four:
+    out[i] = g_i + out[i-4] mod 2^32 from the four values ``prev4`` (zeros
+    by default).  Returns the int32 tensor; ``check`` as in decode()."""
+    _dev_u8(data)
+    n = int(n)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=data.device)
+    elif out.dtype != torch.int32 or out.numel() < n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of at least n elements")
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=data.device)
+    p = None
+    if prev4 is not None:
+        vals = [int(v) & 0xFFFFFFFF for v in prev4]
+        if len(vals) != 4:
+            raise ValueError("prev4 must hold four values")
+        p = (ctypes.c_uint32 * 4)(*vals)
+    st = _lib().vbyte_decode_delta4_async(_ptr(data), data.numel(), _ptr(out), n, p, _ptr(status),
+                                          _stream(stream))
+    _check_call(st, "decode_delta4")
+    if check:
+        v = int(status.item())
+        if v != OK:
+            raise VByteError(v, "decode_delta4")
     return out[:n]
 
 
