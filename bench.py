@@ -239,6 +239,42 @@ def bench_decode64(torch, vbyte, streams, reps=10):
             "pct_hbm_peak": round(100 * alg / (avg / 1e3) / 1e9 / HBM_PEAK_GBPS, 1)}
 
 
+def bench_delta4(torch, vbyte, streams, reps=10):
+    """Blocks-of-four differential decode (vbyte_decode_delta4, reading R14)
+    of the gap-mean-300 stream's bytes: out[i] = g_i + out[i-4], checked
+    against four interleaved cumsums of the gaps."""
+    s = streams[1]
+    n = N_STREAM
+    vbyte.set_tuning(2, 8, 0)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    vbyte.decode_delta4(s["bytes"], n, out=out, status=st, check=True)
+    g = s["gaps_dev"].to(torch.int64) & 0xFFFFFFFF
+    ref = (torch.cumsum(g.view(-1, 4), 0) & 0xFFFFFFFF).view(-1)
+    if not torch.equal(ref, out.to(torch.int64) & 0xFFFFFFFF):
+        raise RuntimeError("blocks-of-four decode differs from the interleaved cumsums")
+    del ref, g
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(reps):
+        e0.record()
+        vbyte.decode_delta4(s["bytes"], n, out=out, status=st, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    if int(st.item()) != 0:
+        raise RuntimeError("blocks-of-four decode status")
+    avg = sum(ms) / len(ms)
+    alg = s["bytes"].numel() + 4 * n
+    return {"workload": "differences between blocks of four (y_i = g_i + y_(i-4)) over the "
+                        "64Mi-gap stream (gap mean 300)",
+            "n": n, "bytes_in": int(s["bytes"].numel()), "tuning": "segs 2, waves 8",
+            "kernels": "k4_agg + k4_scan + k4_known", "ms": round(avg, 4),
+            "gints_per_s": round(n / (avg / 1e3) / 1e9, 2),
+            "alg_gbps": round(alg / (avg / 1e3) / 1e9, 1),
+            "pct_hbm_peak": round(100 * alg / (avg / 1e3) / 1e9 / HBM_PEAK_GBPS, 1)}
+
+
 def build_index(torch, vbyte, workloads):
     """Config 3: 100,000 Zipf-length lists of gaps, VByte-encoded on the GPU
     with per-list byte offsets."""
@@ -489,21 +525,30 @@ def summarize_trace(trace_csv, stats_csv, out_md, command_line):
     return {"calls": len(calls), "kernels": names}
 
 
-PROFILE_TRACE64 = os.path.join(ROOT, "profiles", "decode64_delta_64Mi_kernel_trace.md")
-DECODE64_KERNELS = ("k64_agg<", "k64_scan", "k64_known<")
+# the other bench lines whose kernels get a trace summary: (kernels, the
+# call's last kernel, summary file, title)
+SIDE_TRACES = {
+    "decode64": (("k64_agg<", "k64_scan", "k64_known<"), "k64_known<",
+                 os.path.join(ROOT, "profiles", "decode64_delta_64Mi_kernel_trace.md"),
+                 "64-bit differential decode of the 64Mi-gap stream (gap mean 300)"),
+    "delta4": (("k4_agg<", "k4_scan", "k4_known<"), "k4_known<",
+               os.path.join(ROOT, "profiles", "decode_delta4_64Mi_kernel_trace.md"),
+               "blocks-of-four differential decode of the 64Mi-gap stream (gap mean 300)"),
+}
 
 
-def summarize_trace64(trace_csv, out_md, command_line):
-    """Per-call durations of the 64-bit decode's kernels (the decode64 line of
-    bench.py) from a rocprofv3 --kernel-trace run."""
+def summarize_side_trace(which, trace_csv, command_line):
+    """Per-call durations of one side line's kernels (the decode64 or delta4
+    entry of bench.py) from a rocprofv3 --kernel-trace run."""
     import csv
+    kernels, last, out_md, title = SIDE_TRACES[which]
     rows = [r for r in csv.DictReader(open(trace_csv))
-            if any(k in r["Kernel_Name"] for k in DECODE64_KERNELS)]
+            if any(k in r["Kernel_Name"] for k in kernels)]
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
     calls, cur = [], []
     for r in rows:
         cur.append(r)
-        if "k64_known<" in r["Kernel_Name"]:
+        if last in r["Kernel_Name"]:
             calls.append(cur)
             cur = []
 
@@ -515,7 +560,7 @@ def summarize_trace64(trace_csv, out_md, command_line):
         if short_kernel(r["Kernel_Name"]) not in names:
             names.append(short_kernel(r["Kernel_Name"]))
     with open(out_md, "w") as fh:
-        fh.write("# Kernel trace: 64-bit differential decode of the 64Mi-gap stream (gap mean 300)\n\n")
+        fh.write(f"# Kernel trace: {title}\n\n")
         fh.write("Command (run from the repository root on one MI355X):\n\n")
         fh.write(f"    {command_line}\n\n")
         span = [(int(c[-1]["End_Timestamp"]) - int(c[0]["Start_Timestamp"])) / 1e3 for c in calls]
@@ -536,8 +581,8 @@ def main():
         o = summarize_trace(sys.argv[2], sys.argv[3], PROFILE_TRACE, sys.argv[4])
         print(json.dumps(o))
         return
-    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace64":
-        print(json.dumps(summarize_trace64(sys.argv[2], PROFILE_TRACE64, sys.argv[3])))
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-side-trace":
+        print(json.dumps(summarize_side_trace(sys.argv[2], sys.argv[3], sys.argv[4])))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
         fetch_csv, write_csv = sys.argv[2], sys.argv[3]
@@ -555,6 +600,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the config-3 batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the config-4 serving run")
     ap.add_argument("--no-decode64", action="store_true", help="skip the 64-bit decode line")
+    ap.add_argument("--no-delta4", action="store_true", help="skip the blocks-of-four decode line")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's current tiling instead of autotuning each stream "
                          "(profiling runs: every decode dispatch then uses one tiling)")
@@ -681,6 +727,9 @@ def main():
     if not args.no_decode64:
         log("64-bit decode ...")
         res["decode64"] = bench_decode64(torch, vbyte, streams)
+    if not args.no_delta4:
+        log("blocks-of-four decode ...")
+        res["delta4"] = bench_delta4(torch, vbyte, streams)
     if not (args.no_batched and args.no_serving):
         from paper_1503_07387_amd import serve
         idx = build_index(torch, vbyte, workloads)
