@@ -9,7 +9,7 @@ Every function follows Plaisance, Kurz, Lemire, "Vectorized VByte Decoding":
 the byte format of section 1 and Table 1, Algorithm 1 for decoding, and the
 differential coding of section 1 / section 4 (inclusive prefix sum mod 2^32),
 and the same format for 64-bit integers (section 1; reading R13).
-The readings taken where the paper is silent (R1-R14) are listed at the top of
+The readings taken where the paper is silent (R1-R15) are listed at the top of
 ``vbyte_oracle.c``.  All functions are pinned by ``tests/test_oracle_pins.py``.
 """
 from .oracle import (  # noqa: F401
@@ -17,5 +17,5 @@ from .oracle import (  # noqa: F401
     build, lib_path, code_length, encode, encode_delta, encoded_size, count,
     validate, decode, decode_delta, decode_delta_m1, encode_delta_m1, decode_next, decode_batch,
     code_length64, encoded_size64, encode64, encode_delta64, validate64, decode64, decode64_delta,
-    decode_delta4, encode_delta4,
+    decode_delta4, encode_delta4, intersect_pieces,
 )

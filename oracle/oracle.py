@@ -223,6 +223,40 @@ def decode_next(b, off, k, prev=0, delta=0, lib=None):
     return int(st), y[:m.value].copy(), int(no.value), int(npv.value)
 
 
+def intersect_pieces(a, na, b_ids, piece, prev=0, lib=None):
+    """List intersection by a bounded-buffer consumer (section 5 decodes long
+    lists piece by piece into a small buffer; reading R15): the differential
+    list a (na identifiers, from prev) is decoded in pieces of at most
+    `piece` integers (decode_next, reading R12), and every identifier of a,
+    in order, that occurs in the sorted array b_ids is kept (numpy isin).
+    Status: the worst status of a piece (a failing piece leaves the cursor,
+    so later pieces fail alike), else ETRUNC when fewer than na codes were
+    found, else ECOUNT when bytes remain after the na-th code.
+    Returns (status, matches)."""
+    lib = lib or load()
+    a = _as_u8(a)
+    b_ids = np.asarray(b_ids, dtype=np.uint32)
+    off, done, pv, worst = 0, 0, int(prev) & 0xFFFFFFFF, OK
+    keep = []
+    for _ in range((int(na) + piece - 1) // piece):
+        st, y, noff, npv = decode_next(a, off, piece, pv, 1, lib=lib)
+        if st != OK:
+            worst = max(worst, st)
+            continue
+        take = y[:max(0, min(y.size, int(na) - done))]
+        keep.append(take[np.isin(take, b_ids)])
+        done += y.size
+        off, pv = noff, npv
+    out = np.concatenate(keep) if keep else np.zeros(0, np.uint32)
+    if worst != OK:
+        return worst, out
+    if done < int(na):
+        return ETRUNC, out
+    if off < a.size or done > int(na):
+        return ECOUNT, out
+    return OK, out
+
+
 def decode_batch(b, byte_off, out_off, prevs=None, delta=False, lib=None):
     """BATCH over CSR offsets (delta: 0/False plain, 1/True differences,
     2 differences minus one).  Returns (status, out, per-list status)."""

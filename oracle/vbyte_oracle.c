@@ -40,6 +40,10 @@
  *       (zero for a list coded from its start, which makes x_1..x_4 coded
  *       as themselves); a stream continued from an earlier piece passes the
  *       piece's last four values.
+ *   R15 a list intersection consumer of resumable pieces (oracle.py,
+ *       intersect_pieces): a failing piece leaves the cursor; the status is
+ *       the worst piece status, else ETRUNC for fewer codes than the list's
+ *       count, else ECOUNT for bytes left after its last code.
  *   R13 64-bit integers (section 1: the format applies to 64-bit integers
  *       as well): at most 10 bytes per code, the tenth carrying bit 63; ten
  *       or more consecutive continuation bytes -> EMALFORMED; a tenth byte

@@ -477,6 +477,31 @@ def pin_delta4_roundtrip_and_resume(lib):
     assert oracle.decode_delta4(b, x.size - 1, lib=lib)[0] == ECOUNT
 
 
+# ---------------------------------------------------------------- intersection (R15)
+def pin_intersect_brute_force(lib):
+    rng = np.random.default_rng(46)
+    for trial in range(60):
+        na = int(rng.integers(0, 300))
+        ids = np.sort(rng.choice(2000, size=na, replace=False)).astype(np.uint32)
+        prev = int(rng.integers(0, 5))
+        ids = ids + np.uint32(prev)
+        bset = set(int(v) for v in rng.choice(2400, size=int(rng.integers(0, 400)), replace=False))
+        b_ids = np.array(sorted(bset), np.uint32)
+        a = oracle.encode_delta(ids, prev, lib=lib)
+        piece = int(rng.choice([1, 2, 7, 64, 1000]))
+        st, got = oracle.intersect_pieces(a, na, b_ids, piece, prev, lib=lib)
+        want = [int(v) for v in ids if int(v) in bset]     # Python sets, in list order
+        assert st == OK and [int(v) for v in got] == want, (trial, piece)
+    # statuses: too few codes, codes left over, a malformed run
+    ids = np.arange(10, 1010, 3, dtype=np.uint32)
+    a = oracle.encode_delta(ids, 0, lib=lib)
+    assert oracle.intersect_pieces(a, ids.size + 1, ids, 64, lib=lib)[0] == ETRUNC
+    assert oracle.intersect_pieces(a, ids.size - 1, ids, 64, lib=lib)[0] == ECOUNT
+    bad = a.copy()
+    bad[100:105] = 0x80
+    assert oracle.intersect_pieces(bad, ids.size, ids, 64, lib=lib)[0] == EMALFORMED
+
+
 # ---------------------------------------------------------------- 64-bit (R13)
 M64 = (1 << 64) - 1
 
@@ -596,4 +621,5 @@ ALL_PINS = [pin_table1, pin_fig1, pin_closed_form_boundaries, pin_length_closed_
             pin_status_readings,
             pin_fifth_byte_wrap, pin_overlong, pin_batch,
             pin64_closed_form_boundaries, pin64_protobuf, pin64_delta_bigint, pin64_statuses,
-            pin64_agrees_with_32, pin_delta4_example_and_closed_form, pin_delta4_roundtrip_and_resume]
+            pin64_agrees_with_32, pin_delta4_example_and_closed_form, pin_delta4_roundtrip_and_resume,
+            pin_intersect_brute_force]
