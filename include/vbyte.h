@@ -160,6 +160,31 @@ vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32
                                      int delta, const vbyte_cursor *d_in, vbyte_cursor *d_out,
                                      int32_t *d_status, void *stream);
 
+/* List intersection by a consumer of resumable pieces (section 5 decodes
+ * long lists piece by piece into a buffer that stays in cache; this fuses
+ * that decode with a consumer).  The differential list a (na identifiers,
+ * from a_prev) is decoded `piece` integers at a time into a buffer of the
+ * library (vbyte_decode_next_async, at most 2 segments per wavefront); after
+ * each piece, its identifiers that occur in the sorted array b[0..nb) are
+ * appended, in list order, to out.  No host synchronisation between pieces,
+ * and the long list is never written out whole.
+ *   a: device bytes; b, out: device uint32, 4-byte aligned; b sorted
+ *   ascending (duplicates allowed).  Every identifier of a that occurs in b
+ *   is kept (duplicates in a too).
+ *   *d_count (device uint64): the number of matches; only out[0..out_cap)
+ *   is written, so a count above out_cap means matches were dropped.
+ *   *d_status (device int32): the worst status of a piece (a failing piece
+ *   leaves the cursor, so later pieces fail alike), else VBYTE_ETRUNC when
+ *   a holds fewer than na codes, else VBYTE_ECOUNT when bytes remain after
+ *   its na-th code, else VBYTE_OK.
+ *   piece: 1 .. 2^26 integers; the library keeps a buffer of 5 bytes per
+ *   integer of the piece per stream.
+ * Returns VBYTE_EINVAL for bad arguments before enqueuing anything. */
+vbyte_status vbyte_intersect_async(const uint8_t *a, size_t a_nbytes, size_t na, uint32_t a_prev,
+                                   const uint32_t *b, size_t nb, size_t piece, uint32_t *out,
+                                   size_t out_cap, uint64_t *d_count, int32_t *d_status,
+                                   void *stream);
+
 /* Number of terminator bytes (top bit 0) in bytes[0..nbytes), i.e. the
  * number of codes a valid stream holds (section 1: one terminator per
  * integer).  Written to the device word *d_count. */

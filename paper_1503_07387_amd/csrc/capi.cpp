@@ -49,6 +49,10 @@ struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
     uint64_t launches = 0;
+    // the intersection consumer's buffers (piece, flags, counts, cursors),
+    // apart from `ptr` because the piece decodes use that
+    void *aux = nullptr;
+    size_t aux_bytes = 0;
 };
 
 std::mutex g_mu;
@@ -57,8 +61,10 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 struct Cleanup {
     ~Cleanup() {
         // Process exit: the runtime may already be torn down; release quietly.
-        for (auto &kv : g_ws)
+        for (auto &kv : g_ws) {
             if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+            if (kv.second.aux) (void)hipFree(kv.second.aux);
+        }
     }
 } g_cleanup;
 
@@ -104,6 +110,31 @@ vbyte_status get_ws(hipStream_t stream, size_t need, int launches, Workspace **o
 }
 
 uint8_t *ws_base(Workspace *w) { return (uint8_t *)w->ptr; }
+
+// The consumer buffers of workspace w, at least `need` bytes (grown on
+// demand; their contents are initialised by the kernels that use them).
+vbyte_status aux_area(Workspace *w, hipStream_t s, size_t need, uint8_t **p) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (w->aux_bytes < need) {
+        if (w->aux) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            (void)hipFree(w->aux);
+            w->aux = nullptr;
+            w->aux_bytes = 0;
+        }
+        const size_t sz = (need + 255) & ~(size_t)255;
+        hipError_t e = hipMalloc(&w->aux, sz);
+        if (e != hipSuccess) {
+            w->aux = nullptr;
+            std::snprintf(g_last_error, sizeof g_last_error, "hipMalloc(%zu): %s", sz, hipGetErrorString(e));
+            return VBYTE_ENOMEM;
+        }
+        w->aux_bytes = sz;
+    }
+    *p = (uint8_t *)w->aux;
+    return VBYTE_OK;
+}
 
 constexpr uint64_t kMaxBytes = 1ull << 36;
 
@@ -442,6 +473,60 @@ vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32
     e = launch_resume_finish(bytes, cin, (uint64_t *)d_out, scratch, d_status, out, k, nbytes,
                              window, delta, s);
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "cursor update");
+}
+
+vbyte_status vbyte_intersect_async(const uint8_t *a, size_t a_nbytes, size_t na, uint32_t a_prev,
+                                   const uint32_t *b, size_t nb, size_t piece, uint32_t *out,
+                                   size_t out_cap, uint64_t *d_count, int32_t *d_status,
+                                   void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (piece == 0 || piece > (1ull << 26)) return VBYTE_EINVAL;
+    if (a_nbytes >= kMaxBytes || (a_nbytes > 0 && !a)) return VBYTE_EINVAL;
+    if ((nb > 0 && !b) || ((uintptr_t)b & 3u)) return VBYTE_EINVAL;
+    if ((out_cap > 0 && !out) || ((uintptr_t)out & 3u)) return VBYTE_EINVAL;
+    if (!d_count || ((uintptr_t)d_count & 7u) || !d_status || ((uintptr_t)d_status & 3u))
+        return VBYTE_EINVAL;
+    // piece buffer, flags, per-workgroup counts, two cursors, piece status, pending
+    const uint64_t blocks = (piece + kIsectElemsPerBlock - 1) / kIsectElemsPerBlock;
+    const size_t off_flags = (piece * 4 + 255) & ~(size_t)255;
+    const size_t off_counts = (off_flags + blocks * kIsectElemsPerBlock + 255) & ~(size_t)255;
+    const size_t off_cur = (off_counts + blocks * 4 + 255) & ~(size_t)255;
+    const size_t need = off_cur + 256;
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, kHeaderBytes, 0, &w);
+    if (st != VBYTE_OK) return st;
+    uint8_t *p = nullptr;
+    st = aux_area(w, s, need, &p);
+    if (st != VBYTE_OK) return st;
+    uint64_t *cur[2] = {(uint64_t *)(p + off_cur), (uint64_t *)(p + off_cur + 64)};
+    IsectArgs ia{};
+    ia.piece = (const uint32_t *)p;
+    ia.piece_status = (const int32_t *)(p + off_cur + 128);
+    ia.na = na;
+    ia.b = b;
+    ia.nb = nb;
+    ia.flags = p + off_flags;
+    ia.wg_counts = (uint32_t *)(p + off_counts);
+    ia.out = out;
+    ia.out_cap = out_cap;
+    ia.d_count = d_count;
+    ia.pending = (uint64_t *)(p + off_cur + 192);
+    ia.d_status = d_status;
+    hipError_t e = launch_isect_init(ia, cur[0], a_prev, s);
+    if (e != hipSuccess) return hip_fail(e, "intersect init");
+    const uint64_t npieces = (na + piece - 1) / piece;
+    for (uint64_t k = 0; k < npieces; ++k) {
+        uint64_t *cin = cur[k & 1], *cout = cur[(k + 1) & 1];
+        st = vbyte_decode_next_async(a, a_nbytes, (uint32_t *)p, piece, 1, (const vbyte_cursor *)cin,
+                                     (vbyte_cursor *)cout, (int32_t *)ia.piece_status, stream);
+        if (st != VBYTE_OK) return st;
+        ia.cin = cin;
+        ia.cout = cout;
+        e = launch_isect_piece(ia, piece, s);
+        if (e != hipSuccess) return hip_fail(e, "intersect piece");
+    }
+    e = launch_isect_finish(ia, cur[npieces & 1], a_nbytes, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "intersect finish");
 }
 
 vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count, void *stream) {

@@ -1859,6 +1859,131 @@ hipError_t launch4_t(const Stream4Args &a, int wpb, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ============================================================ intersection
+// A consumer of resumable pieces: after each piece of the long list has
+// been decoded into the piece buffer, k_isect_mark flags its identifiers
+// that occur in the sorted array b (one binary search per thread, then a
+// forward walk over b for the thread's next identifiers) and counts them
+// per workgroup, and k_isect_write appends the flagged ones, in order, after
+// the matches of the earlier pieces.  The running match count lives in
+// d_count; the pieces' totals are folded into it by the next piece's mark
+// kernel (and by the finish kernel), so no kernel reads a word that another
+// workgroup of the same kernel writes.
+constexpr u32 kIsectBlock = 256;
+constexpr u32 kIsectPer = 4;   // identifiers per thread
+constexpr u32 kIsectSpan = kIsectBlock * kIsectPer;
+static_assert(kIsectSpan == kIsectElemsPerBlock, "consumer workgroup span");
+
+// Identifiers of this piece to consider: those decoded (cursor difference)
+// up to the list's count.
+__device__ __forceinline__ u64 isect_count(const IsectArgs &a) {
+    const u64 before = a.cin[1], m = a.cout[1] - before;
+    const u64 left = a.na > before ? a.na - before : 0;
+    return m < left ? m : left;
+}
+
+__global__ __launch_bounds__(kIsectBlock) void k_isect_mark(IsectArgs a) {
+    __shared__ u32 wsum[kIsectBlock / kWave];
+    const u32 tid = threadIdx.x, ln = lane_id(), wib = tid >> 6;
+    if (blockIdx.x == 0 && tid == 0) {
+        // fold the previous piece's matches and this piece's status
+        *a.d_count += *a.pending;
+        *a.pending = 0;
+        if (*a.piece_status > *a.d_status) *a.d_status = *a.piece_status;
+    }
+    const u64 m = isect_count(a);
+    const u64 i0 = ((u64)blockIdx.x * kIsectBlock + tid) * kIsectPer;
+    u32 cnt = 0;
+    if (i0 < m) {
+        const u32 x0 = a.piece[i0];
+        u64 lo = 0, hi = a.nb;   // first b[j] >= x0
+        while (lo < hi) {
+            const u64 mid = (lo + hi) >> 1;
+            if (a.b[mid] < x0)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        u64 j = lo;
+        for (u32 e = 0; e < kIsectPer; ++e) {
+            const u64 i = i0 + e;
+            if (i >= m) break;
+            const u32 x = a.piece[i];
+            while (j < a.nb && a.b[j] < x) ++j;
+            const u8 f = (j < a.nb && a.b[j] == x) ? 1 : 0;
+            a.flags[i] = f;
+            cnt += f;
+        }
+    }
+    const u32 ws = wave_sum(cnt);
+    if (ln == 0) wsum[wib] = ws;
+    __syncthreads();
+    if (tid == 0) {
+        u32 t = 0;
+        for (u32 k = 0; k < kIsectBlock / kWave; ++k) t += wsum[k];
+        a.wg_counts[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kIsectBlock) void k_isect_write(IsectArgs a) {
+    __shared__ u32 wsum[kIsectBlock / kWave];
+    __shared__ u64 pre_s;
+    const u32 tid = threadIdx.x, ln = lane_id(), wib = tid >> 6;
+    if (tid == 0) {
+        u64 pre = 0, tot = 0;
+        for (u32 g = 0; g < gridDim.x; ++g) {
+            if (g == blockIdx.x) pre = tot;
+            tot += a.wg_counts[g];
+        }
+        pre_s = pre;
+        if (blockIdx.x == 0) *a.pending = tot;
+    }
+    const u64 m = isect_count(a);
+    const u64 i0 = ((u64)blockIdx.x * kIsectBlock + tid) * kIsectPer;
+    u32 fl = 0, cnt = 0;
+    for (u32 e = 0; e < kIsectPer; ++e) {
+        if (i0 + e < m && a.flags[i0 + e]) {
+            fl |= 1u << e;
+            ++cnt;
+        }
+    }
+    const u32 inc = wave_scan(cnt);
+    if (ln == kWave - 1) wsum[wib] = inc;
+    __syncthreads();
+    u64 base = *a.d_count + pre_s + inc - cnt;
+    for (u32 k = 0; k < wib; ++k) base += wsum[k];
+    for (u32 e = 0; e < kIsectPer; ++e) {
+        if ((fl >> e) & 1u) {
+            if (base < a.out_cap) a.out[base] = a.piece[i0 + e];
+            ++base;
+        }
+    }
+}
+
+// After the last piece: fold the last matches; the status is the worst
+// piece status, else ETRUNC (fewer codes than na) or ECOUNT (bytes left).
+__global__ void k_isect_finish(IsectArgs a, const u64 *cursor, u64 nbytes) {
+    *a.d_count += *a.pending;
+    *a.pending = 0;
+    int32_t st = *a.d_status;
+    if (st == VBYTE_OK) {
+        if (cursor[1] < a.na)
+            st = VBYTE_ETRUNC;
+        else if (cursor[0] < nbytes || cursor[1] > a.na)
+            st = VBYTE_ECOUNT;
+    }
+    *a.d_status = st;
+}
+
+__global__ void k_isect_init(IsectArgs a, u64 *cursor, u64 prev) {
+    cursor[0] = 0;
+    cursor[1] = 0;
+    cursor[2] = prev;
+    *a.d_count = 0;
+    *a.pending = 0;
+    *a.d_status = VBYTE_OK;
+}
+
 // ------------------------------------------------------------ batched lists
 struct ListDesc {
     i64 bb, be, ob, n;
@@ -2376,6 +2501,26 @@ hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int seg
         case 4: return launch_stream_s<4>(a, delta, count_only, wpb, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_isect_init(const IsectArgs &a, uint64_t *cursor, uint64_t prev, hipStream_t s) {
+    k_isect_init<<<1, 1, 0, s>>>(a, cursor, prev);
+    return hipGetLastError();
+}
+
+hipError_t launch_isect_piece(const IsectArgs &a, uint64_t piece, hipStream_t s) {
+    const u32 blocks = (u32)((piece + kIsectSpan - 1) / kIsectSpan);
+    k_isect_mark<<<blocks, kIsectBlock, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_isect_write<<<blocks, kIsectBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_isect_finish(const IsectArgs &a, const uint64_t *cursor, uint64_t nbytes,
+                               hipStream_t s) {
+    k_isect_finish<<<1, 1, 0, s>>>(a, cursor, nbytes);
+    return hipGetLastError();
 }
 
 hipError_t launch4(const Stream4Args &a, int segs, int wpb, hipStream_t s) {

@@ -24,7 +24,7 @@ STATUS_NAMES = {OK: "VBYTE_OK", EINVAL: "VBYTE_EINVAL", ECOUNT: "VBYTE_ECOUNT",
 EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_decode_delta_async", "vbyte_decode_delta_m1", "vbyte_decode_delta_m1_async",
            "vbyte_encode_delta_m1_async", "vbyte_decode_next_async", "vbyte_decode_delta4",
-           "vbyte_decode_delta4_async", "vbyte_decode64",
+           "vbyte_decode_delta4_async", "vbyte_intersect_async", "vbyte_decode64",
            "vbyte_decode64_delta", "vbyte_decode64_async", "vbyte_decode64_delta_async",
            "vbyte_count", "vbyte_decode_batch",
            "vbyte_decode_lists", "vbyte_encode_async", "vbyte_encode_delta_async",
@@ -84,6 +84,7 @@ def _declare(lib):
         "vbyte_decode_next_async": [vp, sz, vp, sz, i32, vp, vp, vp, vp],
         "vbyte_decode_delta4": [vp, sz, vp, sz, c.POINTER(u32)],
         "vbyte_decode_delta4_async": [vp, sz, vp, sz, c.POINTER(u32), vp, vp],
+        "vbyte_intersect_async": [vp, sz, sz, u32, vp, sz, sz, vp, sz, vp, vp, vp],
         "vbyte_decode64": [vp, sz, vp, sz],
         "vbyte_decode64_delta": [vp, sz, vp, sz, c.c_uint64],
         "vbyte_decode64_async": [vp, sz, vp, sz, vp, vp],
@@ -240,6 +241,36 @@ def decode64(data, n, *, delta=False, prev=0, out=None, status=None, stream=None
         if v != OK:
             raise VByteError(v, "decode64")
     return out[:n]
+
+
+def intersect(a, na, b_ids, *, prev=0, piece=1 << 16, out=None, count=None, status=None,
+              stream=None, check=True):
+    """Identifiers of the differential list ``a`` (VByte bytes, ``na``
+    identifiers from ``prev``) that occur in the sorted ``b_ids`` (int32
+    tensor of uint32 values), in list order, by decoding ``a`` in pieces of
+    ``piece`` integers and testing each piece as it is decoded
+    (vbyte_intersect_async).  Returns (matches tensor, count tensor); with
+    ``check`` the call waits and raises VByteError on a data error."""
+    _dev_u8(a)
+    if b_ids.dtype != torch.int32 or not b_ids.is_cuda or not b_ids.is_contiguous():
+        raise ValueError("b_ids must be a contiguous int32 CUDA tensor (uint32 bits)")
+    na = int(na)
+    if out is None:
+        out = torch.empty(max(min(na, 1 << 28), 1), dtype=torch.int32, device=a.device)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=a.device)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=a.device)
+    st = _lib().vbyte_intersect_async(_ptr(a), a.numel(), na, int(prev) & 0xFFFFFFFF, _ptr(b_ids),
+                                      b_ids.numel(), int(piece), _ptr(out), out.numel(), _ptr(count),
+                                      _ptr(status), _stream(stream))
+    _check_call(st, "intersect")
+    if check:
+        v = int(status.item())
+        if v != OK:
+            raise VByteError(v, "intersect")
+        return out[: min(int(count.item()), out.numel())], count
+    return out, count
 
 
 def new_cursor(prev=0, device=None):

@@ -1,0 +1,110 @@
+"""GPU parity of the list intersection by a consumer of resumable pieces
+(vbyte_intersect_async, reading R15) with the oracle's piece-by-piece
+intersection: matches in list order, their count, and the status, over
+piece sizes, list densities, duplicates, a capacity below the match count,
+and the error cases."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import dev, u32
+from paper_1503_07387_amd import vbyte
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def restore_tuning():
+    t = vbyte.get_tuning()
+    yield
+    vbyte.set_tuning(**t)
+
+
+def run(a, na, b_ids, piece, prev=0, cap=None):
+    ad = torch.from_numpy(np.asarray(a, np.uint8)).to(dev())
+    bd = torch.from_numpy(np.ascontiguousarray(b_ids, np.uint32).view(np.int32)).to(dev())
+    cap = max(na, 1) if cap is None else cap
+    out = torch.full((cap + 8,), -1, dtype=torch.int32, device=dev())
+    cnt = torch.empty(1, dtype=torch.int64, device=dev())
+    st = torch.empty(1, dtype=torch.int32, device=dev())
+    vbyte.intersect(ad, na, bd, prev=prev, piece=piece, out=out[:cap], count=cnt, status=st,
+                    check=False)
+    torch.cuda.synchronize()
+    h = u32(out)
+    assert (h[cap:] == 0xFFFFFFFF).all(), "write past out_cap"
+    return int(st.item()), int(cnt.item()), h[:cap]
+
+
+def lists(seed, na, nb, universe, dup=False):
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(universe, size=na, replace=dup)).astype(np.uint32)
+    b = np.sort(rng.choice(universe, size=nb, replace=dup)).astype(np.uint32)
+    return ids, b
+
+
+@pytest.mark.parametrize("piece", [1, 100, 1024, 65_536, 1 << 20])
+@pytest.mark.parametrize("shape", [(200_000, 5_000, 1 << 24), (50_000, 50_000, 200_000),
+                                   (3, 10, 50), (0, 10, 50)])
+def test_matches_oracle(piece, shape):
+    na, nb, universe = shape
+    if piece == 1 and na > 10_000:
+        pytest.skip("one integer per piece: kept to the small lists")
+    ids, b = lists(na + nb + piece, na, nb, universe)
+    a = oracle.encode_delta(ids, 5)
+    st, cnt, got = run(a, na, b, piece, prev=5)
+    sto, want = oracle.intersect_pieces(a, na, b, piece, 5)
+    assert st == sto == vbyte.OK
+    assert cnt == want.size and np.array_equal(got[:cnt], want)
+
+
+def test_duplicates_on_both_sides():
+    rng = np.random.default_rng(9)
+    ids = np.sort(rng.integers(0, 3000, 20_000)).astype(np.uint32)   # many repeats: gaps of 0
+    b = np.sort(rng.integers(0, 3000, 2_000)).astype(np.uint32)
+    a = oracle.encode_delta(ids, 0)
+    for piece in (7, 4096):
+        st, cnt, got = run(a, ids.size, b, piece)
+        sto, want = oracle.intersect_pieces(a, ids.size, b, piece)
+        assert st == sto == vbyte.OK and cnt == want.size and np.array_equal(got[:cnt], want)
+
+
+def test_capacity_below_count():
+    ids, b = lists(10, 100_000, 80_000, 150_000)
+    a = oracle.encode_delta(ids, 0)
+    sto, want = oracle.intersect_pieces(a, ids.size, b, 4096)
+    cap = want.size // 3
+    st, cnt, got = run(a, ids.size, b, 4096, cap=cap)
+    assert st == vbyte.OK and cnt == want.size
+    assert np.array_equal(got[:cap], want[:cap])
+
+
+def test_statuses():
+    ids = np.arange(10, 30_010, 3, dtype=np.uint32)
+    a = oracle.encode_delta(ids, 0)
+    bad = a.copy()
+    bad[5000:5005] = 0x80
+    for piece in (64, 5000):
+        for buf, na in ((a, ids.size + 1), (a, ids.size - 1), (bad, ids.size), (a[:-1], ids.size)):
+            st, cnt, got = run(buf, na, ids, piece)
+            sto, want = oracle.intersect_pieces(buf, na, ids, piece)
+            assert st == sto, (piece, na, st, sto)
+            if st == vbyte.OK:
+                assert np.array_equal(got[:cnt], want)
+    st, cnt, _ = run(np.zeros(0, np.uint8), 0, ids, 64)
+    assert st == vbyte.OK and cnt == 0
+    st, cnt, _ = run(np.zeros(0, np.uint8), 5, ids, 64)
+    assert st == vbyte.ETRUNC and cnt == 0
+
+
+def test_long_list_against_whole_decode():
+    """The 4Mi-identifier list in pieces of 256Ki against the same list
+    decoded whole in one piece: identical matches."""
+    vbyte.set_tuning(2, 8, 0)
+    ids, b = lists(11, 1 << 22, 1 << 16, 1 << 28)
+    a = oracle.encode_delta(ids, 0)
+    s1, c1, g1 = run(a, ids.size, b, 1 << 18)
+    s2, c2, g2 = run(a, ids.size, b, 1 << 22)
+    want = ids[np.isin(ids, b)]
+    assert s1 == s2 == vbyte.OK and c1 == c2 == want.size
+    assert np.array_equal(g1[:c1], want) and np.array_equal(g2[:c2], want)
