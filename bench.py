@@ -275,6 +275,48 @@ def bench_delta4(torch, vbyte, streams, reps=10):
             "pct_hbm_peak": round(100 * alg / (avg / 1e3) / 1e9 / HBM_PEAK_GBPS, 1)}
 
 
+def bench_intersect(torch, vbyte, streams, reps=5):
+    """List intersection by the consumer of resumable pieces
+    (vbyte_intersect_async): the gap-mean-8 stream (64Mi identifiers) against
+    a sorted list of 1Mi identifiers (half drawn from the long list), for
+    several piece sizes; a piece of the whole list is the decode-then-consume
+    baseline.  Checked against torch.isin."""
+    s = streams[0]
+    n = N_STREAM
+    ids = torch.cumsum(s["gaps_dev"].to(torch.int64) & 0xFFFFFFFF, 0)   # no wrap at gap mean 8
+    g = torch.Generator(device="cuda").manual_seed(1503)
+    pick = ids[torch.randint(0, n, (1 << 19,), device="cuda", generator=g)]
+    other = torch.randint(0, int(ids[-1].item()) + 1, (1 << 19,), device="cuda", generator=g)
+    b = torch.sort(torch.cat([pick, other]))[0]
+    want = ids[torch.isin(ids, b)]
+    b32 = b.to(torch.int32)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    vbyte.set_tuning(2, 8, 0)
+    rows = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for piece in (1 << 18, 1 << 20, 1 << 22, n):
+        vbyte.intersect(s["bytes"], n, b32, piece=piece, out=out, count=cnt, status=st, check=False)
+        torch.cuda.synchronize()
+        c = int(cnt.item())
+        if int(st.item()) != 0 or c != want.numel() or \
+                not torch.equal(out[:c].to(torch.int64) & 0xFFFFFFFF, want):
+            raise RuntimeError(f"intersection differs from torch.isin (piece {piece})")
+        e0.record()
+        for _ in range(reps):
+            vbyte.intersect(s["bytes"], n, b32, piece=piece, out=out, count=cnt, status=st,
+                            check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rows.append({"piece": piece, "pieces": (n + piece - 1) // piece,
+                     "piece_buffer_bytes": piece * 5, "ms": round(ms, 4),
+                     "gints_per_s": round(n / (ms / 1e3) / 1e9, 2)})
+    return {"workload": "64Mi-identifier list (gap mean 8) intersected with 1Mi sorted identifiers",
+            "matches": int(want.numel()), "points": rows}
+
+
 def build_index(torch, vbyte, workloads):
     """Config 3: 100,000 Zipf-length lists of gaps, VByte-encoded on the GPU
     with per-list byte offsets."""
@@ -601,6 +643,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the config-4 serving run")
     ap.add_argument("--no-decode64", action="store_true", help="skip the 64-bit decode line")
     ap.add_argument("--no-delta4", action="store_true", help="skip the blocks-of-four decode line")
+    ap.add_argument("--no-intersect", action="store_true", help="skip the intersection line")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's current tiling instead of autotuning each stream "
                          "(profiling runs: every decode dispatch then uses one tiling)")
@@ -730,6 +773,9 @@ def main():
     if not args.no_delta4:
         log("blocks-of-four decode ...")
         res["delta4"] = bench_delta4(torch, vbyte, streams)
+    if not args.no_intersect:
+        log("intersection by pieces ...")
+        res["intersect"] = bench_intersect(torch, vbyte, streams)
     if not (args.no_batched and args.no_serving):
         from paper_1503_07387_amd import serve
         idx = build_index(torch, vbyte, workloads)

@@ -1925,18 +1925,71 @@ __global__ __launch_bounds__(kIsectBlock) void k_isect_mark(IsectArgs a) {
     }
 }
 
-__global__ __launch_bounds__(kIsectBlock) void k_isect_write(IsectArgs a) {
+// Pieces of more than kIsectDirect workgroups: the workgroups' counts
+// become exclusive prefixes in place (one workgroup) and their total goes to
+// pending, before k_isect_write.
+constexpr u32 kIsectDirect = kIsectBlock;
+
+__global__ __launch_bounds__(kScanBlock) void k_isect_scan(IsectArgs a, u32 groups) {
+    __shared__ u32 wc[kScanBlock / kWave];
+    const u32 tid = threadIdx.x, ln = lane_id(), wib = tid >> 6;
+    u64 carry = 0;
+    for (u32 b0 = 0; b0 < groups; b0 += kScanBlock * kScanPer) {
+        const u32 i0 = b0 + tid * kScanPer;
+        u32 c[kScanPer], lc = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            c[k] = i0 + k < groups ? a.wg_counts[i0 + k] : 0u;
+            lc += c[k];
+        }
+        const u32 ci = wave_scan(lc);   // at most 512 x 1024 matches per wavefront
+        if (ln == kWave - 1) wc[wib] = ci;
+        __syncthreads();
+        u64 pre = carry, tot = carry;
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
+            if (k < wib) pre += wc[k];
+            tot += wc[k];
+        }
+        pre += ci - lc;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (i0 + k < groups) a.wg_counts[i0 + k] = (u32)pre;   // a piece has < 2^26 matches
+            pre += c[k];
+        }
+        carry = tot;
+        __syncthreads();
+    }
+    if (tid == 0) *a.pending = carry;
+}
+
+__global__ __launch_bounds__(kIsectBlock) void k_isect_write(IsectArgs a, bool scanned) {
     __shared__ u32 wsum[kIsectBlock / kWave];
     __shared__ u64 pre_s;
     const u32 tid = threadIdx.x, ln = lane_id(), wib = tid >> 6;
-    if (tid == 0) {
-        u64 pre = 0, tot = 0;
-        for (u32 g = 0; g < gridDim.x; ++g) {
-            if (g == blockIdx.x) pre = tot;
-            tot += a.wg_counts[g];
+    if (scanned) {
+        if (tid == 0) pre_s = a.wg_counts[blockIdx.x];
+    } else {
+        // at most kIsectDirect workgroups: one count per thread
+        const u32 c = tid < gridDim.x ? a.wg_counts[tid] : 0u;
+        const u32 before = wave_sum(tid < blockIdx.x ? c : 0u), all = wave_sum(c);
+        if (ln == 0) wsum[wib] = before;
+        __syncthreads();
+        if (tid == 0) {
+            u64 pre = 0;
+            for (u32 k = 0; k < kIsectBlock / kWave; ++k) pre += wsum[k];
+            pre_s = pre;
         }
-        pre_s = pre;
-        if (blockIdx.x == 0) *a.pending = tot;
+        __syncthreads();   // wsum is rewritten below
+        if (blockIdx.x == 0) {
+            if (ln == 0) wsum[wib] = all;
+            __syncthreads();
+            if (tid == 0) {
+                u64 tot = 0;
+                for (u32 k = 0; k < kIsectBlock / kWave; ++k) tot += wsum[k];
+                *a.pending = tot;
+            }
+        }
+        __syncthreads();
     }
     const u64 m = isect_count(a);
     const u64 i0 = ((u64)blockIdx.x * kIsectBlock + tid) * kIsectPer;
@@ -1948,6 +2001,7 @@ __global__ __launch_bounds__(kIsectBlock) void k_isect_write(IsectArgs a) {
         }
     }
     const u32 inc = wave_scan(cnt);
+    __syncthreads();   // wsum is reused
     if (ln == kWave - 1) wsum[wib] = inc;
     __syncthreads();
     u64 base = *a.d_count + pre_s + inc - cnt;
@@ -2513,7 +2567,13 @@ hipError_t launch_isect_piece(const IsectArgs &a, uint64_t piece, hipStream_t s)
     k_isect_mark<<<blocks, kIsectBlock, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_isect_write<<<blocks, kIsectBlock, 0, s>>>(a);
+    const bool scanned = blocks > kIsectDirect;
+    if (scanned) {
+        k_isect_scan<<<1, kScanBlock, 0, s>>>(a, blocks);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_isect_write<<<blocks, kIsectBlock, 0, s>>>(a, scanned);
     return hipGetLastError();
 }
 
