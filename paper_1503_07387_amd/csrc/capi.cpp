@@ -36,7 +36,7 @@ vbyte_status hip_fail(hipError_t e, const char *what) {
 }
 
 // Workspace layout (bytes):
-//   [0, 24)     epoch word and the two batched queue words
+//   [0, 32)     epoch word, the two batched queue words, the tile ticket
 //   [64, 68)    status slot used by the synchronous calls
 //   [128, 152)  batch totals (3 x uint64)
 //   [192, 208)  resumable piece: offset of the code of rank k, code count

@@ -67,6 +67,19 @@ __device__ __forceinline__ u64 aadd(u64 *p, u64 v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Tiles of a look-back launch are numbered in the order their workgroups
+// (or wavefronts) start, by an atomic ticket: a tile then only ever waits
+// for tiles whose tickets running workgroups already hold, whatever else
+// the device is running (a workgroup index would not do: with other
+// kernels resident, a later index can start while an earlier one waits for
+// room on another XCD).  The taker of the last ticket resets the counter
+// for the next launch on this workspace; no ticket is taken after it.
+__device__ __forceinline__ u32 take_ticket(u64 *ctr, u64 total) {
+    const u64 t = aadd(ctr, 1);
+    if (t == total - 1) astore(ctr, 0);
+    return (u32)t;
+}
+
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ u32 lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -850,10 +863,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     const u32 wpb = blockDim.x >> 6;
     u32 *stage = lds + wib * kStageWords;
 
-    // Tile = workgroup index: workgroups are dispatched in index order, so
-    // every tile a look-back waits for is already running.
-    const u32 tile = blockIdx.x;
     if (tid == 0) {
+        sh.item = take_ticket(a.hdr + kTicketWord, a.ntiles);
         sh.epoch = (u32)aload(a.hdr);
         if (PIECE) {
             sh.cur = a.cursor_in[0];
@@ -862,6 +873,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     }
     __syncthreads();
     const u32 epoch = sh.epoch;
+    const u32 tile = (u32)sh.item;
 
     const u64 tb = (u64)wpb * SEGS * kSegBytes;
     TileIn t{};
@@ -939,10 +951,14 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     const u32 wib = tid >> 6;
     const u32 wpb = blockDim.x >> 6;
     u32 *stage = lds + wib * kStageWords;
-    const u32 chunk = blockIdx.x, nch = gridDim.x;
-    if (tid == 0) sh.epoch = (u32)aload(a.hdr);
+    const u32 nch = gridDim.x;
+    if (tid == 0) {
+        sh.item = take_ticket(a.hdr + kTicketWord, nch);
+        sh.epoch = (u32)aload(a.hdr);
+    }
     __syncthreads();
     const u32 epoch = sh.epoch;
+    const u32 chunk = (u32)sh.item;
     const u64 tb = (u64)wpb * SEGS * kSegBytes;
     const u64 t0 = (u64)chunk * a.ntiles / nch, t1 = (u64)(chunk + 1) * a.ntiles / nch;
     TileIn t{};
@@ -2078,10 +2094,14 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
     const u32 tid = threadIdx.x;
     const u32 ln = lane_id();
     const u32 wib = tid >> 6;
-    const u32 blk = blockIdx.x;
-    if (tid == 0) sh_epoch = (u32)aload(a.hdr);
+    __shared__ u32 sh_blk;
+    if (tid == 0) {
+        sh_blk = take_ticket(a.hdr + kTicketWord, gridDim.x);
+        sh_epoch = (u32)aload(a.hdr);
+    }
     __syncthreads();
     const u32 epoch = sh_epoch;
+    const u32 blk = sh_blk;
     const u32 tag = make_tag(epoch);
 
     const u64 i = (u64)blk * kPrepBlock + tid;
@@ -2336,8 +2356,10 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
     const u64 wg = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
     if (wg >= a.ntiles) return;
     u8 *stage = (u8 *)(lds + wib * (kEncodeWaveValues * 5 / 4 + 8));
-    // tile = wavefront index in dispatch order; see k_stream for the epoch
-    const u32 tile = (u32)wg;
+    // tile = this wavefront's ticket (see take_ticket); see k_stream for the epoch
+    u32 tk = 0;
+    if (ln == 0) tk = take_ticket(a.hdr + kTicketWord, a.ntiles);
+    const u32 tile = first_lane(tk);
     const u32 epoch = first_lane((u32)aload(a.hdr));
     const u32 tag = make_tag(epoch);
 

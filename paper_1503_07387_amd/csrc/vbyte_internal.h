@@ -39,10 +39,12 @@ struct Desc {
 };
 static_assert(sizeof(Desc) == 16, "descriptor is 16 bytes");
 
+constexpr int kTicketWord = 3;   // zero between launches (take_ticket)
+
 // Header words: [0] launch epoch, [1] batched large-span queue, [2] batched
-// small-chunk queue.  Tiles of a single-stream launch are workgroup indices
-// (workgroups are dispatched in index order, so a tile's predecessors are
-// running when it looks back); each launch reads the epoch, tags its
+// small-chunk queue, [3] tile ticket.  Tiles of a single-stream launch are
+// numbered by ticket in the order their workgroups start (so a tile's
+// predecessors are running when it looks back); each launch reads the epoch, tags its
 // descriptors with it, and the tile that finishes the chain stores epoch+1,
 // which retires the launch's descriptors for the next one.  Descriptors carry
 // the low 25 bits of the epoch, so the host re-zeroes a workspace before 2^24
