@@ -644,9 +644,9 @@ def main():
     ap.add_argument("--no-decode64", action="store_true", help="skip the 64-bit decode line")
     ap.add_argument("--no-delta4", action="store_true", help="skip the blocks-of-four decode line")
     ap.add_argument("--no-intersect", action="store_true", help="skip the intersection line")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the library's current tiling instead of autotuning each stream "
-                         "(profiling runs: every decode dispatch then uses one tiling)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune each stream's tiling first instead of using the library's "
+                         "default (two passes, 2 segments x 8 wavefronts)")
     ap.add_argument("--tuning", default=None,
                     help="SEGS,WAVES,CHUNK (both streams) or SEGS,WAVES,CHUNK/SEGS,WAVES,CHUNK "
                          "(gap-mean-8 stream / gap-mean-300 stream): use this tiling and "
@@ -685,7 +685,7 @@ def main():
         if fixed:
             sg, wv, ch = (int(x) for x in fixed[min(i, len(fixed) - 1)].split(","))
             vbyte.set_tuning(sg, wv, 0, tiles_per_chunk=ch)
-        elif not args.no_autotune:
+        elif args.autotune:
             vbyte.autotune_decode(s["bytes"], N_STREAM, delta=True, out=s["out"], reps=3)
         tunings.append(vbyte.get_tuning())
         log(f"stream mean {s['mean']}: tuning {tunings[-1]}")

@@ -352,13 +352,16 @@ vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t sm
 void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_list_bytes);
 
 /* Kernel of the single-stream decodes (vbyte_decode*, not the batched
- * forms): 0 (the default) gives every tile its own look-back; k in 1..64
- * gives each workgroup a chunk of k consecutive tiles, which it first reads
- * for their counts and sums, then looks back once for the chunk, then reads
- * again and decodes; -1 decodes in three launches with no look-back: every
- * tile's count and sum, a scan of them in one workgroup, then every tile
- * with its prefix known (the input is read twice).  Returns VBYTE_EINVAL
- * outside -1..64. */
+ * forms): -1 (the default) decodes in three launches with no look-back:
+ * every tile's terminator count and byte sum, a scan of them in one
+ * workgroup, then every tile with its prefix known (the input is read
+ * twice; no workgroup ever waits for another); 0 gives every tile its own
+ * look-back; k in 1..64 gives each workgroup a chunk of k consecutive
+ * tiles, which it first reads for their counts and sums, then looks back
+ * once for the chunk, then reads again and decodes.  The look-back kernels
+ * number their tiles by an atomic ticket, so they are safe next to any
+ * other work on the device, at the cost of that atomic.  Returns
+ * VBYTE_EINVAL outside -1..64. */
 vbyte_status vbyte_set_chunk_tiles(int tiles_per_chunk);
 int vbyte_get_chunk_tiles(void);
 

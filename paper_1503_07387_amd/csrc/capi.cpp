@@ -24,11 +24,11 @@ namespace {
 
 thread_local char g_last_error[256] = "";
 
-std::atomic<int> g_segs{4};
+std::atomic<int> g_segs{2};
 std::atomic<int> g_wpb{8};
 std::atomic<int64_t> g_small{16384};
-std::atomic<int> g_chunk{0};   // single stream: 0 = per-tile look-back, k = chunks of k tiles,
-                               // -1 = three launches with no look-back
+std::atomic<int> g_chunk{-1};  // single stream: -1 = three launches with no look-back (default),
+                               // 0 = per-tile look-back, k = chunks of k tiles
 
 vbyte_status hip_fail(hipError_t e, const char *what) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
