@@ -1738,63 +1738,105 @@ __global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
     }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k4_scan(Stream4Args a) {
-    __shared__ Run4 wtot[kScanBlock / kWave];
-    __shared__ u32 wm[kScanBlock / kWave];
+// Exclusive prefixes of the units in absolute classes.  Each round scans
+// the counts first (plain sums); a unit's class sums, rotated by the count
+// of the codes before it, are then in absolute classes, and four plain
+// scans finish the round: the rotating combination never enters the scan.
+constexpr int kScan4Per = 8;     // units per thread per round of k4_scan
+constexpr int kScan4Block = 512;  // threads of k4_scan (room for its registers)
+
+__global__ __launch_bounds__(kScan4Block) void k4_scan(Stream4Args a) {
+    __shared__ u32 wc[kScan4Block / kWave], wm[kScan4Block / kWave];
+    __shared__ u32 wsc[4][kScan4Block / kWave];
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
     const u8 last = tid == 0 ? a.base[a.vend - 1] : 0;
-    Run4 carry{0, {a.prev4[0], a.prev4[1], a.prev4[2], a.prev4[3]}};
+    u64 carry_c = 0;
+    u32 carry_s[4] = {a.prev4[0], a.prev4[1], a.prev4[2], a.prev4[3]};
     bool carry_m = false;
-    for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScanBlock * kScanPer) {
-        const u64 i0 = b0 + (u64)tid * kScanPer;
-        Run4 mine{0, {0, 0, 0, 0}};
+    for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScan4Block * kScan4Per) {
+        const u64 i0 = b0 + (u64)tid * kScan4Per;
+        // pass 1: counts only (the slots are read again from cache below,
+        // which keeps this kernel within its registers)
+        u32 cnt[kScan4Per];
+        u32 lc = 0;
         bool m = false;
-        for (int k = 0; k < kScanPer; ++k) {
+#pragma unroll
+        for (int k = 0; k < kScan4Per; ++k) {
+            cnt[k] = 0;
             if (i0 + k < a.nunits) {
-                mine = join4(mine, get4(a.slots + 2 * (i0 + k)));
+                const uint4 q = a.slots[2 * (i0 + k)];
+                cnt[k] = q.x;   // a unit's count: at most its bytes
                 m |= a.slots[2 * (i0 + k) + 1].z != 0;
             }
+            lc += cnt[k];
         }
-        // inclusive scan over the wavefront's lanes (lane order = unit order)
-        Run4 inc = mine;
-#pragma unroll
-        for (u32 d = 1; d < kWave; d <<= 1) {
-            Run4 o;
-            o.c = __shfl_up(inc.c, d, kWave);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) o.s[c] = __shfl_up(inc.s[c], d, kWave);
-            if (ln >= d) inc = join4(o, inc);
-        }
+        const u32 ci = wave_scan(lc);   // 64 x 8 units of at most 16 KiB
         const bool anym = ballot(m) != 0;
         if (ln == kWave - 1) {
-            wtot[wib] = inc;
+            wc[wib] = ci;
             wm[wib] = anym ? 1u : 0u;
         }
         __syncthreads();
-        Run4 pre = carry;
-        for (u32 k = 0; k < wib; ++k) pre = join4(pre, wtot[k]);
-        // exclusive within the wavefront: the lane below's inclusive value
-        Run4 below;
-        below.c = __shfl_up(inc.c, 1, kWave);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) below.s[c] = __shfl_up(inc.s[c], 1, kWave);
-        if (ln > 0) pre = join4(pre, below);
-        for (int k = 0; k < kScanPer; ++k) {
-            if (i0 + k < a.nunits) {
-                const Run4 r = get4(a.slots + 2 * (i0 + k));
-                put4(a.slots + 2 * (i0 + k), pre);
-                pre = join4(pre, r);
-            }
-        }
-        Run4 tot = carry;
-        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
-            tot = join4(tot, wtot[k]);
+        u64 pc = carry_c, tc = carry_c;
+        for (u32 k = 0; k < kScan4Block / kWave; ++k) {
+            if (k < wib) pc += wc[k];
+            tc += wc[k];
             carry_m |= wm[k] != 0;
         }
-        carry = tot;
+        pc += ci - lc;
+        // pass 2: class sums in absolute classes
+        u64 cc = pc;
+        u32 ls[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < kScan4Per; ++k) {
+            if (i0 + k < a.nunits) {
+                u32 t[4];
+                rot4(get4(a.slots + 2 * (i0 + k)).s, (u32)cc, t);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) ls[c] += t[c];
+            }
+            cc += cnt[k];
+        }
+        u32 si[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            si[c] = wave_scan(ls[c]);
+            if (ln == kWave - 1) wsc[c][wib] = si[c];
+        }
         __syncthreads();
+        u32 ps[4], ts[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ps[c] = ts[c] = carry_s[c];
+#pragma unroll
+        for (u32 k = 0; k < kScan4Block / kWave; ++k) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const u32 v = wsc[c][k];
+                ps[c] += k < wib ? v : 0u;
+                ts[c] += v;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ps[c] += si[c] - ls[c];
+        // pass 3: the exclusive prefixes, in place
+        cc = pc;
+#pragma unroll
+        for (int k = 0; k < kScan4Per; ++k) {
+            if (i0 + k < a.nunits) {
+                u32 t[4];
+                rot4(get4(a.slots + 2 * (i0 + k)).s, (u32)cc, t);
+                put4(a.slots + 2 * (i0 + k), Run4{cc, {ps[0], ps[1], ps[2], ps[3]}});
+#pragma unroll
+                for (int c = 0; c < 4; ++c) ps[c] += t[c];
+            }
+            cc += cnt[k];
+        }
+        carry_c = tc;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) carry_s[c] = ts[c];
+        __syncthreads();   // wc, wm and wsc are rewritten by the next round
     }
-    if (tid == 0) *a.d_status = final_status(carry_m, last, carry.c, a.n);
+    if (tid == 0) *a.d_status = final_status(carry_m, last, carry_c, a.n);
 }
 
 template <int SEGS>
@@ -1866,7 +1908,7 @@ hipError_t launch4_t(const Stream4Args &a, int wpb, hipStream_t s) {
     k4_agg<SEGS><<<blocks, wpb * kWave, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k4_scan<<<1, kScanBlock, 0, s>>>(a);
+    k4_scan<<<1, kScan4Block, 0, s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const u64 ngroups = (a.vend + SEGS * kSegBytes - 1) / (SEGS * kSegBytes);
