@@ -1101,76 +1101,75 @@ __global__ __launch_bounds__(kMaxBlock) void k_tile_agg(StreamArgs a) {
 
 constexpr int kScanBlock = 1024;
 
-constexpr int kScanPer = 8;   // tiles per thread per round
+constexpr int kScanPer = 8;   // slots per lane per round
 
+// The scans below run in one workgroup, so one CU's memory pipeline carries
+// all their slot traffic: every access is coalesced.  In a round wavefront
+// w owns the kWave x kScanPer consecutive slots from b0 + w kWave kScanPer,
+// lane l the slots l, l + 64, ... of them; a wavefront's exclusive prefix
+// is taken in that order by one wave scan per row of 64.
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
     __shared__ u32 wc[kScanBlock / kWave], ws[kScanBlock / kWave], wm[kScanBlock / kWave];
-    __shared__ u64 carry_c;
-    __shared__ u32 carry_s, carry_m;
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
-    if (tid == 0) {
-        carry_c = 0;
-        carry_s = a.prev;
-        carry_m = 0;
-    }
-    __syncthreads();
+    const u8 lastb = a.base[a.vend - 1];   // one address for all: in flight with the first slots
+    const u64 lastt = a.ntiles - 1;        // ntiles >= 1
+    u64 carry_c = 0;
+    u32 carry_s = a.prev;
+    bool carry_m = false;
     for (u64 b0 = 0; b0 < a.ntiles; b0 += (u64)kScanBlock * kScanPer) {
-        const u64 i0 = b0 + (u64)tid * kScanPer;
-        u32 c[kScanPer], sm[kScanPer];
+        const u64 i0 = b0 + (u64)wib * (kWave * kScanPer) + ln;
+        // every load issued before the first use: indexes past the end read
+        // the last slot and count as zero
+        Desc d[kScanPer];
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const u64 i = i0 + (u64)q * kWave;
+            d[q] = a.desc[i < lastt ? i : lastt];
+        }
+        u32 pc[kScanPer], ps[kScanPer];
+        u32 rc = 0, rs = 0;   // the wavefront's running totals (64 x 8 tiles fit 32 bits)
         bool m = false;
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
-            c[q] = sm[q] = 0;
-            if (i0 + q < a.ntiles) {
-                const Desc d = a.desc[i0 + q];
-                c[q] = (u32)(d.c & kCountMask);   // at most the tile's bytes
-                m |= ((d.c >> 37) & 1u) != 0;
-                sm[q] = (u32)d.s;
-            }
+            const bool in = i0 + (u64)q * kWave < a.ntiles;
+            const u32 c = in ? (u32)(d[q].c & kCountMask) : 0u;   // at most the tile's bytes
+            const u32 sm = in ? (u32)d[q].s : 0u;
+            m |= in && ((d[q].c >> 37) & 1u) != 0;
+            const u32 ci = wave_scan(c), si = wave_scan(sm);
+            pc[q] = rc + ci - c;
+            ps[q] = rs + si - sm;
+            rc += read_lane(ci, 63);
+            rs += read_lane(si, 63);
         }
-        u32 lc = 0, ls = 0;
-#pragma unroll
-        for (int q = 0; q < kScanPer; ++q) {
-            lc += c[q];
-            ls += sm[q];
-        }
-        // 64 x 8 tiles' counts fit 32 bits
-        const u32 ci = wave_scan(lc), si = wave_scan(ls);
         const bool anym = ballot(m) != 0;
-        if (ln == kWave - 1) {
-            wc[wib] = ci;
-            ws[wib] = si;
+        if (ln == 0) {
+            wc[wib] = rc;
+            ws[wib] = rs;
             wm[wib] = anym ? 1u : 0u;
         }
         __syncthreads();
-        u64 pc = carry_c;
-        u32 ps = carry_s;
-        for (u32 k = 0; k < wib; ++k) {
-            pc += wc[k];
-            ps += ws[k];
+        u64 oc = carry_c;
+        u32 os = carry_s;
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
+            if (k == wib) {
+                oc = carry_c;
+                os = carry_s;
+            }
+            carry_c += wc[k];
+            carry_s += ws[k];
+            carry_m |= wm[k] != 0;
         }
-        pc += ci - lc;
-        ps += si - ls;
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
-            if (i0 + q < a.ntiles) {
-                a.desc[i0 + q].c = pc;
-                a.desc[i0 + q].s = ps;
-            }
-            pc += c[q];
-            ps += sm[q];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (u32 k = 0; k < kScanBlock / kWave; ++k) {
-                carry_c += wc[k];
-                carry_s += ws[k];
-                carry_m |= wm[k];
+            const u64 i = i0 + (u64)q * kWave;
+            if (i < a.ntiles) {
+                a.desc[i].c = oc + pc[q];
+                a.desc[i].s = os + ps[q];
             }
         }
-        __syncthreads();
+        __syncthreads();   // wc, ws and wm are rewritten by the next round
     }
-    if (tid == 0) *a.d_status = final_status(carry_m != 0, a.base[a.vend - 1], carry_c, a.n);
+    if (tid == 0) *a.d_status = final_status(carry_m, lastb, carry_c, a.n);
 }
 
 template <int D, int SEGS>
@@ -1295,11 +1294,29 @@ __device__ __forceinline__ void load12(const u8 *base, i64 v, u64 lo, u64 hi, bo
     }
 }
 
-// Wavefront sum of 64-bit values.
+// One step of a 64-bit wavefront scan: add the DPP-selected lane's value.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ void add64_dpp(u32 &lo, u32 &hi) {
+    const u32 yl = dpp_zero<CTRL, ROWS>(lo), yh = dpp_zero<CTRL, ROWS>(hi);
+    lo += yl;
+    hi += yh + (lo < yl ? 1u : 0u);
+}
+// Inclusive wave64 prefix sum mod 2^64: the steps of wave_scan on both
+// halves, with the carry of the low half.
+__device__ __forceinline__ u64 wave_scan64(u64 x) {
+    u32 lo = (u32)x, hi = (u32)(x >> 32);
+    add64_dpp<0x111>(lo, hi);
+    add64_dpp<0x112>(lo, hi);
+    add64_dpp<0x114>(lo, hi);
+    add64_dpp<0x118>(lo, hi);
+    add64_dpp<0x142, 0xA>(lo, hi);
+    add64_dpp<0x143, 0xC>(lo, hi);
+    return ((u64)hi << 32) | lo;
+}
+// Wavefront sum of 64-bit values (the same on every lane).
 __device__ __forceinline__ u64 wave_sum64(u64 x) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, kWave);
-    return x;
+    const u64 t = wave_scan64(x);
+    return ((u64)read_lane((u32)(t >> 32), 63) << 32) | read_lane((u32)t, 63);
 }
 
 template <int D, int SEGS>
@@ -1350,73 +1367,68 @@ __global__ __launch_bounds__(kMaxBlock) void k64_agg(Stream64Args a) {
     if (ln == 0) a.slots[u] = make_uint4(ucont, wmal ? 1u : 0u, (u32)usum, (u32)(usum >> 32));
 }
 
-// Inclusive wavefront scan of 64-bit values.
-__device__ __forceinline__ u64 wave_scan64(u64 x) {
-    const u32 ln = lane_id();
-#pragma unroll
-    for (u32 d = 1; d < kWave; d <<= 1) {
-        const u64 y = __shfl_up(x, d, kWave);
-        if (ln >= d) x += y;
-    }
-    return x;
-}
 
 __global__ __launch_bounds__(kScanBlock) void k64_scan(Stream64Args a) {
     __shared__ u32 wc[kScanBlock / kWave], wm[kScanBlock / kWave];
     __shared__ u64 ws[kScanBlock / kWave];
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
-    const u8 last = tid == 0 ? a.base[a.vend - 1] : 0;
+    const u8 lastb = a.base[a.vend - 1];   // one address for all: in flight with the first slots
+    const u64 lastu = a.nunits - 1;        // nunits >= 1
     u64 carry_c = 0, carry_s = a.prev;
     bool carry_m = false;
+    // the layout of k_tile_scan: coalesced rows of 64 slots per wavefront
     for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScanBlock * kScanPer) {
-        const u64 i0 = b0 + (u64)tid * kScanPer;
+        const u64 i0 = b0 + (u64)wib * (kWave * kScanPer) + ln;
         uint4 q[kScanPer];
 #pragma unroll
-        for (int k = 0; k < kScanPer; ++k)
-            q[k] = i0 + k < a.nunits ? a.slots[i0 + k] : make_uint4(0, 0, 0, 0);
-        u32 lc = 0;
-        u64 ls = 0;
+        for (int k = 0; k < kScanPer; ++k) {
+            const u64 i = i0 + (u64)k * kWave;
+            q[k] = a.slots[i < lastu ? i : lastu];   // past the end: counted as zero
+        }
+        u32 pc[kScanPer];
+        u64 ps[kScanPer];
+        u32 rc = 0;   // 64 x 8 units of at most 16 KiB: the counts fit 32 bits
+        u64 rs = 0;
         bool m = false;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            lc += q[k].x;
-            ls += q[k].z | ((u64)q[k].w << 32);
-            m |= q[k].y != 0;
+            const bool in = i0 + (u64)k * kWave < a.nunits;
+            const u32 c = in ? q[k].x : 0u;
+            const u64 sm = in ? (q[k].z | ((u64)q[k].w << 32)) : 0ull;
+            m |= in && q[k].y != 0;
+            const u32 ci = wave_scan(c);
+            const u64 si = wave_scan64(sm);
+            pc[k] = rc + ci - c;
+            ps[k] = rs + si - sm;
+            rc += read_lane(ci, 63);
+            rs += ((u64)read_lane((u32)(si >> 32), 63) << 32) | read_lane((u32)si, 63);
         }
-        // 64 x 8 units of at most 16 KiB: the counts fit 32 bits
-        const u32 ci = wave_scan(lc);
-        const u64 si = wave_scan64(ls);
         const bool anym = ballot(m) != 0;
-        if (ln == kWave - 1) {
-            wc[wib] = ci;
-            ws[wib] = si;
+        if (ln == 0) {
+            wc[wib] = rc;
+            ws[wib] = rs;
             wm[wib] = anym ? 1u : 0u;
         }
         __syncthreads();
-        u64 pc = carry_c, rc = carry_c, ps = carry_s, rs = carry_s;
+        u64 oc = carry_c, os = carry_s;
         for (u32 k = 0; k < kScanBlock / kWave; ++k) {
-            if (k < wib) {
-                pc += wc[k];
-                ps += ws[k];
+            if (k == wib) {
+                oc = carry_c;
+                os = carry_s;
             }
-            rc += wc[k];
-            rs += ws[k];
+            carry_c += wc[k];
+            carry_s += ws[k];
             carry_m |= wm[k] != 0;
         }
-        carry_c = rc;
-        carry_s = rs;
-        pc += ci - lc;
-        ps += si - ls;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            if (i0 + k < a.nunits)
-                a.slots[i0 + k] = make_uint4((u32)pc, (u32)(pc >> 32), (u32)ps, (u32)(ps >> 32));
-            pc += q[k].x;
-            ps += q[k].z | ((u64)q[k].w << 32);
+            const u64 i = i0 + (u64)k * kWave;
+            const u64 c = oc + pc[k], sv = os + ps[k];
+            if (i < a.nunits) a.slots[i] = make_uint4((u32)c, (u32)(c >> 32), (u32)sv, (u32)(sv >> 32));
         }
-        __syncthreads();
+        __syncthreads();   // wc, ws and wm are rewritten by the next round
     }
-    if (tid == 0) *a.d_status = final_status(carry_m, last, carry_c, a.n);
+    if (tid == 0) *a.d_status = final_status(carry_m, lastb, carry_c, a.n);
 }
 
 // Assembly of a lane's 64-bit codes from byte 24 down to byte 0 of the
@@ -1603,8 +1615,9 @@ hipError_t launch64_t(const Stream64Args &a, int wpb, hipStream_t s) {
 // segments, one group per wavefront; k4_agg summarises every group and
 // unit, k4_scan turns the units into exclusive prefixes (absolute classes,
 // from prev4) and writes the status, k4_known decodes one group per
-// wavefront.  Codes are counted exactly (those that begin in the group and
-// end in the stream), so no straddle correction is needed.
+// wavefront.  A group's codes are those that begin in it and end in the
+// stream: the aggregate takes them as byte sums by class (d4_sums), the
+// decode assembles them (d4_group).
 
 struct Run4 {
     u64 c;
@@ -1653,7 +1666,7 @@ __device__ __forceinline__ u32 add_by_class(const u32 (&u)[16], u32 emit, u32 cl
 }
 
 // One group's segments: masks and values of every segment, and what the
-// caller does with them (summary or decode).  Returns the malformed flag.
+// caller does with them (the decode).  Returns the malformed flag.
 struct D4Seg {
     u32 emit;
     u32 u[16];
@@ -1705,6 +1718,148 @@ __device__ __forceinline__ bool d4_group(const Stream4Args &a, u64 wv, F &&f) {
     return mal;
 }
 
+// A lane's byte sums by class.  The class of a byte is the rank mod 4, from
+// the group's first code, of the code that holds it: B (the class of the
+// code running into the lane) plus the codes beginning at or before the
+// byte in the lane.  Each class sum is the byte-sum identity of seg_bytes
+// over the bytes of that class, the class masks coming from a byte lookup
+// (v_perm) of the per-byte class; classes 0..2 are added to s[0..2] and
+// all bytes to s[3].
+__device__ __forceinline__ void class_bytes(const u32 (&w)[4], u32 below, u32 emit, u32 B,
+                                            u32 (&s)[4]) {
+    u32 c[5];
+    c[0] = (below >> 7) & 0x01010101u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k + 1] = (w[k] >> 7) & 0x01010101u;
+    u32 g[4], m1[4], cls[4], any2 = 0;
+    u32 q = B * 0x01010101u;
+    u32 t0[4] = {0, 0, 0, 0}, t1[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        g[k] = w[k] & 0x7F7F7F7Fu;
+        m1[k] = __builtin_amdgcn_alignbyte(c[k + 1], c[k], 3);
+        any2 |= m1[k] & __builtin_amdgcn_alignbyte(c[k + 1], c[k], 2);
+        // code starts of the dword as 0x01 bytes, then per byte B + the
+        // starts at or before it (at most 3 + 16, no carry between bytes)
+        const u32 st = ((((emit >> (4 * k)) & 0xFu) * 0x00204081u) & 0x01010101u);
+        const u32 p = st * 0x01010101u + q;
+        q = (p >> 24) * 0x01010101u;
+        cls[k] = p & 0x03030303u;
+        t0[3] = __builtin_amdgcn_sad_u8(g[k], 0u, t0[3]);
+        t1[3] = __builtin_amdgcn_udot4(g[k], m1[k], t1[3], false);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const u32 mk = __builtin_amdgcn_perm(0u, 1u << (8 * cc), cls[k]);
+            t0[cc] = __builtin_amdgcn_udot4(g[k], mk, t0[cc], false);
+            t1[cc] = __builtin_amdgcn_udot4(g[k], mk & m1[k], t1[cc], false);
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) s[cc] += t0[cc] + 127u * t1[cc];
+    if (ballot(any2 != 0) != 0) {
+        u32 t2[4] = {0, 0, 0, 0}, t3[4] = {0, 0, 0, 0}, t4[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u32 m2 = m1[k] & __builtin_amdgcn_alignbyte(c[k + 1], c[k], 2);
+            const u32 m3 = m2 & __builtin_amdgcn_alignbyte(c[k + 1], c[k], 1);
+            const u32 m4 = m3 & c[k];
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const u32 mk = cc < 3 ? __builtin_amdgcn_perm(0u, 1u << (8 * cc), cls[k]) : 0x01010101u;
+                t2[cc] = __builtin_amdgcn_udot4(g[k], mk & m2, t2[cc], false);
+                t3[cc] = __builtin_amdgcn_udot4(g[k], mk & m3, t3[cc], false);
+                t4[cc] = __builtin_amdgcn_udot4(g[k], mk & m4, t4[cc], false);
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) s[cc] += 16256u * t2[cc] + 2080768u * t3[cc] + 266338304u * t4[cc];
+    }
+}
+
+// The code that runs across a boundary, seen from before it: last4 holds
+// the 4 bytes before the boundary, ha the 4 after (valid bytes flagged in
+// bits 0..3 of hav).  rest = the byte-sum terms of the code's bytes after
+// the boundary; returns whether such a code ends in the valid bytes.
+__device__ __forceinline__ bool code_tail(u32 last4, u32 ha, u32 hav, u32 &rest) {
+    const u32 p0 = (u32)__builtin_clz(~(top4(last4) << 28));
+    rest = 0;
+    if (!p0) return false;
+#pragma unroll
+    for (u32 j = 0; j < 4; ++j) {
+        if (!((hav >> j) & 1u)) return false;
+        const u32 b = (ha >> (8 * j)) & 0xFFu;
+        const u32 sh = 7u * (p0 + j);
+        if (sh < 32) rest += (b & 0x7Fu) << sh;
+        if (b < 0x80u) return true;
+    }
+    return false;
+}
+
+// One group's summary (its count and class sums, from its first code) by
+// byte sums, no code assembled: per-lane class sums, then the bytes of the
+// code that runs into the group (all of class 3, i.e. rank -1) taken out
+// of class 3 and the bytes after the group of the code that runs out of it
+// added to that code's class.  Returns the malformed flag.
+template <bool EDGE, int SEGS>
+__device__ __forceinline__ bool d4_sums(const Stream4Args &a, u64 wv, Run4 &grp) {
+    const u32 ln = lane_id();
+    u32 w[SEGS][4], valid[SEGS];
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
+        if (EDGE) {
+            load16_guarded(a.base, v, a.vstart, a.vend, w[s], valid[s]);
+        } else {
+            load16(a.base + v, w[s]);
+            valid[s] = 0xFFFFu;
+        }
+    }
+    u32 hb, hbv, ha, hav;
+    if (EDGE) {
+        load4_guarded(a.base, (i64)wv - 4, a.vstart, a.vend, hb, hbv);
+        load4_guarded(a.base, (i64)(wv + SEGS * kSegBytes), a.vstart, a.vend, ha, hav);
+    } else {
+        hb = *(const u32 *)(a.base + wv - 4);
+        ha = *(const u32 *)(a.base + wv + SEGS * kSegBytes);
+        hbv = hav = 0xFu;
+    }
+    bool mal = false;
+    u32 acc[4] = {0, 0, 0, 0};
+    u32 cnt = 0;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 l0w = s == 0 ? hb : read_lane(w[s - 1][3], 63);
+        const u32 below = from_lane_below(w[s][3], l0w);
+        bool below_ok = true;
+        if (EDGE) {
+            const u32 l0v = s == 0 ? (hbv << 12) : read_lane(valid[s - 1], 63);
+            below_ok = ((from_lane_below(valid[s], l0v) >> 15) & 1u) != 0;
+        }
+        const u32 ab = from_lane_above(w[s][0], s + 1 < SEGS ? read_lane(w[s + 1][0], 0) : ha);
+        const u32 abv = EDGE ? from_lane_above(valid[s], s + 1 < SEGS ? read_lane(valid[s + 1], 0) : hav) & 0xFu
+                             : 0xFu;
+        const SegMask m = seg_mask<EDGE>(w[s], valid[s], below, below_ok, ab, abv);
+        mal |= m.mal;
+        const u32 cl = __builtin_popcount(m.emit);
+        const u32 ci = wave_scan(cl);
+        class_bytes(w[s], below, m.emit, (cnt + ci - cl - 1u) & 3u, acc);
+        cnt += read_lane(ci, 63);
+    }
+    u32 S[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) S[c] = wave_sum(acc[c]);
+    S[3] -= S[0] + S[1] + S[2];
+    S[3] -= straddle(hb, read_lane(w[0][0], 0), read_lane(w[0][1], 0)).rest;
+    u32 rest;
+    if (code_tail(read_lane(w[SEGS - 1][3], 63), ha, hav, rest)) {
+        const u32 lc = (cnt - 1u) & 3u;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) S[c] += lc == (u32)c ? rest : 0u;
+    }
+    grp = Run4{cnt, {S[0], S[1], S[2], S[3]}};
+    return mal;
+}
+
 template <int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
     constexpr u32 W = SEGS * kSegBytes;
@@ -1716,18 +1871,9 @@ __global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
     for (u32 g = 0; g < kUnitGroups; ++g) {
         const u64 wv = (u * kUnitGroups + g) * W;
         if (wv >= a.vend) break;
-        Run4 grp{0, {0, 0, 0, 0}};
-        auto f = [&](const D4Seg &sg) {
-            const u32 cl = __builtin_popcount(sg.emit);
-            const u32 ci = wave_scan(cl);
-            u32 s[4] = {0, 0, 0, 0};
-            add_by_class(sg.u, sg.emit, (u32)(grp.c + ci - cl) & 3u, s);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) grp.s[c] += wave_sum(s[c]);
-            grp.c += read_lane(ci, 63);
-        };
+        Run4 grp;
         const bool interior = wv >= 16 && wv + W + 4 <= a.vend;
-        mal |= interior ? d4_group<false, SEGS>(a, wv, f) : d4_group<true, SEGS>(a, wv, f);
+        mal |= interior ? d4_sums<false, SEGS>(a, wv, grp) : d4_sums<true, SEGS>(a, wv, grp);
         if (ln == 0) put4(a.gslots + 2 * (u * kUnitGroups + g), grp);
         unit = join4(unit, grp);
     }
@@ -1738,112 +1884,103 @@ __global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
     }
 }
 
-// Exclusive prefixes of the units in absolute classes.  Each round scans
-// the counts first (plain sums); a unit's class sums, rotated by the count
-// of the codes before it, are then in absolute classes, and four plain
-// scans finish the round: the rotating combination never enters the scan.
-constexpr int kScan4Per = 8;     // units per thread per round of k4_scan
-constexpr int kScan4Block = 512;  // threads of k4_scan (room for its registers)
-
-__global__ __launch_bounds__(kScan4Block) void k4_scan(Stream4Args a) {
-    __shared__ u32 wc[kScan4Block / kWave], wm[kScan4Block / kWave];
-    __shared__ u32 wsc[4][kScan4Block / kWave];
+// Exclusive prefixes of the units in absolute classes, in the coalesced
+// layout of k_tile_scan.  Each round scans the counts first (plain sums); a
+// unit's class sums, rotated by the count of the codes before it, are then
+// in absolute classes, and four plain scans finish the round: the rotating
+// combination never enters a scan.
+__global__ __launch_bounds__(kScanBlock) void k4_scan(Stream4Args a) {
+    __shared__ u32 wc[kScanBlock / kWave], wm[kScanBlock / kWave];
+    __shared__ u32 wsc[4][kScanBlock / kWave];
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
-    const u8 last = tid == 0 ? a.base[a.vend - 1] : 0;
+    const u8 lastb = a.base[a.vend - 1];   // one address for all: in flight with the first slots
+    const u64 lastu = a.nunits - 1;        // nunits >= 1
     u64 carry_c = 0;
     u32 carry_s[4] = {a.prev4[0], a.prev4[1], a.prev4[2], a.prev4[3]};
     bool carry_m = false;
-    for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScan4Block * kScan4Per) {
-        const u64 i0 = b0 + (u64)tid * kScan4Per;
-        // pass 1: counts only (the slots are read again from cache below,
-        // which keeps this kernel within its registers)
-        u32 cnt[kScan4Per];
-        u32 lc = 0;
+    for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScanBlock * kScanPer) {
+        const u64 i0 = b0 + (u64)wib * (kWave * kScanPer) + ln;
+        uint4 lo[kScanPer], hi[kScanPer];
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const u64 i = i0 + (u64)k * kWave;
+            const u64 j = i < lastu ? i : lastu;   // past the end: counted as zero
+            lo[k] = a.slots[2 * j];
+            hi[k] = a.slots[2 * j + 1];
+        }
+        // counts
+        u32 pc[kScanPer];
+        u32 rc = 0;   // 64 x 8 units of at most 16 KiB: fits 32 bits
         bool m = false;
 #pragma unroll
-        for (int k = 0; k < kScan4Per; ++k) {
-            cnt[k] = 0;
-            if (i0 + k < a.nunits) {
-                const uint4 q = a.slots[2 * (i0 + k)];
-                cnt[k] = q.x;   // a unit's count: at most its bytes
-                m |= a.slots[2 * (i0 + k) + 1].z != 0;
-            }
-            lc += cnt[k];
+        for (int k = 0; k < kScanPer; ++k) {
+            const bool in = i0 + (u64)k * kWave < a.nunits;
+            const u32 c = in ? lo[k].x : 0u;   // a unit's count: at most its bytes
+            m |= in && hi[k].z != 0;
+            const u32 ci = wave_scan(c);
+            pc[k] = rc + ci - c;
+            rc += read_lane(ci, 63);
         }
-        const u32 ci = wave_scan(lc);   // 64 x 8 units of at most 16 KiB
         const bool anym = ballot(m) != 0;
-        if (ln == kWave - 1) {
-            wc[wib] = ci;
+        if (ln == 0) {
+            wc[wib] = rc;
             wm[wib] = anym ? 1u : 0u;
         }
         __syncthreads();
-        u64 pc = carry_c, tc = carry_c;
-        for (u32 k = 0; k < kScan4Block / kWave; ++k) {
-            if (k < wib) pc += wc[k];
-            tc += wc[k];
+        u64 oc = carry_c;
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
+            if (k == wib) oc = carry_c;
+            carry_c += wc[k];
             carry_m |= wm[k] != 0;
         }
-        pc += ci - lc;
-        // pass 2: class sums in absolute classes
-        u64 cc = pc;
-        u32 ls[4] = {0, 0, 0, 0};
+        // class sums in absolute classes, then their scans
+        u32 ps[kScanPer][4];
+        u32 rs[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < kScan4Per; ++k) {
-            if (i0 + k < a.nunits) {
-                u32 t[4];
-                rot4(get4(a.slots + 2 * (i0 + k)).s, (u32)cc, t);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) ls[c] += t[c];
-            }
-            cc += cnt[k];
-        }
-        u32 si[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            si[c] = wave_scan(ls[c]);
-            if (ln == kWave - 1) wsc[c][wib] = si[c];
-        }
-        __syncthreads();
-        u32 ps[4], ts[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) ps[c] = ts[c] = carry_s[c];
-#pragma unroll
-        for (u32 k = 0; k < kScan4Block / kWave; ++k) {
+        for (int k = 0; k < kScanPer; ++k) {
+            const bool in = i0 + (u64)k * kWave < a.nunits;
+            const u32 s4[4] = {in ? lo[k].z : 0u, in ? lo[k].w : 0u, in ? hi[k].x : 0u, in ? hi[k].y : 0u};
+            u32 t[4];
+            rot4(s4, (u32)(oc + pc[k]), t);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const u32 v = wsc[c][k];
-                ps[c] += k < wib ? v : 0u;
-                ts[c] += v;
+                const u32 si = wave_scan(t[c]);
+                ps[k][c] = rs[c] + si - t[c];
+                rs[c] += read_lane(si, 63);
+            }
+        }
+        if (ln == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) wsc[c][wib] = rs[c];
+        }
+        __syncthreads();
+        u32 os[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) os[c] = carry_s[c];
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (k == wib) os[c] = carry_s[c];
+                carry_s[c] += wsc[c][k];
             }
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) ps[c] += si[c] - ls[c];
-        // pass 3: the exclusive prefixes, in place
-        cc = pc;
-#pragma unroll
-        for (int k = 0; k < kScan4Per; ++k) {
-            if (i0 + k < a.nunits) {
-                u32 t[4];
-                rot4(get4(a.slots + 2 * (i0 + k)).s, (u32)cc, t);
-                put4(a.slots + 2 * (i0 + k), Run4{cc, {ps[0], ps[1], ps[2], ps[3]}});
-#pragma unroll
-                for (int c = 0; c < 4; ++c) ps[c] += t[c];
-            }
-            cc += cnt[k];
+        for (int k = 0; k < kScanPer; ++k) {
+            const u64 i = i0 + (u64)k * kWave;
+            if (i < a.nunits)
+                put4(a.slots + 2 * i, Run4{oc + pc[k], {os[0] + ps[k][0], os[1] + ps[k][1], os[2] + ps[k][2],
+                                                        os[3] + ps[k][3]}});
         }
-        carry_c = tc;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) carry_s[c] = ts[c];
         __syncthreads();   // wc, wm and wsc are rewritten by the next round
     }
-    if (tid == 0) *a.d_status = final_status(carry_m, last, carry_c, a.n);
+    if (tid == 0) *a.d_status = final_status(carry_m, lastb, carry_c, a.n);
 }
 
 template <int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k4_known(Stream4Args a) {
     constexpr u32 W = SEGS * kSegBytes;
     extern __shared__ __align__(16) u32 lds[];
-    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
+    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
     const u64 gi = (u64)blockIdx.x * wpb + wib;
     const u64 wv = gi * W;
     if (wv >= a.vend) return;   // whole wavefronts only: no workgroup barrier below
@@ -1908,7 +2045,7 @@ hipError_t launch4_t(const Stream4Args &a, int wpb, hipStream_t s) {
     k4_agg<SEGS><<<blocks, wpb * kWave, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k4_scan<<<1, kScan4Block, 0, s>>>(a);
+    k4_scan<<<1, kScanBlock, 0, s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const u64 ngroups = (a.vend + SEGS * kSegBytes - 1) / (SEGS * kSegBytes);
@@ -1996,8 +2133,10 @@ __global__ __launch_bounds__(kScanBlock) void k_isect_scan(IsectArgs a, u32 grou
         const u32 i0 = b0 + tid * kScanPer;
         u32 c[kScanPer], lc = 0;
 #pragma unroll
+        for (int k = 0; k < kScanPer; ++k) c[k] = a.wg_counts[i0 + k < groups ? i0 + k : groups - 1];
+#pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            c[k] = i0 + k < groups ? a.wg_counts[i0 + k] : 0u;
+            c[k] = i0 + k < groups ? c[k] : 0u;   // all loads issued first (groups >= 1)
             lc += c[k];
         }
         const u32 ci = wave_scan(lc);   // at most 512 x 1024 matches per wavefront
