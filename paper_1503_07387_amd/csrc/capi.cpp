@@ -261,8 +261,11 @@ vbyte_status decode4_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, 
     const uint64_t nunits = nbytes ? (a.vstart + nbytes + unit - 1) / unit : 0;
     if (nunits >= (1ull << 31)) return VBYTE_EINVAL;
     a.nunits = (uint32_t)nunits;
+    const uint64_t nblocks = (nunits + wpb - 1) / wpb;   // aggregate workgroups
+    a.nblocks = (uint32_t)nblocks;
+    a.block_units = (uint32_t)wpb;
     Workspace *w = nullptr;
-    vbyte_status st = get_ws(s, kHeaderBytes + nunits * 32 * (1 + kUnit64Groups), 0, &w);
+    vbyte_status st = get_ws(s, kHeaderBytes + (nunits * (1 + kUnit64Groups) + nblocks) * 32, 0, &w);
     if (st != VBYTE_OK) return st;
     if (!d_status) {
         d_status = (int32_t *)(ws_base(w) + kStatusOff);
@@ -274,6 +277,7 @@ vbyte_status decode4_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, 
     }
     a.slots = (uint4 *)(ws_base(w) + kHeaderBytes);
     a.gslots = a.slots + 2 * nunits;
+    a.bslots = a.gslots + 2 * nunits * kUnit64Groups;
     a.d_status = d_status;
     hipError_t e = launch4(a, segs, wpb, s);
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode_delta4 launch");

@@ -1104,10 +1104,15 @@ constexpr int kScanBlock = 1024;
 constexpr int kScanPer = 8;   // slots per lane per round
 
 // The scans below run in one workgroup, so one CU's memory pipeline carries
-// all their slot traffic: every access is coalesced.  In a round wavefront
-// w owns the kWave x kScanPer consecutive slots from b0 + w kWave kScanPer,
-// lane l the slots l, l + 64, ... of them; a wavefront's exclusive prefix
-// is taken in that order by one wave scan per row of 64.
+// all their slot traffic and one CU issues all their instructions: every
+// access is coalesced and a round has only as many rows as it needs.  A
+// round of R rows (R = 8, or fewer for the last round) gives wavefront w
+// the kWave x R consecutive slots from b0 + w kWave R, lane l the slots l,
+// l + 64, ... of them; a wavefront's exclusive prefix is taken in that
+// order by one wave scan per row of 64, and rows past R are skipped.
+__device__ __forceinline__ u32 scan_rows(u64 left) {
+    return left >= (u64)kScanBlock * kScanPer ? (u32)kScanPer : (u32)((left + kScanBlock - 1) / kScanBlock);
+}
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
     __shared__ u32 wc[kScanBlock / kWave], ws[kScanBlock / kWave], wm[kScanBlock / kWave];
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
@@ -1116,8 +1121,9 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
     u64 carry_c = 0;
     u32 carry_s = a.prev;
     bool carry_m = false;
-    for (u64 b0 = 0; b0 < a.ntiles; b0 += (u64)kScanBlock * kScanPer) {
-        const u64 i0 = b0 + (u64)wib * (kWave * kScanPer) + ln;
+    for (u64 b0 = 0, rows = 0; b0 < a.ntiles; b0 += (u64)kScanBlock * rows) {
+        rows = scan_rows(a.ntiles - b0);
+        const u64 i0 = b0 + (u64)wib * (kWave * rows) + ln;
         // every load issued before the first use: indexes past the end read
         // the last slot and count as zero
         Desc d[kScanPer];
@@ -1131,6 +1137,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
         bool m = false;
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
+            if ((u32)q >= rows) break;
             const bool in = i0 + (u64)q * kWave < a.ntiles;
             const u32 c = in ? (u32)(d[q].c & kCountMask) : 0u;   // at most the tile's bytes
             const u32 sm = in ? (u32)d[q].s : 0u;
@@ -1162,7 +1169,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
             const u64 i = i0 + (u64)q * kWave;
-            if (i < a.ntiles) {
+            if ((u32)q < rows && i < a.ntiles) {
                 a.desc[i].c = oc + pc[q];
                 a.desc[i].s = os + ps[q];
             }
@@ -1377,8 +1384,9 @@ __global__ __launch_bounds__(kScanBlock) void k64_scan(Stream64Args a) {
     u64 carry_c = 0, carry_s = a.prev;
     bool carry_m = false;
     // the layout of k_tile_scan: coalesced rows of 64 slots per wavefront
-    for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScanBlock * kScanPer) {
-        const u64 i0 = b0 + (u64)wib * (kWave * kScanPer) + ln;
+    for (u64 b0 = 0, rows = 0; b0 < a.nunits; b0 += (u64)kScanBlock * rows) {
+        rows = scan_rows(a.nunits - b0);
+        const u64 i0 = b0 + (u64)wib * (kWave * rows) + ln;
         uint4 q[kScanPer];
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
@@ -1392,6 +1400,7 @@ __global__ __launch_bounds__(kScanBlock) void k64_scan(Stream64Args a) {
         bool m = false;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
+            if ((u32)k >= rows) break;
             const bool in = i0 + (u64)k * kWave < a.nunits;
             const u32 c = in ? q[k].x : 0u;
             const u64 sm = in ? (q[k].z | ((u64)q[k].w << 32)) : 0ull;
@@ -1424,7 +1433,7 @@ __global__ __launch_bounds__(kScanBlock) void k64_scan(Stream64Args a) {
         for (int k = 0; k < kScanPer; ++k) {
             const u64 i = i0 + (u64)k * kWave;
             const u64 c = oc + pc[k], sv = os + ps[k];
-            if (i < a.nunits) a.slots[i] = make_uint4((u32)c, (u32)(c >> 32), (u32)sv, (u32)(sv >> 32));
+            if ((u32)k < rows && i < a.nunits) a.slots[i] = make_uint4((u32)c, (u32)(c >> 32), (u32)sv, (u32)(sv >> 32));
         }
         __syncthreads();   // wc, ws and wm are rewritten by the next round
     }
@@ -1612,10 +1621,10 @@ hipError_t launch64_t(const Stream64Args &a, int wpb, hipStream_t s) {
 // with S[c] the sum of its codes of rank = c mod 4 counted from the run's
 // first code; two runs combine as (cA + cB, SA[c] + SB[(c - cA) mod 4]).
 // Same layout as the 64-bit decode: units of kUnitGroups groups of SEGS
-// segments, one group per wavefront; k4_agg summarises every group and
-// unit, k4_scan turns the units into exclusive prefixes (absolute classes,
-// from prev4) and writes the status, k4_known decodes one group per
-// wavefront.  A group's codes are those that begin in it and end in the
+// segments, one unit per wavefront of the aggregate; k4_agg summarises
+// every group, and every unit within its workgroup (block), k4_scan turns
+// the blocks into exclusive prefixes (absolute classes, from prev4) and
+// writes the status, k4_known decodes one group per wavefront.  A group's codes are those that begin in it and end in the
 // stream: the aggregate takes them as byte sums by class (d4_sums), the
 // decode assembles them (d4_group).
 
@@ -1647,22 +1656,6 @@ __device__ __forceinline__ void put4(uint4 *slot, const Run4 &r) {
 __device__ __forceinline__ Run4 get4(const uint4 *slot) {
     const uint4 a = slot[0], b = slot[1];
     return Run4{a.x | ((u64)a.y << 32), {a.z, a.w, b.x, b.y}};
-}
-
-// Add the lane's codes (flagged in emit, values u) to s by class, the first
-// of them of class `cls`; returns the class after the last.
-__device__ __forceinline__ u32 add_by_class(const u32 (&u)[16], u32 emit, u32 cls, u32 (&s)[4]) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        if ((emit >> j) & 1u) {
-            s[0] += cls == 0 ? u[j] : 0u;
-            s[1] += cls == 1 ? u[j] : 0u;
-            s[2] += cls == 2 ? u[j] : 0u;
-            s[3] += cls == 3 ? u[j] : 0u;
-            cls = (cls + 1) & 3u;
-        }
-    }
-    return cls;
 }
 
 // One group's segments: masks and values of every segment, and what the
@@ -1860,31 +1853,56 @@ __device__ __forceinline__ bool d4_sums(const Stream4Args &a, u64 wv, Run4 &grp)
     return mal;
 }
 
+// One wavefront per unit; the block (workgroup) then combines its units
+// through LDS: each unit's slot gets its exclusive prefix within the
+// block, the block's slot the block's summary and malformed flag, so that
+// the scan runs over blocks only.  No wavefront waits for the others: each
+// posts its unit and takes a ticket, and the one that takes the last
+// ticket combines the block.
 template <int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
     constexpr u32 W = SEGS * kSegBytes;
+    __shared__ u32 uc[kMaxWaves], us[4][kMaxWaves], um[kMaxWaves], done;
     const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
+    if (threadIdx.x == 0) done = 0;
+    __syncthreads();
     const u64 u = (u64)blockIdx.x * wpb + wib;
-    if (u >= a.nunits) return;   // whole wavefronts only: no workgroup barrier below
     Run4 unit{0, {0, 0, 0, 0}};
     bool mal = false;
-    for (u32 g = 0; g < kUnitGroups; ++g) {
-        const u64 wv = (u * kUnitGroups + g) * W;
-        if (wv >= a.vend) break;
-        Run4 grp;
-        const bool interior = wv >= 16 && wv + W + 4 <= a.vend;
-        mal |= interior ? d4_sums<false, SEGS>(a, wv, grp) : d4_sums<true, SEGS>(a, wv, grp);
-        if (ln == 0) put4(a.gslots + 2 * (u * kUnitGroups + g), grp);
-        unit = join4(unit, grp);
+    if (u < a.nunits) {
+        for (u32 g = 0; g < kUnitGroups; ++g) {
+            const u64 wv = (u * kUnitGroups + g) * W;
+            if (wv >= a.vend) break;
+            Run4 grp;
+            const bool interior = wv >= 16 && wv + W + 4 <= a.vend;
+            mal |= interior ? d4_sums<false, SEGS>(a, wv, grp) : d4_sums<true, SEGS>(a, wv, grp);
+            if (ln == 0) put4(a.gslots + 2 * (u * kUnitGroups + g), grp);
+            unit = join4(unit, grp);
+        }
     }
     const bool wmal = ballot(mal) != 0;
+    u32 ticket = 0;
     if (ln == 0) {
-        put4(a.slots + 2 * u, unit);
-        a.slots[2 * u + 1].z = wmal ? 1u : 0u;
+        uc[wib] = (u32)unit.c;   // at most the unit's bytes
+#pragma unroll
+        for (int c = 0; c < 4; ++c) us[c][wib] = unit.s[c];
+        um[wib] = wmal ? 1u : 0u;
+        ticket = __hip_atomic_fetch_add(&done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    if (read_lane(ticket, 0) != wpb - 1 || ln != 0) return;
+    const u64 u0 = (u64)blockIdx.x * wpb;
+    Run4 pre{0, {0, 0, 0, 0}};
+    u32 mt = 0;
+    for (u32 k = 0; k < wpb; ++k) {
+        if (u0 + k < a.nunits) put4(a.slots + 2 * (u0 + k), pre);
+        pre = join4(pre, Run4{uc[k], {us[0][k], us[1][k], us[2][k], us[3][k]}});
+        mt |= um[k];
+    }
+    put4(a.bslots + 2 * blockIdx.x, pre);
+    a.bslots[2 * blockIdx.x + 1].z = mt;
 }
 
-// Exclusive prefixes of the units in absolute classes, in the coalesced
+// Exclusive prefixes of the blocks in absolute classes, in the coalesced
 // layout of k_tile_scan.  Each round scans the counts first (plain sums); a
 // unit's class sums, rotated by the count of the codes before it, are then
 // in absolute classes, and four plain scans finish the round: the rotating
@@ -1894,28 +1912,30 @@ __global__ __launch_bounds__(kScanBlock) void k4_scan(Stream4Args a) {
     __shared__ u32 wsc[4][kScanBlock / kWave];
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
     const u8 lastb = a.base[a.vend - 1];   // one address for all: in flight with the first slots
-    const u64 lastu = a.nunits - 1;        // nunits >= 1
+    const u64 lastu = a.nblocks - 1;       // nblocks >= 1
     u64 carry_c = 0;
     u32 carry_s[4] = {a.prev4[0], a.prev4[1], a.prev4[2], a.prev4[3]};
     bool carry_m = false;
-    for (u64 b0 = 0; b0 < a.nunits; b0 += (u64)kScanBlock * kScanPer) {
-        const u64 i0 = b0 + (u64)wib * (kWave * kScanPer) + ln;
+    for (u64 b0 = 0, rows = 0; b0 < a.nblocks; b0 += (u64)kScanBlock * rows) {
+        rows = scan_rows(a.nblocks - b0);
+        const u64 i0 = b0 + (u64)wib * (kWave * rows) + ln;
         uint4 lo[kScanPer], hi[kScanPer];
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             const u64 i = i0 + (u64)k * kWave;
             const u64 j = i < lastu ? i : lastu;   // past the end: counted as zero
-            lo[k] = a.slots[2 * j];
-            hi[k] = a.slots[2 * j + 1];
+            lo[k] = a.bslots[2 * j];
+            hi[k] = a.bslots[2 * j + 1];
         }
         // counts
         u32 pc[kScanPer];
-        u32 rc = 0;   // 64 x 8 units of at most 16 KiB: fits 32 bits
+        u32 rc = 0;   // 64 x 8 blocks of at most 16 units of 16 KiB
         bool m = false;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            const bool in = i0 + (u64)k * kWave < a.nunits;
-            const u32 c = in ? lo[k].x : 0u;   // a unit's count: at most its bytes
+            if ((u32)k >= rows) break;
+            const bool in = i0 + (u64)k * kWave < a.nblocks;
+            const u32 c = in ? lo[k].x : 0u;   // a block's count: at most its bytes
             m |= in && hi[k].z != 0;
             const u32 ci = wave_scan(c);
             pc[k] = rc + ci - c;
@@ -1938,7 +1958,8 @@ __global__ __launch_bounds__(kScanBlock) void k4_scan(Stream4Args a) {
         u32 rs[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
-            const bool in = i0 + (u64)k * kWave < a.nunits;
+            if ((u32)k >= rows) break;
+            const bool in = i0 + (u64)k * kWave < a.nblocks;
             const u32 s4[4] = {in ? lo[k].z : 0u, in ? lo[k].w : 0u, in ? hi[k].x : 0u, in ? hi[k].y : 0u};
             u32 t[4];
             rot4(s4, (u32)(oc + pc[k]), t);
@@ -1967,8 +1988,8 @@ __global__ __launch_bounds__(kScanBlock) void k4_scan(Stream4Args a) {
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             const u64 i = i0 + (u64)k * kWave;
-            if (i < a.nunits)
-                put4(a.slots + 2 * i, Run4{oc + pc[k], {os[0] + ps[k][0], os[1] + ps[k][1], os[2] + ps[k][2],
+            if ((u32)k < rows && i < a.nblocks)
+                put4(a.bslots + 2 * i, Run4{oc + pc[k], {os[0] + ps[k][0], os[1] + ps[k][1], os[2] + ps[k][2],
                                                         os[3] + ps[k][3]}});
         }
         __syncthreads();   // wc, wm and wsc are rewritten by the next round
@@ -1987,49 +2008,72 @@ __global__ __launch_bounds__(kMaxBlock) void k4_known(Stream4Args a) {
     u32 *rows = lds + wib * kStageWords;
     const u64 uu = gi / kUnitGroups;
     const u32 g = (u32)(gi % kUnitGroups);
-    // prefix: the unit's (absolute classes, from prev4), then the groups
-    // before g in it
-    Run4 run = get4(a.slots + 2 * uu);
+    // prefix: the block's (absolute classes, from prev4), the unit's within
+    // the block, then the groups before g in the unit
+    Run4 run = join4(get4(a.bslots + 2 * (uu / a.block_units)), get4(a.slots + 2 * uu));
     for (u32 h = 0; h < g; ++h) run = join4(run, get4(a.gslots + 2 * (uu * kUnitGroups + h)));
+    // A segment's codes are compacted in LDS by their rank p in the
+    // segment (16 ranks per lane, 18 words per lane so that 8-byte reads of
+    // consecutive lanes hit distinct banks; the two spare words of a lane
+    // take the writes of its bytes that begin no code).  A code's class is
+    // then fixed by p mod 4 = its index mod 4 in the lane's 16, so the
+    // running values are per-index sums: 3 adds per index in the lane, 4 wave
+    // scans, the carried values rotated by the class of the segment's first
+    // code.  The rows of 64 ranks are then stored as consecutive words.
     auto f = [&](const D4Seg &sg) {
+        const u32 ln = lane_id();
         const u32 cl = __builtin_popcount(sg.emit);
         const u32 ci = wave_scan(cl);
         const u32 segcnt = read_lane(ci, 63);
-        // class sums of this lane's codes, classes from the global rank
-        const u32 cls0 = (u32)(run.c + ci - cl) & 3u;
-        u32 s[4] = {0, 0, 0, 0};
-        add_by_class(sg.u, sg.emit, cls0, s);
-        // running value per class before the lane: run.s + lanes below
-        u32 base[4];
+        const u32 cls0 = (u32)run.c & 3u;
+        uint2 *mine = (uint2 *)(rows + kRowStride * ln);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const u32 inc = wave_scan(s[c]);
-            base[c] = run.s[c] + inc - s[c];
-            run.s[c] += read_lane(inc, 63);
-        }
-        u32 v[16];
-        u32 cls = cls0;
+        for (int m = 0; m < 8; ++m) mine[m] = make_uint2(0u, 0u);
+        wave_lds_sync();
+        const u32 spare = kRowStride * ln + 16u;
+        u32 p = ci - cl;   // rank of the lane's first code in the segment
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            const u32 b = cls == 0 ? base[0] : cls == 1 ? base[1] : cls == 2 ? base[2] : base[3];
-            const u32 y = b + sg.u[j];
-            v[j] = y;
-            if ((sg.emit >> j) & 1u) {
-                base[0] = cls == 0 ? y : base[0];
-                base[1] = cls == 1 ? y : base[1];
-                base[2] = cls == 2 ? y : base[2];
-                base[3] = cls == 3 ? y : base[3];
-                cls = (cls + 1) & 3u;
-            }
+            const u32 e = (sg.emit >> j) & 1u;
+            rows[e ? p + ((p >> 4) << 1) : spare] = sg.u[j];
+            p += e;
         }
+        wave_lds_sync();
+        u32 v[16];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const uint2 t = mine[m];
+            v[2 * m] = t.x;
+            v[2 * m + 1] = t.y;
+        }
+#pragma unroll
+        for (int k = 4; k < 16; ++k) v[k] += v[k - 4];
+        // index class r holds the codes of class (cls0 + r) mod 4
+        u32 carried[4], tot[4];
+        rot4(run.s, 4u - cls0, carried);   // carried[r] = run.s[(cls0 + r) mod 4]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const u32 inc = wave_scan(v[12 + r]);
+            tot[r] = read_lane(inc, 63);
+            carried[r] += inc - v[12 + r];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] += carried[k & 3];
+        u32 add[4];
+        rot4(tot, cls0, add);   // add[c] = tot[(c - cls0) mod 4]
+#pragma unroll
+        for (int c = 0; c < 4; ++c) run.s[c] += add[c];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) mine[m] = make_uint2(v[2 * m], v[2 * m + 1]);
+        wave_lds_sync();
         const u64 gbase = run.c;
-        if (gbase < a.n && segcnt) {
-            u32 *out_seg = a.out + gbase;
-            if (gbase + segcnt <= a.n)
-                store_rows<false, false>(rows, v, sg.emit, out_seg, 0u, 0u);
-            else
-                store_rows<true, false>(rows, v, sg.emit, out_seg, (u32)(a.n - gbase), 0u);
+        const u32 nrows = (segcnt + kWave - 1) / kWave;
+        for (u32 q = 0; q < nrows; ++q) {
+            const u32 pos = q * kWave + ln;
+            const u32 y = rows[pos + ((pos >> 4) << 1)];
+            if (pos < segcnt && gbase + pos < a.n) a.out[gbase + pos] = y;
         }
+        wave_lds_sync();   // the next segment rewrites the rows
         run.c += segcnt;
     };
     const bool interior = wv >= 16 && wv + W + 4 <= a.vend;
@@ -2041,8 +2085,8 @@ __global__ __launch_bounds__(kMaxBlock) void k4_known(Stream4Args a) {
 
 template <int SEGS>
 hipError_t launch4_t(const Stream4Args &a, int wpb, hipStream_t s) {
-    const u32 blocks = (a.nunits + wpb - 1) / wpb;
-    k4_agg<SEGS><<<blocks, wpb * kWave, 0, s>>>(a);
+    if (a.block_units != (u32)wpb || a.nblocks != (a.nunits + wpb - 1) / wpb) return hipErrorInvalidValue;
+    k4_agg<SEGS><<<a.nblocks, wpb * kWave, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k4_scan<<<1, kScanBlock, 0, s>>>(a);

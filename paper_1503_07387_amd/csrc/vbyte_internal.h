@@ -101,8 +101,11 @@ struct Stream4Args {
     uint64_t n;
     uint32_t prev4[4];
     uint32_t nunits;
-    uint4 *slots;    // 2 per unit: its summary, then its exclusive prefix
+    uint32_t nblocks;       // aggregate workgroups: block_units units each
+    uint32_t block_units;
+    uint4 *slots;    // 2 per unit: its exclusive prefix within its block
     uint4 *gslots;   // 2 per group (kUnit64Groups per unit): its summary
+    uint4 *bslots;   // 2 per block: its summary, then its exclusive prefix
     int32_t *d_status;
 };
 
