@@ -203,7 +203,7 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
 
 
 def bench_decode64(torch, vbyte, streams, reps=10):
-    """64-bit differential decode (vbyte_decode64_delta, reading R13) of the
+    """64-bit differential decode (vbyte_decode64_delta) of the
     gap-mean-300 stream.  Codes of values below 2^32 are the same bytes in
     both widths, so the stream is a valid 64-bit code stream; decoding it from
     prev = 2^40 gives 64-bit identifiers.  Checked against a 64-bit cumsum."""
@@ -240,7 +240,7 @@ def bench_decode64(torch, vbyte, streams, reps=10):
 
 
 def bench_delta4(torch, vbyte, streams, reps=10):
-    """Blocks-of-four differential decode (vbyte_decode_delta4, reading R14)
+    """Blocks-of-four differential decode (vbyte_decode_delta4)
     of the gap-mean-300 stream's bytes: out[i] = g_i + out[i-4], checked
     against four interleaved cumsums of the gaps."""
     s = streams[1]

@@ -26,15 +26,15 @@
  *     stream.  Work is enqueued in stream order; calls on one stream are
  *     ordered, calls on different streams are independent (each stream has
  *     its own workspace).
- *   Strict semantics (paper silent; readings R3-R6).  A stream is valid iff
+ *   Strict semantics (the paper is silent on these).  A stream is valid iff
  *     bytes[0..nbytes) is exactly n codes ending at its last byte:
  *       VBYTE_EMALFORMED  five or more consecutive bytes >= 0x80 anywhere;
  *       VBYTE_ETRUNC      last byte >= 0x80, or fewer than n terminators;
  *       VBYTE_ECOUNT      more than n terminators.
  *     When several hold, the larger code wins (EMALFORMED > ETRUNC >
  *     ECOUNT), the same classification as the CPU oracle.  A fifth byte in
- *     [16,128) is accepted and wraps mod 2^32 (R4); over-long codes such as
- *     80 00 are accepted (R5).
+ *     [16,128) is accepted and wraps mod 2^32; over-long codes such as
+ *     80 00 are accepted.
  *   Errors.  Argument errors (VBYTE_EINVAL) are returned before anything is
  *     enqueued.  Data errors of *_async calls land in the caller's device
  *     status word, written once by the kernel (no zero-initialisation

@@ -198,7 +198,7 @@ vbyte_status decode_sync(const uint8_t *bytes, size_t nbytes, uint32_t *out, siz
     return (vbyte_status)h;
 }
 
-// Enqueues a 64-bit single-stream decode (reading R13); status as in
+// Enqueues a 64-bit single-stream decode; status as in
 // decode_stream.
 vbyte_status decode64_stream(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
                              uint64_t prev, int delta, int32_t *d_status, hipStream_t s,
@@ -239,7 +239,7 @@ vbyte_status decode64_stream(const uint8_t *bytes, size_t nbytes, uint64_t *out,
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode64 launch");
 }
 
-// Enqueues a blocks-of-four decode (reading R14); status as in decode_stream.
+// Enqueues a blocks-of-four decode; status as in decode_stream.
 vbyte_status decode4_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
                             const uint32_t *prev4, int32_t *d_status, hipStream_t s,
                             int32_t **slot = nullptr) {

@@ -841,7 +841,7 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
     return res;
 }
 
-// Status of a finished stream or list (readings R3-R6): malformed first,
+// Status of a finished stream or list: malformed first,
 // then truncated (last byte continues, or too few integers), then count.
 __device__ __forceinline__ int32_t final_status(bool mal, u8 last_byte, u64 total, u64 n) {
     if (mal) return VBYTE_EMALFORMED;
@@ -1207,7 +1207,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
 }
 
 // ============================================================ 64-bit codes
-// The byte format for 64-bit integers (reading R13): up to ten 7-bit
+// The byte format for 64-bit integers: up to ten 7-bit
 // groups, a run of ten continuation bytes is malformed, a tenth group
 // wraps mod 2^64, differences are summed mod 2^64.  Decoded in two passes
 // with no look-back, one unit of kUnitGroups x SEGS 1 KiB segments per
@@ -1614,7 +1614,7 @@ hipError_t launch64_t(const Stream64Args &a, int wpb, hipStream_t s) {
 }
 
 // ============================================================ blocks of four
-// Differences between blocks of four (reading R14): y_i = g_i + y_(i-4),
+// Differences between blocks of four: y_i = g_i + y_(i-4),
 // i.e. four interleaved prefix sums by rank mod 4, from the four values
 // prev4.  A code's class is its rank mod 4, known only once the count of
 // the codes before it is, so a run of codes is summarised by (count, S[4])

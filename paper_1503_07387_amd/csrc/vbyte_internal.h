@@ -73,7 +73,7 @@ struct StreamArgs {
     uint64_t *scratch;
 };
 
-// Single-stream decode of 64-bit codes (reading R13), in units of
+// Single-stream decode of 64-bit codes, in units of
 // kUnit64Groups x SEGS segments per wavefront with one 16-byte slot per unit
 // in `slots`.
 constexpr int kUnit64Groups = 8;
@@ -90,9 +90,9 @@ struct Stream64Args {
     int32_t *d_status;
 };
 
-// Single-stream decode with differences between blocks of four (reading
-// R14), in the layout of Stream64Args; a slot is 32 bytes (count and the
-// four class sums).
+// Single-stream decode with differences between blocks of four (y_i = g_i +
+// y_(i-4)), in the layout of Stream64Args; a slot is 32 bytes (count and the
+// four class sums by rank mod 4).
 struct Stream4Args {
     const uint8_t *base;   // 16-byte aligned, <= bytes
     uint64_t vstart;       // bytes - base (0..15)
