@@ -2066,12 +2066,22 @@ __global__ __launch_bounds__(kMaxBlock) void k4_known(Stream4Args a) {
 #pragma unroll
         for (int m = 0; m < 8; ++m) mine[m] = make_uint2(v[2 * m], v[2 * m + 1]);
         wave_lds_sync();
+        // ranks below lim are stored: rank 64 q + ln sits at word 72 q + wl;
+        // the stores take a scalar base and the lane's byte offset
         const u64 gbase = run.c;
-        const u32 nrows = (segcnt + kWave - 1) / kWave;
-        for (u32 q = 0; q < nrows; ++q) {
-            const u32 pos = q * kWave + ln;
-            const u32 y = rows[pos + ((pos >> 4) << 1)];
-            if (pos < segcnt && gbase + pos < a.n) a.out[gbase + pos] = y;
+        const u64 room = gbase < a.n ? a.n - gbase : 0;
+        const u32 lim = first_lane(room < segcnt ? (u32)room : segcnt);
+        const u64 op = (u64)(uintptr_t)(a.out + (gbase < a.n ? gbase : 0));
+        gbyte *ob = (gbyte *)(uintptr_t)(((u64)first_lane((u32)(op >> 32)) << 32) | first_lane((u32)op));
+        const u32 wl = ln + ((ln >> 4) << 1);
+        const u32 nr = (lim + kWave - 1) / kWave;
+        u32 yv[16];   // all 16 rows read first (words of this wavefront's area)
+#pragma unroll
+        for (u32 q = 0; q < 16; ++q) yv[q] = rows[wl + 72u * q];
+#pragma unroll
+        for (u32 q = 0; q < 16; ++q) {
+            if (q >= nr) break;
+            if (q * kWave + ln < lim) *(gword *)(ob + ((q * kWave + ln) << 2)) = yv[q];
         }
         wave_lds_sync();   // the next segment rewrites the rows
         run.c += segcnt;
