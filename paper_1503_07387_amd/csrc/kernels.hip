@@ -1467,6 +1467,35 @@ __device__ __forceinline__ u64 horner64(const u32 (&w)[4], u32 a0, u32 a1, u32 a
     return 0 - nu;
 }
 
+typedef __attribute__((address_space(1))) u64 gdword;
+
+// store_rows for 64-bit candidates: lane L's 16 candidates sit at words
+// kRow64Stride * L + 2 j of `rows`; row k covers bytes 64k .. 64k+63 (the
+// masks of lanes 4k .. 4k+3), lane i of the wavefront takes byte 64k + i,
+// whose slot is the row's base plus the flagged bytes below it (mbcnt of the
+// row mask, which also becomes the exec mask of the row's store).  Slots
+// below `lim` only when GUARD.
+template <bool GUARD>
+__device__ __forceinline__ void store_rows64(const u32 *rows, u32 emit, u64 *out_seg, u32 lim) {
+    const u32 ln = lane_id();
+    const u32 e2 = emit | (dpp_zero<0x101>(emit) << 16);   // row_shl:1
+    const u32 src = kRow64Stride * (ln >> 4) + 2u * (ln & 15u);
+    const u64 op = (u64)(uintptr_t)out_seg;
+    gbyte *ob = (gbyte *)(uintptr_t)(((u64)first_lane((u32)(op >> 32)) << 32) | first_lane((u32)op));
+    u32 base = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const u32 lo = read_lane(e2, 4 * k), hi = read_lane(e2, 4 * k + 2);
+        const u64 rm = ((u64)hi << 32) | lo;
+        if (__builtin_amdgcn_inverse_ballot_w64(rm)) {
+            const u32 slot = base + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            if (!GUARD || slot < lim)
+                *(gdword *)(ob + (slot << 3)) = *(const u64 *)(rows + src + 4u * kRow64Stride * k);
+        }
+        base += (u32)__builtin_popcountll(rm);
+    }
+}
+
 template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k64_known(Stream64Args a) {
     constexpr bool DELTA = D != 0;
@@ -1575,23 +1604,10 @@ __global__ __launch_bounds__(kMaxBlock) void k64_known(Stream64Args a) {
                 *(uint4 *)(row + j) = make_uint4((u32)r[j], (u32)(r[j] >> 32), (u32)r[j + 1],
                                                  (u32)(r[j + 1] >> 32));
             wave_lds_sync();
-            const u64 lim = a.n - cnt;
-            u64 rowbase = 0;
-            for (u32 k = 0; k < 16; ++k) {
-                const u64 mask = (u64)read_lane(emit, 4 * k) | ((u64)read_lane(emit, 4 * k + 1) << 16) |
-                                 ((u64)read_lane(emit, 4 * k + 2) << 32) |
-                                 ((u64)read_lane(emit, 4 * k + 3) << 48);
-                if (!mask) continue;
-                const u32 below_in_row = __builtin_amdgcn_mbcnt_hi(
-                    (u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
-                const u64 slot = rowbase + below_in_row;
-                if (((mask >> ln) & 1u) && slot < lim) {
-                    const u32 src = (4 * k + (ln >> 4)) * kRow64Stride + 2 * (ln & 15);
-                    const u64 v = *(const u64 *)(rows + src);
-                    a.out[cnt + slot] = v;
-                }
-                rowbase += __builtin_popcountll(mask);
-            }
+            if (cnt + segcnt <= a.n)
+                store_rows64<false>(rows, emit, a.out + cnt, 0u);
+            else
+                store_rows64<true>(rows, emit, a.out + cnt, (u32)(a.n - cnt));
             wave_lds_sync();
         }
         cnt += segcnt;
