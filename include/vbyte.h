@@ -340,7 +340,10 @@ vbyte_status vbyte_encode_batch(const uint32_t *values, size_t n, const int64_t 
 
 /* ------------------------------------------------------------ utilities */
 
-/* Bytes of device workspace a single-stream call on nbytes input uses. */
+/* Bytes of device workspace that a single-stream call (32-bit, 64-bit or
+ * blocks-of-four decode) on nbytes input uses at most under the current
+ * tuning.  The library allocates and keeps one workspace per stream; this
+ * reports its size, it allocates nothing. */
 size_t vbyte_workspace_size(size_t nbytes);
 
 /* Tuning knobs of the decode kernels (0 keeps a value unchanged):

@@ -677,7 +677,17 @@ vbyte_status vbyte_encode_batch(const uint32_t *values, size_t n, const int64_t 
 }
 
 size_t vbyte_workspace_size(size_t nbytes) {
-    return kHeaderBytes + stream_tiles(15, nbytes, g_segs.load(), 1) * sizeof(Desc);
+    // the largest of the single-stream forms at the current segment count
+    // and the smallest workgroups: the 32-bit decode's tile descriptors, the
+    // 64-bit decode's unit and group slots (16 bytes), the blocks-of-four
+    // decode's unit, group and block slots (32 bytes; a block holds at least
+    // one unit)
+    const uint64_t d32 = stream_tiles(15, nbytes, g_segs.load(), 1) * sizeof(Desc);
+    const uint64_t unit = (uint64_t)kUnit64Groups * std::min(g_segs.load(), 2) * kSegBytes;
+    const uint64_t nunits = (15 + nbytes + unit - 1) / unit;
+    const uint64_t d64 = nunits * 16 * (1 + kUnit64Groups);
+    const uint64_t d4 = (nunits * (1 + kUnit64Groups) + nunits) * 32;
+    return kHeaderBytes + std::max(d32, std::max(d64, d4));
 }
 
 vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t small_list_bytes) {

@@ -73,3 +73,29 @@ def test_header_status_numbers_match_oracle_readings():
     assert nums["OK"] == oracle.OK and nums["ECOUNT"] == oracle.ECOUNT
     assert nums["ETRUNC"] == oracle.ETRUNC and nums["EMALFORMED"] == oracle.EMALFORMED
     assert nums["EINVAL"] == oracle.EINVAL
+
+
+def test_workspace_size_covers_every_single_stream_form():
+    # the 32-bit decode's 16-byte tile descriptors, the 64-bit decode's
+    # 16-byte unit and group slots and the blocks-of-four decode's 32-byte
+    # unit, group and block slots, at the smallest tiles (1 KiB segments,
+    # one wavefront per workgroup, 15 bytes of misalignment)
+    from paper_1503_07387_amd import vbyte
+    lib = vbyte.load(_lib_path())
+    import ctypes as C
+    segs, wpb, small = C.c_int(), C.c_int(), C.c_int64()
+    lib.vbyte_get_tuning(C.byref(segs), C.byref(wpb), C.byref(small))
+    try:
+        assert lib.vbyte_set_tuning(1, 1, 0) == vbyte.OK
+        prev = 0
+        for nbytes in (0, 1, 1023, 8192, 123457, 1 << 20, 111_023_732):
+            ws = lib.vbyte_workspace_size(nbytes)
+            tiles = -(-(15 + nbytes) // 1024)
+            units = -(-(15 + nbytes) // 8192)
+            assert ws >= 256 + 16 * tiles
+            assert ws >= 256 + 16 * 9 * units
+            assert ws >= 256 + 32 * (9 * units + units)
+            assert ws >= prev
+            prev = ws
+    finally:
+        lib.vbyte_set_tuning(segs.value, wpb.value, small.value)
