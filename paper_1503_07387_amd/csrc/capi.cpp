@@ -327,10 +327,11 @@ vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan) {
     plan->wpb = wpb;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
     }
-    plan->grid = cus * std::max(1, 16 / wpb);
+    plan->grid = cus * std::max(1, kBatchWavesPerCu / wpb);
     return VBYTE_OK;
 }
 

@@ -223,5 +223,6 @@ constexpr int kEncodeWaveValues = 1024;   // values per encoder tile (one wavefr
 constexpr int kPrepBlock = 256;           // lists per prep workgroup
 constexpr int kSpanTiles = 1;             // large-list tiles per batched work item
 constexpr int kSmallChunk = 64;           // small lists per batched work item
+constexpr int kBatchWavesPerCu = 16;      // resident wavefronts per CU of the persistent batched decode
 
 }  // namespace vb
