@@ -1214,8 +1214,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
 // wavefront (taken a group of SEGS segments at a time):
 // k64_agg gives every unit its number of terminators, its byte sum (each
 // byte's group at weight 2^(7p), p the continuation bytes right before it,
-// capped at 9) and a malformed flag, and every group of it its own
-// terminators and byte sum; k64_scan makes the units' totals exclusive
+// capped at 9) and a malformed flag, and every group of it the
+// terminators and byte sum of the groups before it in the unit; k64_scan
+// makes the units' totals exclusive
 // prefixes and writes the status; k64_known decodes one group per
 // wavefront from its unit's prefix, the groups before it in the unit and
 // the code that straddles the group's start (the same identity as the
@@ -1366,7 +1367,8 @@ __global__ __launch_bounds__(kMaxBlock) void k64_agg(Stream64Args a) {
         const u64 lo = wv > a.vstart ? wv : a.vstart;
         const u64 hi = wv + W < a.vend ? wv + W : a.vend;
         const u32 terms = (u32)(hi - lo) - cont;
-        if (ln == 0) a.gslots[u * kUnitGroups + g] = make_uint4(terms, 0u, (u32)sum, (u32)(sum >> 32));
+        // the group's slot: the terminators and byte sum of the groups before it in the unit
+        if (ln == 0) a.gslots[u * kUnitGroups + g] = make_uint4(ucont, 0u, (u32)usum, (u32)(usum >> 32));
         ucont += terms;
         usum += sum;
     }
@@ -1510,19 +1512,9 @@ __global__ __launch_bounds__(kMaxBlock) void k64_known(Stream64Args a) {
     const u64 uu = gi / kUnitGroups;
     const u32 g = (u32)(gi % kUnitGroups);
     // prefix: the unit's (scanned from prev) plus the groups before g in it
-    const uint4 pre = a.slots[uu];
-    u64 cnt = pre.x | ((u64)pre.y << 32);
-    u64 sum = pre.z | ((u64)pre.w << 32);
-    {
-        u64 gc = 0, gs = 0;
-        if (ln < g) {
-            const uint4 q = a.gslots[uu * kUnitGroups + ln];
-            gc = q.x;
-            gs = q.z | ((u64)q.w << 32);
-        }
-        cnt += wave_sum64(gc);
-        sum += wave_sum64(gs);
-    }
+    const uint4 pre = a.slots[uu], gpre = a.gslots[uu * kUnitGroups + g];
+    u64 cnt = (pre.x | ((u64)pre.y << 32)) + gpre.x;
+    u64 sum = (pre.z | ((u64)pre.w << 32)) + (gpre.z | ((u64)gpre.w << 32));
     // interior: the group, 12 bytes before and 12 after lie inside the stream
     const bool interior = wv >= 1024 && wv + W + 12 <= a.vend;
     u32 w[SEGS][4], valid[SEGS], bl[3], blv, af[3], afv;
@@ -1637,12 +1629,14 @@ hipError_t launch64_t(const Stream64Args &a, int wpb, hipStream_t s) {
 // with S[c] the sum of its codes of rank = c mod 4 counted from the run's
 // first code; two runs combine as (cA + cB, SA[c] + SB[(c - cA) mod 4]).
 // Same layout as the 64-bit decode: units of kUnitGroups groups of SEGS
-// segments, one unit per wavefront of the aggregate; k4_agg summarises
-// every group, and every unit within its workgroup (block), k4_scan turns
-// the blocks into exclusive prefixes (absolute classes, from prev4) and
-// writes the status, k4_known decodes one group per wavefront.  A group's codes are those that begin in it and end in the
-// stream: the aggregate takes them as byte sums by class (d4_sums), the
-// decode assembles them (d4_group).
+// segments, one unit per wavefront of the aggregate; k4_agg gives every
+// group the summary of the groups before it in its unit, and every unit
+// the summary of the units before it in its workgroup (block); k4_scan
+// turns the blocks into exclusive prefixes (absolute classes, from prev4)
+// and writes the status; k4_known decodes one group per wavefront from
+// those three prefixes.  A group's codes are those that begin in it and
+// end in the stream: the aggregate takes them as byte sums by class
+// (d4_sums), the decode assembles them (d4_group).
 
 struct Run4 {
     u64 c;
@@ -1892,7 +1886,7 @@ __global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
             Run4 grp;
             const bool interior = wv >= 16 && wv + W + 4 <= a.vend;
             mal |= interior ? d4_sums<false, SEGS>(a, wv, grp) : d4_sums<true, SEGS>(a, wv, grp);
-            if (ln == 0) put4(a.gslots + 2 * (u * kUnitGroups + g), grp);
+            if (ln == 0) put4(a.gslots + 2 * (u * kUnitGroups + g), unit);   // the groups before it
             unit = join4(unit, grp);
         }
     }
@@ -2026,8 +2020,8 @@ __global__ __launch_bounds__(kMaxBlock) void k4_known(Stream4Args a) {
     const u32 g = (u32)(gi % kUnitGroups);
     // prefix: the block's (absolute classes, from prev4), the unit's within
     // the block, then the groups before g in the unit
-    Run4 run = join4(get4(a.bslots + 2 * (uu / a.block_units)), get4(a.slots + 2 * uu));
-    for (u32 h = 0; h < g; ++h) run = join4(run, get4(a.gslots + 2 * (uu * kUnitGroups + h)));
+    Run4 run = join4(join4(get4(a.bslots + 2 * (uu / a.block_units)), get4(a.slots + 2 * uu)),
+                     get4(a.gslots + 2 * (uu * kUnitGroups + g)));
     // A segment's codes are compacted in LDS by their rank p in the
     // segment (16 ranks per lane, 18 words per lane so that 8-byte reads of
     // consecutive lanes hit distinct banks; the two spare words of a lane

@@ -86,7 +86,7 @@ struct Stream64Args {
     uint64_t prev;
     uint32_t nunits;
     uint4 *slots;    // per unit: its totals, then its exclusive prefix
-    uint4 *gslots;   // per group (kUnit64Groups per unit): its own totals
+    uint4 *gslots;   // per group (kUnit64Groups per unit): the totals of the groups before it in the unit
     int32_t *d_status;
 };
 
@@ -104,7 +104,7 @@ struct Stream4Args {
     uint32_t nblocks;       // aggregate workgroups: block_units units each
     uint32_t block_units;
     uint4 *slots;    // 2 per unit: its exclusive prefix within its block
-    uint4 *gslots;   // 2 per group (kUnit64Groups per unit): its summary
+    uint4 *gslots;   // 2 per group (kUnit64Groups per unit): the summary of the groups before it in the unit
     uint4 *bslots;   // 2 per block: its summary, then its exclusive prefix
     int32_t *d_status;
 };
