@@ -1727,7 +1727,11 @@ __device__ __forceinline__ bool d4_group(const Stream4Args &a, u64 wv, F &&f) {
 // byte in the lane.  Each class sum is the byte-sum identity of seg_bytes
 // over the bytes of that class, the class masks coming from a byte lookup
 // (v_perm) of the per-byte class; classes 0..2 are added to s[0..2] and
-// all bytes to s[3].
+// all bytes to s[3].  Away from the stream's ends (not EDGE) every byte
+// after a terminator begins a code, so the start marks are the complement
+// of the marks of bytes after a continuation byte; at the ends they come
+// from emit.
+template <bool EDGE>
 __device__ __forceinline__ void class_bytes(const u32 (&w)[4], u32 below, u32 emit, u32 B,
                                             u32 (&s)[4]) {
     u32 c[5];
@@ -1744,9 +1748,10 @@ __device__ __forceinline__ void class_bytes(const u32 (&w)[4], u32 below, u32 em
         any2 |= m1[k] & __builtin_amdgcn_alignbyte(c[k + 1], c[k], 2);
         // code starts of the dword as 0x01 bytes, then per byte B + the
         // starts at or before it (at most 3 + 16, no carry between bytes)
-        const u32 st = ((((emit >> (4 * k)) & 0xFu) * 0x00204081u) & 0x01010101u);
+        const u32 st = EDGE ? ((((emit >> (4 * k)) & 0xFu) * 0x00204081u) & 0x01010101u)
+                            : m1[k] ^ 0x01010101u;
         const u32 p = st * 0x01010101u + q;
-        q = (p >> 24) * 0x01010101u;
+        q = __builtin_amdgcn_perm(p, p, 0x03030303u);   // byte 3 of p in every byte
         cls[k] = p & 0x03030303u;
         t0[3] = __builtin_amdgcn_sad_u8(g[k], 0u, t0[3]);
         t1[3] = __builtin_amdgcn_udot4(g[k], m1[k], t1[3], false);
@@ -1845,7 +1850,7 @@ __device__ __forceinline__ bool d4_sums(const Stream4Args &a, u64 wv, Run4 &grp)
         mal |= m.mal;
         const u32 cl = __builtin_popcount(m.emit);
         const u32 ci = wave_scan(cl);
-        class_bytes(w[s], below, m.emit, (cnt + ci - cl - 1u) & 3u, acc);
+        class_bytes<EDGE>(w[s], below, m.emit, (cnt + ci - cl - 1u) & 3u, acc);
         cnt += read_lane(ci, 63);
     }
     u32 S[4];
