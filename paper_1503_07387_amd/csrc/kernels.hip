@@ -1,6 +1,8 @@
 // kernels.hip -- gfx950 (MI355X) kernels of libvbyte: VByte decoding of
-// uint32 (plain and differential), terminator counting, encoding, and the
-// batched / persistent decode of many posting lists.
+// uint32 (plain and differential, differences minus one), terminator
+// counting, encoding, the batched / persistent decode of many posting
+// lists, resumable decoding in pieces with a list-intersection consumer,
+// differences between blocks of four, and 64-bit integers.
 //
 // Method: Plaisance, Kurz, Lemire, "Vectorized VByte Decoding".  The byte
 // format is that of section 1 / Table 1; a code ends at its terminator byte
@@ -21,9 +23,13 @@
 //    pmovmskb continuation mask (complemented).  A lane owns the integers
 //    whose code begins in its bytes (the byte before is a terminator); their
 //    count is a popcount and the wave sum gives the segment's count.
-//  * Ranks across tiles come from a single-pass decoupled look-back over
-//    per-tile descriptors (tile count, tile gap sum, malformed flag), so the
-//    stream is read once.
+//  * Ranks across tiles come, by default, from two passes: per-tile
+//    terminator counts and byte sums that need no decoding, one scan over
+//    the tiles, then the decode with each tile's prefix given (the input is
+//    read twice, nothing waits).  The one-launch alternative is a decoupled
+//    look-back over per-tile descriptors (tile count, tile gap sum,
+//    malformed flag), tiles numbered by an atomic ticket; the batched decode
+//    and the resumable pieces use it.
 //  * Each lane evaluates Algorithm 1's sum for every byte position at once,
 //    in Horner form from its last byte down, so that each code's integer is
 //    left at the code's first byte (the fifth group's weight 2^28 wraps mod
@@ -31,9 +37,9 @@
 //    LDS and stores each 64-byte row of the segment with one masked store of
 //    consecutive words, the slots given by mbcnt over the row's mask.
 //  * The differential form keeps lane-local suffix sums during assembly and
-//    adds a wave scan of lane sums, the tile's exclusive prefix sum from the
-//    look-back and the caller's start value, all mod 2^32 (the wave-level
-//    counterpart of the 4-wide shift-and-add prefix sum of section 4).
+//    adds a wave scan of lane sums, the tile's exclusive prefix sum and the
+//    caller's start value, all mod 2^32 (the wave-level counterpart of the
+//    4-wide shift-and-add prefix sum of section 4).
 //  * Descriptor words are published and read with relaxed agent-scope 64-bit
 //    atomics that bypass the per-XCD L2, so no cache-flushing fence is
 //    needed between tiles on different XCDs.
