@@ -1509,7 +1509,8 @@ __global__ __launch_bounds__(kMaxBlock) void k64_known(Stream64Args a) {
     constexpr bool DELTA = D != 0;
     constexpr u32 W = SEGS * kSegBytes;
     extern __shared__ __align__(16) u32 lds[];
-    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
+    // wib as a scalar: the prefix slots are scalar loads
+    const u32 wib = first_lane(threadIdx.x >> 6), wpb = blockDim.x >> 6, ln = lane_id();
     // one group of SEGS segments per wavefront: group gi = unit uu, group g of it
     const u64 gi = (u64)blockIdx.x * wpb + wib;
     const u64 wv = gi * W;
@@ -2022,7 +2023,9 @@ template <int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k4_known(Stream4Args a) {
     constexpr u32 W = SEGS * kSegBytes;
     extern __shared__ __align__(16) u32 lds[];
-    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    // wib is the same on every lane: as a scalar, the prefix slots below are
+    // scalar loads and their joins scalar arithmetic
+    const u32 wib = first_lane(threadIdx.x >> 6), wpb = blockDim.x >> 6;
     const u64 gi = (u64)blockIdx.x * wpb + wib;
     const u64 wv = gi * W;
     if (wv >= a.vend) return;   // whole wavefronts only: no workgroup barrier below
