@@ -1885,7 +1885,7 @@ template <int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
     constexpr u32 W = SEGS * kSegBytes;
     __shared__ u32 uc[kMaxWaves], us[4][kMaxWaves], um[kMaxWaves], done;
-    const u32 wib = threadIdx.x >> 6, wpb = blockDim.x >> 6, ln = lane_id();
+    const u32 wib = first_lane(threadIdx.x >> 6), wpb = blockDim.x >> 6, ln = lane_id();   // wib: scalar
     if (threadIdx.x == 0) done = 0;
     __syncthreads();
     const u64 u = (u64)blockIdx.x * wpb + wib;
