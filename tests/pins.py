@@ -531,6 +531,9 @@ def pin64_closed_form_boundaries(lib):
             assert oracle.code_length64(v, lib=lib) == len(b)
             st, y = oracle.decode64(b, 1, lib=lib)
             assert st == OK and int(y[0]) == v
+        # ENC64's size of the three boundary values: the sum of their lengths
+        assert oracle.encoded_size64(np.array(list(cases), dtype=np.uint64), lib=lib) == \
+            sum(len(b) for b in cases.values())
     # the top group of a 10-byte code holds bit 63 only
     fixed = {0: b"\x00", M64: b"\xff" * 9 + b"\x01", 1 << 63: b"\x80" * 9 + b"\x01",
              (1 << 63) - 1: b"\xff" * 8 + b"\x7f", M32: b"\xff\xff\xff\xff\x0f"}
@@ -553,6 +556,9 @@ def pin64_protobuf(lib):
     x = np.array(vals, dtype=np.uint64)
     ours = oracle.encode64(x, lib=lib).tobytes()
     assert ours == pb_encode(vals), "ENC64 differs from protobuf varint"
+    # the size of the whole coded sequence, against protobuf's byte count
+    assert oracle.encoded_size64(x, lib=lib) == len(pb_encode(vals))
+    assert oracle.encoded_size64(x[1:], lib=lib) == len(pb_encode(vals[1:]))
     assert pb_decode64(ours, len(vals)) == vals
     st, y = oracle.decode64(ours, len(vals), lib=lib)
     assert st == OK and [int(t) for t in y] == vals

@@ -68,6 +68,10 @@ MUTANTS = [
     ("delta64_no_prev", "uint64_t run = prev;", "uint64_t run = 0;"),
     ("enc64_cont_on_last", "dst[pos++] = (j + 1 < len) ? (uint8_t)(group | 0x80u) : group;",
      "dst[pos++] = (j < len) ? (uint8_t)(group | 0x80u) : group;"),
+    ("size64_skip_first", "for (size_t i = 0; i < n; i++) total += (size_t)orc_code_length64(x[i]);",
+     "for (size_t i = 1; i < n; i++) total += (size_t)orc_code_length64(x[i]);"),
+    ("size64_len32", "total += (size_t)orc_code_length64(x[i]);",
+     "total += (size_t)orc_code_length((uint32_t)x[i]);"),
     ("encdelta64_sign", "uint64_t gap = x[i] - last;", "uint64_t gap = last - x[i];"),
 ]
 
