@@ -55,6 +55,13 @@
 extern "C" {
 #endif
 
+/* Status codes.  The three data errors are numbered by precedence,
+ * VBYTE_ECOUNT 2 < VBYTE_ETRUNC 3 < VBYTE_EMALFORMED 4, so that the status of
+ * a stream with several faults, and the worst status of a batch, is the
+ * numerically largest one.  This differs from an earlier draft of this
+ * interface that numbered them in the order a decoder meets them
+ * (ETRUNC 2, EMALFORMED 3, ECOUNT 4): compare against the names, never
+ * against literal numbers.  The values below are fixed by this header. */
 typedef enum vbyte_status {
     VBYTE_OK = 0,
     VBYTE_EINVAL = 1,      /* bad argument: NULL pointer, misaligned out, size limit, bad offsets */

@@ -8,7 +8,9 @@ built (``python -m paper_1503_07387_amd.build``); there is no fallback.
 
 uint32 results are returned as ``torch.int32`` tensors holding the same bits.
 """
+import contextlib
 import ctypes
+import functools
 import os
 
 import torch
@@ -124,6 +126,19 @@ def _declare(lib):
     return lib
 
 
+def _on_stream(fn):
+    """Run the wrapped call with ``stream`` (when one is given) as torch's
+    current stream: tensors the call allocates belong to that stream, and a
+    status or count read back with ``.item()`` is copied on that stream, after
+    the kernels that write it."""
+    @functools.wraps(fn)
+    def call(*args, stream=None, **kw):
+        ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+        with ctx:
+            return fn(*args, stream=stream, **kw)
+    return call
+
+
 def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -151,6 +166,7 @@ def _mode(delta, minus_one):
     return 1 if delta else 0
 
 
+@_on_stream
 def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=None, stream=None,
            check=True):
     """Decode ``n`` uint32 from the VByte bytes ``data`` (uint8 CUDA tensor).
@@ -187,6 +203,7 @@ def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=No
     return out[:n]
 
 
+@_on_stream
 def decode_delta4(data, n, *, prev4=None, out=None, status=None, stream=None, check=True):
     """Decode ``n`` uint32 coded as differences between blocks of four:
     out[i] = g_i + out[i-4] mod 2^32 from the four values ``prev4`` (zeros
@@ -215,6 +232,7 @@ def decode_delta4(data, n, *, prev4=None, out=None, status=None, stream=None, ch
     return out[:n]
 
 
+@_on_stream
 def decode64(data, n, *, delta=False, prev=0, out=None, status=None, stream=None, check=True):
     """Decode ``n`` uint64 from the 64-bit VByte bytes ``data`` (uint8 CUDA
     tensor; codes of up to 10 bytes).  ``delta``: inclusive prefix sum from
@@ -243,6 +261,7 @@ def decode64(data, n, *, delta=False, prev=0, out=None, status=None, stream=None
     return out[:n]
 
 
+@_on_stream
 def intersect(a, na, b_ids, *, prev=0, piece=1 << 16, out=None, count=None, status=None,
               stream=None, check=True):
     """Identifiers of the differential list ``a`` (VByte bytes, ``na``
@@ -280,6 +299,7 @@ def new_cursor(prev=0, device=None):
                         device=device or torch.device("cuda"))
 
 
+@_on_stream
 def decode_next(data, k, out, cursor_in, cursor_out, *, delta=False, minus_one=False, status=None,
                 stream=None):
     """Decode the next piece of at most k integers of ``data`` into out[0..k)
@@ -301,6 +321,7 @@ def decode_next(data, k, out, cursor_in, cursor_out, *, delta=False, minus_one=F
     return status
 
 
+@_on_stream
 def count(data, *, stream=None, result=None):
     """Number of terminator bytes (codes) in ``data``; returns a Python int
     (or fills the uint64 slot of ``result``, an int64 CUDA tensor, without
@@ -313,6 +334,7 @@ def count(data, *, stream=None, result=None):
     return int(res.item())
 
 
+@_on_stream
 def decode_batch(data, byte_off, out_off, *, delta=False, minus_one=False, prevs=None, out=None,
                  list_status=None, stream=None):
     """Batched CSR decode.  byte_off/out_off: int64 CUDA tensors of nlists+1.
@@ -331,6 +353,7 @@ def decode_batch(data, byte_off, out_off, *, delta=False, minus_one=False, prevs
     return out, list_status
 
 
+@_on_stream
 def decode_lists(data, rows, list_bytes, out, *, delta=False, minus_one=False, prevs=None,
                  list_status=None, stream=None):
     """Gather-form batch: rows is an int64 CUDA tensor [nlists, 4] of
@@ -387,6 +410,7 @@ def _points(arr, n):
             for p in arr[:n]]
 
 
+@_on_stream
 def autotune_decode(data, n, *, delta=False, out=None, reps=5, stream=None):
     """Run the library's autotuner on a single-stream decode of `data` and
     apply the fastest tiling; returns the timed candidates."""
@@ -404,6 +428,7 @@ def autotune_decode(data, n, *, delta=False, out=None, reps=5, stream=None):
     return _points(arr, cnt.value)
 
 
+@_on_stream
 def autotune_batch(data, byte_off, out_off, *, delta=False, out=None, reps=3, stream=None):
     """Run the library's autotuner on a batched CSR decode and apply the
     fastest tiling and small-list threshold; returns the timed candidates."""
@@ -423,6 +448,7 @@ def autotune_batch(data, byte_off, out_off, *, delta=False, out=None, reps=3, st
     return _points(arr, cnt.value)
 
 
+@_on_stream
 def encode(values, *, delta=False, minus_one=False, prev=0, out=None, nbytes=None, stream=None,
            trim=True):
     """Canonical VByte encoding on the GPU of an int32/uint32-bits CUDA tensor.
@@ -451,6 +477,7 @@ def encode(values, *, delta=False, minus_one=False, prev=0, out=None, nbytes=Non
     return out, nbytes
 
 
+@_on_stream
 def encode_batch(values, vals_off, *, stream=None):
     """Batched CSR encoding on the GPU.  values: int32 CUDA tensor (uint32
     bits, all lists concatenated); vals_off: int64 CUDA tensor of nlists+1

@@ -75,6 +75,22 @@ def test_header_status_numbers_match_oracle_readings():
     assert nums["EINVAL"] == oracle.EINVAL
 
 
+def test_status_numbers_are_fixed():
+    # the numbering is part of the ABI: data errors ordered by precedence
+    # (ECOUNT < ETRUNC < EMALFORMED), the binding's constants the same
+    from paper_1503_07387_amd import vbyte
+    text = open(HEADER).read()
+    nums = dict((k, int(v)) for k, v in re.findall(r"VBYTE_(\w+)\s*=\s*(\d+)", text))
+    want = {"OK": 0, "EINVAL": 1, "ECOUNT": 2, "ETRUNC": 3, "EMALFORMED": 4, "EHIP": 5,
+            "ENOMEM": 6}
+    assert nums == want
+    for k, v in want.items():
+        assert getattr(vbyte, k) == v
+    lib = vbyte.load(_lib_path())
+    for k, v in want.items():
+        assert lib.vbyte_status_str(v).decode() == "VBYTE_" + k
+
+
 def test_workspace_size_covers_every_single_stream_form():
     # the 32-bit decode's 16-byte tile descriptors, the 64-bit decode's
     # 16-byte unit and group slots and the blocks-of-four decode's 32-byte
