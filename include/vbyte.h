@@ -93,6 +93,55 @@ vbyte_status vbyte_decode_async(const uint8_t *bytes, size_t nbytes, uint32_t *o
 vbyte_status vbyte_decode_delta_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
                                       size_t n, uint32_t prev, int32_t *d_status, void *stream);
 
+/* Kernel tuning of one single-stream decode, for vbyte_decode_ex.  A call
+ * that passes its own tuning is unaffected by the process-wide defaults
+ * (vbyte_set_tuning, vbyte_set_chunk_tiles, vbyte_set_flow_grid), so calls
+ * on different streams, or threads, can use different tilings at once.
+ *   segs_per_wave    1 KiB segments per wavefront of a tile: 1, 2 or 4
+ *   waves_per_block  wavefronts per workgroup (a tile): 1 .. 8
+ *   schedule         how tiles learn their prefix (count of integers and
+ *                    gap sum of the stream before them):
+ *                    VBYTE_SCHED_ONE_READ  one persistent launch, every
+ *                        input byte read once: each tile's aggregate is
+ *                        published as soon as its bytes arrive and the tile
+ *                        is decoded two rounds later from registers;
+ *                    VBYTE_SCHED_TWO_PASS  tile aggregates, a one-workgroup
+ *                        scan, then the decode (the input is read twice);
+ *                    VBYTE_SCHED_LOOKBACK  one launch, a decoupled look-back
+ *                        per tile;
+ *                    k = 1..64  chunks of k tiles per workgroup
+ *   grid             VBYTE_SCHED_ONE_READ only: workgroups (0 = 16
+ *                    wavefronts per compute unit; at most 512)
+ *   recompute        VBYTE_SCHED_ONE_READ only, diagnostic: 1 makes every
+ *                    workgroup compute the aggregates it needs from the
+ *                    bytes instead of reading them (same result, slower);
+ *                    0 otherwise */
+typedef struct vbyte_tuning {
+    int segs_per_wave;
+    int waves_per_block;
+    int schedule;
+    int grid;
+    int recompute;
+} vbyte_tuning;
+
+enum {
+    VBYTE_SCHED_ONE_READ = -2,
+    VBYTE_SCHED_TWO_PASS = -1,
+    VBYTE_SCHED_LOOKBACK = 0
+};
+
+/* DEC, DEC_DELTA or differences minus one (mode 0, 1, 2; see
+ * vbyte_decode_async, vbyte_decode_delta_async, vbyte_decode_delta_m1_async)
+ * with an explicit tuning (NULL = the process-wide defaults).  Arguments,
+ * statuses and ownership as in vbyte_decode_async; VBYTE_EINVAL for a
+ * tuning field out of range, a mode outside 0..2 or d_status NULL. */
+vbyte_status vbyte_decode_ex(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                             uint32_t prev, int mode, const vbyte_tuning *tuning, int32_t *d_status,
+                             void *stream);
+
+/* Fills *t with the current process-wide defaults. */
+void vbyte_tuning_default(vbyte_tuning *t);
+
 /* Differences minus one (section 1, "Differential coding": with no repeated
  * value, every difference after the first is coded less one, x_1 - 0,
  * x_2 - x_1 - 1, ...): out[0] = prev + g_0 and out[i] = out[i-1] + g_i + 1
@@ -362,7 +411,11 @@ vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t sm
 void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_list_bytes);
 
 /* Kernel of the single-stream decodes (vbyte_decode*, not the batched
- * forms): -1 (the default) decodes in three launches with no look-back:
+ * forms): -2 (VBYTE_SCHED_ONE_READ) decodes in one persistent launch that
+ * reads every input byte once (see vbyte_tuning); its waits are bounded (an
+ * aggregate not published in time is computed from the bytes by the
+ * reader), so it needs neither a ticket nor co-resident workgroups.
+ * -1 (the default) decodes in three launches with no look-back:
  * every tile's terminator count and byte sum, a scan of them in one
  * workgroup, then every tile with its prefix known (the input is read
  * twice; no workgroup ever waits for another); 0 gives every tile its own
@@ -371,9 +424,14 @@ void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_l
  * once for the chunk, then reads again and decodes.  The look-back kernels
  * number their tiles by an atomic ticket, so they are safe next to any
  * other work on the device, at the cost of that atomic.  Returns
- * VBYTE_EINVAL outside -1..64. */
+ * VBYTE_EINVAL outside -2..64. */
 vbyte_status vbyte_set_chunk_tiles(int tiles_per_chunk);
 int vbyte_get_chunk_tiles(void);
+
+/* Workgroups of the one-launch decode (schedule -2) by default: 0 (the
+ * default) gives 16 wavefronts per compute unit; at most 512.  Returns
+ * VBYTE_EINVAL outside 0..512. */
+vbyte_status vbyte_set_flow_grid(int grid);
 
 /* Autotuner of the tiling.  Times the caller's workload under each candidate
  * tiling (reps calls each after one untimed call, HIP events on `stream`),

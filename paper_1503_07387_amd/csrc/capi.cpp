@@ -28,7 +28,9 @@ std::atomic<int> g_segs{2};
 std::atomic<int> g_wpb{8};
 std::atomic<int64_t> g_small{16384};
 std::atomic<int> g_chunk{-1};  // single stream: -1 = three launches with no look-back (default),
+                               // -2 = one launch reading the input once,
                                // 0 = per-tile look-back, k = chunks of k tiles
+std::atomic<int> g_flow_grid{0};   // workgroups of the one-launch decode (0: per CU count)
 
 vbyte_status hip_fail(hipError_t e, const char *what) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
@@ -138,18 +140,55 @@ vbyte_status aux_area(Workspace *w, hipStream_t s, size_t need, uint8_t **p) {
 
 constexpr uint64_t kMaxBytes = 1ull << 36;
 
-// Enqueues a single-stream decode.  With d_status == nullptr the status goes
-// to the workspace's own slot, returned through *slot (synchronous calls).
+// Compute units of the current device (hipDeviceAttributeMultiprocessorCount).
+int device_cus() {
+    static std::atomic<int> cached[64];   // per device ordinal (zero-initialised)
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev >= 0 && dev < 64 && (v = cached[dev].load(std::memory_order_relaxed)) > 0) return v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+        return 256;
+    if (dev >= 0 && dev < 64) cached[dev].store(v, std::memory_order_relaxed);
+    return v;
+}
+
+
+// The process-wide defaults as a per-call tuning.
+vbyte_tuning default_tuning() {
+    vbyte_tuning t{};
+    t.segs_per_wave = g_segs.load();
+    t.waves_per_block = g_wpb.load();
+    t.schedule = g_chunk.load();
+    t.grid = g_flow_grid.load();
+    t.recompute = 0;
+    return t;
+}
+
+bool tuning_ok(const vbyte_tuning &t) {
+    const int sg = t.segs_per_wave;
+    if (sg != 1 && sg != 2 && sg != 4) return false;
+    if (t.waves_per_block < 1 || t.waves_per_block > 8) return false;
+    if (t.schedule < kScheduleFlow || t.schedule > 64) return false;
+    if (t.grid < 0 || t.grid > kFlowMaxGrid) return false;
+    return t.recompute == 0 || t.recompute == 1;
+}
+
+// Enqueues a single-stream decode with tuning `tu` (nullptr: the process
+// defaults).  With d_status == nullptr the status goes to the workspace's
+// own slot, returned through *slot (synchronous calls).
 vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
                            uint32_t prev, int delta, int32_t *d_status, hipStream_t s,
-                           int32_t **slot = nullptr) {
+                           int32_t **slot = nullptr, const vbyte_tuning *tu = nullptr) {
+    const vbyte_tuning tun = tu ? *tu : default_tuning();
+    if (!tuning_ok(tun)) return VBYTE_EINVAL;
+    if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     if (nbytes >= kMaxBytes) return VBYTE_EINVAL;
     if (nbytes > 0 && !bytes) return VBYTE_EINVAL;
     if (n > 0 && !out) return VBYTE_EINVAL;
     if (((uintptr_t)out & 3u) != 0) return VBYTE_EINVAL;
     if (((uintptr_t)d_status & 3u) != 0) return VBYTE_EINVAL;
     if (!d_status && !slot) return VBYTE_EINVAL;
-    const int segs = g_segs.load(), wpb = g_wpb.load();
+    const int segs = tun.segs_per_wave, wpb = tun.waves_per_block;
     StreamArgs a{};
     a.vstart = (uintptr_t)bytes & 15u;
     a.base = bytes - a.vstart;
@@ -160,7 +199,7 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
     const uint64_t ntiles = nbytes ? stream_tiles(a.vstart, nbytes, segs, wpb) : 0;
     if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
     a.ntiles = (uint32_t)ntiles;
-    const int chunk = g_chunk.load();
+    const int chunk = tun.schedule;
     const uint64_t nchunks = chunk > 0 ? (ntiles + chunk - 1) / chunk : 0;
     const uint64_t ndesc = chunk > 0 ? nchunks : ntiles;
     Workspace *w = nullptr;
@@ -178,9 +217,18 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
     a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
     a.d_status = d_status;
     a.d_count = nullptr;
-    hipError_t e = chunk > 0    ? launch_chunks(a, delta, segs, wpb, (uint32_t)nchunks, s)
-                   : chunk < 0 ? launch_two_pass(a, delta, segs, wpb, s)
-                               : launch_stream(a, delta, 0, segs, wpb, s);
+    hipError_t e;
+    if (chunk == kScheduleFlow) {
+        FlowArgs f{};
+        f.s = a;
+        f.ctr = (uint64_t *)(ws_base(w) + kFlowCtrOff);
+        f.recompute = (uint32_t)tun.recompute;
+        e = launch_flow(f, delta, segs, wpb, tun.grid, device_cus(), s);
+    } else {
+        e = chunk > 0   ? launch_chunks(a, delta, segs, wpb, (uint32_t)nchunks, s)
+            : chunk < 0 ? launch_two_pass(a, delta, segs, wpb, s)
+                        : launch_stream(a, delta, 0, segs, wpb, s);
+    }
     return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode launch");
 }
 
@@ -384,6 +432,24 @@ vbyte_status vbyte_decode_async(const uint8_t *bytes, size_t nbytes, uint32_t *o
 vbyte_status vbyte_decode_delta_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
                                       size_t n, uint32_t prev, int32_t *d_status, void *stream) {
     return decode_stream(bytes, nbytes, out, n, prev, 1, d_status, (hipStream_t)stream);
+}
+
+vbyte_status vbyte_decode_ex(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                             uint32_t prev, int mode, const vbyte_tuning *tuning, int32_t *d_status,
+                             void *stream) {
+    if (!d_status) return VBYTE_EINVAL;
+    return decode_stream(bytes, nbytes, out, n, prev, mode, d_status, (hipStream_t)stream, nullptr,
+                         tuning);
+}
+
+void vbyte_tuning_default(vbyte_tuning *t) {
+    if (t) *t = default_tuning();
+}
+
+vbyte_status vbyte_set_flow_grid(int grid) {
+    if (grid < 0 || grid > kFlowMaxGrid) return VBYTE_EINVAL;
+    g_flow_grid.store(grid);
+    return VBYTE_OK;
 }
 
 vbyte_status vbyte_decode_delta_m1(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
@@ -703,7 +769,7 @@ vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t sm
 }
 
 vbyte_status vbyte_set_chunk_tiles(int tiles_per_chunk) {
-    if (tiles_per_chunk < -1 || tiles_per_chunk > 64) return VBYTE_EINVAL;
+    if (tiles_per_chunk < kScheduleFlow || tiles_per_chunk > 64) return VBYTE_EINVAL;
     g_chunk.store(tiles_per_chunk);
     return VBYTE_OK;
 }

@@ -44,6 +44,8 @@
 //    atomics that bypass the per-XCD L2, so no cache-flushing fence is
 //    needed between tiles on different XCDs.
 
+#include <atomic>
+
 #include "vbyte_internal.h"
 #include "vbyte.h"
 
@@ -639,6 +641,7 @@ constexpr int kAgg = 2;     // this wavefront's count and sum only; no synchroni
 constexpr int kKnown = 3;   // decode with the exclusive prefix given in TileIn
 constexpr int kPiece = 4;   // kFull, and record where the code of rank n begins
 constexpr int kKnownB = 5;  // kKnown with the prefix in byte form (see k_tile_agg)
+constexpr int kKnownW = 6;  // every wavefront alone, its own prefix in byte form given (no barrier)
 
 constexpr int kMaxWaves = 16;
 constexpr int kMaxBlock = 8 * kWave;   // at most 8 wavefronts per workgroup
@@ -672,40 +675,61 @@ __device__ __forceinline__ TileSum tile_sum(const WgShared &sh, u32 wpb) {
     return r;
 }
 
-// D: 0 plain, 1 differences (inclusive prefix sum), 2 differences minus one
-// (the prefix sum plus each integer's rank).
-template <int D, int KIND, int SEGS, bool EDGE>
-__device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared &sh, u32 wib,
-                                            u32 wpb) {
-    constexpr bool DELTA = D != 0, RANK = D == 2;
-    constexpr bool COUNT = KIND == kCount, AGG = KIND == kAgg;
-    constexpr bool KNOWN = KIND == kKnown || KIND == kKnownB;
-    constexpr bool PIECE = KIND == kPiece;
-    const u32 ln = lane_id();
-    const u64 wv = t.tv + (u64)wib * (SEGS * kSegBytes);   // this wavefront's first byte
+// A wavefront's share of a tile in registers: its SEGS segments (16 bytes
+// per lane each, with validity bits for the guarded edge form), the 4 bytes
+// before them and the 4 after them.
+template <int SEGS>
+struct TileRegs {
     u32 w[SEGS][4];
     u32 valid[SEGS];
+    u32 hb, hbv, ha, hav;
+};
+
+// Loads the wavefront's share of the tile whose wavefront range starts at
+// byte wv of the aligned base: unguarded in the interior, byte by byte at the
+// stream's edges.  AFTER: also the 4 bytes after the range.
+template <int SEGS, bool EDGE, bool AFTER>
+__device__ __forceinline__ void load_tile(const u8 *base, u64 vstart, u64 vend, u64 wv,
+                                          TileRegs<SEGS> &x) {
+    const u32 ln = lane_id();
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
         const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
         if (EDGE) {
-            load16_guarded(t.base, v, t.vstart, t.vend, w[s], valid[s]);
+            load16_guarded(base, v, vstart, vend, x.w[s], x.valid[s]);
         } else {
-            load16(t.base + v, w[s]);
-            valid[s] = 0xFFFFu;
+            load16(base + v, x.w[s]);
+            x.valid[s] = 0xFFFFu;
         }
     }
-    // the 4 bytes before the wavefront's bytes and the 4 after them
-    u32 hb, hbv, ha = 0, hav = 0;
+    x.ha = 0;
+    x.hav = 0;
     if (EDGE) {
-        load4_guarded(t.base, (i64)wv - 4, t.vstart, t.vend, hb, hbv);
-        if (!COUNT) load4_guarded(t.base, (i64)(wv + SEGS * kSegBytes), t.vstart, t.vend, ha, hav);
+        load4_guarded(base, (i64)wv - 4, vstart, vend, x.hb, x.hbv);
+        if (AFTER) load4_guarded(base, (i64)(wv + SEGS * kSegBytes), vstart, vend, x.ha, x.hav);
     } else {
-        hb = *(const u32 *)(t.base + wv - 4);
-        hbv = 0xFu;
-        if (!COUNT) ha = *(const u32 *)(t.base + wv + SEGS * kSegBytes);
-        hav = 0xFu;
+        x.hb = *(const u32 *)(base + wv - 4);
+        x.hbv = 0xFu;
+        if (AFTER) x.ha = *(const u32 *)(base + wv + SEGS * kSegBytes);
+        x.hav = 0xFu;
     }
+}
+
+// D: 0 plain, 1 differences (inclusive prefix sum), 2 differences minus one
+// (the prefix sum plus each integer's rank).  The tile's bytes come in `x`.
+template <int D, int KIND, int SEGS, bool EDGE>
+__device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs<SEGS> &x, u32 *rows,
+                                                 WgShared &sh, u32 wib, u32 wpb) {
+    constexpr bool DELTA = D != 0, RANK = D == 2;
+    constexpr bool COUNT = KIND == kCount, AGG = KIND == kAgg;
+    constexpr bool KNOWN = KIND == kKnown || KIND == kKnownB;
+    constexpr bool PIECE = KIND == kPiece;
+    constexpr bool WAVE = KIND == kKnownW;
+    const u32 ln = lane_id();
+    const u64 wv = t.tv + (u64)wib * (SEGS * kSegBytes);   // this wavefront's first byte
+    const auto &w = x.w;
+    const auto &valid = x.valid;
+    const u32 hb = x.hb, hbv = x.hbv, ha = x.ha, hav = x.hav;
 
     // Phase 1: masks, counts (and for DELTA the integers and sums).
     u32 emit[SEGS], above[SEGS], segbase[SEGS], segcnt[SEGS];
@@ -756,51 +780,61 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
     }
     const bool wmal = ballot(mal) != 0;
     if (AGG) return TileOut{ctot, wmal, stot};
-    if (ln == 0) {
-        sh.wcnt[wib] = ctot;
-        sh.wsum[wib] = stot;
-        sh.wmal[wib] = wmal ? 1u : 0u;
-    }
-    __syncthreads();
-    u32 wex_c = 0, wex_s = 0;
-    for (u32 k = 0; k < wib; ++k) {
-        wex_c += sh.wcnt[k];
-        wex_s += sh.wsum[k];
-    }
-    const TileSum tsum = tile_sum(sh, wpb);
-
-    // Wavefront 0 publishes the aggregate, looks back, publishes the
-    // inclusive prefix and hands the exclusive prefix to the others; the
-    // aggregate and the inclusive prefix are stored by the same wavefront,
-    // in that order.
-    if (wib == 0) {
-        Prefix ex;
-        if (KNOWN) {
-            ex = Prefix{t.known_c, t.known_s, t.known_mal};
-            if (KIND == kKnownB) {
-                const Straddle st = straddle(hb, read_lane(w[0][0], 0), read_lane(w[0][1], 0));
-                ex.c += st.code;
-                ex.s += st.rest;
-            }
-        } else if (t.didx == t.dfirst) {
-            ex = Prefix{0, t.prev, false};
-        } else {
-            if (ln == 0) publish<DELTA>(&t.desc[t.didx], t.tag, false, tsum.mal, tsum.c, tsum.s);
-            ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag);
-        }
+    u64 exc;
+    u32 exs, wex_c = 0, wex_s = 0;
+    TileOut res;
+    if constexpr (WAVE) {
+        // the wavefront's own prefix plus the code straddling its first byte
+        const Straddle st = straddle(hb, read_lane(w[0][0], 0), read_lane(w[0][1], 0));
+        exc = t.known_c + st.code;
+        exs = t.known_s + st.rest;
+        res = TileOut{exc + ctot, false, exs + stot};
+    } else {
         if (ln == 0) {
-            if (!KNOWN)
-                publish<DELTA>(&t.desc[t.didx], t.tag, true, ex.mal || tsum.mal, ex.c + tsum.c,
-                               ex.s + tsum.s);
-            sh.excl_c = ex.c;
-            sh.excl_s = ex.s;
-            sh.excl_mal = ex.mal ? 1u : 0u;
+            sh.wcnt[wib] = ctot;
+            sh.wsum[wib] = stot;
+            sh.wmal[wib] = wmal ? 1u : 0u;
         }
+        __syncthreads();
+        for (u32 k = 0; k < wib; ++k) {
+            wex_c += sh.wcnt[k];
+            wex_s += sh.wsum[k];
+        }
+        const TileSum tsum = tile_sum(sh, wpb);
+
+        // Wavefront 0 publishes the aggregate, looks back, publishes the
+        // inclusive prefix and hands the exclusive prefix to the others; the
+        // aggregate and the inclusive prefix are stored by the same wavefront,
+        // in that order.
+        if (wib == 0) {
+            Prefix ex;
+            if (KNOWN) {
+                ex = Prefix{t.known_c, t.known_s, t.known_mal};
+                if (KIND == kKnownB) {
+                    const Straddle st = straddle(hb, read_lane(w[0][0], 0), read_lane(w[0][1], 0));
+                    ex.c += st.code;
+                    ex.s += st.rest;
+                }
+            } else if (t.didx == t.dfirst) {
+                ex = Prefix{0, t.prev, false};
+            } else {
+                if (ln == 0) publish<DELTA>(&t.desc[t.didx], t.tag, false, tsum.mal, tsum.c, tsum.s);
+                ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag);
+            }
+            if (ln == 0) {
+                if (!KNOWN)
+                    publish<DELTA>(&t.desc[t.didx], t.tag, true, ex.mal || tsum.mal, ex.c + tsum.c,
+                                   ex.s + tsum.s);
+                sh.excl_c = ex.c;
+                sh.excl_s = ex.s;
+                sh.excl_mal = ex.mal ? 1u : 0u;
+            }
+        }
+        __syncthreads();
+        exc = sh.excl_c;
+        exs = sh.excl_s;
+        res = TileOut{exc + tsum.c, sh.excl_mal != 0 || tsum.mal, exs + tsum.s};
     }
-    __syncthreads();
-    const u64 exc = sh.excl_c;
-    const u32 exs = sh.excl_s;
-    const TileOut res{exc + tsum.c, sh.excl_mal != 0 || tsum.mal, exs + tsum.s};
     if (COUNT) return res;
 
     // Phase 2: store each segment's integers.
@@ -845,6 +879,16 @@ __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared
             store_rows<true, RANK>(rows, u, emit[s], out_seg, (u32)(t.n - gbase), (u32)gbase);
     }
     return res;
+}
+
+// run_tile_regs with the wavefront's bytes loaded first.
+template <int D, int KIND, int SEGS, bool EDGE>
+__device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared &sh, u32 wib,
+                                            u32 wpb) {
+    TileRegs<SEGS> x;
+    load_tile<SEGS, EDGE, KIND != kCount>(t.base, t.vstart, t.vend,
+                                          t.tv + (u64)wib * (SEGS * kSegBytes), x);
+    return run_tile_regs<D, KIND, SEGS, EDGE>(t, x, rows, sh, wib, wpb);
 }
 
 // Status of a finished stream or list: malformed first,
@@ -1210,6 +1254,423 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
         (void)run_tile<D, kKnownB, SEGS, false>(t, stage, sh, wib, wpb);
     else
         (void)run_tile<D, kKnownB, SEGS, true>(t, stage, sh, wib, wpb);
+}
+
+// ============================================================ one launch, one read
+// Single stream in one persistent launch that reads every input byte once
+// and never waits without bound.  Workgroup r (of G) owns tiles k G + r,
+// k = 0, 1, ...: in round k it loads tile k G + r into registers and
+// publishes that tile's aggregate (terminator count, byte sum, malformed
+// flag: the slot k_tile_agg writes, tagged with the launch), and it decodes
+// the tile it loaded two rounds earlier, whose bytes are still in registers.
+// The exclusive prefix of tile (k-2) G + r is the running total of rounds
+// before k-2 plus the aggregates of ranks below r in round k-2; one
+// wavefront reads round k-2's G aggregates (at most 16 per lane), which were
+// published a round ago, and also adds all of them to the running total.
+// An aggregate that is not there yet is read again a few times from the
+// coherent level, then computed from the tile's bytes by the reader itself,
+// so a workgroup that has not been scheduled (another kernel holds the
+// device) delays no other: forward progress needs no co-residency and no
+// ticket.  The last workgroup to finish (counted in groups of 64) writes the
+// status and advances the launch epoch.
+constexpr int kFlowMaxSlots = kFlowMaxGrid / kWave;   // aggregates per lane
+// How long a reader waits for a missing aggregate before it takes the
+// producer to be absent (not scheduled, because other work holds the
+// device) and computes the value itself: 200 us of the 100 MHz reference
+// clock.  A producer found absent is not waited for again in later rounds
+// (unless its values show up at the first read).
+constexpr u64 kFlowWaitTicks = 20000;
+// LDS words of one ring slot of one wavefront: SEGS segments, then the two
+// halo words (padded to 16 bytes).
+template <int SEGS>
+constexpr u32 kFlowSlotWords = SEGS * kWave * 4 + 4;
+
+struct FlowVal {
+    u32 c, s;
+    bool m;
+};
+
+// A tile's aggregate in one 64-bit word, stored and read whole:
+// [63:50] tag (valid bit and the low 13 bits of the epoch), [49] malformed,
+// [48:32] terminators (a tile holds at most 32 KiB), [31:0] byte sum.
+__device__ __forceinline__ u32 flow_tag(u32 epoch) { return 0x2000u | (epoch & 0x1FFFu); }
+__device__ __forceinline__ u64 flow_pack(u32 tag, bool mal, u32 c, u32 s) {
+    return ((u64)tag << 50) | ((u64)(mal ? 1u : 0u) << 49) | ((u64)(c & 0x1FFFFu) << 32) | s;
+}
+
+// The aggregate of one tile computed by one wavefront from the bytes (the
+// value k_tile_agg and the flow's own aggregate step produce): terminators
+// in the tile's part of the stream, byte sum, malformed run.
+template <int D, int SEGS>
+__device__ FlowVal tile_agg_alone(const StreamArgs &a, u64 tile, u32 wpb) {
+    const u32 ln = lane_id();
+    const u64 tb = (u64)wpb * SEGS * kSegBytes;
+    const u64 tv = tile * tb;
+    u32 cont = 0, sum = 0;
+    bool mal = false;
+    for (u32 q = 0; q < wpb; ++q) {
+        const u64 wv = tv + (u64)q * (SEGS * kSegBytes);
+        u32 w[SEGS][4], valid, hb, hbv;
+#pragma unroll
+        for (int s = 0; s < SEGS; ++s)
+            load16_guarded(a.base, wv + (u64)s * kSegBytes + 16u * ln, a.vstart, a.vend, w[s], valid);
+        load4_guarded(a.base, (i64)wv - 4, a.vstart, a.vend, hb, hbv);
+#pragma unroll
+        for (int s = 0; s < SEGS; ++s) {
+            const u32 below = from_lane_below(w[s][3], s == 0 ? hb : read_lane(w[s - 1][3], 63));
+            seg_bytes<D != 0>(w[s], below, cont, sum, mal);
+        }
+    }
+    const u64 lo = tv > a.vstart ? tv : a.vstart;
+    const u64 hi = tv + tb < a.vend ? tv + tb : a.vend;
+    FlowVal v;
+    v.c = (u32)(hi - lo) - wave_sum(cont);
+    v.s = D ? wave_sum(sum) : 0u;
+    v.m = ballot(mal) != 0;
+    return v;
+}
+
+// Sums round kk's aggregates (tiles t0 .. t0 + nr - 1; lane l slot q holds
+// rank l + 64 q) over the ranks below `r` (below) and over all ranks (all):
+// a first read through the caches, then for what it lacked coherent
+// re-reads or the bytes themselves.
+template <int D, int SEGS>
+__device__ void flow_round_sums(const StreamArgs &a, u64 *agg, u64 t0, u32 nr, u32 r, u32 tag,
+                                u32 wpb, bool recompute, u32 &absent, FlowVal &below,
+                                FlowVal &all) {
+    const u32 ln = lane_id();
+    u32 pend = 0;   // slots not read yet
+    below = FlowVal{0, 0, false};
+    all = FlowVal{0, 0, false};
+    auto take = [&](u32 q, u64 w) {
+        const u32 cc = (u32)(w >> 32) & 0x1FFFFu, ss = (u32)w;
+        const bool mm = ((w >> 49) & 1u) != 0;
+        all.c += cc;
+        all.s += ss;
+        all.m |= mm;
+        if (ln + 64u * q < r) {
+            below.c += cc;
+            below.s += ss;
+            below.m |= mm;
+        }
+    };
+    // first read through the caches, in batches of 8 slots per lane: one
+    // line serves every workgroup of an XCD, and a stale line only means a
+    // coherent re-read below
+    constexpr int kBatch = 8;
+#pragma unroll
+    for (int q0 = 0; q0 < kFlowMaxSlots; q0 += kBatch) {
+        if (64u * q0 >= nr) break;
+        u64 v[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const u32 rho = ln + 64u * (q0 + q);
+            v[q] = (!recompute && rho < nr) ? agg[t0 + rho] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            if (ln + 64u * (q0 + q) >= nr) continue;
+            if (!recompute && (u32)(v[q] >> 50) == tag)
+                take(q0 + q, v[q]);
+            else
+                pend |= 1u << (q0 + q);
+        }
+    }
+    // producers that are running publish soon: wait for them (coherent
+    // re-reads), up to kFlowWaitTicks; those already found absent are not
+    // waited for
+    absent &= pend;
+    u32 wait = recompute ? 0u : pend & ~absent;
+    const u64 t_start = __builtin_amdgcn_s_memrealtime();
+    while (ballot(wait != 0) != 0) {
+        if (__builtin_amdgcn_s_memrealtime() - t_start > kFlowWaitTicks) {
+            absent |= wait;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        u32 p = wait;
+        while (p) {
+            const u32 q = (u32)__builtin_ctz(p);
+            p &= p - 1u;
+            const u64 w = aload(&agg[t0 + ln + 64u * q]);
+            if ((u32)(w >> 50) == tag) {
+                take(q, w);
+                pend &= ~(1u << q);
+                wait &= ~(1u << q);
+            }
+        }
+    }
+    // still missing: computed from the bytes, one tile at a time by the
+    // whole wavefront, and published (the value its producer would publish),
+    // so that other readers find it instead of computing it again
+    for (u64 m = ballot(pend != 0); m; m = ballot(pend != 0)) {
+        const u32 l = (u32)__builtin_ctzll(m);
+        const u32 q = (u32)__builtin_ctz(read_lane(pend, l));
+        const FlowVal fv = tile_agg_alone<D, SEGS>(a, t0 + l + 64u * q, wpb);
+        if (ln == l) {
+            const u64 w = flow_pack(tag, fv.m, fv.c, fv.s);
+            if (!recompute) astore(&agg[t0 + l + 64u * q], w);
+            take(q, w);
+            pend &= ~(1u << q);
+        }
+    }
+    below.c = wave_sum(below.c);
+    all.c = wave_sum(all.c);
+    if (D) {
+        below.s = wave_sum(below.s);
+        all.s = wave_sum(all.s);
+    }
+    below.m = ballot(below.m) != 0;
+    all.m = ballot(all.m) != 0;
+}
+
+// Per-wavefront partial of a tile's aggregate: terminators in the
+// wavefront's range, its byte sum, malformed run seen.
+template <int D, int SEGS, bool EDGE>
+__device__ __forceinline__ FlowVal wave_partial(const StreamArgs &a, const TileRegs<SEGS> &x, u64 wv) {
+    u32 cont = 0, sum = 0;
+    bool mal = false;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 below = from_lane_below(x.w[s][3], s == 0 ? x.hb : read_lane(x.w[s - 1][3], 63));
+        seg_bytes<D != 0>(x.w[s], below, cont, sum, mal);
+    }
+    const u64 lo = wv > a.vstart ? wv : a.vstart;
+    const u64 hi = wv + SEGS * kSegBytes < a.vend ? wv + SEGS * kSegBytes : a.vend;
+    FlowVal v;
+    v.c = (hi > lo ? (u32)(hi - lo) : 0u) - wave_sum(cont);
+    v.s = D ? wave_sum(sum) : 0u;
+    v.m = ballot(mal) != 0;
+    return v;
+}
+
+// Workgroup layout: wavefront 0 is the control wavefront, wavefronts
+// 1 .. nd (nd = blockDim / 64 - 1) decode; a tile is nd x SEGS segments,
+// decode wavefront d + 1 owning segments [d SEGS, (d + 1) SEGS).  Round k:
+//  * decode wavefront d loads its share of tile k G + r into registers,
+//    decodes its share of the tile of round k - 3 (kept in an LDS ring)
+//    with its own exclusive prefix (computed by the control wavefront in
+//    round k - 1), writes its partial aggregate of tile k and the tile's
+//    bytes to LDS;
+//  * the control wavefront publishes the aggregate of the tile of round
+//    k - 1 (the sum of its partials), reads round k - 2's aggregates of all
+//    G workgroups (published one round earlier), and turns them, with the
+//    partials of its own tile of round k - 2, into the exclusive prefix of
+//    every decode wavefront's share of that tile;
+//  * one barrier ends the round.
+// No wavefront holds both roles' registers, and the decode waits on nothing
+// but the round's barrier.
+template <int D, int SEGS>
+__global__ __launch_bounds__(kMaxBlock + kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_flow(FlowArgs f) {
+    constexpr u32 kRing = 3;   // tiles of rounds k - 3 .. k - 1
+    extern __shared__ __align__(16) u32 lds[];
+    __shared__ WgShared sh;    // unused by the per-wavefront decode
+    __shared__ u32 p_c[kRing][kMaxWaves], p_s[kRing][kMaxWaves], p_m[kRing][kMaxWaves];
+    __shared__ u64 w_c[2][kMaxWaves];
+    __shared__ u32 w_s[2][kMaxWaves];
+    __shared__ u32 f_epoch;
+    const StreamArgs &a = f.s;
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u32 nd = (blockDim.x >> 6) - 1;   // decode wavefronts
+    const u32 d = wib - 1;                 // decode wavefront index (wib >= 1)
+    const u32 G = gridDim.x, r = blockIdx.x;
+    const u64 tb = (u64)nd * SEGS * kSegBytes;
+    if (tid == 0) f_epoch = (u32)aload(a.hdr);
+    __syncthreads();
+    const u32 epoch = f_epoch;
+    const u32 tag = flow_tag(epoch);
+    u64 *const agg = (u64 *)a.desc;   // one word per tile
+    const u32 rounds = f.rounds;
+
+    if (wib == 0) {
+        // ---------------------------------------------------- control
+        u64 bc = 0;
+        u32 bs = a.prev;
+        bool bm = false;
+        u32 absent = 0;
+        for (u32 k = 0; k < rounds + 3; ++k) {
+            // round k-2's aggregates (read below)
+            const bool rd = k >= 2 && k - 2 < rounds;
+            const u64 t0 = rd ? (u64)(k - 2) * G : 0;
+            const u64 left = a.ntiles - t0;
+            const u32 nr = left < G ? (u32)left : G;
+            // publish the aggregate of this workgroup's tile of round k-1
+            if (k >= 1 && k - 1 < rounds) {
+                const u64 tp = (u64)(k - 1) * G + r;
+                if (tp < a.ntiles && ln == 0) {
+                    const u32 sl = (k - 1) % kRing;
+                    u32 ct = 0, st = 0, mt = 0;
+                    for (u32 q = 0; q < nd; ++q) {
+                        ct += p_c[sl][q];
+                        st += p_s[sl][q];
+                        mt |= p_m[sl][q];
+                    }
+                    astore(&agg[tp], flow_pack(tag, mt != 0, ct, st));
+                }
+            }
+            if (rd) {
+                FlowVal below, all;
+                flow_round_sums<D, SEGS>(a, agg, t0, nr, r, tag, nd, f.recompute != 0, absent,
+                                         below, all);
+                // exclusive prefixes of the decode wavefronts' shares of
+                // tile (k-2) G + r, for its decode in round k+1
+                if (t0 + r < a.ntiles && ln == 0) {
+                    const u32 sl = (k - 2) % kRing;
+                    u64 c = bc + below.c;
+                    u32 sm = bs + below.s;
+                    for (u32 q = 0; q < nd; ++q) {
+                        w_c[k & 1u][q] = c;
+                        w_s[k & 1u][q] = sm;
+                        c += p_c[sl][q];
+                        sm += p_s[sl][q];
+                    }
+                }
+                bc += all.c;
+                bs += all.s;
+                bm |= all.m;
+            }
+            __syncthreads();
+        }
+        // Completion, counted per group of 64 workgroups then over the
+        // groups: the last one writes the status (every control wavefront
+        // holds the same totals) and advances the epoch, after which no
+        // workgroup of this launch reads an aggregate again.
+        if (ln == 0) {
+            const u32 ng = (G + 63) / 64, grp = r / 64;
+            const u32 gsize = grp + 1 < ng ? 64u : G - 64u * grp;
+            if (aadd(&f.ctr[grp], 1) == gsize - 1) {
+                astore(&f.ctr[grp], 0);
+                if (aadd(&f.ctr[kFlowMaxGroups], 1) == ng - 1) {
+                    astore(&f.ctr[kFlowMaxGroups], 0);
+                    *a.d_status = final_status(bm, a.base[a.vend - 1], bc, a.n);
+                    astore(a.hdr, (u64)epoch + 1);
+                }
+            }
+        }
+        return;
+    }
+
+    // -------------------------------------------------------- decode
+    u32 *stage = lds + d * kStageWords;
+    u32 *ring = lds + nd * kStageWords + d * kRing * kFlowSlotWords<SEGS>;
+    TileIn t{};
+    t.base = a.base;
+    t.vstart = a.vstart;
+    t.vend = a.vend;
+    t.out = a.out;
+    t.n = a.n;
+    // the loads of a round's tile are issued one round ahead, so that a
+    // whole round of work hides their latency
+    auto tile_of = [&](u32 k, u64 &tv, u64 &wv, bool &has, bool &inner) {
+        const u64 ta = (u64)k * G + r;
+        has = k < rounds && ta < a.ntiles;
+        tv = ta * tb;
+        wv = tv + (u64)d * (SEGS * kSegBytes);
+        inner = has && ta > 0 && tv + tb + 4 <= a.vend;
+    };
+    TileRegs<SEGS> xc, xn;   // this round's tile, the next round's
+    u64 tvc, wvc;
+    bool hasc, inc;
+    tile_of(0, tvc, wvc, hasc, inc);
+    if (inc) load_tile<SEGS, false, true>(a.base, a.vstart, a.vend, wvc, xc);
+    for (u32 k = 0; k < rounds + 3; ++k) {
+        u64 tvn, wvn;
+        bool hasn, inn;
+        tile_of(k + 1, tvn, wvn, hasn, inn);
+        if (inn) load_tile<SEGS, false, true>(a.base, a.vstart, a.vend, wvn, xn);
+
+        // partial aggregate of this round's tile, and its bytes to the ring
+        if (hasc) {
+            FlowVal v;
+            if (inc) {
+                v = wave_partial<D, SEGS, false>(a, xc, wvc);
+            } else {
+                TileRegs<SEGS> e;
+                load_tile<SEGS, true, false>(a.base, a.vstart, a.vend, wvc, e);
+                v = wave_partial<D, SEGS, true>(a, e, wvc);
+            }
+            if (ln == 0) {
+                p_c[k % kRing][d] = v.c;
+                p_s[k % kRing][d] = v.s;
+                p_m[k % kRing][d] = v.m ? 1u : 0u;
+            }
+        }
+
+        // decode this wavefront's share of the tile of round k - 3, then
+        // put this round's tile in its ring slot
+        u32 *slot = ring + (k % kRing) * kFlowSlotWords<SEGS>;
+        if (k >= 3) {
+            const u64 td = (u64)(k - 3) * G + r;
+            if (td < a.ntiles) {
+                t.tv = td * tb;
+                t.known_c = w_c[(k - 1) & 1u][d];
+                t.known_s = w_s[(k - 1) & 1u][d];
+                if (td > 0 && t.tv + tb + 4 <= a.vend) {   // interior: its bytes are in the ring
+                    TileRegs<SEGS> x3;
+#pragma unroll
+                    for (int sg = 0; sg < SEGS; ++sg) {
+                        const uint4 q = *(const uint4 *)(slot + (sg * kWave + ln) * 4);
+                        x3.w[sg][0] = q.x;
+                        x3.w[sg][1] = q.y;
+                        x3.w[sg][2] = q.z;
+                        x3.w[sg][3] = q.w;
+                        x3.valid[sg] = 0xFFFFu;
+                    }
+                    x3.hb = slot[SEGS * kWave * 4];
+                    x3.ha = slot[SEGS * kWave * 4 + 1];
+                    x3.hbv = x3.hav = 0xFu;
+                    (void)run_tile_regs<D, kKnownW, SEGS, false>(t, x3, stage, sh, d, nd);
+                } else {
+                    (void)run_tile<D, kKnownW, SEGS, true>(t, stage, sh, d, nd);
+                }
+            }
+        }
+        if (inc) {
+#pragma unroll
+            for (int sg = 0; sg < SEGS; ++sg)
+                *(uint4 *)(slot + (sg * kWave + ln) * 4) =
+                    make_uint4(xc.w[sg][0], xc.w[sg][1], xc.w[sg][2], xc.w[sg][3]);
+            if (ln == 0) {
+                slot[SEGS * kWave * 4] = xc.hb;
+                slot[SEGS * kWave * 4 + 1] = xc.ha;
+            }
+        }
+        __syncthreads();
+        xc = xn;
+        tvc = tvn;
+        wvc = wvn;
+        hasc = hasn;
+        inc = inn;
+    }
+}
+
+template <int D, int SEGS>
+hipError_t launch_flow_t(FlowArgs f, int wpb, int grid, int cus, hipStream_t s) {
+    const size_t lds = (size_t)wpb * (kStageWords + 3 * kFlowSlotWords<SEGS>) * sizeof(u32);
+    const int threads = (wpb + 1) * kWave;
+    if (grid <= 0) {
+        static std::atomic<int> occ[9];   // per wpb (zero-initialised statics)
+        int b = occ[wpb].load(std::memory_order_relaxed);
+        if (b <= 0) {
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_flow<D, SEGS>, threads, lds);
+            if (e != hipSuccess) return e;
+            b = b > 0 ? b : 1;
+            occ[wpb].store(b, std::memory_order_relaxed);
+        }
+        grid = cus * b;
+    }
+    if (grid > kFlowMaxGrid) grid = kFlowMaxGrid;
+    if ((u64)grid > f.s.ntiles) grid = (int)f.s.ntiles;
+    if (grid < 1) grid = 1;
+    f.rounds = (u32)((f.s.ntiles + grid - 1) / grid);
+    hipLaunchKernelGGL((k_flow<D, SEGS>), dim3(grid), dim3(threads), lds, s, f);
+    return hipGetLastError();
+}
+template <int SEGS>
+hipError_t launch_flow_s(const FlowArgs &f, int delta, int wpb, int grid, int cus, hipStream_t s) {
+    return delta == 2 ? launch_flow_t<2, SEGS>(f, wpb, grid, cus, s)
+           : delta   ? launch_flow_t<1, SEGS>(f, wpb, grid, cus, s)
+                     : launch_flow_t<0, SEGS>(f, wpb, grid, cus, s);
 }
 
 // ============================================================ 64-bit codes
@@ -2877,6 +3338,17 @@ hipError_t launch64(const Stream64Args &a, int delta, int segs, int wpb, hipStre
         case 1: return delta ? launch64_t<1, 1>(a, wpb, s) : launch64_t<0, 1>(a, wpb, s);
         case 2: return delta ? launch64_t<1, 2>(a, wpb, s) : launch64_t<0, 2>(a, wpb, s);
         default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_flow(const FlowArgs &f, int delta, int segs, int wpb, int grid, int cus,
+                       hipStream_t s) {
+    if (grid < 0 || grid > kFlowMaxGrid || wpb < 1 || wpb > 8) return hipErrorInvalidValue;
+    switch (segs) {
+    case 1: return launch_flow_s<1>(f, delta, wpb, grid, cus, s);
+    case 2: return launch_flow_s<2>(f, delta, wpb, grid, cus, s);
+    case 4: return launch_flow_s<4>(f, delta, wpb, grid, cus, s);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -23,7 +23,9 @@ constexpr int kStageWords = 64 * 18;
 
 // Workspace layout: a 256-byte header, then one look-back descriptor per
 // tile (or per work item of a batched launch), then batch work tables.
-constexpr size_t kHeaderBytes = 256;
+constexpr size_t kHeaderBytes = 512;
+// Header bytes [256, 512): the completion counters of the one-launch decode.
+constexpr size_t kFlowCtrOff = 256;
 
 // Look-back descriptor of one tile: two self-contained 64-bit words, each
 // holding a tag that names the launch, an "inclusive" flag and a payload.
@@ -47,9 +49,9 @@ constexpr int kTicketWord = 3;   // zero between launches (take_ticket)
 // predecessors are running when it looks back); each launch reads the epoch, tags its
 // descriptors with it, and the tile that finishes the chain stores epoch+1,
 // which retires the launch's descriptors for the next one.  Descriptors carry
-// the low 25 bits of the epoch, so the host re-zeroes a workspace before 2^24
-// launches.
-constexpr uint64_t kEpochLaunchLimit = (1ull << 24);
+// the low 25 bits of the epoch (the one-launch decode's aggregate words the
+// low 13 bits), so the host re-zeroes a workspace before 2^13 launches.
+constexpr uint64_t kEpochLaunchLimit = (1ull << 13);
 
 struct StreamArgs {
     const uint8_t *base;   // 16-byte aligned, <= bytes
@@ -71,6 +73,20 @@ struct StreamArgs {
     const uint64_t *cursor_in;
     uint64_t window;
     uint64_t *scratch;
+};
+
+// Single-stream decode in one persistent launch of `grid` workgroups that
+// reads the input once (k_flow): tile (k, r) = k * grid + r, s.desc holds one
+// tagged aggregate per tile; ctr points at kFlowMaxGroups + 1 completion
+// counters (zero between launches).
+constexpr int kFlowMaxGroups = 16;
+constexpr int kFlowMaxGrid = kFlowMaxGroups * 64;
+constexpr int kScheduleFlow = -2;   // the schedule number of the one-launch decode
+struct FlowArgs {
+    StreamArgs s;
+    uint64_t *ctr;
+    uint32_t rounds;      // ceil(s.ntiles / grid), set by launch_flow
+    uint32_t recompute;   // diagnostic: take every aggregate from the bytes
 };
 
 // Single-stream decode of 64-bit codes, in units of
@@ -182,6 +198,11 @@ hipError_t launch_chunks(const StreamArgs &a, int delta, int segs, int wpb, uint
 // a one-workgroup scan that also writes the status, decode with the prefix
 // known); one descriptor slot per tile.
 hipError_t launch_two_pass(const StreamArgs &a, int delta, int segs, int wpb, hipStream_t s);
+// Single-stream decode in one launch of `grid` persistent workgroups (0: as
+// many as are resident at once on `cus` compute units; at most
+// kFlowMaxGrid), every input byte read once (k_flow); f.rounds is set here.
+hipError_t launch_flow(const FlowArgs &f, int delta, int segs, int wpb, int grid, int cus,
+                       hipStream_t s);
 // 64-bit decode: unit aggregates, a one-workgroup scan (status), decode;
 // segs 1 or 2.
 hipError_t launch64(const Stream64Args &a, int delta, int segs, int wpb, hipStream_t s);

@@ -33,7 +33,8 @@ EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_encode_batch", "vbyte_server_create", "vbyte_server_destroy",
            "vbyte_server_run", "vbyte_batch_graph_create", "vbyte_batch_graph_launch",
            "vbyte_batch_graph_destroy", "vbyte_autotune_decode", "vbyte_autotune_batch",
-           "vbyte_set_chunk_tiles", "vbyte_get_chunk_tiles",
+           "vbyte_set_chunk_tiles", "vbyte_get_chunk_tiles", "vbyte_set_flow_grid",
+           "vbyte_decode_ex", "vbyte_tuning_default",
            "vbyte_workspace_size", "vbyte_set_tuning", "vbyte_get_tuning",
            "vbyte_status_str", "vbyte_last_error"]
 
@@ -42,6 +43,31 @@ class TunePoint(ctypes.Structure):
     _fields_ = [("segs_per_wave", ctypes.c_int), ("waves_per_block", ctypes.c_int),
                 ("small_list_bytes", ctypes.c_int64), ("tiles_per_chunk", ctypes.c_int),
                 ("ms", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    """vbyte_tuning: the kernel tuning of one single-stream decode."""
+    _fields_ = [("segs_per_wave", ctypes.c_int), ("waves_per_block", ctypes.c_int),
+                ("schedule", ctypes.c_int), ("grid", ctypes.c_int), ("recompute", ctypes.c_int)]
+
+
+SCHED_ONE_READ, SCHED_TWO_PASS, SCHED_LOOKBACK = -2, -1, 0
+
+
+def make_tuning(segs_per_wave=None, waves_per_block=None, schedule=None, grid=None, recompute=0):
+    """A Tuning from the process defaults, with the given fields replaced."""
+    t = Tuning()
+    _lib().vbyte_tuning_default(ctypes.byref(t))
+    if segs_per_wave is not None:
+        t.segs_per_wave = int(segs_per_wave)
+    if waves_per_block is not None:
+        t.waves_per_block = int(waves_per_block)
+    if schedule is not None:
+        t.schedule = int(schedule)
+    if grid is not None:
+        t.grid = int(grid)
+    t.recompute = int(recompute)
+    return t
 
 
 class VByteError(RuntimeError):
@@ -100,6 +126,8 @@ def _declare(lib):
         "vbyte_encode_batch": [vp, sz, vp, sz, vp, sz, vp, vp, vp],
         "vbyte_set_tuning": [i32, i32, i64],
         "vbyte_set_chunk_tiles": [i32],
+        "vbyte_set_flow_grid": [i32],
+        "vbyte_decode_ex": [vp, sz, vp, sz, u32, i32, vp, vp, vp],
         "vbyte_batch_graph_create": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, c.POINTER(vp)],
         "vbyte_batch_graph_launch": [vp, vp],
         "vbyte_autotune_decode": [vp, sz, vp, sz, i32, i32, vp, c.POINTER(TunePoint), sz,
@@ -111,6 +139,8 @@ def _declare(lib):
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = c.c_int
+    lib.vbyte_tuning_default.argtypes = [vp]
+    lib.vbyte_tuning_default.restype = None
     lib.vbyte_get_chunk_tiles.argtypes = []
     lib.vbyte_get_chunk_tiles.restype = c.c_int
     lib.vbyte_batch_graph_destroy.argtypes = [vp]
@@ -168,7 +198,7 @@ def _mode(delta, minus_one):
 
 @_on_stream
 def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=None, stream=None,
-           check=True):
+           check=True, tuning=None):
     """Decode ``n`` uint32 from the VByte bytes ``data`` (uint8 CUDA tensor).
     ``delta``: inclusive prefix sum of the gaps from ``prev``; ``minus_one``:
     differences minus one (vbyte_decode_delta_m1).
@@ -176,6 +206,8 @@ def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=No
     Returns the int32 tensor of results.  With ``check`` the call waits for
     the kernel and raises VByteError on a data error; otherwise the status is
     left in ``status`` (an int32 CUDA tensor of one element) for the caller.
+    ``tuning``: a Tuning (make_tuning) for this call only (vbyte_decode_ex);
+    None uses the process-wide defaults.
     """
     _dev_u8(data)
     n = int(n)
@@ -187,7 +219,10 @@ def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=No
         status = torch.empty(1, dtype=torch.int32, device=data.device)
     s = _stream(stream)
     L = _lib()
-    if minus_one:
+    if tuning is not None:
+        st = L.vbyte_decode_ex(_ptr(data), data.numel(), _ptr(out), n, int(prev) & 0xFFFFFFFF,
+                               _mode(delta, minus_one), ctypes.byref(tuning), _ptr(status), s)
+    elif minus_one:
         st = L.vbyte_decode_delta_m1_async(_ptr(data), data.numel(), _ptr(out), n,
                                            int(prev) & 0xFFFFFFFF, _ptr(status), s)
     elif delta:
@@ -498,11 +533,17 @@ def encode_batch(values, vals_off, *, stream=None):
 
 def set_tuning(segs_per_wave=0, waves_per_block=0, small_list_bytes=0, tiles_per_chunk=None):
     """Set the kernel tuning (0 keeps a value); tiles_per_chunk selects the
-    single-stream kernel (0: per-tile look-back, k: chunks of k tiles)."""
+    single-stream kernel (-2: one read, -1: two passes, 0: per-tile
+    look-back, k: chunks of k tiles)."""
     _check_call(_lib().vbyte_set_tuning(int(segs_per_wave), int(waves_per_block),
                                         int(small_list_bytes)), "set_tuning")
     if tiles_per_chunk is not None:
         _check_call(_lib().vbyte_set_chunk_tiles(int(tiles_per_chunk)), "set_chunk_tiles")
+
+
+def set_flow_grid(grid=0):
+    """Default workgroups of the one-read schedule (0: 16 wavefronts per CU)."""
+    _check_call(_lib().vbyte_set_flow_grid(int(grid)), "set_flow_grid")
 
 
 def get_tuning():

@@ -80,6 +80,7 @@ def test_status_numbers_are_fixed():
     # (ECOUNT < ETRUNC < EMALFORMED), the binding's constants the same
     from paper_1503_07387_amd import vbyte
     text = open(HEADER).read()
+    text = text[text.index("typedef enum vbyte_status {"):text.index("} vbyte_status;")]
     nums = dict((k, int(v)) for k, v in re.findall(r"VBYTE_(\w+)\s*=\s*(\d+)", text))
     want = {"OK": 0, "EINVAL": 1, "ECOUNT": 2, "ETRUNC": 3, "EMALFORMED": 4, "EHIP": 5,
             "ENOMEM": 6}

@@ -42,7 +42,7 @@ def two_streams(calls, reps=4):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("tiling", [(4, 8, 0), (1, 2, 0), (4, 8, 4), (2, 8, -1)])
+@pytest.mark.parametrize("tiling", [(4, 8, 0), (1, 2, 0), (4, 8, 4), (2, 8, -1), (2, 8, -2), (1, 2, -2)])
 def test_two_single_stream_decodes(tiling):
     vbyte.set_tuning(tiling[0], tiling[1], 0, tiles_per_chunk=tiling[2])
     ins = []

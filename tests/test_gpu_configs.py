@@ -40,7 +40,7 @@ def chunked_tuning():
     vbyte.set_tuning(**t)
 
 
-@pytest.mark.parametrize("chunk", [0, 2, 8, -1])
+@pytest.mark.parametrize("chunk", [0, 2, 8, -1, -2])
 @pytest.mark.parametrize("mean", [8, 300])
 def test_config2_differential_streams(mean, chunk, chunked_tuning):
     vbyte.set_tuning(tiles_per_chunk=chunk)
@@ -85,7 +85,7 @@ def mix():
     return x, b
 
 
-@pytest.mark.parametrize("chunk", [0, 16, -1])
+@pytest.mark.parametrize("chunk", [0, 16, -1, -2])
 def test_config5_plain(mix, chunk, chunked_tuning):
     vbyte.set_tuning(tiles_per_chunk=chunk)
     x, b = mix
@@ -100,7 +100,7 @@ def test_config5_plain(mix, chunk, chunked_tuning):
     assert sto == oracle.OK and np.array_equal(y[3 * k:4 * k], yo)
 
 
-@pytest.mark.parametrize("chunk", [0, -1])
+@pytest.mark.parametrize("chunk", [0, -1, -2])
 def test_config5_delta(mix, chunk, chunked_tuning):
     vbyte.set_tuning(tiles_per_chunk=chunk)
     x, b = mix

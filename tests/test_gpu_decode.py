@@ -14,11 +14,13 @@ pytestmark = pytest.mark.gpu
 DEFAULT_TUNING = None
 
 
-@pytest.fixture(autouse=True, params=[0, 3, -1], ids=["tile_lookback", "chunks_of_3", "two_pass"])
+@pytest.fixture(autouse=True, params=[0, 3, -1, -2],
+                ids=["tile_lookback", "chunks_of_3", "two_pass", "one_read"])
 def restore_tuning(request):
-    """Every test runs with the three single-stream kernels: one look-back
-    per tile, chunks of 3 tiles per workgroup, and the three launches with
-    no look-back (tile byte sums, scan, decode)."""
+    """Every test runs with the four single-stream schedules: one look-back
+    per tile, chunks of 3 tiles per workgroup, the three launches with no
+    look-back (tile byte sums, scan, decode), and the one launch that reads
+    every byte once (persistent rounds, aggregates published per tile)."""
     t = vbyte.get_tuning()
     vbyte.set_tuning(tiles_per_chunk=request.param)
     yield

@@ -40,7 +40,8 @@ def check(b, n, prev=0, boff=0, ooff=0):
         assert np.array_equal(y, yo), f"first mismatch at {np.nonzero(y != yo)[0][:1]}"
 
 
-@pytest.mark.parametrize("tiling", [(4, 8, 0), (1, 2, 0), (2, 4, 0), (4, 8, 4), (2, 4, 2), (2, 8, -1), (1, 2, -1)])
+@pytest.mark.parametrize("tiling", [(4, 8, 0), (1, 2, 0), (2, 4, 0), (4, 8, 4), (2, 4, 2), (2, 8, -1), (1, 2, -1),
+                                    (2, 8, -2), (1, 2, -2)])
 @pytest.mark.parametrize("kind", ["mixed", "ones", "gaps300"])
 @pytest.mark.parametrize("n", [1, 777, 40_000, 300_001])
 def test_stream_m1(tiling, kind, n):
@@ -131,7 +132,7 @@ def test_batch_and_graph_m1(small):
         g.close()
 
 
-@pytest.mark.parametrize("chunk", [0, 4, -1])
+@pytest.mark.parametrize("chunk", [0, 4, -1, -2])
 @pytest.mark.parametrize("mean", [8, 300])
 def test_full_size_stream_m1(mean, chunk):
     vbyte.set_tuning(tiles_per_chunk=chunk)
