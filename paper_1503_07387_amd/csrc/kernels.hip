@@ -1644,6 +1644,13 @@ __global__ __launch_bounds__(kMaxBlock + kWave) __attribute__((amdgpu_waves_per_
     }
 }
 
+// Launches k_flow with wpb decode wavefronts and the control wavefront per
+// workgroup.  grid 0: the workgroups that can be resident at once per CU
+// (the occupancy the runtime reports for this kernel, its workgroup size
+// and LDS; one less when it reports 3 or more, because it rounds the
+// register allocation more finely than the hardware and a workgroup that
+// is not resident is one whose aggregates the others must compute) times
+// the CU count, at most kFlowMaxGrid and one per tile.
 template <int D, int SEGS>
 hipError_t launch_flow_t(FlowArgs f, int wpb, int grid, int cus, hipStream_t s) {
     const size_t lds = (size_t)wpb * (kStageWords + 3 * kFlowSlotWords<SEGS>) * sizeof(u32);
@@ -1654,7 +1661,7 @@ hipError_t launch_flow_t(FlowArgs f, int wpb, int grid, int cus, hipStream_t s) 
         if (b <= 0) {
             hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_flow<D, SEGS>, threads, lds);
             if (e != hipSuccess) return e;
-            b = b > 0 ? b : 1;
+            b = b >= 3 ? b - 1 : (b > 0 ? b : 1);
             occ[wpb].store(b, std::memory_order_relaxed);
         }
         grid = cus * b;
