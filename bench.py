@@ -1,15 +1,20 @@
 """Benchmark of the VByte decode hot path on one MI355X.
 
-A step is one pass of the whole hot path over the benchmark workload: the
-differential decode (VByte gaps -> uint32 document identifiers, wrapping
-prefix sum) of two synthetic single streams of 64Mi gaps each, one with
-geometric gaps of mean 8 (almost only 1-byte codes) and one of mean 300
-(a 35/65 mix of 1- and 2-byte codes).  The inputs are generated, VByte-encoded
-on the GPU by the library's encoder and resident in HBM before timing starts.
+A step is one pass of the hot path over the headline workload: the plain
+single-stream decode (VByte bytes -> uint32) of 2^30 values, 5 % 5-byte codes
+and otherwise a 50/50 mix of 1- and 2-byte codes (1.80 GB in, 4 GiB out),
+drawn with a fixed seed, VByte-encoded on the GPU and resident in HBM before
+timing starts.  Beside it (side lines, each its own entry in the JSON): the
+differential decode of the same bytes, the 2^20-value uniform-length stream
+(the small case), the differential decode of two 64Mi-gap streams (gap means
+8 and 300), the one-read schedule, 64-bit and blocks-of-four decodes, the
+intersection consumer, the encoder, the batched decode of 100,000 lists and
+the serving loop over them.
 
 Printed: one JSON line with throughput (Gints/s), the HBM roofline of the
-decode kernel (algorithmic bytes in + 4n out per launch over the launch's
-HIP-event time), and the scalar CPU oracle timed on the host as a baseline.
+decode (algorithmic bytes in + 4n out per call over the call's HIP-event
+time), and the scalar CPU oracle timed on the host, on one core and on all
+cores, as a baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -26,9 +31,14 @@ sys.path.insert(0, ROOT)
 METRIC = "Gints/s + HBM GB/s (% peak), batched vs plain per-list; p50/p99 query latency"
 HBM_PEAK_GBPS = 8000.0
 N_STREAM = 1 << 26
+N_MIX = 1 << 30               # the headline stream: 2^30 values of the 1/2/5-byte mix
+N_UNIFORM = 1 << 20           # the small case: uniform code lengths 1..5
 COPY_ELEMS = 1 << 26          # calibration copy: 256 MiB read + 256 MiB written
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "decode_delta_64Mi_counters.json")
-PROFILE_TRACE = os.path.join(ROOT, "profiles", "decode_delta_64Mi_kernel_trace.md")
+FLUSH_BYTES = 1 << 30         # written before a "flushed" call: four times the 256 MB MALL
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "decode_plain_1Gi_mix_counters.json")
+PROFILE_TRACE = os.path.join(ROOT, "profiles", "decode_plain_1Gi_mix_kernel_trace.md")
+# the library's default single-stream schedule, named explicitly per call
+HEADLINE_TUNING = {"segs_per_wave": 2, "waves_per_block": 8, "schedule": -1}
 KERNEL_SRC = os.path.join(ROOT, "paper_1503_07387_amd", "csrc", "kernels.hip")
 
 
@@ -88,28 +98,88 @@ def verify(torch, streams):
             raise RuntimeError(f"decoded identifiers differ from the gap prefix sum (mean {s['mean']})")
 
 
-def cpu_baseline(streams, budget_s=15.0):
-    """The scalar oracle (plain C, one thread) on the same workload: decode of
-    whole streams, repeated until about budget_s of CPU work is spent."""
+def shard_starts(b, parts):
+    """Byte offsets that cut the VByte stream b into `parts` shards at code
+    boundaries: each cut moves forward from i * len / parts to the byte after
+    the next terminator (host logic of the multi-core baseline)."""
+    import numpy as np
+    cuts = [0]
+    nb = b.size
+    for i in range(1, parts):
+        x = max(i * nb // parts, cuts[-1])
+        while x < nb and b[x] >= 0x80:
+            x += 1
+        x = min(x + 1, nb)
+        cuts.append(x)
+    cuts.append(nb)
+    return np.array(cuts, dtype=np.int64)
+
+
+def cpu_baseline(b, x, reps=5):
+    """The scalar oracle (plain C: validation then Algorithm 1) decoding the
+    headline stream on the host: on one core, and on every core available
+    to this process with the stream cut into one shard per core at code
+    boundaries, a counting pass per shard (its integers, hence the shard's
+    output offset) and then a decode pass per shard, both timed.  Median of
+    `reps` runs each; the output is allocated and touched before timing."""
+    import ctypes
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
-    host = [(s["bytes"].cpu().numpy(), s["gaps"].size) for s in streams]
-    ints = 0
-    t0 = time.perf_counter()
-    passes = 0
-    while True:
-        for b, n in host:
-            st, _ = oracle.decode_delta(b, n, 0)
-            if st != oracle.OK:
-                raise RuntimeError("oracle failed on the benchmark stream")
-            ints += n
-        passes += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or passes >= 10:
-            break
-    return {"value": ints / el / 1e9, "unit": "Gints/s", "cores": 1, "kind": "oracle",
-            "sample": f"{passes} pass(es) over both 64Mi-gap streams (the full workload), "
-                      f"scalar C oracle (Algorithm 1 + wrapping prefix sum), 1 thread, "
-                      f"{el:.1f}s wall"}
+    lib = oracle.oracle.load()
+    n = x.size
+    y = np.empty(n, dtype=np.uint32)
+    y.fill(0)
+    bp = b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    yp = y.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    one = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        st = lib.orc_decode(bp, b.size, yp, n)
+        one.append(time.perf_counter() - t0)
+        if st != oracle.OK:
+            raise RuntimeError("oracle failed on the benchmark stream")
+    if not np.array_equal(y, x):
+        raise RuntimeError("oracle output differs from the drawn values")
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cuts = shard_starts(b, cores)
+    base = b.ctypes.data
+    ybase = y.ctypes.data
+
+    def count(k):
+        p = ctypes.cast(base + int(cuts[k]), ctypes.POINTER(ctypes.c_uint8))
+        return int(lib.orc_count(p, int(cuts[k + 1] - cuts[k])))
+
+    def dec(args):
+        k, off, m = args
+        p = ctypes.cast(base + int(cuts[k]), ctypes.POINTER(ctypes.c_uint8))
+        q = ctypes.cast(ybase + 4 * off, ctypes.POINTER(ctypes.c_uint32))
+        return lib.orc_decode(p, int(cuts[k + 1] - cuts[k]), q, m)
+
+    y.fill(0)
+    allc = []
+    with ThreadPoolExecutor(cores) as ex:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            counts = list(ex.map(count, range(cores)))
+            offs = np.concatenate([[0], np.cumsum(counts)])
+            sts = list(ex.map(dec, [(k, int(offs[k]), counts[k]) for k in range(cores)]))
+            allc.append(time.perf_counter() - t0)
+            if any(st != oracle.OK for st in sts) or int(offs[-1]) != n:
+                raise RuntimeError("sharded oracle decode failed")
+    if not np.array_equal(y, x):
+        raise RuntimeError("sharded oracle output differs from the drawn values")
+    med1 = sorted(one)[reps // 2]
+    medn = sorted(allc)[reps // 2]
+    alg = b.size + 4 * n
+    return {"value": round(n / medn / 1e9, 4), "unit": "Gints/s", "cores": cores, "kind": "oracle",
+            "one_core_gints_per_s": round(n / med1 / 1e9, 4),
+            "one_core_alg_gbps": round(alg / med1 / 1e9, 2),
+            "all_cores_alg_gbps": round(alg / medn / 1e9, 2),
+            "sample": f"the whole headline stream ({n} values, {b.size} bytes), plain decode by the "
+                      f"scalar C oracle (validation pass then Algorithm 1), median of {reps} runs: "
+                      f"1 core {med1:.2f} s; {cores} cores (one shard per core cut at code "
+                      f"boundaries, a counting pass and a decode pass, both timed) {medn:.2f} s"}
 
 
 # Kernels of one single-stream decode call: the look-back kernel alone, the
@@ -146,11 +216,15 @@ def describe_tuning(t):
     return f"{mode} (segs {t['segs_per_wave']}, waves {t['waves_per_block']})"
 
 
-def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
+HEADLINE_KINDS = ("plain decode of the 2^30-value mix",)
+
+
+def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines, kinds=HEADLINE_KINDS):
     """Turn two rocprofv3 --pmc runs of `bench.py --calibrate-copy` (one with
     FETCH_SIZE, one with WRITE_SIZE; values in KiB per dispatch) into HBM
-    bytes per decode launch.  Each counter is scaled by what it reads for the
-    256 MiB calibration copy (known bytes / counted bytes)."""
+    bytes per decode call.  Each counter is scaled by what it reads for the
+    256 MiB calibration copy (known bytes / counted bytes).  Decode calls
+    cycle through `kinds` in dispatch order (one kind: every call alike)."""
     import csv
 
     def load(path, counter):
@@ -167,13 +241,14 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
         factor = known / copy
         dec = group_calls(rows, lambda r: float(r["Counter_Value"]) * 1024 * factor)
         res[name] = {"copy_counted_bytes": copy, "factor": factor, "decode_bytes": dec}
-    # dispatches alternate: gap-mean-8 stream, gap-mean-300 stream
     f, w = res["FETCH_SIZE"]["decode_bytes"], res["WRITE_SIZE"]["decode_bytes"]
     per = []
-    for k in range(2):
-        fk = f[k::2]
-        wk = w[k::2]
-        per.append({"fetch_bytes": sum(fk) / len(fk), "write_bytes": sum(wk) / len(wk),
+    nk = len(kinds)
+    for k in range(nk):
+        fk = f[k::nk]
+        wk = w[k::nk]
+        per.append({"kind": kinds[k], "calls": len(fk), "fetch_bytes": sum(fk) / len(fk),
+                    "write_bytes": sum(wk) / len(wk),
                     "hbm_bytes": sum(fk) / len(fk) + sum(wk) / len(wk)})
     out = {"kernels": "all kernels of one decode call (" + ", ".join(DECODE_KERNELS) + ")",
            "kernel_source_sha256_16": kernel_source_hash(),
@@ -186,17 +261,17 @@ def summarize_pmc(fetch_csv, write_csv, out_json, out_md, command_lines):
     with open(out_json, "w") as fh:
         json.dump(out, fh, indent=1)
     with open(out_md, "w") as fh:
-        fh.write("# HBM traffic of the differential decode, 2 x 64Mi-gap streams\n\n")
+        fh.write("# HBM traffic per decode call: " + "; ".join(kinds) + "\n\n")
         fh.write("Counters from two rocprofv3 runs (one counter each), scaled by the same counter\n"
                  "read for a plain 256 MiB device copy in the same process, summed over the\n"
                  "kernels of one decode call.\n\n")
         for c in command_lines:
             fh.write(f"    {c}\n")
         fh.write(f"\nFETCH_SIZE factor {out['fetch_factor']:.4f}, WRITE_SIZE factor {out['write_factor']:.4f}\n\n")
-        fh.write("| stream | fetch MB | write MB | HBM MB |\n|---|---|---|---|\n")
-        for name, p in zip(("gap mean 8", "gap mean 300"), per):
-            fh.write(f"| {name} | {p['fetch_bytes'] / 1e6:.1f} | {p['write_bytes'] / 1e6:.1f} | "
-                     f"{p['hbm_bytes'] / 1e6:.1f} |\n")
+        fh.write("| call | calls | fetch MB | write MB | HBM MB |\n|---|---|---|---|---|\n")
+        for p in per:
+            fh.write(f"| {p['kind']} | {p['calls']} | {p['fetch_bytes'] / 1e6:.1f} | "
+                     f"{p['write_bytes'] / 1e6:.1f} | {p['hbm_bytes'] / 1e6:.1f} |\n")
         fh.write(f"\nkernel source sha256[:16] (comments and blank space removed) = "
                  f"{out['kernel_source_sha256_16']}\n")
     return out
@@ -443,8 +518,13 @@ def bench_batched(torch, vbyte, serve, idx, reps=10):
             "gather_one_launch_ms": round(res[True][0], 3),
             "per_list_launches_ms": round(res[False][0], 3),
             "per_list_launches": res[False][1],
-            "speedup_batched_vs_per_list": round(res[False][0] / batched_ms, 1),
-            "speedup_graph_vs_per_list": round(res[False][0] / graph_ms, 1)}
+            # like for like: both sides through the server, host clock from
+            # submission to completion
+            "speedup_batched_vs_per_list": round(res[False][0] / res[True][0], 1),
+            # the per-list server time against the GPU-event time of one
+            # eager batched call or graph replay (two different clocks)
+            "per_list_server_ms_over_batched_event_ms": round(res[False][0] / batched_ms, 1),
+            "per_list_server_ms_over_graph_event_ms": round(res[False][0] / graph_ms, 1)}
 
 
 def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
@@ -504,7 +584,7 @@ def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
             "points": points, "per_list_launches_at_half_saturation": per_list}
 
 
-def summarize_trace(trace_csv, stats_csv, out_md, command_line):
+def summarize_trace(trace_csv, stats_csv, out_md, command_line, kinds=HEADLINE_KINDS):
     """Turn a rocprofv3 --kernel-trace --stats run of bench.py (with a fixed
     --tuning, so that every decode call runs the same kernels) into the
     per-stream duration table of profiles/decode_delta_64Mi_kernel_trace.md:
@@ -529,27 +609,28 @@ def summarize_trace(trace_csv, stats_csv, out_md, command_line):
     def dur(r):
         return (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
 
+    nk = len(kinds)
     with open(out_md, "w") as fh:
-        fh.write("# Kernel trace: differential decode, 2 x 64Mi-gap streams (bench.py workload)\n\n")
+        fh.write("# Kernel trace: " + "; ".join(kinds) + " (bench.py)\n\n")
         fh.write("Command (run from the repository root on one MI355X):\n\n")
         fh.write(f"    {command_line}\n\n")
         fh.write("Kernels of one decode call: " + ", ".join(f"`{n}`" for n in names) + ".\n")
-        fh.write("Calls alternate between the gap-mean-8 stream and the gap-mean-300 stream "
-                 "(first the warm-up steps, then the timed ones).\n\n")
-        fh.write("| stream | calls | kernel sum avg us | span avg us | span min us | span max us |\n"
+        fh.write("Calls in dispatch order (first the warm-up steps, then the timed ones)"
+                 + (", cycling through the kinds above" if nk > 1 else "") + ".\n\n")
+        fh.write("| call | calls | kernel sum avg us | span avg us | span min us | span max us |\n"
                  "|---|---|---|---|---|---|\n")
-        for k, name in enumerate(("gap mean 8", "gap mean 300")):
-            cs = calls[k::2]
+        for k, name in enumerate(kinds):
+            cs = calls[k::nk]
             if not cs:
                 continue
             ksum = [sum(dur(r) for r in c) for c in cs]
             span = [(int(c[-1]["End_Timestamp"]) - int(c[0]["Start_Timestamp"])) / 1e3 for c in cs]
             fh.write(f"| {name} | {len(cs)} | {sum(ksum) / len(ksum):.1f} | {sum(span) / len(span):.1f} | "
                      f"{min(span):.1f} | {max(span):.1f} |\n")
-        fh.write("\nPer kernel (average us per call):\n\n| stream | " + " | ".join(names) + " |\n|---|"
+        fh.write("\nPer kernel (average us per call):\n\n| call | " + " | ".join(names) + " |\n|---|"
                  + "---|" * len(names) + "\n")
-        for k, name in enumerate(("gap mean 8", "gap mean 300")):
-            cs = calls[k::2]
+        for k, name in enumerate(kinds):
+            cs = calls[k::nk]
             if not cs:
                 continue
             cells = []
@@ -618,6 +699,180 @@ def summarize_side_trace(which, trace_csv, command_line):
     return {"calls": len(calls), "kernels": names}
 
 
+def device_info(torch):
+    """Name, architecture and CU count of the GPU, ROCm and HIP versions,
+    host cores."""
+    p = torch.cuda.get_device_properties(0)
+    rocm = None
+    try:
+        with open("/opt/rocm/.info/version") as fh:
+            rocm = fh.read().strip()
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"gpu": p.name, "arch": getattr(p, "gcnArchName", None), "cus": p.multi_processor_count,
+            "hbm_gib": round(p.total_memory / 2 ** 30, 1), "rocm": rocm, "hip": torch.version.hip,
+            "torch": torch.__version__, "host_cores": cores}
+
+
+def make_mix(torch, vbyte, workloads):
+    """The headline stream: 2^30 values of the 1/2/5-byte mix, encoded on the
+    GPU."""
+    import numpy as np
+    t0 = time.time()
+    x = workloads.worst_case_mix(N_MIX, workers=16)
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    enc = vbyte.encode(xd)
+    torch.cuda.synchronize()
+    log(f"mix: {N_MIX} values -> {enc.numel()} bytes ({enc.numel() / N_MIX:.4f} B/int), "
+        f"prepared in {time.time() - t0:.1f}s")
+    return {"x": x, "x_dev": xd, "bytes": enc}
+
+
+class Flusher:
+    """Writes FLUSH_BYTES before a call so that its input is not served by
+    the 256 MB Infinity Cache (MALL) from an earlier call."""
+
+    def __init__(self, torch):
+        self.buf = torch.empty(FLUSH_BYTES, dtype=torch.uint8, device="cuda")
+
+    def __call__(self):
+        self.buf.zero_()
+
+
+def event_times(torch, fn, reps, before=None):
+    """HIP-event time (ms) of each of `reps` calls of fn on the current
+    stream; `before` runs ahead of each call, outside the events."""
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(reps):
+        if before is not None:
+            before()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return ms
+
+
+def line(n, bytes_in, ms, out_bytes_per_int=4):
+    """Throughput fields of a decode that took `ms` per call."""
+    alg = bytes_in + out_bytes_per_int * n
+    return {"ms": round(ms, 4), "gints_per_s": round(n / (ms / 1e3) / 1e9, 2),
+            "alg_gbps": round(alg / (ms / 1e3) / 1e9, 1),
+            "pct_hbm_peak": round(100 * alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 1)}
+
+
+def median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def bench_mix_delta(torch, vbyte, mix, flush, tuning, reps=10):
+    """Differential decode (wrapping prefix sum from prev 0) of the headline
+    stream's bytes, checked against a cumsum of the drawn values."""
+    n = N_MIX
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def call():
+        vbyte.decode(mix["bytes"], n, delta=True, out=out, status=st, check=False, tuning=tuning)
+
+    call()
+    torch.cuda.synchronize()
+    ref = (torch.cumsum(mix["x_dev"].to(torch.int64) & 0xFFFFFFFF, 0) & 0xFFFFFFFF).to(torch.int32)
+    if int(st.item()) != 0 or not torch.equal(ref, out):
+        raise RuntimeError("differential decode of the mix differs from the cumsum")
+    del ref
+    warm = median(event_times(torch, call, reps))
+    cold = median(event_times(torch, call, reps, before=flush))
+    r = {"workload": "differential decode (wrapping uint32 prefix sum) of the 2^30-value 1/2/5-byte "
+                     "mix, the headline stream's bytes", "n": n, "bytes_in": int(mix["bytes"].numel()),
+         "tuning": dict(HEADLINE_TUNING), "back_to_back": line(n, mix["bytes"].numel(), warm),
+         "mall_flushed": line(n, mix["bytes"].numel(), cold)}
+    del out
+    return r
+
+
+def bench_one_read(torch, vbyte, mix, flush, reps=10):
+    """The one-read schedule (one persistent launch) on the headline
+    stream, plain and differential, against the same check."""
+    n = N_MIX
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    T = vbyte.make_tuning(2, 7, vbyte.SCHED_ONE_READ)
+    res = {"workload": "plain and differential decode of the 2^30-value mix with the one-read "
+                       "schedule (k_flow, segs 2, 7 decode wavefronts + 1 control)"}
+    for delta in (False, True):
+        def call():
+            vbyte.decode(mix["bytes"], n, delta=delta, out=out, status=st, check=False, tuning=T)
+        call()
+        torch.cuda.synchronize()
+        if delta:
+            ok = torch.equal((torch.cumsum(mix["x_dev"].to(torch.int64) & 0xFFFFFFFF, 0)
+                              & 0xFFFFFFFF).to(torch.int32), out)
+        else:
+            ok = torch.equal(mix["x_dev"], out)
+        if int(st.item()) != 0 or not ok:
+            raise RuntimeError("one-read decode differs")
+        res["delta" if delta else "plain"] = {
+            "back_to_back": line(n, mix["bytes"].numel(), median(event_times(torch, call, reps))),
+            "mall_flushed": line(n, mix["bytes"].numel(),
+                                 median(event_times(torch, call, reps, before=flush)))}
+    del out
+    return res
+
+
+def bench_uniform(torch, vbyte, workloads, flush, tuning, reps=30):
+    """The small case: plain decode of 2^20 values with uniform code
+    lengths 1..5 (3.1 MB in, 4.2 MB out), with the MALL flushed before each
+    call and back to back (input and output then in the MALL)."""
+    import numpy as np
+    x, _ = workloads.uniform_lengths(n=N_UNIFORM)
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    enc = vbyte.encode(xd)
+    out = torch.empty(x.size, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def call():
+        vbyte.decode(enc, x.size, out=out, status=st, check=False, tuning=tuning)
+
+    call()
+    torch.cuda.synchronize()
+    if int(st.item()) != 0 or not torch.equal(out, xd):
+        raise RuntimeError("uniform-length decode differs from the drawn values")
+    cold = event_times(torch, call, reps, before=flush)
+    warm = event_times(torch, call, reps)
+    return {"workload": "plain decode of 2^20 values, code length uniform in 1..5",
+            "n": int(x.size), "bytes_in": int(enc.numel()), "tuning": dict(HEADLINE_TUNING),
+            "mall_flushed": line(x.size, enc.numel(), median(cold)),
+            "mall_flushed_min_ms": round(min(cold), 4),
+            "back_to_back": line(x.size, enc.numel(), median(warm))}
+
+
+def bench_config2(torch, vbyte, streams, flush, tuning, reps=10):
+    """Differential decode of the two 64Mi-gap streams (gap means 8 and 300),
+    each call timed alone, back to back and with the MALL flushed."""
+    rows = []
+    for s in streams:
+        def call():
+            vbyte.decode(s["bytes"], N_STREAM, delta=True, prev=0, out=s["out"], status=s["status"],
+                         check=False, tuning=tuning)
+        call()
+        torch.cuda.synchronize()
+        verify(torch, [s])
+        warm = median(event_times(torch, call, reps))
+        cold = median(event_times(torch, call, reps, before=flush))
+        rows.append({"gap_mean": s["mean"], "n": N_STREAM, "bytes_in": int(s["bytes"].numel()),
+                     "back_to_back": line(N_STREAM, s["bytes"].numel(), warm),
+                     "mall_flushed": line(N_STREAM, s["bytes"].numel(), cold)})
+    return {"workload": "differential decode of two single streams of 64Mi uint32 gaps "
+                        "(geometric, means 8 and 300)", "tuning": dict(HEADLINE_TUNING),
+            "streams": rows}
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-trace":
         o = summarize_trace(sys.argv[2], sys.argv[3], PROFILE_TRACE, sys.argv[4])
@@ -638,19 +893,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline decode only (profiling runs): no side lines, no "
+                         "CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the config-3 batched comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the config-4 serving run")
     ap.add_argument("--no-decode64", action="store_true", help="skip the 64-bit decode line")
     ap.add_argument("--no-delta4", action="store_true", help="skip the blocks-of-four decode line")
     ap.add_argument("--no-intersect", action="store_true", help="skip the intersection line")
-    ap.add_argument("--autotune", action="store_true",
-                    help="autotune each stream's tiling first instead of using the library's "
-                         "default (two passes, 2 segments x 8 wavefronts)")
-    ap.add_argument("--tuning", default=None,
-                    help="SEGS,WAVES,CHUNK (both streams) or SEGS,WAVES,CHUNK/SEGS,WAVES,CHUNK "
-                         "(gap-mean-8 stream / gap-mean-300 stream): use this tiling and "
-                         "single-stream kernel instead of autotuning (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 256 MiB (int32 tensor copy) before the "
                          "steps, as the reference kernel for scaling HBM byte counters")
@@ -666,9 +916,25 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     vbyte._lib()
-    streams = make_streams(torch, vbyte, workloads)
-    alg_bytes = [s["bytes"].numel() + 4 * N_STREAM for s in streams]
+    info = device_info(torch)
+    log(f"device: {info}")
+    mix = make_mix(torch, vbyte, workloads)
+    n = N_MIX
+    nbytes = int(mix["bytes"].numel())
+    alg = nbytes + 4 * n
+    tuning = vbyte.make_tuning(**HEADLINE_TUNING)
     stream = torch.cuda.current_stream()
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def call():
+        vbyte.decode(mix["bytes"], n, out=out, status=status, check=False, tuning=tuning)
+
+    def verify_mix():
+        if int(status.item()) != 0:
+            raise RuntimeError(f"decode status {int(status.item())}")
+        if not torch.equal(out, mix["x_dev"]):
+            raise RuntimeError("decoded values differ from the drawn values")
 
     if args.calibrate_copy:
         a = torch.arange(COPY_ELEMS, dtype=torch.int32, device="cuda")
@@ -678,65 +944,31 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    # the tiling of each stream picked by the library's autotuner (untimed)
-    tunings = []
-    fixed = args.tuning.split("/") if args.tuning else []
-    for i, s in enumerate(streams):
-        if fixed:
-            sg, wv, ch = (int(x) for x in fixed[min(i, len(fixed) - 1)].split(","))
-            vbyte.set_tuning(sg, wv, 0, tiles_per_chunk=ch)
-        elif args.autotune:
-            vbyte.autotune_decode(s["bytes"], N_STREAM, delta=True, out=s["out"], reps=3)
-        tunings.append(vbyte.get_tuning())
-        log(f"stream mean {s['mean']}: tuning {tunings[-1]}")
-
-    def decode_call(i):
-        s = streams[i]
-        vbyte.set_tuning(**tunings[i])
-        vbyte.decode(s["bytes"], N_STREAM, delta=True, prev=0, out=s["out"],
-                     status=s["status"], check=False)
-
-    def step(events=None):
-        for i in range(len(streams)):
-            if events is not None:
-                events[i][0].record(stream)
-            decode_call(i)
-            if events is not None:
-                events[i][1].record(stream)
-
     for _ in range(args.warmup):
-        step()
+        call()
     torch.cuda.synchronize()
-    verify(torch, streams)
+    verify_mix()
+    out.fill_(0)
+    torch.cuda.synchronize()
 
-    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-            for _ in streams] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+           for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        evs[k][0].record(stream)
+        call()
+        evs[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    verify(torch, streams)
+    verify_mix()
 
-    kernel_ms = [[evs[k][i][0].elapsed_time(evs[k][i][1]) for k in range(args.steps)]
-                 for i in range(len(streams))]
-    avg_ms = [sum(v) / len(v) for v in kernel_ms]
+    kernel_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    avg_ms = sum(kernel_ms) / len(kernel_ms)
     ms_per_step = wall * 1e3 / args.steps
-    ints_per_step = N_STREAM * len(streams)
-    value = ints_per_step / (ms_per_step / 1e3) / 1e9
-    achieved = sum(alg_bytes) / (sum(avg_ms) / 1e3) / 1e9   # GB/s over both launches
-    per_stream = []
-    for i, s in enumerate(streams):
-        per_stream.append({
-            "gap_mean": s["mean"], "n": N_STREAM, "bytes_in": int(s["bytes"].numel()),
-            "tuning": tunings[i],
-            "kernel_ms": round(avg_ms[i], 4),
-            "gints_per_s": round(N_STREAM / (avg_ms[i] / 1e3) / 1e9, 2),
-            "alg_gbps": round(alg_bytes[i] / (avg_ms[i] / 1e3) / 1e9, 1),
-            "pct_hbm_peak": round(100 * alg_bytes[i] / (avg_ms[i] / 1e3) / 1e9 / HBM_PEAK_GBPS, 1),
-        })
-    traffic = measured_traffic(alg_bytes)
+    value = n / (ms_per_step / 1e3) / 1e9
+    achieved = alg / (avg_ms / 1e3) / 1e9
+    traffic = measured_traffic([alg])
     if traffic is not None:
         traffic = round(traffic)
     res = {
@@ -752,21 +984,43 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "differential VByte decode of two single streams of 64Mi uint32 "
-                               "gaps each (geometric gaps, mean 8 and mean 300), wrapping prefix sum",
-                   "n_per_stream": N_STREAM, "streams": 2, "gap_means": [8, 300],
-                   "tuning": tunings},
+        "config": {"workload": "plain single-stream VByte decode of 2^30 uint32 values, 5 % 5-byte "
+                               "codes >= 2^28, else 50/50 1-byte and 2-byte codes (1.80 GB in, "
+                               "4 GiB out)",
+                   "n": n, "bytes_in": nbytes, "tuning": dict(HEADLINE_TUNING)},
+        "device": info,
+        "kernel_ms": {"avg": round(avg_ms, 4), "min": round(min(kernel_ms), 4),
+                      "max": round(max(kernel_ms), 4)},
         "hbm_gbps": round(achieved, 1),
         "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBPS, 2),
-        "streams": per_stream,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic,
-                     "kernel": "the whole decode call of each stream, all its launches: "
-                               + "; ".join(f"mean {s['mean']}: {describe_tuning(t)}"
-                                           for s, t in zip(streams, tunings)),
-                     "alg_bytes_per_launch": alg_bytes},
+                     "kernel": "the whole decode call, all its launches: " + describe_tuning(
+                         {"tiles_per_chunk": HEADLINE_TUNING["schedule"],
+                          "segs_per_wave": HEADLINE_TUNING["segs_per_wave"],
+                          "waves_per_block": HEADLINE_TUNING["waves_per_block"]}),
+                     "alg_bytes_per_launch": alg},
     }
+    if args.only_headline:
+        print(json.dumps(res), flush=True)
+        return
+    flush = Flusher(torch)
+    cold = event_times(torch, call, 10, before=flush)
+    res["headline_mall_flushed"] = line(n, nbytes, median(cold))
+    del out
+    log("differential decode of the mix ...")
+    res["config5_delta"] = bench_mix_delta(torch, vbyte, mix, flush, tuning)
+    log("one-read schedule ...")
+    res["one_read"] = bench_one_read(torch, vbyte, mix, flush)
+    log("uniform-length stream ...")
+    res["config1_plain"] = bench_uniform(torch, vbyte, workloads, flush, tuning)
+    mix_host = (mix["bytes"].cpu().numpy(), mix["x"])
+    del mix
+    torch.cuda.empty_cache()
+    streams = make_streams(torch, vbyte, workloads)
+    log("64Mi-gap streams ...")
+    res["config2_delta"] = bench_config2(torch, vbyte, streams, flush, tuning)
     if not args.no_decode64:
         log("64-bit decode ...")
         res["decode64"] = bench_decode64(torch, vbyte, streams)
@@ -776,6 +1030,8 @@ def main():
     if not args.no_intersect:
         log("intersection by pieces ...")
         res["intersect"] = bench_intersect(torch, vbyte, streams)
+    del streams
+    torch.cuda.empty_cache()
     if not (args.no_batched and args.no_serving):
         from paper_1503_07387_amd import serve
         idx = build_index(torch, vbyte, workloads)
@@ -788,7 +1044,7 @@ def main():
         del idx
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        res["cpu_baseline"] = cpu_baseline(streams, args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline(*mix_host)
     print(json.dumps(res), flush=True)
 
 

@@ -149,12 +149,19 @@ def worst_case_mix_chunk(chunk_index, chunk=MIX_CHUNK, seed=SEED_MIX):
     return vals
 
 
-def worst_case_mix(n=1 << 30, seed=SEED_MIX):
-    """The full mix as one uint32 array (chunked draws, see module doc)."""
+def worst_case_mix(n=1 << 30, seed=SEED_MIX, workers=8):
+    """The full mix as one uint32 array (chunked draws, see module doc).
+    Chunks are drawn by `workers` threads (numpy releases the GIL while it
+    draws); the result does not depend on their number."""
+    from concurrent.futures import ThreadPoolExecutor
     out = np.empty(n, dtype=np.uint32)
     nchunks = (n + MIX_CHUNK - 1) // MIX_CHUNK
-    for c in range(nchunks):
+
+    def fill(c):
         a = c * MIX_CHUNK
         b = min(n, a + MIX_CHUNK)
         out[a:b] = worst_case_mix_chunk(c, seed=seed)[: b - a]
+
+    with ThreadPoolExecutor(max(1, int(workers))) as ex:
+        list(ex.map(fill, range(nchunks)))
     return out

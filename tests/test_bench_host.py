@@ -73,7 +73,7 @@ def test_counter_summary_scales_by_the_copy_and_groups_calls(tmp_path):
     write_pmc(fcsv, "FETCH_SIZE", fetch)
     write_pmc(wcsv, "WRITE_SIZE", write)
     out = bench.summarize_pmc(str(fcsv), str(wcsv), str(tmp_path / "c.json"), str(tmp_path / "c.md"),
-                              ["cmd-f", "cmd-w"])
+                              ["cmd-f", "cmd-w"], kinds=("gap mean 8", "gap mean 300"))
     assert abs(out["fetch_factor"] - 2.0) < 1e-12 and abs(out["write_factor"] - 1.0) < 1e-12
     kib = 1024.0
     p8, p300 = out["per_stream"]
@@ -84,3 +84,27 @@ def test_counter_summary_scales_by_the_copy_and_groups_calls(tmp_path):
     assert out["kernel_source_sha256_16"] == bench.kernel_source_hash()
     assert json.load(open(tmp_path / "c.json"))["commands"] == ["cmd-f", "cmd-w"]
     assert "cmd-f" in open(tmp_path / "c.md").read()
+    # one kind: every call alike, averaged over all four
+    one = bench.summarize_pmc(str(fcsv), str(wcsv), str(tmp_path / "d.json"), str(tmp_path / "d.md"),
+                              ["cmd"])
+    assert len(one["per_stream"]) == 1 and one["per_stream"][0]["calls"] == 4
+    assert abs(one["per_stream"][0]["write_bytes"] - kib * 151) < 1e-6
+
+
+def test_shards_cut_at_code_boundaries():
+    import numpy as np
+    import oracle
+    x = np.random.default_rng(3).integers(0, 1 << 32, 5000, dtype=np.uint64).astype(np.uint32)
+    x[::3] &= 0x7F
+    b = oracle.encode(x)
+    for parts in (1, 2, 7, 64):
+        cuts = bench.shard_starts(b, parts)
+        assert cuts[0] == 0 and cuts[-1] == b.size and (np.diff(cuts) >= 0).all()
+        got = []
+        for k in range(parts):
+            sh = b[cuts[k]:cuts[k + 1]]
+            assert sh.size == 0 or (sh[-1] < 0x80 and (k == 0 or b[cuts[k] - 1] < 0x80))
+            st, y = oracle.decode(sh, oracle.count(sh))
+            assert st == oracle.OK
+            got.append(y)
+        assert np.array_equal(np.concatenate(got), x)
