@@ -142,6 +142,23 @@ vbyte_status vbyte_decode_ex(const uint8_t *bytes, size_t nbytes, uint32_t *out,
 /* Fills *t with the current process-wide defaults. */
 void vbyte_tuning_default(vbyte_tuning *t);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * decode of vbyte_decode_ex (mode 0 plain, 1 differential, 2 differences
+ * minus one) with the two-pass schedule at the default tiling (2 segments x
+ * 8 wavefronts), whose tile slots live in a fixed device array of 4 MiB per
+ * GPU inside the library instead of the per-stream workspace.  It calls no
+ * hipMalloc, hipFree or other allocating routine.  Limit: 262,144 tiles of
+ * 16 KiB, i.e. nbytes (plus the misalignment of `bytes`, 0..15) at most
+ * 4 GiB; larger streams get VBYTE_EINVAL (with vbyte_last_error saying so)
+ * before anything is enqueued.  Every call on a GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must be serialised by the caller; calls on one stream are ordered.
+ * The array needs no initialisation (every slot a call reads it writes
+ * first).  Asynchronous: data errors land in d_status (required). */
+vbyte_status vbyte_decode_noalloc(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                  uint32_t prev, int mode, int32_t *d_status, void *stream);
+
 /* Differences minus one (section 1, "Differential coding": with no repeated
  * value, every difference after the first is coded less one, x_1 - 0,
  * x_2 - x_1 - 1, ...): out[0] = prev + g_0 and out[i] = out[i-1] + g_i + 1

@@ -442,6 +442,42 @@ vbyte_status vbyte_decode_ex(const uint8_t *bytes, size_t nbytes, uint32_t *out,
                          tuning);
 }
 
+vbyte_status vbyte_decode_noalloc(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
+                                  uint32_t prev, int mode, int32_t *d_status, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (mode < 0 || mode > 2 || !d_status || ((uintptr_t)d_status & 3u) != 0) return VBYTE_EINVAL;
+    if (nbytes >= kMaxBytes || (nbytes > 0 && !bytes) || (n > 0 && !out)) return VBYTE_EINVAL;
+    if (((uintptr_t)out & 3u) != 0) return VBYTE_EINVAL;
+    StreamArgs a{};
+    a.vstart = (uintptr_t)bytes & 15u;
+    a.base = bytes - a.vstart;
+    a.vend = a.vstart + nbytes;
+    a.out = out;
+    a.n = n;
+    a.prev = prev;
+    const uint64_t ntiles = nbytes ? stream_tiles(a.vstart, nbytes, kNoAllocSegs, kNoAllocWaves) : 0;
+    if (ntiles * sizeof(Desc) > kNoAllocScratchBytes) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "vbyte_decode_noalloc: %zu bytes need %llu tile slots, more than the %zu the "
+                      "scratch array holds",
+                      nbytes, (unsigned long long)ntiles, kNoAllocScratchBytes / sizeof(Desc));
+        return VBYTE_EINVAL;
+    }
+    if (nbytes == 0) {
+        hipError_t e = launch_set_status(d_status, n == 0 ? VBYTE_OK : VBYTE_ETRUNC, s);
+        return e == hipSuccess ? VBYTE_OK : hip_fail(e, "set status");
+    }
+    void *scr = nullptr;
+    hipError_t e = noalloc_scratch(&scr);
+    if (e != hipSuccess) return hip_fail(e, "scratch symbol address");
+    a.ntiles = (uint32_t)ntiles;
+    a.desc = (Desc *)scr;
+    a.hdr = nullptr;
+    a.d_status = d_status;
+    e = launch_two_pass(a, mode, kNoAllocSegs, kNoAllocWaves, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "decode launch");
+}
+
 void vbyte_tuning_default(vbyte_tuning *t) {
     if (t) *t = default_tuning();
 }

@@ -45,6 +45,7 @@
 //    needed between tiles on different XCDs.
 
 #include <atomic>
+#include <mutex>
 
 #include "vbyte_internal.h"
 #include "vbyte.h"
@@ -3436,6 +3437,32 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
     if (blocks > 4096) blocks = 4096;
     k_zero<<<(unsigned)blocks, 256, 0, s>>>((uint4 *)p, n16);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ allocation-free decode
+// The tile slots of vbyte_decode_noalloc, one copy per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not a
+// device address: host code uses only the address hipGetSymbolAddress
+// returns for the current device, taken once per device below.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void **ptr) {
+    static std::mutex mu;
+    static void *addr[kNoAllocMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace vb

@@ -217,6 +217,16 @@ hipError_t launch_encode(const EncodeArgs &a, hipStream_t s);
 hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
                                 uint64_t nb, hipStream_t s);
 hipError_t launch_set_status(int32_t *d_status, int32_t value, hipStream_t s);
+
+// Allocation-free decode (vbyte_decode_noalloc): the two-pass schedule at
+// the default tiling with its tile slots (16 bytes each) in a file-scope
+// device array of kNoAllocScratchBytes per GPU.  noalloc_scratch returns
+// that array's address on the current device (hipGetSymbolAddress, taken
+// once per device and kept).
+constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+constexpr int kNoAllocSegs = 2, kNoAllocWaves = 8;
+hipError_t noalloc_scratch(void **ptr);
 hipError_t launch_set_u64(uint64_t *p, uint64_t value, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t value, hipStream_t s);

@@ -34,7 +34,7 @@ EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_server_run", "vbyte_batch_graph_create", "vbyte_batch_graph_launch",
            "vbyte_batch_graph_destroy", "vbyte_autotune_decode", "vbyte_autotune_batch",
            "vbyte_set_chunk_tiles", "vbyte_get_chunk_tiles", "vbyte_set_flow_grid",
-           "vbyte_decode_ex", "vbyte_tuning_default",
+           "vbyte_decode_ex", "vbyte_tuning_default", "vbyte_decode_noalloc",
            "vbyte_workspace_size", "vbyte_set_tuning", "vbyte_get_tuning",
            "vbyte_status_str", "vbyte_last_error"]
 
@@ -128,6 +128,7 @@ def _declare(lib):
         "vbyte_set_chunk_tiles": [i32],
         "vbyte_set_flow_grid": [i32],
         "vbyte_decode_ex": [vp, sz, vp, sz, u32, i32, vp, vp, vp],
+        "vbyte_decode_noalloc": [vp, sz, vp, sz, u32, i32, vp, vp],
         "vbyte_batch_graph_create": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, c.POINTER(vp)],
         "vbyte_batch_graph_launch": [vp, vp],
         "vbyte_autotune_decode": [vp, sz, vp, sz, i32, i32, vp, c.POINTER(TunePoint), sz,
@@ -235,6 +236,24 @@ def decode(data, n, *, delta=False, minus_one=False, prev=0, out=None, status=No
         v = int(status.item())
         if v != OK:
             raise VByteError(v, "decode")
+    return out[:n]
+
+
+@_on_stream
+def decode_noalloc(data, n, out, status, *, delta=False, minus_one=False, prev=0, stream=None):
+    """vbyte_decode_noalloc: decode into the caller's `out` (int32, at least
+    n elements) with the status in `status` (int32 CUDA tensor of one
+    element), allocating nothing; asynchronous.  Raises VByteError for
+    argument errors (a stream beyond the library's fixed scratch array)."""
+    _dev_u8(data)
+    n = int(n)
+    if out.dtype != torch.int32 or out.numel() < n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of at least n elements")
+    if status.dtype != torch.int32 or status.numel() < 1:
+        raise ValueError("status must be an int32 tensor of one element")
+    st = _lib().vbyte_decode_noalloc(_ptr(data), data.numel(), _ptr(out), n, int(prev) & 0xFFFFFFFF,
+                                     _mode(delta, minus_one), _ptr(status), _stream(stream))
+    _check_call(st, "decode_noalloc")
     return out[:n]
 
 
