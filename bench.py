@@ -185,7 +185,7 @@ def cpu_baseline(b, x, reps=5):
 # Kernels of one single-stream decode call: the look-back kernel alone, the
 # chunked kernel alone, or the two-pass sequence (tile sums, scan, decode);
 # a call ends with its last kernel.
-DECODE_KERNELS = ("k_stream<", "k_chunks<", "k_tile_agg<", "k_tile_scan", "k_known<")
+DECODE_KERNELS = ("k_stream<", "k_chunks<", "k_tile_agg<", "k_tile_block", "k_known<")
 CALL_END_KERNELS = ("k_stream<", "k_chunks<", "k_known<")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
@@ -211,7 +211,8 @@ def group_calls(rows, value):
 
 def describe_tuning(t):
     c = t.get("tiles_per_chunk", 0)
-    mode = ("two-pass: k_tile_agg + k_tile_scan + k_known" if c < 0 else
+    mode = ("two-pass: k_tile_agg + k_tile_block_sums + k_tile_block_scan + k_known" if c == -1 else
+            "one read: k_flow" if c == -2 else
             "look-back: k_stream" if c == 0 else f"chunks of {c} tiles: k_chunks")
     return f"{mode} (segs {t['segs_per_wave']}, waves {t['waves_per_block']})"
 

@@ -148,9 +148,10 @@ void vbyte_tuning_default(vbyte_tuning *t);
  * minus one) with the two-pass schedule at the default tiling (2 segments x
  * 8 wavefronts), whose tile slots live in a fixed device array of 4 MiB per
  * GPU inside the library instead of the per-stream workspace.  It calls no
- * hipMalloc, hipFree or other allocating routine.  Limit: 262,144 tiles of
- * 16 KiB, i.e. nbytes (plus the misalignment of `bytes`, 0..15) at most
- * 4 GiB; larger streams get VBYTE_EINVAL (with vbyte_last_error saying so)
+ * hipMalloc, hipFree or other allocating routine.  Limit: 262,016 tiles of
+ * 16 KiB (one 16-byte slot per tile plus one per 2048 tiles), i.e. nbytes
+ * (plus the misalignment of `bytes`, 0..15) just under 4 GiB (4,292,870,144
+ * bytes); larger streams get VBYTE_EINVAL (with vbyte_last_error saying so)
  * before anything is enqueued.  Every call on a GPU shares that GPU's array:
  * calls that overlap in time on one GPU (other streams, other threads) race
  * and must be serialised by the caller; calls on one stream are ordered.
@@ -432,10 +433,11 @@ void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_l
  * reads every input byte once (see vbyte_tuning); its waits are bounded (an
  * aggregate not published in time is computed from the bytes by the
  * reader), so it needs neither a ticket nor co-resident workgroups.
- * -1 (the default) decodes in three launches with no look-back:
- * every tile's terminator count and byte sum, a scan of them in one
- * workgroup, then every tile with its prefix known (the input is read
- * twice; no workgroup ever waits for another); 0 gives every tile its own
+ * -1 (the default) decodes in two passes, four launches, with no
+ * look-back: every tile's terminator count and byte sum, a scan of them
+ * (block totals, then every block of 2048 tiles from the totals before it),
+ * then every tile with its prefix known (the input is read twice; no
+ * workgroup ever waits for another); 0 gives every tile its own
  * look-back; k in 1..64 gives each workgroup a chunk of k consecutive
  * tiles, which it first reads for their counts and sums, then looks back
  * once for the chunk, then reads again and decodes.  The look-back kernels

@@ -27,7 +27,7 @@ thread_local char g_last_error[256] = "";
 std::atomic<int> g_segs{2};
 std::atomic<int> g_wpb{8};
 std::atomic<int64_t> g_small{16384};
-std::atomic<int> g_chunk{-1};  // single stream: -1 = three launches with no look-back (default),
+std::atomic<int> g_chunk{-1};  // single stream: -1 = two passes, four launches, no look-back (default),
                                // -2 = one launch reading the input once,
                                // 0 = per-tile look-back, k = chunks of k tiles
 std::atomic<int> g_flow_grid{0};   // workgroups of the one-launch decode (0: per CU count)
@@ -201,7 +201,7 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
     a.ntiles = (uint32_t)ntiles;
     const int chunk = tun.schedule;
     const uint64_t nchunks = chunk > 0 ? (ntiles + chunk - 1) / chunk : 0;
-    const uint64_t ndesc = chunk > 0 ? nchunks : ntiles;
+    const uint64_t ndesc = chunk > 0 ? nchunks : chunk == -1 ? two_pass_slots(ntiles) : ntiles;
     Workspace *w = nullptr;
     vbyte_status st = get_ws(s, kHeaderBytes + ndesc * sizeof(Desc), ntiles ? 1 : 0, &w);
     if (st != VBYTE_OK) return st;
@@ -456,7 +456,7 @@ vbyte_status vbyte_decode_noalloc(const uint8_t *bytes, size_t nbytes, uint32_t 
     a.n = n;
     a.prev = prev;
     const uint64_t ntiles = nbytes ? stream_tiles(a.vstart, nbytes, kNoAllocSegs, kNoAllocWaves) : 0;
-    if (ntiles * sizeof(Desc) > kNoAllocScratchBytes) {
+    if (two_pass_slots(ntiles) * sizeof(Desc) > kNoAllocScratchBytes) {
         std::snprintf(g_last_error, sizeof g_last_error,
                       "vbyte_decode_noalloc: %zu bytes need %llu tile slots, more than the %zu the "
                       "scratch array holds",
@@ -785,7 +785,7 @@ size_t vbyte_workspace_size(size_t nbytes) {
     // 64-bit decode's unit and group slots (16 bytes), the blocks-of-four
     // decode's unit, group and block slots (32 bytes; a block holds at least
     // one unit)
-    const uint64_t d32 = stream_tiles(15, nbytes, g_segs.load(), 1) * sizeof(Desc);
+    const uint64_t d32 = two_pass_slots(stream_tiles(15, nbytes, g_segs.load(), 1)) * sizeof(Desc);
     const uint64_t unit = (uint64_t)kUnit64Groups * std::min(g_segs.load(), 2) * kSegBytes;
     const uint64_t nunits = (15 + nbytes + unit - 1) / unit;
     const uint64_t d64 = nunits * 16 * (1 + kUnit64Groups);

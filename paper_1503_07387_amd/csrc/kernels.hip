@@ -531,7 +531,7 @@ __device__ __forceinline__ void store_dense(const u32 *stage, u32 amis, u32 *out
 // [start, x) of the stream, that byte sum counts every code that begins
 // before x except the bytes at or after x of the code that straddles x, and
 // the terminators before x count the codes that end before x.  k_tile_agg
-// produces both per tile, k_tile_scan adds them up, and the tile at x adds
+// produces both per tile, the block scans add them up, and the tile at x adds
 // the straddling code from its own first bytes (straddle()).
 //
 // seg_bytes adds a lane's 16 bytes w (with the 4 bytes before them in
@@ -1083,10 +1083,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
 }
 
 // ------------------------------------------------------------ two passes
-// Single stream in three launches with no look-back: k_tile_agg stores every
+// Single stream in four launches with no look-back: k_tile_agg stores every
 // tile's number of terminators, byte sum (seg_bytes) and malformed flag in
-// its descriptor slot, k_tile_scan (one workgroup) turns them into
-// exclusive prefixes in place and writes the status (the number of integers
+// its descriptor slot, k_tile_block_sums and k_tile_block_scan turn them
+// into exclusive prefixes in place (block totals, then every block scanned
+// from the totals before it) and write the status (the number of integers
 // of a stream is its number of terminators), and k_known decodes every tile
 // with that prefix plus the code that straddles the tile's start.  The
 // slots hold plain values with bits 63:38 clear, which no tagged descriptor
@@ -1164,16 +1165,16 @@ constexpr int kScanPer = 8;   // slots per lane per round
 __device__ __forceinline__ u32 scan_rows(u64 left) {
     return left >= (u64)kScanBlock * kScanPer ? (u32)kScanPer : (u32)((left + kScanBlock - 1) / kScanBlock);
 }
-__global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
+// Exclusive prefixes, in place, of the tile slots [i_begin, i_end), from
+// the carry (count, sum, malformed) before i_begin; the carry leaves with
+// the totals through i_end.  One workgroup of kScanBlock threads.
+__device__ __forceinline__ void scan_span(const StreamArgs &a, u64 i_begin, u64 i_end, u64 &carry_c,
+                                          u32 &carry_s, bool &carry_m) {
     __shared__ u32 wc[kScanBlock / kWave], ws[kScanBlock / kWave], wm[kScanBlock / kWave];
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
-    const u8 lastb = a.base[a.vend - 1];   // one address for all: in flight with the first slots
-    const u64 lastt = a.ntiles - 1;        // ntiles >= 1
-    u64 carry_c = 0;
-    u32 carry_s = a.prev;
-    bool carry_m = false;
-    for (u64 b0 = 0, rows = 0; b0 < a.ntiles; b0 += (u64)kScanBlock * rows) {
-        rows = scan_rows(a.ntiles - b0);
+    const u64 last = i_end - 1;   // i_end > i_begin
+    for (u64 b0 = i_begin, rows = 0; b0 < i_end; b0 += (u64)kScanBlock * rows) {
+        rows = scan_rows(i_end - b0);
         const u64 i0 = b0 + (u64)wib * (kWave * rows) + ln;
         // every load issued before the first use: indexes past the end read
         // the last slot and count as zero
@@ -1181,7 +1182,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
             const u64 i = i0 + (u64)q * kWave;
-            d[q] = a.desc[i < lastt ? i : lastt];
+            d[q] = a.desc[i < last ? i : last];
         }
         u32 pc[kScanPer], ps[kScanPer];
         u32 rc = 0, rs = 0;   // the wavefront's running totals (64 x 8 tiles fit 32 bits)
@@ -1189,7 +1190,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
             if ((u32)q >= rows) break;
-            const bool in = i0 + (u64)q * kWave < a.ntiles;
+            const bool in = i0 + (u64)q * kWave < i_end;
             const u32 c = in ? (u32)(d[q].c & kCountMask) : 0u;   // at most the tile's bytes
             const u32 sm = in ? (u32)d[q].s : 0u;
             m |= in && ((d[q].c >> 37) & 1u) != 0;
@@ -1220,14 +1221,102 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(StreamArgs a) {
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
             const u64 i = i0 + (u64)q * kWave;
-            if ((u32)q < rows && i < a.ntiles) {
+            if ((u32)q < rows && i < i_end) {
                 a.desc[i].c = oc + pc[q];
                 a.desc[i].s = os + ps[q];
             }
         }
         __syncthreads();   // wc, ws and wm are rewritten by the next round
     }
-    if (tid == 0) *a.d_status = final_status(carry_m, lastb, carry_c, a.n);
+}
+
+// The scan of the tile slots over many workgroups, in two launches:
+// k_tile_block_sums writes the totals of every block of kScanSpan slots
+// (count with the malformed flag in bit 37, sum) to bsum; k_tile_block_scan
+// gives each block its carry from the totals before it and scans the block
+// in place; the block holding the last tile writes the stream's status.
+constexpr u64 kScanSpan = kTwoPassScanSpan;   // tile slots per scan workgroup
+static_assert(kScanSpan == 2 * kScanBlock, "two slots per thread");
+
+__global__ __launch_bounds__(kScanBlock) void k_tile_block_sums(StreamArgs a, Desc *bsum) {
+    __shared__ u64 bc[kScanBlock / kWave];
+    __shared__ u32 bs[kScanBlock / kWave], bm[kScanBlock / kWave];
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u64 i0 = (u64)blockIdx.x * kScanSpan;
+    const u64 i1 = i0 + kScanSpan < a.ntiles ? i0 + kScanSpan : a.ntiles;
+    u64 c = 0;
+    u32 sm = 0;
+    bool m = false;
+    for (u64 i = i0 + tid; i < i1; i += kScanBlock) {
+        const Desc d = a.desc[i];
+        c += d.c & kCountMask;
+        sm += (u32)d.s;
+        m |= ((d.c >> 37) & 1u) != 0;
+    }
+    const u32 clo = wave_sum((u32)c);   // a span's count fits 32 bits
+    sm = wave_sum(sm);
+    const bool wm = ballot(m) != 0;
+    if (ln == 0) {
+        bc[wib] = clo;
+        bs[wib] = sm;
+        bm[wib] = wm ? 1u : 0u;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        u64 tc = 0;
+        u32 ts = 0, tm = 0;
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
+            tc += bc[k];
+            ts += bs[k];
+            tm |= bm[k];
+        }
+        bsum[blockIdx.x].c = tc | ((u64)tm << 37);
+        bsum[blockIdx.x].s = ts;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_tile_block_scan(StreamArgs a, const Desc *bsum) {
+    __shared__ u64 pc_sh;
+    __shared__ u32 ps_sh, pm_sh, all_m_sh;
+    const u32 tid = threadIdx.x, ln = lane_id();
+    const u32 b = blockIdx.x, nb = gridDim.x;
+    const u8 lastb = a.base[a.vend - 1];
+    if (tid < kWave) {
+        // the carry: totals of the blocks before this one (and the
+        // malformed flag of all blocks, for the last block's status)
+        u64 c = 0;
+        u32 sm = 0;
+        bool m = false, mall = false;
+        for (u32 k = ln; k < nb; k += kWave) {
+            const Desc d = bsum[k];
+            const bool mk = ((d.c >> 37) & 1u) != 0;
+            mall |= mk;
+            if (k < b) {
+                c += d.c & kCountMask;
+                sm += (u32)d.s;
+                m |= mk;
+            }
+        }
+        // 64-bit lane counts summed as 24 low bits and the rest (each part
+        // fits 32 bits over 64 lanes for counts below 2^56)
+        const u32 clo = wave_sum((u32)c & 0xFFFFFFu), chi = wave_sum((u32)(c >> 24));
+        sm = wave_sum(sm);
+        const bool bmal = ballot(m) != 0, amal = ballot(mall) != 0;
+        if (tid == 0) {
+            pc_sh = ((u64)chi << 24) + clo;
+            ps_sh = a.prev + sm;
+            pm_sh = bmal ? 1u : 0u;
+            all_m_sh = amal ? 1u : 0u;
+        }
+    }
+    __syncthreads();
+    u64 carry_c = pc_sh;
+    u32 carry_s = ps_sh;
+    bool carry_m = pm_sh != 0;
+    const u64 i0 = (u64)b * kScanSpan;
+    const u64 i1 = i0 + kScanSpan < a.ntiles ? i0 + kScanSpan : a.ntiles;
+    scan_span(a, i0, i1, carry_c, carry_s, carry_m);
+    if (b == nb - 1 && tid == 0) *a.d_status = final_status(all_m_sh != 0, lastb, carry_c, a.n);
 }
 
 template <int D, int SEGS>
@@ -1860,7 +1949,7 @@ __global__ __launch_bounds__(kScanBlock) void k64_scan(Stream64Args a) {
     const u64 lastu = a.nunits - 1;        // nunits >= 1
     u64 carry_c = 0, carry_s = a.prev;
     bool carry_m = false;
-    // the layout of k_tile_scan: coalesced rows of 64 slots per wavefront
+    // the layout of scan_span: coalesced rows of 64 slots per wavefront
     for (u64 b0 = 0, rows = 0; b0 < a.nunits; b0 += (u64)kScanBlock * rows) {
         rows = scan_rows(a.nunits - b0);
         const u64 i0 = b0 + (u64)wib * (kWave * rows) + ln;
@@ -2394,7 +2483,7 @@ __global__ __launch_bounds__(kMaxBlock) void k4_agg(Stream4Args a) {
 }
 
 // Exclusive prefixes of the blocks in absolute classes, in the coalesced
-// layout of k_tile_scan.  Each round scans the counts first (plain sums); a
+// layout of scan_span.  Each round scans the counts first (plain sums); a
 // unit's class sums, rotated by the count of the codes before it, are then
 // in absolute classes, and four plain scans finish the round: the rotating
 // combination never enters a scan.
@@ -3254,7 +3343,13 @@ hipError_t launch_two_pass_t(const StreamArgs &a, int wpb, hipStream_t s) {
     k_tile_agg<D, SEGS><<<a.ntiles, wpb * kWave, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_tile_scan<<<1, kScanBlock, 0, s>>>(a);
+    // the block totals sit right after the tile slots
+    Desc *bsum = a.desc + a.ntiles;
+    const u32 nblocks = (u32)((a.ntiles + kScanSpan - 1) / kScanSpan);
+    k_tile_block_sums<<<nblocks, kScanBlock, 0, s>>>(a, bsum);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tile_block_scan<<<nblocks, kScanBlock, 0, s>>>(a, bsum);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);

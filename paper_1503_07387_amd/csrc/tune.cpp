@@ -5,7 +5,7 @@
 // events on the caller's stream, keeps the fastest and applies it with
 // vbyte_set_tuning / vbyte_set_chunk_tiles.  Candidates: 1 KiB segments per
 // wavefront {2, 4} x wavefronts per workgroup {4, 8} x single-stream kernel
-// {-1 (three launches), 0 (look-back per tile), chunks of 2, 4, 8, 16
+// {-1 (two passes), 0 (look-back per tile), chunks of 2, 4, 8, 16
 // tiles} for a single stream; for the batched form {2, 4} x
 // {4, 8} x small-list threshold {4, 16, 64, 256} KiB.  The
 // tuning is process-wide, so no other decode should run meanwhile.

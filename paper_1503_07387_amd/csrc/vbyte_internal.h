@@ -194,10 +194,16 @@ hipError_t launch_resume_finish(const uint8_t *bytes, const uint64_t *cursor_in,
 // descriptor per chunk).
 hipError_t launch_chunks(const StreamArgs &a, int delta, int segs, int wpb, uint32_t nchunks,
                          hipStream_t s);
-// Single-stream decode in three launches with no look-back (tile aggregates,
-// a one-workgroup scan that also writes the status, decode with the prefix
-// known); one descriptor slot per tile.
+// Single-stream decode in four launches with no look-back: tile aggregates,
+// block totals of the tile slots, a scan of every block from the totals
+// before it (the last block writes the status), decode with the prefix
+// known.  Slots: one per tile, then one per block of kTwoPassScanSpan tiles
+// (two_pass_slots).
 hipError_t launch_two_pass(const StreamArgs &a, int delta, int segs, int wpb, hipStream_t s);
+constexpr uint64_t kTwoPassScanSpan = 2048;
+inline uint64_t two_pass_slots(uint64_t ntiles) {
+    return ntiles + (ntiles + kTwoPassScanSpan - 1) / kTwoPassScanSpan;
+}
 // Single-stream decode in one launch of `grid` persistent workgroups (0: as
 // many as are resident at once on `cus` compute units; at most
 // kFlowMaxGrid), every input byte read once (k_flow); f.rounds is set here.

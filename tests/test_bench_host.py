@@ -56,7 +56,7 @@ def write_pmc(path, counter, rows):
 
 def test_counter_summary_scales_by_the_copy_and_groups_calls(tmp_path):
     copy_kib = bench.COPY_ELEMS * 4 / 1024
-    agg, scan, known = "void vb::k_tile_agg<1, 2>(x)", "vb::k_tile_scan(x)", "void vb::k_known<1, 2>(x)"
+    agg, scan, known = "void vb::k_tile_agg<1, 2>(x)", "vb::k_tile_block_scan(x)", "void vb::k_known<1, 2>(x)"
     other = "void at::native::elementwise_kernel(x)"
     # FETCH counts half the copy (factor 2); WRITE counts all of it (factor 1)
     fetch = [(bench.COPY_KERNEL, copy_kib / 2), (other, 999.0),
