@@ -112,3 +112,30 @@ def test_two_encodes():
         want = oracle.encode(x)
         assert int(nb.item()) == want.size
         assert np.array_equal(o[:want.size].cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("pair", [((4, 8, 0), (1, 2, -1)), ((2, 8, -1), (1, 4, 3)),
+                                  ((2, 7, -2), (4, 4, 0))])
+def test_per_call_tilings_on_two_streams(pair):
+    """vbyte_decode_ex with a different tiling and schedule on each of two
+    streams at once: each result bit-exact against the oracle, and the
+    process-wide defaults untouched."""
+    before = vbyte.get_tuning()
+    ins = []
+    for mean, (sg, wv, sch) in zip((8, 300), pair):
+        g = workloads.geometric_gaps(n=1 << 23, mean=mean)
+        b = oracle.encode(g)
+        ins.append((g, torch.from_numpy(b).cuda(), torch.empty(g.size, dtype=torch.int32, device="cuda"),
+                    torch.empty(1, dtype=torch.int32, device="cuda"), vbyte.make_tuning(sg, wv, sch)))
+
+    def call(i):
+        g, d, out, st, T = ins[i]
+        return lambda: vbyte.decode(d, g.size, delta=True, prev=i, out=out, status=st, check=False,
+                                    tuning=T)
+
+    two_streams([call(0), call(1)])
+    for i, (g, d, out, st, T) in enumerate(ins):
+        sto, ref = oracle.decode_delta(d.cpu().numpy(), g.size, i)
+        assert int(st.item()) == sto == oracle.OK
+        assert np.array_equal(u32(out), ref)
+    assert vbyte.get_tuning() == before

@@ -93,3 +93,42 @@ def test_admission_waits_for_pool_memory(index):
     lat2, stats2, _ = srv.run(np.zeros(2), big + [terms[0]], capture=False)
     srv.close()
     assert stats2["rejected"] == 1 and lat2[0] == -1.0 and lat2[1] > 0
+
+
+@pytest.fixture(scope="module")
+def config3():
+    """The batched workload's index: 100,000 Zipf-length lists (2^28
+    integers, the longest 4Mi), coded by the oracle."""
+    d = workloads.zipf_lists()
+    gaps, out_off = d["gaps"], d["out_off"]
+    b = oracle.encode(gaps)
+    nl = d["lengths"].size
+    byte_off = np.zeros(nl + 1, np.int64)
+    for i in range(nl):
+        byte_off[i + 1] = byte_off[i] + oracle.encoded_size(gaps[out_off[i]:out_off[i + 1]])
+    assert byte_off[-1] == b.size
+    return {"bytes": b, "byte_off": byte_off, "counts": d["lengths"].astype(np.int64),
+            "rank_of": d["rank_of"], "dev": torch.from_numpy(b).cuda()}
+
+
+def test_config3_alone_equals_in_mix(config3):
+    """Queries of 2-8 Zipf(1.0) terms over the config-3 index, rank r the
+    r-th longest list (so a quarter of the terms hit the 4Mi lists), served
+    at a rate above saturation: a request's result is the same alone and in
+    the mix, and equals the oracle's decode of its lists."""
+    nl = config3["counts"].size
+    pos_of_rank = np.argsort(config3["rank_of"])
+    arr, ranks = workloads.query_stream(240, 1e6, nlists=nl, seed=12)
+    terms = [pos_of_rank[r] for r in ranks]
+    assert sum(int((config3["counts"][t] == 1 << 22).any()) for t in terms) > 20
+    srv = serve.Server(config3["dev"], config3["byte_off"], config3["counts"], pool_bytes=3 << 30,
+                       nstreams=4, max_batch_requests=64)
+    _, stats, (mix, moff) = srv.run(arr, terms, capture=True)
+    assert stats["worst_status"] == vbyte.OK and stats["rejected"] == 0
+    assert stats["mean_batch_requests"] > 1.0
+    hm = u32(mix)
+    for r in (0, 3, 50, 121, 239):
+        _, _, (alone, aoff) = srv.run(np.zeros(1), [terms[r]], capture=True)
+        assert np.array_equal(u32(alone)[:aoff[1]], hm[moff[r]:moff[r + 1]]), r
+        assert np.array_equal(hm[moff[r]:moff[r + 1]], expected(config3, terms[r])), r
+    srv.close()
