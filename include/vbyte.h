@@ -69,7 +69,8 @@ typedef enum vbyte_status {
     VBYTE_ETRUNC = 3,      /* last byte >= 0x80 or fewer terminators than n */
     VBYTE_EMALFORMED = 4,  /* a run of >= 5 continuation bytes */
     VBYTE_EHIP = 5,        /* a HIP runtime call failed */
-    VBYTE_ENOMEM = 6       /* workspace allocation failed */
+    VBYTE_ENOMEM = 6,      /* workspace allocation failed */
+    VBYTE_ESTALLED = 7     /* a look-back gave up waiting (vbyte_set_spin_limit): output unreliable */
 } vbyte_status;
 
 /* ------------------------------------------------------------ single stream */
@@ -446,6 +447,21 @@ void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_l
  * VBYTE_EINVAL outside -2..64. */
 vbyte_status vbyte_set_chunk_tiles(int tiles_per_chunk);
 int vbyte_get_chunk_tiles(void);
+
+/* Bound of the look-back waits (the look-back, chunked and resumable-piece
+ * decodes, the batched decode and the encoder): a tile that has read its
+ * predecessors' descriptors `rounds` times without finding one ready gives
+ * up, and the call reports VBYTE_ESTALLED (its output is then unreliable;
+ * vbyte_count reports a count of UINT64_MAX) instead of waiting forever.
+ * The tickets that number the tiles make every wait end in practice; the
+ * bound guards against a lost predecessor.  0 restores the default
+ * (2^20 round trips, a second or more).  A status written by the last tile
+ * before a stall elsewhere was seen can still read VBYTE_OK only if the
+ * stalled tile's predecessor published in the instant between; the stalled
+ * tile then overwrites it with VBYTE_ESTALLED when it finishes.  Applies to
+ * calls enqueued afterwards; for testing the bound, a small value makes
+ * tiles give up quickly. */
+vbyte_status vbyte_set_spin_limit(uint32_t rounds);
 
 /* Workgroups of the one-launch decode (schedule -2) by default: 0 (the
  * default) gives 16 wavefronts per compute unit; at most 512.  Returns

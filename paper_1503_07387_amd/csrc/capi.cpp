@@ -31,6 +31,7 @@ std::atomic<int> g_chunk{-1};  // single stream: -1 = two passes, four launches,
                                // -2 = one launch reading the input once,
                                // 0 = per-tile look-back, k = chunks of k tiles
 std::atomic<int> g_flow_grid{0};   // workgroups of the one-launch decode (0: per CU count)
+std::atomic<uint32_t> g_spin_limit{kDefaultSpinLimit};
 
 vbyte_status hip_fail(hipError_t e, const char *what) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
@@ -190,6 +191,7 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
     if (!d_status && !slot) return VBYTE_EINVAL;
     const int segs = tun.segs_per_wave, wpb = tun.waves_per_block;
     StreamArgs a{};
+    a.spin_limit = spin_limit();
     a.vstart = (uintptr_t)bytes & 15u;
     a.base = bytes - a.vstart;
     a.vend = a.vstart + nbytes;
@@ -347,6 +349,8 @@ vbyte_status decode64_sync(const uint8_t *bytes, size_t nbytes, uint64_t *out, s
 
 }  // namespace
 
+uint32_t spin_limit() { return g_spin_limit.load(std::memory_order_relaxed); }
+
 vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan) {
     if (!a.list_status || ((uintptr_t)a.list_status & 3u)) return VBYTE_EINVAL;
     if (!a.bytes && a.nbytes) return VBYTE_EINVAL;
@@ -449,6 +453,7 @@ vbyte_status vbyte_decode_noalloc(const uint8_t *bytes, size_t nbytes, uint32_t 
     if (nbytes >= kMaxBytes || (nbytes > 0 && !bytes) || (n > 0 && !out)) return VBYTE_EINVAL;
     if (((uintptr_t)out & 3u) != 0) return VBYTE_EINVAL;
     StreamArgs a{};
+    a.spin_limit = spin_limit();
     a.vstart = (uintptr_t)bytes & 15u;
     a.base = bytes - a.vstart;
     a.vend = a.vstart + nbytes;
@@ -480,6 +485,11 @@ vbyte_status vbyte_decode_noalloc(const uint8_t *bytes, size_t nbytes, uint32_t 
 
 void vbyte_tuning_default(vbyte_tuning *t) {
     if (t) *t = default_tuning();
+}
+
+vbyte_status vbyte_set_spin_limit(uint32_t rounds) {
+    g_spin_limit.store(rounds ? rounds : kDefaultSpinLimit);
+    return VBYTE_OK;
 }
 
 vbyte_status vbyte_set_flow_grid(int grid) {
@@ -562,6 +572,7 @@ vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32
     uint64_t *scratch = (uint64_t *)(ws_base(w) + kPieceOff);
     const uint64_t *cin = (const uint64_t *)d_in;
     StreamArgs a{};
+    a.spin_limit = spin_limit();
     const uint8_t *p = nbytes ? bytes : (const uint8_t *)d_in;   // any readable address
     a.vstart = (uintptr_t)p & 15u;
     a.base = p - a.vstart;
@@ -647,6 +658,7 @@ vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count,
     }
     const int segs = g_segs.load(), wpb = g_wpb.load();
     StreamArgs a{};
+    a.spin_limit = spin_limit();
     a.vstart = (uintptr_t)bytes & 15u;
     a.base = bytes - a.vstart;
     a.vend = a.vstart + nbytes;
@@ -673,6 +685,7 @@ vbyte_status vbyte_decode_batch(const uint8_t *bytes, size_t nbytes, const int64
     if (nlists > 0 && (!byte_off || !out_off)) return VBYTE_EINVAL;
     if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     ListArgs a{};
+    a.spin_limit = spin_limit();
     a.bytes = bytes;
     a.nbytes = nbytes;
     a.nout = nout;
@@ -694,6 +707,7 @@ vbyte_status vbyte_decode_lists(const uint8_t *bytes, size_t nbytes, const int64
     if (nlists > 0 && !lists) return VBYTE_EINVAL;
     if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     ListArgs a{};
+    a.spin_limit = spin_limit();
     a.bytes = bytes;
     a.nbytes = nbytes;
     a.nout = nout;
@@ -723,6 +737,7 @@ static vbyte_status encode_common(const uint32_t *values, size_t n, uint32_t pre
     const uint64_t ntiles = (n + kEncodeWaveValues - 1) / kEncodeWaveValues;
     if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
     EncodeArgs a{};
+    a.spin_limit = spin_limit();
     a.values = values;
     a.n = n;
     a.prev = prev;
@@ -827,6 +842,7 @@ const char *vbyte_status_str(vbyte_status st) {
         case VBYTE_EMALFORMED: return "VBYTE_EMALFORMED";
         case VBYTE_EHIP: return "VBYTE_EHIP";
         case VBYTE_ENOMEM: return "VBYTE_ENOMEM";
+        case VBYTE_ESTALLED: return "VBYTE_ESTALLED";
     }
     return "VBYTE_UNKNOWN";
 }

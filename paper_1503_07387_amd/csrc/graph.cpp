@@ -49,6 +49,7 @@ vbyte_status vbyte_batch_graph_create(const uint8_t *bytes, size_t nbytes, const
     if (nlists == 0 || !byte_off || !out_off) return VBYTE_EINVAL;
     if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     ListArgs a{};
+    a.spin_limit = spin_limit();
     a.bytes = bytes;
     a.nbytes = nbytes;
     a.nout = nout;

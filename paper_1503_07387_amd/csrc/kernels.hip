@@ -156,6 +156,7 @@ struct Prefix {
     u64 c;
     u32 s;
     bool mal;
+    bool stalled;   // the look-back gave up after its round limit (the prefix is wrong)
 };
 
 // Decoupled look-back: exclusive prefix of descriptor `idx` over the chain
@@ -168,15 +169,18 @@ struct Prefix {
 // a whole window without meeting an inclusive prefix widens the next round
 // to kLookbackWindows windows, so that a look-back far behind the chain of
 // inclusive prefixes catches up in one more round trip instead of one per 64
-// tiles.
+// tiles.  The wait is bounded: after `limit` round trips that found a
+// predecessor not ready, the look-back gives up and says so (stalled), so
+// that a lost predecessor ends the launch with a status instead of a hang.
 template <bool SUM>
-__device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first, u32 tag) {
+__device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first, u32 tag, u32 limit) {
     const u32 ln = lane_id();
     u64 acc_c = 0;
     u32 acc_s = 0;
     bool acc_m = false;
     i64 pos = idx - 1;
     u32 nw = 1;
+    u32 waits = 0;
     for (;;) {
         u64 cw[kLookbackWindows], sw[kLookbackWindows];
 #pragma unroll
@@ -231,10 +235,22 @@ __device__ __forceinline__ Prefix lookback(const Desc *desc, i64 idx, i64 first,
         }
         if (done) break;
         pos -= consumed;
-        if (consumed == 0) __builtin_amdgcn_s_sleep(1);
+        if (consumed == 0) {
+            if (++waits > limit) return Prefix{acc_c, acc_s, acc_m, true};
+            __builtin_amdgcn_s_sleep(1);
+        }
         nw = stopped ? 1u : (u32)kLookbackWindows;
     }
-    return Prefix{acc_c, acc_s, acc_m};
+    return Prefix{acc_c, acc_s, acc_m, false};
+}
+
+// The stall word of a workspace holds epoch + 1 once a look-back of that
+// launch gave up; later launches (other epochs) ignore it.
+__device__ __forceinline__ void mark_stalled(u64 *stall, u32 epoch) {
+    astore(stall, (u64)epoch + 1);
+}
+__device__ __forceinline__ bool launch_stalled(const u64 *stall, u32 epoch) {
+    return aload(stall) == (u64)epoch + 1;
 }
 
 // ------------------------------------------------------------ byte loads
@@ -627,12 +643,16 @@ struct TileIn {
     bool known_mal;
     // resumable pieces: receives the offset (from vstart) of the code of rank n
     u64 *pos_out;
+    // look-back bound and the workspace's stall word
+    u32 spin_limit;
+    u64 *stall;
 };
 
 struct TileOut {
     u64 total;   // integers up to and including this tile (kAgg: of the wavefront)
     bool mal;
     u32 sum;     // inclusive wrapping sum (kAgg: of the wavefront)
+    bool stalled = false;   // this tile's look-back gave up
 };
 
 // What run_tile does with a tile.
@@ -659,6 +679,7 @@ struct WgShared {
     u64 item;
     u64 cur;    // resumable pieces: the piece's first byte and its prev
     u32 cprev;
+    u32 stalled;   // the tile's look-back gave up
 };
 
 // Totals of the tile's wavefronts, read from `sh`.
@@ -820,7 +841,8 @@ __device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs
                 ex = Prefix{0, t.prev, false};
             } else {
                 if (ln == 0) publish<DELTA>(&t.desc[t.didx], t.tag, false, tsum.mal, tsum.c, tsum.s);
-                ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag);
+                ex = lookback<DELTA>(t.desc, t.didx, t.dfirst, t.tag, t.spin_limit);
+                if (ex.stalled && ln == 0) mark_stalled(t.stall, t.tag & 0x1FFFFFFu);
             }
             if (ln == 0) {
                 if (!KNOWN)
@@ -829,12 +851,13 @@ __device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs
                 sh.excl_c = ex.c;
                 sh.excl_s = ex.s;
                 sh.excl_mal = ex.mal ? 1u : 0u;
+                sh.stalled = ex.stalled ? 1u : 0u;
             }
         }
         __syncthreads();
         exc = sh.excl_c;
         exs = sh.excl_s;
-        res = TileOut{exc + tsum.c, sh.excl_mal != 0 || tsum.mal, exs + tsum.s};
+        res = TileOut{exc + tsum.c, sh.excl_mal != 0 || tsum.mal, exs + tsum.s, sh.stalled != 0};
     }
     if (COUNT) return res;
 
@@ -954,6 +977,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     t.didx = tile;
     t.dfirst = 0;
     t.tag = make_tag(epoch);
+    t.spin_limit = a.spin_limit;
+    t.stall = a.hdr + kStallWord;
     const bool interior = tile > 0 && t.tv + tb + 4 <= t.vend;
     TileOut r;
     if (interior)
@@ -962,24 +987,35 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
         r = run_tile<D, KIND, SEGS, true>(t, stage, sh, wib, wpb);
 
     if (tile == a.ntiles - 1 && tid == 0) {
+        const bool stalled = launch_stalled(t.stall, epoch);
         if (COUNT) {
-            *a.d_count = r.total;
+            *a.d_count = stalled ? ~0ull : r.total;
         } else if (PIECE) {
             // a piece: more codes than n are fine; a short piece that ends
             // inside a code is truncated
             a.scratch[1] = r.total;
             const bool cut = r.total < a.n && t.vend > t.vstart && t.base[t.vend - 1] >= 0x80;
-            *a.d_status = bad_cursor ? VBYTE_EINVAL
+            *a.d_status = stalled    ? VBYTE_ESTALLED
+                          : bad_cursor ? VBYTE_EINVAL
                           : r.mal    ? VBYTE_EMALFORMED
                           : cut      ? VBYTE_ETRUNC
                                      : VBYTE_OK;
         } else {
             const u8 last = a.base[a.vend - 1];
-            *a.d_status = final_status(r.mal, last, r.total, a.n);
+            *a.d_status = stalled ? VBYTE_ESTALLED : final_status(r.mal, last, r.total, a.n);
         }
         // The last tile's look-back has ended, so every tile has published
         // and therefore read the epoch: retire this launch's descriptors.
         astore(a.hdr, (u64)epoch + 1);
+    }
+    // a tile whose look-back gave up after the status was written says so
+    // itself, once its stores are done
+    if (r.stalled && tid == 0) {
+        if (COUNT)
+            __hip_atomic_store(a.d_count, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_store(a.d_status, (int32_t)VBYTE_ESTALLED, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1048,7 +1084,8 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
             ex = Prefix{0, a.prev, false};
         } else {
             if (ln == 0) publish<DELTA>(&a.desc[chunk], t.tag, false, csum.mal, csum.c, csum.s);
-            ex = lookback<DELTA>(a.desc, chunk, 0, t.tag);
+            ex = lookback<DELTA>(a.desc, chunk, 0, t.tag, a.spin_limit);
+            if (ex.stalled && ln == 0) mark_stalled(a.hdr + kStallWord, epoch);
         }
         if (ln == 0) {
             publish<DELTA>(&a.desc[chunk], t.tag, true, ex.mal || csum.mal, ex.c + csum.c,
@@ -1056,9 +1093,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
             sh.excl_c = ex.c;
             sh.excl_s = ex.s;
             sh.excl_mal = ex.mal ? 1u : 0u;
+            sh.stalled = ex.stalled ? 1u : 0u;
         }
     }
     __syncthreads();
+    const bool chunk_stalled = sh.stalled != 0;
     t.known_c = sh.excl_c;
     t.known_s = sh.excl_s;
     t.known_mal = sh.excl_mal != 0;
@@ -1076,10 +1115,14 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     }
     if (chunk == nch - 1 && tid == 0) {
         const u8 last = a.base[a.vend - 1];
-        *a.d_status = final_status(r.mal, last, r.total, a.n);
+        *a.d_status = launch_stalled(a.hdr + kStallWord, epoch) ? VBYTE_ESTALLED
+                                                                : final_status(r.mal, last, r.total, a.n);
         // the last chunk's look-back has ended: every chunk has read the epoch
         astore(a.hdr, (u64)epoch + 1);
     }
+    if (chunk_stalled && tid == 0)
+        __hip_atomic_store(a.d_status, (int32_t)VBYTE_ESTALLED, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------ two passes
@@ -2958,7 +3001,11 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
             ex = Prefix{0, 0, false};
         } else {
             if (ln == 0) publish<true>(&a.prep_desc[blk], tag, false, false, bl, bs);
-            ex = lookback<true>(a.prep_desc, blk, 0, tag);
+            ex = lookback<true>(a.prep_desc, blk, 0, tag, a.spin_limit);
+            if (ex.stalled && ln == 0) {
+                mark_stalled(a.hdr + kStallWord, epoch);
+                astore(&a.totals[2], 2);   // read by the decode launch after this one
+            }
         }
         if (ln == 0) {
             publish<true>(&a.prep_desc[blk], tag, true, false, ex.c + bl, ex.s + bs);
@@ -2967,9 +3014,10 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
             if (blk == nblocks - 1) {
                 const u64 L = ex.c + bl, S = (u64)ex.s + bs;
                 const bool fits = L + S <= a.max_items;
-                astore(&a.totals[0], fits ? L : 0);
-                astore(&a.totals[1], fits ? S : 0);
-                astore(&a.totals[2], fits ? 0 : 1);
+                const bool stalled = launch_stalled(a.hdr + kStallWord, epoch);
+                astore(&a.totals[0], fits && !stalled ? L : 0);
+                astore(&a.totals[1], fits && !stalled ? S : 0);
+                astore(&a.totals[2], stalled ? 2 : fits ? 0 : 1);
                 astore(a.hdr, (u64)epoch + 1);   // every block has published
             }
         }
@@ -3069,7 +3117,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     const u32 epoch = sh.epoch;
     const u64 L = aload(&a.totals[0]);
     const u64 S = aload(&a.totals[1]);
-    const bool failed = aload(&a.totals[2]) != 0;
+    const u64 fail_code = aload(&a.totals[2]);   // 1: the work table was too small; 2: prep stalled
+    const bool failed = fail_code != 0;
     const u64 G = gridDim.x;
     const u64 tb = (u64)wpb * SEGS * kSegBytes;
     u64 *qlarge = a.hdr + 1;
@@ -3103,6 +3152,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
         t.desc = a.desc;
         t.dfirst = (i64)(k - sp) * kSpanTiles;
         t.tag = make_tag(epoch);
+        t.spin_limit = a.spin_limit;
+        t.stall = a.hdr + kStallWord;
         const u64 tiles = (t.vend + tb - 1) / tb;
         const u64 t0 = (u64)sp * kSpanTiles;
         const u64 t1 = t0 + kSpanTiles < tiles ? t0 + kSpanTiles : tiles;
@@ -3113,7 +3164,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
             const TileOut r = interior ? run_tile<D, kFull, SEGS, false>(t, stage, sh, wib, wpb)
                                        : run_tile<D, kFull, SEGS, true>(t, stage, sh, wib, wpb);
             if (ti == tiles - 1 && tid == 0)
-                a.list_status[li] = final_status(r.mal, t.base[t.vend - 1], r.total, t.n);
+                a.list_status[li] = launch_stalled(t.stall, epoch)
+                                        ? VBYTE_ESTALLED
+                                        : final_status(r.mal, t.base[t.vend - 1], r.total, t.n);
+            if (r.stalled && tid == 0)
+                __hip_atomic_store(&a.list_status[li], (int32_t)VBYTE_ESTALLED, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 
@@ -3151,7 +3207,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     if (failed) {
         const u64 nthreads = (u64)gridDim.x * blockDim.x;
         for (u64 i = (u64)blockIdx.x * blockDim.x + tid; i < a.nlists; i += nthreads)
-            a.list_status[i] = VBYTE_EINVAL;
+            a.list_status[i] = fail_code == 2 ? VBYTE_ESTALLED : VBYTE_EINVAL;
     }
 }
 
@@ -3202,7 +3258,7 @@ __global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
         ex = Prefix{0, 0, false};
     } else {
         if (ln == 0) publish<false>(&a.desc[tile], tag, false, false, tilebytes, 0);
-        ex = lookback<false>(a.desc, tile, 0, tag);
+        ex = lookback<false>(a.desc, tile, 0, tag, a.spin_limit);
     }
     if (ln == 0) publish<false>(&a.desc[tile], tag, true, false, ex.c + tilebytes, 0);
     const u64 gb = ex.c;   // byte offset of this tile

@@ -42,6 +42,13 @@ struct Desc {
 static_assert(sizeof(Desc) == 16, "descriptor is 16 bytes");
 
 constexpr int kTicketWord = 3;   // zero between launches (take_ticket)
+// Header word 4: the stall word (epoch + 1 once a look-back of that launch
+// gave up).  Look-backs give up after this many round trips that found a
+// predecessor not ready (about a second or more); vbyte_set_spin_limit
+// changes it for later calls.
+constexpr int kStallWord = 4;
+constexpr uint32_t kDefaultSpinLimit = 1u << 20;
+uint32_t spin_limit();
 
 // Header words: [0] launch epoch, [1] batched large-span queue, [2] batched
 // small-chunk queue, [3] tile ticket.  Tiles of a single-stream launch are
@@ -73,6 +80,7 @@ struct StreamArgs {
     const uint64_t *cursor_in;
     uint64_t window;
     uint64_t *scratch;
+    uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
 };
 
 // Single-stream decode in one persistent launch of `grid` workgroups that
@@ -166,6 +174,7 @@ struct ListArgs {
     uint64_t *totals;          // [0] large spans L, [1] small lists S, [2] 1 if the table
                                // overflowed (written by the prep kernel)
     uint32_t wpb;              // wavefronts per workgroup (small lists per work item)
+    uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
 };
 
 struct EncodeArgs {
@@ -179,6 +188,7 @@ struct EncodeArgs {
     uint32_t ntiles;
     uint64_t *hdr;
     Desc *desc;
+    uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
 };
 
 // Launchers (kernels.hip).

@@ -18,10 +18,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvbyte.so")
 
-OK, EINVAL, ECOUNT, ETRUNC, EMALFORMED, EHIP, ENOMEM = range(7)
+OK, EINVAL, ECOUNT, ETRUNC, EMALFORMED, EHIP, ENOMEM, ESTALLED = range(8)
 STATUS_NAMES = {OK: "VBYTE_OK", EINVAL: "VBYTE_EINVAL", ECOUNT: "VBYTE_ECOUNT",
                 ETRUNC: "VBYTE_ETRUNC", EMALFORMED: "VBYTE_EMALFORMED",
-                EHIP: "VBYTE_EHIP", ENOMEM: "VBYTE_ENOMEM"}
+                EHIP: "VBYTE_EHIP", ENOMEM: "VBYTE_ENOMEM", ESTALLED: "VBYTE_ESTALLED"}
 
 EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_decode_delta_async", "vbyte_decode_delta_m1", "vbyte_decode_delta_m1_async",
@@ -35,6 +35,7 @@ EXPORTS = ["vbyte_decode", "vbyte_decode_delta", "vbyte_decode_async",
            "vbyte_batch_graph_destroy", "vbyte_autotune_decode", "vbyte_autotune_batch",
            "vbyte_set_chunk_tiles", "vbyte_get_chunk_tiles", "vbyte_set_flow_grid",
            "vbyte_decode_ex", "vbyte_tuning_default", "vbyte_decode_noalloc",
+           "vbyte_set_spin_limit",
            "vbyte_workspace_size", "vbyte_set_tuning", "vbyte_get_tuning",
            "vbyte_status_str", "vbyte_last_error"]
 
@@ -127,6 +128,7 @@ def _declare(lib):
         "vbyte_set_tuning": [i32, i32, i64],
         "vbyte_set_chunk_tiles": [i32],
         "vbyte_set_flow_grid": [i32],
+        "vbyte_set_spin_limit": [u32],
         "vbyte_decode_ex": [vp, sz, vp, sz, u32, i32, vp, vp, vp],
         "vbyte_decode_noalloc": [vp, sz, vp, sz, u32, i32, vp, vp],
         "vbyte_batch_graph_create": [vp, sz, vp, vp, sz, vp, sz, vp, i32, vp, c.POINTER(vp)],
@@ -379,7 +381,8 @@ def decode_next(data, k, out, cursor_in, cursor_out, *, delta=False, minus_one=F
 def count(data, *, stream=None, result=None):
     """Number of terminator bytes (codes) in ``data``; returns a Python int
     (or fills the uint64 slot of ``result``, an int64 CUDA tensor, without
-    waiting when given)."""
+    waiting when given).  A count whose look-back gave up (VBYTE_ESTALLED,
+    see set_spin_limit) reads as -1 (2^64 - 1 as int64)."""
     _dev_u8(data)
     res = result if result is not None else torch.empty(1, dtype=torch.int64, device=data.device)
     _check_call(_lib().vbyte_count(_ptr(data), data.numel(), _ptr(res), _stream(stream)), "count")
@@ -558,6 +561,11 @@ def set_tuning(segs_per_wave=0, waves_per_block=0, small_list_bytes=0, tiles_per
                                         int(small_list_bytes)), "set_tuning")
     if tiles_per_chunk is not None:
         _check_call(_lib().vbyte_set_chunk_tiles(int(tiles_per_chunk)), "set_chunk_tiles")
+
+
+def set_spin_limit(rounds=0):
+    """Look-back round trips before a waiting tile gives up (0: default)."""
+    _check_call(_lib().vbyte_set_spin_limit(int(rounds)), "set_spin_limit")
 
 
 def set_flow_grid(grid=0):

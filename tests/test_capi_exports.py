@@ -83,7 +83,7 @@ def test_status_numbers_are_fixed():
     text = text[text.index("typedef enum vbyte_status {"):text.index("} vbyte_status;")]
     nums = dict((k, int(v)) for k, v in re.findall(r"VBYTE_(\w+)\s*=\s*(\d+)", text))
     want = {"OK": 0, "EINVAL": 1, "ECOUNT": 2, "ETRUNC": 3, "EMALFORMED": 4, "EHIP": 5,
-            "ENOMEM": 6}
+            "ENOMEM": 6, "ESTALLED": 7}
     assert nums == want
     for k, v in want.items():
         assert getattr(vbyte, k) == v
