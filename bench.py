@@ -853,6 +853,36 @@ def bench_uniform(torch, vbyte, workloads, flush, tuning, reps=30):
             "back_to_back": line(x.size, enc.numel(), median(warm))}
 
 
+def bench_encoder(torch, vbyte, streams, flush, reps=10):
+    """The GPU encoder on both 64Mi-gap streams (values -> canonical codes),
+    checked against the bytes the decode lines use; algorithmic bytes are
+    4n in + the encoded bytes out."""
+    rows = []
+    for s in streams:
+        n = s["gaps"].size
+        out = torch.empty(5 * n, dtype=torch.uint8, device="cuda")
+        nb = torch.empty(1, dtype=torch.int64, device="cuda")
+
+        def call():
+            vbyte.encode(s["gaps_dev"], out=out, nbytes=nb, trim=False)
+
+        call()
+        torch.cuda.synchronize()
+        m = int(nb.item())
+        if m != s["bytes"].numel() or not torch.equal(out[:m], s["bytes"]):
+            raise RuntimeError("encoder output differs")
+        for label, before in (("back_to_back", None), ("mall_flushed", flush)):
+            ms = median(event_times(torch, call, reps, before=before))
+            alg = 4 * n + m
+            rows.append({"gap_mean": s["mean"], "timing": label, "n": n, "bytes_out": m,
+                         "ms": round(ms, 4), "gints_per_s": round(n / (ms / 1e3) / 1e9, 2),
+                         "alg_gbps": round(alg / (ms / 1e3) / 1e9, 1),
+                         "pct_hbm_peak": round(100 * alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 1)})
+        del out
+    return {"workload": "VByte encoding of the two 64Mi-gap streams (k_enc_len, k_enc_bsum, "
+                        "k_enc_bscan, k_enc_write)", "rows": rows}
+
+
 def bench_config2(torch, vbyte, streams, flush, tuning, reps=10):
     """Differential decode of the two 64Mi-gap streams (gap means 8 and 300),
     each call timed alone, back to back and with the MALL flushed."""
@@ -1022,6 +1052,8 @@ def main():
     streams = make_streams(torch, vbyte, workloads)
     log("64Mi-gap streams ...")
     res["config2_delta"] = bench_config2(torch, vbyte, streams, flush, tuning)
+    log("encoder ...")
+    res["encoder"] = bench_encoder(torch, vbyte, streams, flush)
     if not args.no_decode64:
         log("64-bit decode ...")
         res["decode64"] = bench_decode64(torch, vbyte, streams)

@@ -734,23 +734,27 @@ static vbyte_status encode_common(const uint32_t *values, size_t n, uint32_t pre
         hipError_t e = launch_set_u64(d_nbytes, 0, s);
         return e == hipSuccess ? VBYTE_OK : hip_fail(e, "set nbytes");
     }
-    const uint64_t ntiles = (n + kEncodeWaveValues - 1) / kEncodeWaveValues;
-    if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
-    EncodeArgs a{};
-    a.spin_limit = spin_limit();
-    a.values = values;
+    if (n >= (1ull << 40)) return VBYTE_EINVAL;
+    EncArgs a{};
+    a.e0 = ((uintptr_t)values >> 2) & 3u;
+    a.vbase = values - a.e0;
     a.n = n;
     a.prev = prev;
     a.delta = delta;
     a.bytes = bytes;
     a.capacity = capacity;
     a.d_nbytes = d_nbytes;
-    a.ntiles = (uint32_t)ntiles;
+    a.nchunks = (a.e0 + n + kEncChunk - 1) / kEncChunk;
+    const uint64_t nsb = (a.nchunks + 8 * 1024 - 1) / (8 * 1024);
+    // workspace: chunk counts (4 B), chunk offsets (8 B), scan block totals (8 B)
+    const size_t off_pre = kHeaderBytes + ((a.nchunks * 4 + 15) & ~(uint64_t)15);
+    const size_t off_bsum = off_pre + a.nchunks * 8;
     Workspace *w = nullptr;
-    vbyte_status st = get_ws(s, kHeaderBytes + ntiles * sizeof(Desc), 1, &w);
+    vbyte_status st = get_ws(s, off_bsum + nsb * 8, 0, &w);
     if (st != VBYTE_OK) return st;
-    a.hdr = (uint64_t *)ws_base(w);
-    a.desc = (Desc *)(ws_base(w) + kHeaderBytes);
+    a.csum = (uint32_t *)(ws_base(w) + kHeaderBytes);
+    a.cpre = (uint64_t *)(ws_base(w) + off_pre);
+    a.bsum = (uint64_t *)(ws_base(w) + off_bsum);
     hipError_t e = launch_encode(a, s);
     if (e != hipSuccess) return hip_fail(e, "encode launch");
     if (nbounds) {

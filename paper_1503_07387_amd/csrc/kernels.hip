@@ -3214,115 +3214,224 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
 // ------------------------------------------------------------ encoder
 // Canonical ENC (section 1): L(x) bytes, 7 bits each, least significant
 // first, top bit set on all but the last.  delta: 1 codes x_i - x_(i-1),
-// 2 codes x_i - x_(i-1) - 1 after the first (x_(-1) = prev).  One wavefront encodes 1024
-// values per tile: lane lengths -> wave scan -> look-back for the tile's
-// byte offset -> bytes assembled in LDS -> stored to HBM.
+// 2 codes x_i - x_(i-1) - 1 after the first (x_(-1) = prev).
+//
+// Two passes over the values with no look-back.  The values are addressed
+// from the 16-byte-aligned element at or below values[0] (e0 elements
+// before it); chunk c is aligned elements [256 c, 256 c + 256): one 128-bit
+// load per lane of a wavefront.  k_enc_len stores each chunk's byte count;
+// k_enc_bsum / k_enc_bscan turn the counts into exclusive byte offsets (the
+// last block writes the total); k_enc_write loads the chunk again, gives
+// every value its byte offset (lane scan plus the chunk offset) and builds
+// the chunk's bytes in LDS by OR-ing each code, shifted to its byte offset,
+// into the one or two dwords it touches (codes never overlap, so the ORs
+// assemble the bytes exactly); the dwords then go out as 16-byte stores,
+// with byte stores at the chunk's two edges.  k_enc_bounds gives every CSR
+// list boundary its byte offset: the chunk offset plus the lengths of the
+// values before it in its chunk.
 __device__ __forceinline__ u32 code_len(u32 x) {
-    const u32 bits = 32u - (u32)__builtin_clz(x | 1u);
-    return (bits + 6u) / 7u;
+    return 1u + (x >= (1u << 7)) + (x >= (1u << 14)) + (x >= (1u << 21)) + (x >= (1u << 28));
 }
 
-__global__ __launch_bounds__(256) void k_encode(EncodeArgs a) {
-    extern __shared__ __align__(16) u32 lds[];
-    const u32 ln = lane_id();
-    const u32 wib = threadIdx.x >> 6;
-    const u64 wg = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
-    if (wg >= a.ntiles) return;
-    u8 *stage = (u8 *)(lds + wib * (kEncodeWaveValues * 5 / 4 + 8));
-    // tile = this wavefront's ticket (see take_ticket); see k_stream for the epoch
-    u32 tk = 0;
-    if (ln == 0) tk = take_ticket(a.hdr + kTicketWord, a.ntiles);
-    const u32 tile = first_lane(tk);
-    const u32 epoch = first_lane((u32)aload(a.hdr));
-    const u32 tag = make_tag(epoch);
+// The code of x in a 64-bit word (bytes 0..L-1, the rest zero).
+__device__ __forceinline__ u64 code_bytes(u32 x, u32 len) {
+    u64 c = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const u64 g = (x >> (7 * j)) & 0x7Fu;
+        const u64 b = (u32)j + 1 < len ? g | 0x80u : g;
+        c |= (u32)j < len ? b << (8 * j) : 0ull;
+    }
+    return c;
+}
 
-    // lane owns values [v0, v0 + 16)
-    const u64 v0 = (u64)tile * kEncodeWaveValues + 16u * ln;
-    u32 x[16];
-    u32 lanebytes = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const u64 i = v0 + k;
-        u32 v = 0;
-        if (i < a.n) {
-            v = a.values[i];
-            if (a.delta) v -= (i == 0) ? a.prev : a.values[i - 1] + (a.delta == 2 ? 1u : 0u);
-        }
-        x[k] = v;
-        lanebytes += (i < a.n) ? code_len(v) : 0u;
-    }
-    const u32 bi = wave_scan(lanebytes);
-    const u32 tilebytes = read_lane(bi, 63);
-    Prefix ex;
-    if (tile == 0) {
-        ex = Prefix{0, 0, false};
+// Lane l's four values of chunk c (aligned elements 256 c + 4 l .. + 3) as
+// the integers to code (values, or their differences), with a validity
+// mask (bit j: element j is values[i] for some 0 <= i < n).
+__device__ __forceinline__ u32 enc_load(const EncArgs &a, u64 c, u32 (&v)[4]) {
+    const u32 ln = lane_id();
+    const u64 a0 = c * kEncChunk + 4u * ln;   // aligned index of element 0
+    const u64 lo = a.e0, hi = a.e0 + a.n;     // valid aligned indices
+    u32 valid = 0;
+    if (a0 >= lo && a0 + 4 <= hi) {
+        const uint4 q = *(const uint4 *)(a.vbase + a0);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+        valid = 0xFu;
     } else {
-        if (ln == 0) publish<false>(&a.desc[tile], tag, false, false, tilebytes, 0);
-        ex = lookback<false>(a.desc, tile, 0, tag, a.spin_limit);
-    }
-    if (ln == 0) publish<false>(&a.desc[tile], tag, true, false, ex.c + tilebytes, 0);
-    const u64 gb = ex.c;   // byte offset of this tile
-    const u32 mis = (u32)(((uintptr_t)a.bytes + gb) & 3u);
-    // assemble into LDS at stage[mis + local offset]
-    u32 off = mis + bi - lanebytes;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (v0 + k < a.n) {
-            const u32 v = x[k];
-            const u32 len = code_len(v);
-            for (u32 j = 0; j < len; ++j) {
-                const u32 g = (v >> (7 * j)) & 0x7Fu;
-                stage[off + j] = (u8)(j + 1 < len ? (g | 0x80u) : g);
+        for (int k = 0; k < 4; ++k) {
+            const u64 ai = a0 + k;
+            v[k] = 0;
+            if (ai >= lo && ai < hi) {
+                v[k] = a.vbase[ai];
+                valid |= 1u << k;
             }
-            off += len;
+        }
+    }
+    if (a.delta) {
+        // the value before each element: the lane's own, the lane below's
+        // last, or (lane 0) the element before the chunk, or prev
+        const u64 c0 = c * kEncChunk;
+        u32 before_chunk = a.prev;
+        if (c0 > lo && c0 - 1 < hi) before_chunk = a.vbase[c0 - 1];
+        const u32 below = from_lane_below(v[3], before_chunk);
+        const u32 m1 = a.delta == 2 ? 1u : 0u;
+        u32 p = below;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u64 ai = a0 + k;
+            const u32 x = v[k];
+            // the first value takes prev, with no minus one
+            const bool first = ai == lo;
+            v[k] = first ? x - a.prev : x - p - m1;
+            p = x;
+        }
+    }
+    return valid;
+}
+
+__global__ __launch_bounds__(256) void k_enc_len(EncArgs a) {
+    const u32 ln = lane_id();
+    const u64 c = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (c >= a.nchunks) return;
+    u32 v[4];
+    const u32 valid = enc_load(a, c, v);
+    u32 len = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) len += (valid >> k) & 1u ? code_len(v[k]) : 0u;
+    len = wave_sum(len);
+    if (ln == 0) a.csum[c] = len;
+}
+
+constexpr u64 kEncScanSpan = 8 * kScanBlock;   // chunk counts per scan workgroup (8 per thread)
+
+__global__ __launch_bounds__(kScanBlock) void k_enc_bsum(EncArgs a) {
+    __shared__ u64 ws[kScanBlock / kWave];
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u64 i0 = (u64)blockIdx.x * kEncScanSpan;
+    u64 sum = 0;
+    for (u64 i = i0 + tid; i < i0 + kEncScanSpan && i < a.nchunks; i += kScanBlock) sum += a.csum[i];
+    const u32 w = wave_sum((u32)sum);   // at most 8 x 1280 per lane
+    if (ln == 0) ws[wib] = w;
+    __syncthreads();
+    if (tid == 0) {
+        u64 t = 0;
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) t += ws[k];
+        a.bsum[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_enc_bscan(EncArgs a) {
+    __shared__ u64 carry_sh, wtot[kScanBlock / kWave];
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u32 b = blockIdx.x, nb = gridDim.x;
+    if (tid < kWave) {
+        u64 c = 0;
+        for (u32 k = ln; k < b; k += kWave) c += a.bsum[k];
+        // 64-bit lane sums as 24 low bits and the rest
+        const u32 lo = wave_sum((u32)c & 0xFFFFFFu), hi = wave_sum((u32)(c >> 24));
+        if (tid == 0) carry_sh = ((u64)hi << 24) + lo;
+    }
+    // thread t holds the 8 consecutive counts 8 t .. 8 t + 7 of the block
+    const u64 i0 = (u64)b * kEncScanSpan + 8u * tid;
+    u32 cnt[8], lsum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        cnt[k] = i0 + k < a.nchunks ? a.csum[i0 + k] : 0u;
+        lsum += cnt[k];
+    }
+    const u32 incl = wave_scan(lsum);   // a wavefront's 512 counts fit 32 bits
+    if (ln == 63) wtot[wib] = incl;
+    __syncthreads();
+    u64 off = carry_sh;
+    for (u32 k = 0; k < wib; ++k) off += wtot[k];
+    off += incl - lsum;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (i0 + k < a.nchunks) a.cpre[i0 + k] = off;
+        off += cnt[k];
+    }
+    if (b == nb - 1 && tid == kScanBlock - 1) *a.d_nbytes = off;   // the last thread's end: the total
+}
+
+__global__ __launch_bounds__(256) void k_enc_write(EncArgs a) {
+    extern __shared__ __align__(16) u32 lds[];
+    const u32 ln = lane_id(), wib = threadIdx.x >> 6;
+    const u64 c = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (c >= a.nchunks) return;
+    u32 *st = lds + wib * kEncStageWords;
+    u32 v[4];
+    const u32 valid = enc_load(a, c, v);
+    u32 len[4], lsum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        len[k] = (valid >> k) & 1u ? code_len(v[k]) : 0u;
+        lsum += len[k];
+    }
+    const u32 incl = wave_scan(lsum);
+    const u32 total = read_lane(incl, 63);
+    const u64 base = a.cpre[c];
+    // the stage starts at the 16-byte boundary at or below base
+    const u32 mis = (u32)(((uintptr_t)a.bytes + base) & 15u);
+    const u32 nwords = (mis + total + 3) >> 2;
+    for (u32 q = ln; q < nwords; q += kWave) st[q] = 0;
+    wave_lds_sync();
+    u32 off = mis + incl - lsum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (len[k]) {
+            const u64 code = code_bytes(v[k], len[k]) << (8 * (off & 3u));
+            const u32 w0 = off >> 2;
+            atomicOr(&st[w0], (u32)code);
+            if ((u32)(code >> 32)) atomicOr(&st[w0 + 1], (u32)(code >> 32));
+            off += len[k];
         }
     }
     wave_lds_sync();
-    // store: words covering [gb - mis, gb + tilebytes); edge words byte by byte
-    const u32 nwords = (mis + tilebytes + 3) >> 2;
-    const u32 *sw = (const u32 *)stage;
-    u8 *obase = a.bytes + gb - mis;
-    for (u32 q = ln; q < nwords; q += kWave) {
-        const u32 b0 = q << 2;
-        const u64 g0 = gb - mis + b0;
-        if (b0 >= mis && b0 + 4 <= mis + tilebytes && g0 + 4 <= a.capacity) {
-            *(u32 *)(obase + b0) = sw[q];
+    // stores: 16-byte rows of the stage; the first and last rows may hold
+    // bytes of the neighbouring chunks, which are written byte by byte
+    const u64 gb = base - mis;   // byte index of stage byte 0
+    u8 *ob = a.bytes + gb;
+    const u32 nrows = (mis + total + 15) >> 4;
+    const u8 *sb = (const u8 *)st;
+    for (u32 q = ln; q < nrows; q += kWave) {
+        const u32 b0 = q << 4;
+        if (b0 >= mis && b0 + 16 <= mis + total && gb + b0 + 16 <= a.capacity) {
+            *(uint4 *)(ob + b0) = *(const uint4 *)(st + 4 * q);
         } else {
-            for (u32 t = 0; t < 4; ++t) {
-                const u32 b = b0 + t;
-                if (b >= mis && b < mis + tilebytes && g0 + t < a.capacity) obase[b] = stage[b];
+            for (u32 t = 0; t < 16; ++t) {
+                const u32 bb = b0 + t;
+                if (bb >= mis && bb < mis + total && gb + bb < a.capacity) ob[bb] = sb[bb];
             }
         }
     }
-    if (tile == a.ntiles - 1 && ln == 0) {
-        *a.d_nbytes = ex.c + tilebytes;
-        astore(a.hdr, (u64)epoch + 1);
-    }
 }
 
-// Byte offsets of CSR list boundaries after k_encode: boundary i of value
-// offset v = vals_off[i] starts at the inclusive byte count of the tiles
-// before v's tile plus the code lengths of the values of v's tile below v.
-// Reads the encoder's descriptors, which every tile published.
-__global__ void k_encode_bounds(EncodeArgs a, const int64_t *vals_off, int64_t *byte_off,
-                                uint64_t nb) {
-    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_enc_bounds(EncArgs a, const int64_t *vals_off,
+                                                    int64_t *byte_off, u64 nb) {
+    const u32 ln = lane_id();
+    const u64 i = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (i >= nb) return;
-    u64 v = (u64)vals_off[i];
-    if (v > a.n) v = a.n;
-    const u64 tile = v / kEncodeWaveValues;
+    u64 k = (u64)vals_off[i];
+    if (k > a.n) k = a.n;
+    const u64 ak = a.e0 + k;   // aligned index of the boundary
     u64 off;
-    if (tile >= a.ntiles) {
-        off = aload(&a.desc[a.ntiles - 1].c) & kCountMask;
+    if (k == a.n) {
+        off = *a.d_nbytes;
     } else {
-        off = tile ? (aload(&a.desc[tile - 1].c) & kCountMask) : 0;
-        for (u64 j = tile * kEncodeWaveValues; j < v; ++j) {
-            u32 x = a.values[j];
-            if (a.delta) x -= (j == 0) ? a.prev : a.values[j - 1] + (a.delta == 2 ? 1u : 0u);
-            off += code_len(x);
-        }
+        const u64 c = ak / kEncChunk;
+        u32 v[4];
+        const u32 valid = enc_load(a, c, v);
+        u32 len = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            len += ((valid >> q) & 1u) && c * kEncChunk + 4u * ln + q < ak ? code_len(v[q]) : 0u;
+        off = a.cpre[c] + wave_sum(len);
     }
-    byte_off[i] = (int64_t)off;
+    if (ln == 0) byte_off[i] = (int64_t)off;
 }
 
 // ------------------------------------------------------------ small kernels
@@ -3539,18 +3648,28 @@ hipError_t launch_batch(const ListArgs &a, int segs, int wpb, int grid_blocks, h
     }
 }
 
-hipError_t launch_encode(const EncodeArgs &a, hipStream_t s) {
-    const int wpb = 4;
-    const u32 blocks = (a.ntiles + wpb - 1) / wpb;
-    const size_t lds = (size_t)wpb * (kEncodeWaveValues * 5 / 4 + 8) * sizeof(u32);
-    k_encode<<<blocks, wpb * kWave, lds, s>>>(a);
+hipError_t launch_encode(const EncArgs &a, hipStream_t s) {
+    const u32 wpb = 4;
+    const u64 blocks = (a.nchunks + wpb - 1) / wpb;
+    k_enc_len<<<(unsigned)blocks, wpb * kWave, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const u64 nsb = (a.nchunks + kEncScanSpan - 1) / kEncScanSpan;
+    k_enc_bsum<<<(unsigned)nsb, kScanBlock, 0, s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_enc_bscan<<<(unsigned)nsb, kScanBlock, 0, s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_enc_write<<<(unsigned)blocks, wpb * kWave, wpb * kEncStageWords * sizeof(u32), s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
+hipError_t launch_encode_bounds(const EncArgs &a, const int64_t *vals_off, int64_t *byte_off,
                                 uint64_t nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    k_encode_bounds<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(a, vals_off, byte_off, nb);
+    const u32 wpb = 4;
+    k_enc_bounds<<<(unsigned)((nb + wpb - 1) / wpb), wpb * kWave, 0, s>>>(a, vals_off, byte_off, nb);
     return hipGetLastError();
 }
 

@@ -177,18 +177,23 @@ struct ListArgs {
     uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
 };
 
-struct EncodeArgs {
-    const uint32_t *values;
+// Encoder (k_enc_*): values addressed from the 16-byte-aligned element at
+// or below values[0]; chunks of kEncChunk aligned elements.
+constexpr uint64_t kEncChunk = 256;
+constexpr uint32_t kEncStageWords = (kEncChunk * 5 + 16 + 3) / 4 + 4;   // a chunk's bytes, 16-byte shifted
+struct EncArgs {
+    const uint32_t *vbase;   // 16-byte aligned, <= values
+    uint64_t e0;             // values - vbase (0..3 elements)
     uint64_t n;
     uint32_t prev;
-    int delta;
+    int delta;               // 0 values, 1 differences, 2 differences minus one after the first
     uint8_t *bytes;
     uint64_t capacity;
     uint64_t *d_nbytes;
-    uint32_t ntiles;
-    uint64_t *hdr;
-    Desc *desc;
-    uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
+    uint64_t nchunks;        // ceil((e0 + n) / kEncChunk)
+    uint32_t *csum;          // per chunk: bytes of its codes
+    uint64_t *cpre;          // per chunk: exclusive byte offset
+    uint64_t *bsum;          // per scan block of 8192 chunks: bytes
 };
 
 // Launchers (kernels.hip).
@@ -229,8 +234,8 @@ hipError_t launch_isect_init(const IsectArgs &a, uint64_t *cursor, uint64_t prev
 hipError_t launch_isect_piece(const IsectArgs &a, uint64_t piece, hipStream_t s);
 hipError_t launch_isect_finish(const IsectArgs &a, const uint64_t *cursor, uint64_t nbytes,
                                hipStream_t s);
-hipError_t launch_encode(const EncodeArgs &a, hipStream_t s);
-hipError_t launch_encode_bounds(const EncodeArgs &a, const int64_t *vals_off, int64_t *byte_off,
+hipError_t launch_encode(const EncArgs &a, hipStream_t s);
+hipError_t launch_encode_bounds(const EncArgs &a, const int64_t *vals_off, int64_t *byte_off,
                                 uint64_t nb, hipStream_t s);
 hipError_t launch_set_status(int32_t *d_status, int32_t value, hipStream_t s);
 
@@ -266,7 +271,6 @@ inline uint64_t stream_tiles(uint64_t vstart, uint64_t nbytes, int segs, int wpb
     return (vstart + nbytes + tb - 1) / tb;
 }
 
-constexpr int kEncodeWaveValues = 1024;   // values per encoder tile (one wavefront)
 constexpr int kPrepBlock = 256;           // lists per prep workgroup
 constexpr int kSpanTiles = 1;             // large-list tiles per batched work item
 constexpr int kSmallChunk = 64;           // small lists per batched work item
