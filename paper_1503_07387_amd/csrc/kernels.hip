@@ -3229,20 +3229,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
 // with byte stores at the chunk's two edges.  k_enc_bounds gives every CSR
 // list boundary its byte offset: the chunk offset plus the lengths of the
 // values before it in its chunk.
+constexpr int kEncPerWave = 8;        // chunks per wavefront in k_enc_len
+constexpr int kEncWritePerWave = 4;   // chunks per wavefront in k_enc_write
+
 __device__ __forceinline__ u32 code_len(u32 x) {
     return 1u + (x >= (1u << 7)) + (x >= (1u << 14)) + (x >= (1u << 21)) + (x >= (1u << 28));
 }
 
-// The code of x in a 64-bit word (bytes 0..L-1, the rest zero).
+// The code of x in a 64-bit word (bytes 0..L-1, the rest zero): the five
+// 7-bit groups spread to bytes 0..4, continuation bits on bytes 0..L-2.
 __device__ __forceinline__ u64 code_bytes(u32 x, u32 len) {
-    u64 c = 0;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        const u64 g = (x >> (7 * j)) & 0x7Fu;
-        const u64 b = (u32)j + 1 < len ? g | 0x80u : g;
-        c |= (u32)j < len ? b << (8 * j) : 0ull;
-    }
-    return c;
+    const u32 lo = (x & 0x7Fu) | ((x << 1) & 0x7F00u) | ((x << 2) & 0x7F0000u) | ((x << 3) & 0x7F000000u);
+    const u64 c = ((u64)(x >> 28) << 32) | lo;
+    const u64 cont = 0x8080808080ull & ((1ull << (8 * (len - 1))) - 1);   // len >= 1
+    return (c | cont) & ((1ull << (8 * len)) - 1);
 }
 
 // Lane l's four values of chunk c (aligned elements 256 c + 4 l .. + 3) as
@@ -3293,17 +3293,24 @@ __device__ __forceinline__ u32 enc_load(const EncArgs &a, u64 c, u32 (&v)[4]) {
     return valid;
 }
 
+// A wavefront takes kEncPerWave consecutive chunks, all loads issued first.
 __global__ __launch_bounds__(256) void k_enc_len(EncArgs a) {
     const u32 ln = lane_id();
-    const u64 c = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (c >= a.nchunks) return;
-    u32 v[4];
-    const u32 valid = enc_load(a, c, v);
-    u32 len = 0;
+    const u64 c0 = ((u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * kEncPerWave;
+    u32 v[kEncPerWave][4], valid[kEncPerWave];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) len += (valid >> k) & 1u ? code_len(v[k]) : 0u;
-    len = wave_sum(len);
-    if (ln == 0) a.csum[c] = len;
+    for (int q = 0; q < kEncPerWave; ++q)
+        valid[q] = c0 + q < a.nchunks ? enc_load(a, c0 + q, v[q]) : 0u;
+    u32 mine = 0;   // lane q ends up with chunk q's count
+#pragma unroll
+    for (int q = 0; q < kEncPerWave; ++q) {
+        u32 len = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) len += (valid[q] >> k) & 1u ? code_len(v[q][k]) : 0u;
+        len = wave_sum(len);
+        mine = ln == (u32)q ? len : mine;
+    }
+    if (ln < (u32)kEncPerWave && c0 + ln < a.nchunks) a.csum[c0 + ln] = mine;
 }
 
 constexpr u64 kEncScanSpan = 8 * kScanBlock;   // chunk counts per scan workgroup (8 per thread)
@@ -3357,14 +3364,11 @@ __global__ __launch_bounds__(kScanBlock) void k_enc_bscan(EncArgs a) {
     if (b == nb - 1 && tid == kScanBlock - 1) *a.d_nbytes = off;   // the last thread's end: the total
 }
 
-__global__ __launch_bounds__(256) void k_enc_write(EncArgs a) {
-    extern __shared__ __align__(16) u32 lds[];
-    const u32 ln = lane_id(), wib = threadIdx.x >> 6;
-    const u64 c = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (c >= a.nchunks) return;
-    u32 *st = lds + wib * kEncStageWords;
-    u32 v[4];
-    const u32 valid = enc_load(a, c, v);
+// Writes one chunk's codes: lane values v (valid mask), chunk byte offset
+// `base`; st is the wavefront's LDS stage.
+__device__ __forceinline__ void enc_write_chunk(const EncArgs &a, u32 *st, const u32 (&v)[4],
+                                                u32 valid, u64 base) {
+    const u32 ln = lane_id();
     u32 len[4], lsum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -3373,11 +3377,10 @@ __global__ __launch_bounds__(256) void k_enc_write(EncArgs a) {
     }
     const u32 incl = wave_scan(lsum);
     const u32 total = read_lane(incl, 63);
-    const u64 base = a.cpre[c];
     // the stage starts at the 16-byte boundary at or below base
     const u32 mis = (u32)(((uintptr_t)a.bytes + base) & 15u);
     const u32 nwords = (mis + total + 3) >> 2;
-    for (u32 q = ln; q < nwords; q += kWave) st[q] = 0;
+    for (u32 q = ln; 4 * q < nwords; q += kWave) *(uint4 *)(st + 4 * q) = make_uint4(0, 0, 0, 0);
     wave_lds_sync();
     u32 off = mis + incl - lsum;
 #pragma unroll
@@ -3391,22 +3394,47 @@ __global__ __launch_bounds__(256) void k_enc_write(EncArgs a) {
         }
     }
     wave_lds_sync();
-    // stores: 16-byte rows of the stage; the first and last rows may hold
-    // bytes of the neighbouring chunks, which are written byte by byte
+    // stores: dwords of the stage, 256 bytes per wavefront instruction; the
+    // first and last dwords may hold bytes of the neighbouring chunks, whose
+    // bytes of them are written by those chunks, so they go out byte by byte
     const u64 gb = base - mis;   // byte index of stage byte 0
     u8 *ob = a.bytes + gb;
-    const u32 nrows = (mis + total + 15) >> 4;
     const u8 *sb = (const u8 *)st;
-    for (u32 q = ln; q < nrows; q += kWave) {
-        const u32 b0 = q << 4;
-        if (b0 >= mis && b0 + 16 <= mis + total && gb + b0 + 16 <= a.capacity) {
-            *(uint4 *)(ob + b0) = *(const uint4 *)(st + 4 * q);
+    const u32 end = mis + total;
+    for (u32 q = ln; q < nwords; q += kWave) {
+        const u32 b0 = q << 2;
+        if (b0 >= mis && b0 + 4 <= end && gb + b0 + 4 <= a.capacity) {
+            *(u32 *)(ob + b0) = st[q];
         } else {
-            for (u32 t = 0; t < 16; ++t) {
+#pragma unroll
+            for (u32 t = 0; t < 4; ++t) {
                 const u32 bb = b0 + t;
-                if (bb >= mis && bb < mis + total && gb + bb < a.capacity) ob[bb] = sb[bb];
+                if (bb >= mis && bb < end && gb + bb < a.capacity) ob[bb] = sb[bb];
             }
         }
+    }
+    wave_lds_sync();   // the stage is zeroed again for the next chunk
+}
+
+__global__ __launch_bounds__(256) void k_enc_write(EncArgs a) {
+    extern __shared__ __align__(16) u32 lds[];
+    const u32 wib = threadIdx.x >> 6;
+    // the last chunks first: the length pass read them last, so the device
+    // cache (MALL) still holds their values when this pass starts
+    const u64 blk = gridDim.x - 1 - blockIdx.x;
+    const u64 c0 = (blk * (blockDim.x >> 6) + (threadIdx.x >> 6)) * kEncWritePerWave;
+    u32 *st = lds + wib * kEncStageWords;
+    u32 vv[kEncWritePerWave][4], vvalid[kEncWritePerWave];
+    u64 pre[kEncWritePerWave];
+#pragma unroll
+    for (int q = 0; q < kEncWritePerWave; ++q) {
+        vvalid[q] = c0 + q < a.nchunks ? enc_load(a, c0 + q, vv[q]) : 0u;
+        pre[q] = c0 + q < a.nchunks ? a.cpre[c0 + q] : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < kEncWritePerWave; ++q) {
+        if (c0 + q >= a.nchunks) break;
+        enc_write_chunk(a, st, vv[q], vvalid[q], pre[q]);
     }
 }
 
@@ -3650,7 +3678,8 @@ hipError_t launch_batch(const ListArgs &a, int segs, int wpb, int grid_blocks, h
 
 hipError_t launch_encode(const EncArgs &a, hipStream_t s) {
     const u32 wpb = 4;
-    const u64 blocks = (a.nchunks + wpb - 1) / wpb;
+    const u64 per_block = (u64)wpb * kEncPerWave;
+    const u64 blocks = (a.nchunks + per_block - 1) / per_block;
     k_enc_len<<<(unsigned)blocks, wpb * kWave, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -3661,7 +3690,8 @@ hipError_t launch_encode(const EncArgs &a, hipStream_t s) {
     k_enc_bscan<<<(unsigned)nsb, kScanBlock, 0, s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_enc_write<<<(unsigned)blocks, wpb * kWave, wpb * kEncStageWords * sizeof(u32), s>>>(a);
+    const u64 wblocks = (a.nchunks + (u64)wpb * kEncWritePerWave - 1) / ((u64)wpb * kEncWritePerWave);
+    k_enc_write<<<(unsigned)wblocks, wpb * kWave, wpb * kEncStageWords * sizeof(u32), s>>>(a);
     return hipGetLastError();
 }
 

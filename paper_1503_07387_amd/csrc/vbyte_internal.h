@@ -180,7 +180,7 @@ struct ListArgs {
 // Encoder (k_enc_*): values addressed from the 16-byte-aligned element at
 // or below values[0]; chunks of kEncChunk aligned elements.
 constexpr uint64_t kEncChunk = 256;
-constexpr uint32_t kEncStageWords = (kEncChunk * 5 + 16 + 3) / 4 + 4;   // a chunk's bytes, 16-byte shifted
+constexpr uint32_t kEncStageWords = (kEncChunk * 5 + 16 + 3) / 4 + 8;   // a chunk's bytes, 16-byte shifted, zeroed in 16-byte units
 struct EncArgs {
     const uint32_t *vbase;   // 16-byte aligned, <= values
     uint64_t e0;             // values - vbase (0..3 elements)
