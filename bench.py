@@ -528,15 +528,38 @@ def bench_batched(torch, vbyte, serve, idx, reps=10):
             "per_list_server_ms_over_graph_event_ms": round(res[False][0] / graph_ms, 1)}
 
 
-def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
+def bench_serving(torch, vbyte, serve, workloads, idx, nq=10000, warm=1000):
     """Config 4: Poisson queries of 2-8 Zipf(1.0) terms over the config-3
-    index; p50/p99 latency and throughput at fractions of saturation QPS."""
+    index; p50/p99 latency (per request: until its own lists are decoded)
+    and throughput at fractions of saturation QPS, each point nq measured
+    queries after `warm` warm-up ones; a sample of served results checked
+    against the batched decode of the whole index."""
     import numpy as np
     d = idx["lists"]
     pos_of_rank = np.argsort(d["rank_of"])
     bo = idx["byte_off"].cpu().numpy()
     counts = d["lengths"].astype("int64")
     nl = counts.size
+    # served results against the batched decode of every list
+    full, lst = vbyte.decode_batch(idx["bytes"], idx["byte_off"], idx["out_off"], delta=True)
+    torch.cuda.synchronize()
+    if int(lst.max().item()) != 0:
+        raise RuntimeError("batched decode of the index reported a bad list")
+    oo = d["out_off"]
+    arr, ranks = workloads.query_stream(300, 1e6, nlists=nl, seed=workloads.SEED_QUERIES + 7)
+    terms = [pos_of_rank[r] for r in ranks]
+    srv = serve.Server(idx["bytes"], bo, counts, pool_bytes=6 << 30, nstreams=4,
+                       max_batch_requests=64, batching=True, delta=True)
+    _, stt, (res, roff) = srv.run(arr, terms, capture=True)
+    srv.close()
+    if stt["worst_status"] != 0 or (stt["status"] != 0).any():
+        raise RuntimeError("served requests reported a bad status")
+    for r in range(0, len(terms), 7):
+        want = torch.cat([full[int(oo[t]):int(oo[t + 1])] for t in terms[r]])
+        if not torch.equal(res[int(roff[r]):int(roff[r + 1])], want):
+            raise RuntimeError(f"served result {r} differs from the batched decode")
+    checked = len(range(0, len(terms), 7))
+    del full, res
 
     def make(qps, n, seed):
         arr, ranks = workloads.query_stream(n, qps, nlists=nl, seed=seed)
@@ -544,7 +567,7 @@ def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
 
     def run(srv, arr, terms):
         lat, stt, _ = srv.run(arr, terms)
-        if stt["worst_status"] != 0 or stt["rejected"]:
+        if stt["worst_status"] != 0 or stt["rejected"] or (stt["status"] != 0).any():
             raise RuntimeError("serving run reported a bad list or a rejected query")
         lat = lat[warm:] if lat.size > warm else lat
         return lat, stt
@@ -581,6 +604,7 @@ def bench_serving(torch, vbyte, serve, workloads, idx, nq=3000, warm=300):
                         "r-th longest list), Poisson arrivals, differential decode into a 6 GiB "
                         "output pool, 4 streams",
             "queries_per_point": nq, "warmup_queries": warm,
+            "results_checked": f"{checked} of 300 requests served at 1M QPS equal the batched decode",
             "saturation_qps": round(sat_qps, 1), "integers_per_query": round(ints_per_query, 1),
             "points": points, "per_list_launches_at_half_saturation": per_list}
 

@@ -373,12 +373,18 @@ void vbyte_server_destroy(vbyte_server *server);
  * arrival_s[r] seconds after the start (non-decreasing) and asks for lists
  * terms[term_off[r] .. term_off[r+1]).  latency_s[r] (HOST) receives
  * completion minus arrival on the host steady clock, or -1 if the request
- * could never fit the pool.  If results (DEVICE uint32) is not NULL, request
- * r's result is copied to results[result_off[r] ..] (result_off: HOST
- * int64[nreq]).  Blocks until every request has completed. */
+ * could never fit the pool; with batching, a request completes when the
+ * last of its own lists is decoded (the batched kernel decodes small lists
+ * first and stamps each request's completion in host memory), else when
+ * its batch's launches end.  req_status (HOST int32[nreq], may be NULL)
+ * receives each request's status: the largest status of its lists, or
+ * VBYTE_ENOMEM for a request larger than the pool.  If results (DEVICE
+ * uint32) is not NULL, request r's result is copied to
+ * results[result_off[r] ..] (result_off: HOST int64[nreq]).  Blocks until
+ * every request has completed. */
 vbyte_status vbyte_server_run(vbyte_server *server, size_t nreq, const double *arrival_s,
                               const int64_t *term_off, const int64_t *terms, double *latency_s,
-                              uint32_t *results, const int64_t *result_off,
+                              int32_t *req_status, uint32_t *results, const int64_t *result_off,
                               vbyte_serve_stats *stats);
 
 /* ------------------------------------------------------------ encoder */

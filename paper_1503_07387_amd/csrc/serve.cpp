@@ -14,9 +14,13 @@
 //     one batch: its lists become gather rows, copied to the device, and one
 //     vbyte_decode_lists launch decodes them all; with several streams,
 //     batches overlap on the GPU while new requests keep being admitted;
-//   * a batch completes when its event fires: per-list statuses are checked,
-//     latencies taken (host steady clock), results optionally copied out, and
-//     the pool ranges freed.
+//   * a batch's requests are sorted by output size and cut into up to four
+//     groups, smallest first, each decoded by its own launch followed by an
+//     event, so that a request's latency (host steady clock) ends with its
+//     group, not with the largest request of the batch;
+//   * a batch completes when its last event fires: per-list statuses give
+//     each request's status, results are optionally copied out, and the
+//     pool ranges freed.
 // The "per-list launches" mode replaces the batched launch by one
 // single-stream launch per list (the baseline the batched form is compared
 // against).
@@ -39,16 +43,27 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// A batch is decoded in up to kGroups launches: its requests sorted by
+// output size, smallest first, cut into groups of about equal count; each
+// group's launch is followed by an event, so a request's completion is its
+// group's event, not the end of the whole batch.
+constexpr int kGroups = 4;
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t gdone[kGroups] = {};
     int64_t *h_rows = nullptr;    // pinned
     int64_t *d_rows = nullptr;
     int32_t *h_status = nullptr;  // pinned
     int32_t *d_status = nullptr;
     size_t cap_rows = 0;
     bool busy = false;
-    std::vector<size_t> reqs;     // requests of the batch in flight
+    std::vector<size_t> reqs;        // requests of the batch in flight, in group order
+    std::vector<int64_t> req_row0;   // first row of each request of the batch
+    std::vector<size_t> gend;        // end (in reqs) of every group
+    std::vector<char> gseen;         // group completion already taken
+    bool grouped = false;            // the batch's groups have events
     size_t nrows = 0;
 };
 
@@ -116,6 +131,8 @@ static void destroy_slots(vbyte_server *s) {
         if (sl.d_rows) (void)hipFree(sl.d_rows);
         if (sl.h_status) (void)hipHostFree(sl.h_status);
         if (sl.d_status) (void)hipFree(sl.d_status);
+        for (hipEvent_t &e : sl.gdone)
+            if (e) (void)hipEventDestroy(e);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     s->slots.clear();
@@ -167,9 +184,10 @@ vbyte_status vbyte_server_create(const uint8_t *index_bytes, size_t nbytes, cons
     }
     s->slots.resize(cfg->nstreams);
     for (Slot &sl : s->slots) {
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            ensure_rows(sl, 1024) != VBYTE_OK) {
+        bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+        for (hipEvent_t &e : sl.gdone) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (!ok || ensure_rows(sl, 1024) != VBYTE_OK) {
             destroy_slots(s);
             (void)hipFree(s->pool);
             delete s;
@@ -189,7 +207,7 @@ void vbyte_server_destroy(vbyte_server *s) {
 
 vbyte_status vbyte_server_run(vbyte_server *s, size_t nreq, const double *arrival_s,
                               const int64_t *term_off, const int64_t *terms, double *latency_s,
-                              uint32_t *results, const int64_t *result_off,
+                              int32_t *req_status, uint32_t *results, const int64_t *result_off,
                               vbyte_serve_stats *stats) {
     if (!s || (nreq && (!arrival_s || !term_off || !terms || !latency_s))) return VBYTE_EINVAL;
     if (results && !result_off) return VBYTE_EINVAL;
@@ -224,16 +242,38 @@ vbyte_status vbyte_server_run(vbyte_server *s, size_t nreq, const double *arriva
         double now = now_s();
         while (next < nreq && arrival_s[next] <= now) pending.push_back(next++);
 
-        // completions
+        // completions: a request is done when its group's launch has ended
+        // (its group event), at the latest with its batch (the batch event,
+        // which also ends the status and result copies); the batch's pool
+        // ranges are released and its statuses read at the batch event
         for (Slot &sl : s->slots) {
             if (!sl.busy) continue;
+            for (size_t g = 0; sl.grouped && g + 1 < sl.gend.size(); ++g) {
+                if (sl.gseen[g]) continue;
+                hipError_t q = hipEventQuery(sl.gdone[g]);
+                if (q == hipErrorNotReady) break;   // groups end in order
+                if (q != hipSuccess) return VBYTE_EHIP;
+                const double t = now_s();
+                for (size_t k = sl.gend[g]; k < sl.gend[g + 1]; ++k) latency_s[sl.reqs[k]] = t - arrival_s[sl.reqs[k]];
+                sl.gseen[g] = 1;
+                progressed = true;
+            }
             hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
             if (q != hipSuccess) return VBYTE_EHIP;
             const double t = now_s();
-            for (size_t k = 0; k < sl.nrows; ++k) worst = std::max<int32_t>(worst, sl.h_status[k]);
-            for (size_t r : sl.reqs) {
-                latency_s[r] = t - arrival_s[r];
+            for (size_t g = 0; g + 1 < sl.gend.size(); ++g) {
+                if (sl.gseen[g]) continue;
+                for (size_t k = sl.gend[g]; k < sl.gend[g + 1]; ++k) latency_s[sl.reqs[k]] = t - arrival_s[sl.reqs[k]];
+                sl.gseen[g] = 1;
+            }
+            for (size_t k = 0; k < sl.reqs.size(); ++k) {
+                const size_t r = sl.reqs[k];
+                int32_t rs = VBYTE_OK;
+                for (int64_t j = sl.req_row0[k]; j < sl.req_row0[k + 1]; ++j)
+                    rs = std::max<int32_t>(rs, sl.h_status[j]);
+                if (req_status) req_status[r] = rs;
+                worst = std::max<int32_t>(worst, rs);
                 pool.release(pool_off[r], need[r]);
                 ++completed;
             }
@@ -247,11 +287,11 @@ vbyte_status vbyte_server_run(vbyte_server *s, size_t nreq, const double *arriva
             if (sl.busy || pending.empty()) continue;
             std::vector<size_t> batch;
             size_t rows = 0;
-            uint64_t list_bytes = 0;
             while (!pending.empty() && batch.size() < cap) {
                 const size_t r = pending.front();
                 if (need[r] > s->pool_elems) {   // can never fit: reject
                     latency_s[r] = -1.0;
+                    if (req_status) req_status[r] = VBYTE_ENOMEM;
                     ++st.rejected;
                     ++completed;
                     pending.pop_front();
@@ -267,30 +307,49 @@ vbyte_status vbyte_server_run(vbyte_server *s, size_t nreq, const double *arriva
             if (batch.empty()) break;
             vbyte_status es = ensure_rows(sl, rows);
             if (es != VBYTE_OK) return es;
+            // groups: the batch's requests by output size, smallest first
+            std::stable_sort(batch.begin(), batch.end(),
+                             [&](size_t x, size_t y) { return need[x] < need[y]; });
+            const size_t ng = s->cfg.batching ? std::min<size_t>(kGroups, batch.size()) : 1;
+            sl.gend.assign(ng + 1, 0);
+            for (size_t g = 0; g <= ng; ++g) sl.gend[g] = g * batch.size() / ng;
+            sl.gseen.assign(ng, 0);
             size_t k = 0;
-            for (size_t r : batch) {
+            sl.req_row0.assign(batch.size() + 1, 0);
+            for (size_t b = 0; b < batch.size(); ++b) {
+                const size_t r = batch[b];
                 uint64_t pos = pool_off[r];
+                sl.req_row0[b] = (int64_t)k;
                 for (int64_t j = term_off[r]; j < term_off[r + 1]; ++j) {
                     const int64_t t = terms[j];
                     sl.h_rows[4 * k + 0] = s->byte_off[t];
                     sl.h_rows[4 * k + 1] = s->byte_off[t + 1];
                     sl.h_rows[4 * k + 2] = (int64_t)pos;
                     sl.h_rows[4 * k + 3] = s->counts[t];
-                    list_bytes += (uint64_t)(s->byte_off[t + 1] - s->byte_off[t]);
                     pos += (uint64_t)s->counts[t];
                     ++k;
                 }
             }
+            sl.req_row0[batch.size()] = (int64_t)k;
             if (rows) {
                 if (s->cfg.batching) {
                     if (hipMemcpyAsync(sl.d_rows, sl.h_rows, rows * 4 * sizeof(int64_t),
                                        hipMemcpyHostToDevice, sl.stream) != hipSuccess)
                         return VBYTE_EHIP;
-                    vbyte_status ls = vbyte_decode_lists(s->index, s->nbytes, sl.d_rows, rows, list_bytes,
-                                                         s->pool, s->pool_elems, nullptr, delta ? 1 : 0,
-                                                         sl.d_status, sl.stream);
-                    if (ls != VBYTE_OK) return ls;
-                    ++launches;
+                    for (size_t g = 0; g < ng; ++g) {
+                        const int64_t r0 = sl.req_row0[sl.gend[g]], r1 = sl.req_row0[sl.gend[g + 1]];
+                        uint64_t gbytes = 0;
+                        for (int64_t j = r0; j < r1; ++j)
+                            gbytes += (uint64_t)(sl.h_rows[4 * j + 1] - sl.h_rows[4 * j]);
+                        if (r1 > r0) {
+                            vbyte_status ls = vbyte_decode_lists(
+                                s->index, s->nbytes, sl.d_rows + 4 * r0, (size_t)(r1 - r0), gbytes, s->pool,
+                                s->pool_elems, nullptr, delta ? 1 : 0, sl.d_status + r0, sl.stream);
+                            if (ls != VBYTE_OK) return ls;
+                            ++launches;
+                        }
+                        if (hipEventRecord(sl.gdone[g], sl.stream) != hipSuccess) return VBYTE_EHIP;
+                    }
                 } else {
                     for (size_t j = 0; j < rows; ++j) {
                         const int64_t *row = sl.h_rows + 4 * j;
@@ -316,6 +375,9 @@ vbyte_status vbyte_server_run(vbyte_server *s, size_t nreq, const double *arriva
                                    sl.stream) != hipSuccess)
                     return VBYTE_EHIP;
             }
+            // without group launches (one launch per list, or no rows) the
+            // requests complete with the batch event only
+            sl.grouped = s->cfg.batching && rows;
             if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return VBYTE_EHIP;
             sl.reqs = batch;
             sl.nrows = rows;

@@ -35,7 +35,8 @@ def _declare(lib):
     lib.vbyte_server_destroy.argtypes = [c.c_void_p]
     lib.vbyte_server_destroy.restype = None
     lib.vbyte_server_run.argtypes = [c.c_void_p, c.c_size_t, c.c_void_p, c.c_void_p, c.c_void_p,
-                                     c.c_void_p, c.c_void_p, c.c_void_p, c.POINTER(ServeStats)]
+                                     c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p,
+                                     c.POINTER(ServeStats)]
     lib.vbyte_server_run.restype = c.c_int
     lib._serve_declared = True
     return lib
@@ -72,7 +73,8 @@ class Server:
         """Run one open-loop workload.  arrivals: seconds (non-decreasing);
         terms: list of int64 arrays of list indices.  Returns (latencies in
         seconds, stats dict, results) where results is (uint32 CUDA tensor,
-        offsets) when capture is set."""
+        offsets) when capture is set; stats["status"] holds every request's
+        status (int32 array)."""
         torch.cuda.synchronize()
         arrivals = np.ascontiguousarray(arrivals, dtype=np.float64)
         nreq = arrivals.size
@@ -80,6 +82,7 @@ class Server:
         term_off[1:] = np.cumsum([len(t) for t in terms])
         flat = np.ascontiguousarray(np.concatenate(terms) if nreq else np.zeros(0), dtype=np.int64)
         lat = np.zeros(nreq, np.float64)
+        rst = np.zeros(nreq, np.int32)
         res = None
         res_off = None
         if capture:
@@ -89,13 +92,14 @@ class Server:
             res = torch.empty(max(int(res_off[-1]), 1), dtype=torch.int32, device=self.index.device)
         stats = ServeStats()
         st = self.lib.vbyte_server_run(self.handle, nreq, _np_ptr(arrivals), _np_ptr(term_off),
-                                       _np_ptr(flat), _np_ptr(lat),
+                                       _np_ptr(flat), _np_ptr(lat), _np_ptr(rst),
                                        ctypes.c_void_p(res.data_ptr()) if capture else ctypes.c_void_p(0),
                                        _np_ptr(res_off) if capture else ctypes.c_void_p(0),
                                        ctypes.byref(stats))
         if st != vbyte.OK:
             raise vbyte.VByteError(st, "server_run")
         out = {k: getattr(stats, k) for k, _ in ServeStats._fields_}
+        out["status"] = rst
         return lat, out, ((res, res_off) if capture else None)
 
     def close(self):

@@ -132,3 +132,49 @@ def test_config3_alone_equals_in_mix(config3):
         assert np.array_equal(u32(alone)[:aoff[1]], hm[moff[r]:moff[r + 1]]), r
         assert np.array_equal(hm[moff[r]:moff[r + 1]], expected(config3, terms[r])), r
     srv.close()
+
+
+def test_small_request_does_not_wait_for_the_largest_in_its_batch():
+    """Two requests admitted together into one batch: one asks for three
+    16Mi-integer lists, the other for two 100-integer lists.  The small
+    request completes when its own lists are decoded (small lists go first,
+    and its completion is stamped by the kernel), well before the batch
+    ends; both results equal the oracle's."""
+    rng = np.random.default_rng(77)
+    lens = np.array([1 << 24, 1 << 24, 1 << 24, 100, 100, 5], np.int64)
+    gaps = [rng.geometric(1 / 50, int(n)).astype(np.uint32) for n in lens]
+    enc = [oracle.encode(g) for g in gaps]
+    byte_off = np.concatenate([[0], np.cumsum([e.size for e in enc])]).astype(np.int64)
+    b = np.concatenate(enc)
+    idx = {"bytes": b, "byte_off": byte_off, "counts": lens, "dev": torch.from_numpy(b).cuda()}
+    terms = [np.array([0, 1, 2], np.int64), np.array([3, 4], np.int64)]
+    srv = serve.Server(idx["dev"], byte_off, lens, pool_bytes=1 << 30, nstreams=1,
+                       max_batch_requests=8)
+    worst_ratio = 0.0
+    for rep in range(4):
+        lat, stats, (res, off) = srv.run(np.zeros(2), terms, capture=True)
+        assert stats["batches"] == 1 and stats["worst_status"] == vbyte.OK
+        assert (stats["status"] == vbyte.OK).all()
+        h = u32(res)
+        for r in range(2):
+            assert np.array_equal(h[off[r]:off[r + 1]], expected(idx, terms[r])), r
+        if rep:
+            worst_ratio = max(worst_ratio, lat[1] / lat[0])
+    srv.close()
+    assert worst_ratio < 0.5, f"the small request took {worst_ratio:.2f} of the large one's latency"
+
+
+def test_request_status_reports_a_bad_list():
+    rng = np.random.default_rng(78)
+    lens = np.array([1000, 2000, 3000], np.int64)
+    gaps = [rng.geometric(1 / 50, int(n)).astype(np.uint32) for n in lens]
+    enc = [oracle.encode(g) for g in gaps]
+    enc[1][100:106] = 0x80          # list 1 malformed
+    byte_off = np.concatenate([[0], np.cumsum([e.size for e in enc])]).astype(np.int64)
+    b = np.concatenate(enc)
+    srv = serve.Server(torch.from_numpy(b).cuda(), byte_off, lens, pool_bytes=1 << 24, nstreams=2)
+    terms = [np.array([0], np.int64), np.array([0, 1], np.int64), np.array([2], np.int64)]
+    lat, stats, _ = srv.run(np.zeros(3), terms)
+    srv.close()
+    assert stats["status"].tolist() == [vbyte.OK, vbyte.EMALFORMED, vbyte.OK]
+    assert stats["worst_status"] == vbyte.EMALFORMED and (lat > 0).all()
