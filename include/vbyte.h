@@ -26,6 +26,13 @@
  *     stream.  Work is enqueued in stream order; calls on one stream are
  *     ordered, calls on different streams are independent (each stream has
  *     its own workspace).
+ *   Threads.  Calls may come from several host threads.  A call that uses
+ *     a stream's workspace holds that (device, stream)'s lock from its first
+ *     look at the workspace to its last enqueue, and a synchronous call until
+ *     it returns, so calls on one stream from two threads are serialised and
+ *     never share descriptors or a status slot while in flight.  The tuning
+ *     set by vbyte_set_* and the autotuners is process-wide; changing it
+ *     while another thread decodes changes that thread's next call.
  *   Strict semantics (the paper is silent on these).  A stream is valid iff
  *     bytes[0..nbytes) is exactly n codes ending at its last byte:
  *       VBYTE_EMALFORMED  five or more consecutive bytes >= 0x80 anywhere;

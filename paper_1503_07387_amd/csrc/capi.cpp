@@ -60,6 +60,30 @@ struct Workspace {
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+std::map<std::pair<int, hipStream_t>, std::recursive_mutex> g_stream_mu;
+
+// Held by every call that uses a stream's workspace, from its first look at
+// the workspace to its last enqueue (synchronous calls: until they return),
+// so that calls on one stream from several host threads do not interleave
+// their launches on the shared descriptors and status slot.
+class StreamGuard {
+  public:
+    explicit StreamGuard(hipStream_t s) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            mu_ = &g_stream_mu[{dev, s}];
+        }
+        mu_->lock();
+    }
+    ~StreamGuard() { mu_->unlock(); }
+    StreamGuard(const StreamGuard &) = delete;
+    StreamGuard &operator=(const StreamGuard &) = delete;
+
+  private:
+    std::recursive_mutex *mu_;
+};
 
 struct Cleanup {
     ~Cleanup() {
@@ -236,6 +260,7 @@ vbyte_status decode_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, s
 
 vbyte_status decode_sync(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n, uint32_t prev,
                          int delta) {
+    StreamGuard guard_(nullptr);
     hipStream_t s = nullptr;
     int32_t *slot = nullptr;
     vbyte_status st = decode_stream(bytes, nbytes, out, n, prev, delta, nullptr, s, &slot);
@@ -335,6 +360,7 @@ vbyte_status decode4_stream(const uint8_t *bytes, size_t nbytes, uint32_t *out, 
 
 vbyte_status decode64_sync(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
                            uint64_t prev, int delta) {
+    StreamGuard guard_(nullptr);
     hipStream_t s = nullptr;
     int32_t *slot = nullptr;
     vbyte_status st = decode64_stream(bytes, nbytes, out, n, prev, delta, nullptr, s, &slot);
@@ -430,17 +456,20 @@ vbyte_status vbyte_decode_delta(const uint8_t *bytes, size_t nbytes, uint32_t *o
 
 vbyte_status vbyte_decode_async(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
                                 int32_t *d_status, void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return decode_stream(bytes, nbytes, out, n, 0, 0, d_status, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_decode_delta_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
                                       size_t n, uint32_t prev, int32_t *d_status, void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return decode_stream(bytes, nbytes, out, n, prev, 1, d_status, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_decode_ex(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
                              uint32_t prev, int mode, const vbyte_tuning *tuning, int32_t *d_status,
                              void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     if (!d_status) return VBYTE_EINVAL;
     return decode_stream(bytes, nbytes, out, n, prev, mode, d_status, (hipStream_t)stream, nullptr,
                          tuning);
@@ -506,11 +535,13 @@ vbyte_status vbyte_decode_delta_m1(const uint8_t *bytes, size_t nbytes, uint32_t
 vbyte_status vbyte_decode_delta_m1_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
                                          size_t n, uint32_t prev, int32_t *d_status,
                                          void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return decode_stream(bytes, nbytes, out, n, prev, 2, d_status, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_decode_delta4(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t n,
                                  const uint32_t *prev4) {
+    StreamGuard guard_(nullptr);
     hipStream_t s = nullptr;
     int32_t *slot = nullptr;
     vbyte_status st = decode4_stream(bytes, nbytes, out, n, prev4, nullptr, s, &slot);
@@ -526,6 +557,7 @@ vbyte_status vbyte_decode_delta4(const uint8_t *bytes, size_t nbytes, uint32_t *
 vbyte_status vbyte_decode_delta4_async(const uint8_t *bytes, size_t nbytes, uint32_t *out,
                                        size_t n, const uint32_t *prev4, int32_t *d_status,
                                        void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return decode4_stream(bytes, nbytes, out, n, prev4, d_status, (hipStream_t)stream);
 }
 
@@ -540,17 +572,20 @@ vbyte_status vbyte_decode64_delta(const uint8_t *bytes, size_t nbytes, uint64_t 
 
 vbyte_status vbyte_decode64_async(const uint8_t *bytes, size_t nbytes, uint64_t *out, size_t n,
                                   int32_t *d_status, void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return decode64_stream(bytes, nbytes, out, n, 0, 0, d_status, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_decode64_delta_async(const uint8_t *bytes, size_t nbytes, uint64_t *out,
                                         size_t n, uint64_t prev, int32_t *d_status, void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return decode64_stream(bytes, nbytes, out, n, prev, 1, d_status, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32_t *out, size_t k,
                                      int delta, const vbyte_cursor *d_in, vbyte_cursor *d_out,
                                      int32_t *d_status, void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     hipStream_t s = (hipStream_t)stream;
     if (k == 0 || k > (1ull << 40) || !out || ((uintptr_t)out & 3u)) return VBYTE_EINVAL;
     if (!d_in || !d_out || d_in == d_out || ((uintptr_t)d_in & 7u) || ((uintptr_t)d_out & 7u))
@@ -597,6 +632,7 @@ vbyte_status vbyte_intersect_async(const uint8_t *a, size_t a_nbytes, size_t na,
                                    const uint32_t *b, size_t nb, size_t piece, uint32_t *out,
                                    size_t out_cap, uint64_t *d_count, int32_t *d_status,
                                    void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     hipStream_t s = (hipStream_t)stream;
     if (piece == 0 || piece > (1ull << 26)) return VBYTE_EINVAL;
     if (a_nbytes >= kMaxBytes || (a_nbytes > 0 && !a)) return VBYTE_EINVAL;
@@ -648,6 +684,7 @@ vbyte_status vbyte_intersect_async(const uint8_t *a, size_t a_nbytes, size_t na,
 }
 
 vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count, void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     hipStream_t s = (hipStream_t)stream;
     if (!d_count || ((uintptr_t)d_count & 7u)) return VBYTE_EINVAL;
     if (nbytes >= kMaxBytes) return VBYTE_EINVAL;
@@ -682,6 +719,7 @@ vbyte_status vbyte_decode_batch(const uint8_t *bytes, size_t nbytes, const int64
                                 uint32_t *out, size_t nout, const int64_t *out_off, size_t nlists,
                                 const uint32_t *prevs, int delta, int32_t *d_list_status,
                                 void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     if (nlists > 0 && (!byte_off || !out_off)) return VBYTE_EINVAL;
     if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     ListArgs a{};
@@ -704,6 +742,7 @@ vbyte_status vbyte_decode_lists(const uint8_t *bytes, size_t nbytes, const int64
                                 size_t nlists, size_t list_bytes, uint32_t *out, size_t nout,
                                 const uint32_t *prevs, int delta, int32_t *d_list_status,
                                 void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     if (nlists > 0 && !lists) return VBYTE_EINVAL;
     if (delta < 0 || delta > 2) return VBYTE_EINVAL;
     ListArgs a{};
@@ -766,24 +805,28 @@ static vbyte_status encode_common(const uint32_t *values, size_t n, uint32_t pre
 
 vbyte_status vbyte_encode_async(const uint32_t *values, size_t n, uint8_t *bytes, size_t capacity,
                                 uint64_t *d_nbytes, void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return encode_common(values, n, 0, 0, bytes, capacity, d_nbytes, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_encode_delta_async(const uint32_t *values, size_t n, uint32_t prev,
                                       uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
                                       void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return encode_common(values, n, prev, 1, bytes, capacity, d_nbytes, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_encode_delta_m1_async(const uint32_t *values, size_t n, uint32_t prev,
                                          uint8_t *bytes, size_t capacity, uint64_t *d_nbytes,
                                          void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     return encode_common(values, n, prev, 2, bytes, capacity, d_nbytes, (hipStream_t)stream);
 }
 
 vbyte_status vbyte_encode_batch(const uint32_t *values, size_t n, const int64_t *vals_off,
                                 size_t nlists, uint8_t *bytes, size_t capacity, int64_t *byte_off,
                                 uint64_t *d_nbytes, void *stream) {
+    StreamGuard guard_((hipStream_t)stream);
     if (nlists > 0 && (!vals_off || !byte_off)) return VBYTE_EINVAL;
     if (((uintptr_t)byte_off & 7u) || ((uintptr_t)vals_off & 7u)) return VBYTE_EINVAL;
     hipStream_t s = (hipStream_t)stream;

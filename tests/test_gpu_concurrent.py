@@ -139,3 +139,37 @@ def test_per_call_tilings_on_two_streams(pair):
         assert int(st.item()) == sto == oracle.OK
         assert np.array_equal(u32(out), ref)
     assert vbyte.get_tuning() == before
+
+
+def test_host_threads_share_one_stream():
+    """Four host threads decode on one stream at once, each with its own size
+    (so the stream's workspace grows while others use it), checked decodes
+    that read their status back, and asynchronous encodes in between."""
+    from concurrent.futures import ThreadPoolExecutor
+    st = torch.cuda.Stream()
+    sizes = [(1 << 14) + 3, (1 << 18) + 77, (1 << 21) + 5, (1 << 22) + 1001]
+    ins = []
+    for k, n in enumerate(sizes):
+        g = workloads.geometric_gaps(n=n, mean=8 if k % 2 else 300)
+        ins.append((g, torch.from_numpy(oracle.encode(g)).cuda(),
+                    torch.from_numpy(g.view(np.int32)).cuda()))
+    torch.cuda.synchronize()
+
+    def work(k):
+        g, d, gv = ins[k]
+        res = []
+        for _ in range(6):
+            y = vbyte.decode(d, g.size, delta=True, stream=st)
+            b = vbyte.encode(gv, stream=st)
+            res.append((u32(y), b.cpu().numpy()))
+        return res
+
+    with ThreadPoolExecutor(4) as ex:
+        outs = list(ex.map(work, range(4)))
+    torch.cuda.synchronize()
+    for (g, d, gv), res in zip(ins, outs):
+        want = np.cumsum(g, dtype=np.uint64).astype(np.uint32)
+        want_b = oracle.encode(g)
+        for y, b in res:
+            assert np.array_equal(y, want)
+            assert np.array_equal(b, want_b)
