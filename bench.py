@@ -352,11 +352,13 @@ def bench_delta4(torch, vbyte, streams, reps=10):
 
 
 def bench_intersect(torch, vbyte, streams, reps=5):
-    """List intersection by the consumer of resumable pieces
-    (vbyte_intersect_async): the gap-mean-8 stream (64Mi identifiers) against
-    a sorted list of 1Mi identifiers (half drawn from the long list), for
-    several piece sizes; a piece of the whole list is the decode-then-consume
-    baseline.  Checked against torch.isin."""
+    """List intersection with the decode fused into the consumer
+    (vbyte_intersect_async): the gap-mean-8 stream (64Mi identifiers)
+    against a sorted list of 1Mi identifiers (half drawn from the long
+    list), at several piece sizes (the piece size changes only the status of
+    a bad list), beside decode-then-consume (the whole list decoded to HBM by
+    vbyte_decode_delta, then torch.isin and a masked select).  Checked
+    against torch.isin."""
     s = streams[0]
     n = N_STREAM
     ids = torch.cumsum(s["gaps_dev"].to(torch.int64) & 0xFFFFFFFF, 0)   # no wrap at gap mean 8
@@ -369,9 +371,20 @@ def bench_intersect(torch, vbyte, streams, reps=5):
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     cnt = torch.empty(1, dtype=torch.int64, device="cuda")
     st = torch.empty(1, dtype=torch.int32, device="cuda")
-    vbyte.set_tuning(2, 8, 0)
-    rows = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    nbytes = s["bytes"].numel()
+    rows = []
     for piece in (1 << 18, 1 << 20, 1 << 22, n):
         vbyte.intersect(s["bytes"], n, b32, piece=piece, out=out, count=cnt, status=st, check=False)
         torch.cuda.synchronize()
@@ -379,18 +392,29 @@ def bench_intersect(torch, vbyte, streams, reps=5):
         if int(st.item()) != 0 or c != want.numel() or \
                 not torch.equal(out[:c].to(torch.int64) & 0xFFFFFFFF, want):
             raise RuntimeError(f"intersection differs from torch.isin (piece {piece})")
-        e0.record()
-        for _ in range(reps):
-            vbyte.intersect(s["bytes"], n, b32, piece=piece, out=out, count=cnt, status=st,
-                            check=False)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        rows.append({"piece": piece, "pieces": (n + piece - 1) // piece,
-                     "piece_buffer_bytes": piece * 5, "ms": round(ms, 4),
-                     "gints_per_s": round(n / (ms / 1e3) / 1e9, 2)})
+        ms = timed(lambda: vbyte.intersect(s["bytes"], n, b32, piece=piece, out=out, count=cnt,
+                                           status=st, check=False))
+        alg = nbytes + 4 * c   # list bytes read once, matches written
+        rows.append({"piece": piece, "ms": round(ms, 4), "gints_per_s": round(n / (ms / 1e3) / 1e9, 2),
+                     "alg_gbps": round(alg / (ms / 1e3) / 1e9, 1)})
+    dec = torch.empty(n, dtype=torch.int32, device="cuda")
+    bl = b.to(torch.int64)
+
+    def decode_then_consume():
+        vbyte.decode(s["bytes"], n, delta=True, out=dec, status=st, check=False)
+        x = dec.to(torch.int64) & 0xFFFFFFFF
+        return x[torch.isin(x, bl)]
+
+    got = decode_then_consume()
+    if not torch.equal(got, want):
+        raise RuntimeError("decode-then-consume differs from torch.isin")
+    base_ms = timed(decode_then_consume)
     return {"workload": "64Mi-identifier list (gap mean 8) intersected with 1Mi sorted identifiers",
-            "matches": int(want.numel()), "points": rows}
+            "kernels": "k_tile_agg + block scans + k_isect_tiles (count) + k_isect_status + "
+                       "block scans + k_isect_tiles (store)",
+            "matches": int(want.numel()), "points": rows,
+            "workspace_bytes": 32 * ((nbytes + 16383) // 16384),
+            "decode_then_torch_isin_ms": round(base_ms, 4)}
 
 
 def build_index(torch, vbyte, workloads):
@@ -1085,7 +1109,7 @@ def main():
         log("blocks-of-four decode ...")
         res["delta4"] = bench_delta4(torch, vbyte, streams)
     if not args.no_intersect:
-        log("intersection by pieces ...")
+        log("intersection ...")
         res["intersect"] = bench_intersect(torch, vbyte, streams)
     del streams
     torch.cuda.empty_cache()

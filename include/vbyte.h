@@ -242,25 +242,32 @@ vbyte_status vbyte_decode_next_async(const uint8_t *bytes, size_t nbytes, uint32
                                      int delta, const vbyte_cursor *d_in, vbyte_cursor *d_out,
                                      int32_t *d_status, void *stream);
 
-/* List intersection by a consumer of resumable pieces (section 5 decodes
- * long lists piece by piece into a buffer that stays in cache; this fuses
- * that decode with a consumer).  The differential list a (na identifiers,
- * from a_prev) is decoded `piece` integers at a time into a buffer of the
- * library (vbyte_decode_next_async, at most 2 segments per wavefront); after
- * each piece, its identifiers that occur in the sorted array b[0..nb) are
- * appended, in list order, to out.  No host synchronisation between pieces,
- * and the long list is never written out whole.
+/* List intersection with the decode fused into its consumer (section 5
+ * decodes long lists into a buffer that stays in cache and consumes them
+ * from there; here the buffer is the registers of the workgroup that decodes
+ * a tile, so the list's identifiers are never written out).  Every
+ * identifier of the differential list a (na identifiers, from a_prev) that
+ * occurs in the sorted array b[0..nb) is written, in list order, to out.
+ * Two passes over a's bytes give each tile its rank and running identifier
+ * (as the two-pass decode); each tile is then decoded twice, once to count
+ * its matches and, after a scan of the counts, once to store them.  Each
+ * identifier is tested by a binary search in the window of b between the
+ * smallest and largest identifiers of its wavefront, held in LDS when it
+ * has at most 1152 entries.
  *   a: device bytes; b, out: device uint32, 4-byte aligned; b sorted
- *   ascending (duplicates allowed).  Every identifier of a that occurs in b
- *   is kept (duplicates in a too).
+ *   ascending (duplicates allowed), nb < 2^32.  Every identifier of a that
+ *   occurs in b is kept (duplicates in a too).
  *   *d_count (device uint64): the number of matches; only out[0..out_cap)
  *   is written, so a count above out_cap means matches were dropped.
- *   *d_status (device int32): the worst status of a piece (a failing piece
- *   leaves the cursor, so later pieces fail alike), else VBYTE_ETRUNC when
- *   a holds fewer than na codes, else VBYTE_ECOUNT when bytes remain after
- *   its na-th code, else VBYTE_OK.
- *   piece: 1 .. 2^26 integers; the library keeps a buffer of 5 bytes per
- *   integer of the piece per stream.
+ *   *d_status (device int32): the status that decoding a in pieces of
+ *   `piece` integers (vbyte_decode_next_async from the start, a failing
+ *   piece leaving the cursor) gives: the worst piece status, else
+ *   VBYTE_ETRUNC when a holds fewer than na codes, else VBYTE_ECOUNT when
+ *   codes or bytes remain after its na-th code, else VBYTE_OK.  VBYTE_OK
+ *   holds exactly when a is na well-formed codes.  On a data error out and
+ *   *d_count are unspecified.
+ *   piece: 1 .. 2^26 integers; it changes only the status of a bad list.
+ *   Workspace: 32 bytes per 16 KiB of a, per stream.
  * Returns VBYTE_EINVAL for bad arguments before enqueuing anything. */
 vbyte_status vbyte_intersect_async(const uint8_t *a, size_t a_nbytes, size_t na, uint32_t a_prev,
                                    const uint32_t *b, size_t nb, size_t piece, uint32_t *out,

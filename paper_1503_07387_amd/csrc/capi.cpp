@@ -635,52 +635,49 @@ vbyte_status vbyte_intersect_async(const uint8_t *a, size_t a_nbytes, size_t na,
     StreamGuard guard_((hipStream_t)stream);
     hipStream_t s = (hipStream_t)stream;
     if (piece == 0 || piece > (1ull << 26)) return VBYTE_EINVAL;
-    if (a_nbytes >= kMaxBytes || (a_nbytes > 0 && !a)) return VBYTE_EINVAL;
-    if ((nb > 0 && !b) || ((uintptr_t)b & 3u)) return VBYTE_EINVAL;
+    if (a_nbytes >= kMaxBytes || (a_nbytes > 0 && !a) || na >= kMaxBytes) return VBYTE_EINVAL;
+    if ((nb > 0 && !b) || ((uintptr_t)b & 3u) || nb >= (1ull << 32)) return VBYTE_EINVAL;
     if ((out_cap > 0 && !out) || ((uintptr_t)out & 3u)) return VBYTE_EINVAL;
     if (!d_count || ((uintptr_t)d_count & 7u) || !d_status || ((uintptr_t)d_status & 3u))
         return VBYTE_EINVAL;
-    // piece buffer, flags, per-workgroup counts, two cursors, piece status, pending
-    const uint64_t blocks = (piece + kIsectElemsPerBlock - 1) / kIsectElemsPerBlock;
-    const size_t off_flags = (piece * 4 + 255) & ~(size_t)255;
-    const size_t off_counts = (off_flags + blocks * kIsectElemsPerBlock + 255) & ~(size_t)255;
-    const size_t off_cur = (off_counts + blocks * 4 + 255) & ~(size_t)255;
-    const size_t need = off_cur + 256;
-    Workspace *w = nullptr;
-    vbyte_status st = get_ws(s, kHeaderBytes, 0, &w);
-    if (st != VBYTE_OK) return st;
-    uint8_t *p = nullptr;
-    st = aux_area(w, s, need, &p);
-    if (st != VBYTE_OK) return st;
-    uint64_t *cur[2] = {(uint64_t *)(p + off_cur), (uint64_t *)(p + off_cur + 64)};
+    if (a_nbytes == 0) {
+        hipError_t e = launch_set_u64(d_count, 0, s);
+        if (e == hipSuccess) e = launch_set_status(d_status, na == 0 ? VBYTE_OK : VBYTE_ETRUNC, s);
+        return e == hipSuccess ? VBYTE_OK : hip_fail(e, "intersect of an empty list");
+    }
     IsectArgs ia{};
-    ia.piece = (const uint32_t *)p;
-    ia.piece_status = (const int32_t *)(p + off_cur + 128);
+    StreamArgs &sa = ia.s;
+    sa.spin_limit = spin_limit();
+    sa.vstart = (uintptr_t)a & 15u;
+    sa.base = a - sa.vstart;
+    sa.vend = sa.vstart + a_nbytes;
+    sa.n = na;
+    sa.prev = a_prev;
+    const uint64_t ntiles = stream_tiles(sa.vstart, a_nbytes, kIsectSegs, kIsectWaves);
+    if (ntiles >= (1ull << 31)) return VBYTE_EINVAL;
+    sa.ntiles = (uint32_t)ntiles;
+    // two rows of tile slots (the stream's, the matches'), then the totals
+    const uint64_t nslots = two_pass_slots(ntiles);
+    const size_t off_m = kHeaderBytes + nslots * sizeof(Desc);
+    const size_t off_tot = off_m + nslots * sizeof(Desc);
+    Workspace *w = nullptr;
+    vbyte_status st = get_ws(s, off_tot + 64, 0, &w);
+    if (st != VBYTE_OK) return st;
+    sa.hdr = (uint64_t *)ws_base(w);
+    sa.desc = (Desc *)(ws_base(w) + kHeaderBytes);
+    ia.mdesc = (Desc *)(ws_base(w) + off_m);
+    ia.total = (uint64_t *)(ws_base(w) + off_tot);
+    ia.scan_status = (int32_t *)(ws_base(w) + off_tot + 8);
     ia.na = na;
+    ia.piece = piece;
     ia.b = b;
     ia.nb = nb;
-    ia.flags = p + off_flags;
-    ia.wg_counts = (uint32_t *)(p + off_counts);
     ia.out = out;
     ia.out_cap = out_cap;
     ia.d_count = d_count;
-    ia.pending = (uint64_t *)(p + off_cur + 192);
     ia.d_status = d_status;
-    hipError_t e = launch_isect_init(ia, cur[0], a_prev, s);
-    if (e != hipSuccess) return hip_fail(e, "intersect init");
-    const uint64_t npieces = (na + piece - 1) / piece;
-    for (uint64_t k = 0; k < npieces; ++k) {
-        uint64_t *cin = cur[k & 1], *cout = cur[(k + 1) & 1];
-        st = vbyte_decode_next_async(a, a_nbytes, (uint32_t *)p, piece, 1, (const vbyte_cursor *)cin,
-                                     (vbyte_cursor *)cout, (int32_t *)ia.piece_status, stream);
-        if (st != VBYTE_OK) return st;
-        ia.cin = cin;
-        ia.cout = cout;
-        e = launch_isect_piece(ia, piece, s);
-        if (e != hipSuccess) return hip_fail(e, "intersect piece");
-    }
-    e = launch_isect_finish(ia, cur[npieces & 1], a_nbytes, s);
-    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "intersect finish");
+    hipError_t e = launch_isect(ia, s);
+    return e == hipSuccess ? VBYTE_OK : hip_fail(e, "intersect launch");
 }
 
 vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count, void *stream) {

@@ -663,6 +663,12 @@ constexpr int kKnown = 3;   // decode with the exclusive prefix given in TileIn
 constexpr int kPiece = 4;   // kFull, and record where the code of rank n begins
 constexpr int kKnownB = 5;  // kKnown with the prefix in byte form (see k_tile_agg)
 constexpr int kKnownW = 6;  // every wavefront alone, its own prefix in byte form given (no barrier)
+constexpr int kConsume = 7; // kKnownB, each segment's integers handed to a consumer instead of stored
+
+// The consumer of kinds other than kConsume: never called.
+struct NoConsumer {
+    __device__ void take(int, const u32 (&)[16], u32, u64, u64, u32) {}
+};
 
 constexpr int kMaxWaves = 16;
 constexpr int kMaxBlock = 8 * kWave;   // at most 8 wavefronts per workgroup
@@ -739,12 +745,15 @@ __device__ __forceinline__ void load_tile(const u8 *base, u64 vstart, u64 vend, 
 
 // D: 0 plain, 1 differences (inclusive prefix sum), 2 differences minus one
 // (the prefix sum plus each integer's rank).  The tile's bytes come in `x`.
-template <int D, int KIND, int SEGS, bool EDGE>
+template <int D, int KIND, int SEGS, bool EDGE, class CONS = NoConsumer>
 __device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs<SEGS> &x, u32 *rows,
-                                                 WgShared &sh, u32 wib, u32 wpb) {
+                                                 WgShared &sh, u32 wib, u32 wpb,
+                                                 CONS *cons = nullptr) {
     constexpr bool DELTA = D != 0, RANK = D == 2;
     constexpr bool COUNT = KIND == kCount, AGG = KIND == kAgg;
-    constexpr bool KNOWN = KIND == kKnown || KIND == kKnownB;
+    constexpr bool CONSUME = KIND == kConsume;
+    constexpr bool KNOWN = KIND == kKnown || KIND == kKnownB || CONSUME;
+    static_assert(!CONSUME || D == 1, "the consumer takes differential lists");
     constexpr bool PIECE = KIND == kPiece;
     constexpr bool WAVE = KIND == kKnownW;
     const u32 ln = lane_id();
@@ -779,7 +788,8 @@ __device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs
         emit[s] = m.emit;
         mal |= m.mal;
         // dense: all 1024 bytes are terminators and no code enters from below
-        const bool dense = !COUNT && !EDGE && ballot(m.term == 0xFFFFu) == ~0ull && (l0w >> 31) == 0;
+        const bool dense = !COUNT && !CONSUME && !EDGE && ballot(m.term == 0xFFFFu) == ~0ull &&
+                           (l0w >> 31) == 0;
         dmask |= dense ? (1u << s) : 0u;
         segcnt[s] = wave_sum(__builtin_popcount(COUNT ? m.term : m.emit));
         segbase[s] = ctot;
@@ -832,7 +842,7 @@ __device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs
             Prefix ex;
             if (KNOWN) {
                 ex = Prefix{t.known_c, t.known_s, t.known_mal};
-                if (KIND == kKnownB) {
+                if (KIND == kKnownB || CONSUME) {
                     const Straddle st = straddle(hb, read_lane(w[0][0], 0), read_lane(w[0][1], 0));
                     ex.c += st.code;
                     ex.s += st.rest;
@@ -879,6 +889,14 @@ __device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs
             }
         }
         if (gbase >= t.n || segcnt[s] == 0) continue;
+        if constexpr (CONSUME) {
+            u32 u[16];
+            const u32 add = exs + wex_s + sbase[s] + lincl[s];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) u[j] = r[s][j] + add;
+            cons->take(s, u, emit[s], gbase, t.n, segcnt[s]);
+            continue;
+        }
         if (dmask & (1u << s)) {
             *(uint4 *)(rows + 4 * ln) = make_uint4(w[s][0], w[s][1], w[s][2], w[s][3]);
             wave_lds_sync();
@@ -906,13 +924,13 @@ __device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs
 }
 
 // run_tile_regs with the wavefront's bytes loaded first.
-template <int D, int KIND, int SEGS, bool EDGE>
+template <int D, int KIND, int SEGS, bool EDGE, class CONS = NoConsumer>
 __device__ __forceinline__ TileOut run_tile(const TileIn &t, u32 *rows, WgShared &sh, u32 wib,
-                                            u32 wpb) {
+                                            u32 wpb, CONS *cons = nullptr) {
     TileRegs<SEGS> x;
     load_tile<SEGS, EDGE, KIND != kCount>(t.base, t.vstart, t.vend,
                                           t.tv + (u64)wib * (SEGS * kSegBytes), x);
-    return run_tile_regs<D, KIND, SEGS, EDGE>(t, x, rows, sh, wib, wpb);
+    return run_tile_regs<D, KIND, SEGS, EDGE, CONS>(t, x, rows, sh, wib, wpb, cons);
 }
 
 // Status of a finished stream or list: malformed first,
@@ -1359,7 +1377,10 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_block_scan(StreamArgs a, co
     const u64 i0 = (u64)b * kScanSpan;
     const u64 i1 = i0 + kScanSpan < a.ntiles ? i0 + kScanSpan : a.ntiles;
     scan_span(a, i0, i1, carry_c, carry_s, carry_m);
-    if (b == nb - 1 && tid == 0) *a.d_status = final_status(all_m_sh != 0, lastb, carry_c, a.n);
+    if (b == nb - 1 && tid == 0) {
+        *a.d_status = final_status(all_m_sh != 0, lastb, carry_c, a.n);
+        if (a.d_count) *a.d_count = carry_c;   // the stream's terminators, when asked for
+    }
 }
 
 template <int D, int SEGS>
@@ -2734,184 +2755,317 @@ hipError_t launch4_t(const Stream4Args &a, int wpb, hipStream_t s) {
 }
 
 // ============================================================ intersection
-// A consumer of resumable pieces: after each piece of the long list has
-// been decoded into the piece buffer, k_isect_mark flags its identifiers
-// that occur in the sorted array b (one binary search per thread, then a
-// forward walk over b for the thread's next identifiers) and counts them
-// per workgroup, and k_isect_write appends the flagged ones, in order, after
-// the matches of the earlier pieces.  The running match count lives in
-// d_count; the pieces' totals are folded into it by the next piece's mark
-// kernel (and by the finish kernel), so no kernel reads a word that another
-// workgroup of the same kernel writes.
-constexpr u32 kIsectBlock = 256;
-constexpr u32 kIsectPer = 4;   // identifiers per thread
-constexpr u32 kIsectSpan = kIsectBlock * kIsectPer;
-static_assert(kIsectSpan == kIsectElemsPerBlock, "consumer workgroup span");
+// List intersection with the decode and the consumer fused, so that the
+// list's identifiers never leave the chip (section 5 consumes a list from a
+// buffer that stays in cache; here the buffer is a tile's registers).  The
+// tile slots come from the two-pass aggregate and scan (k_tile_agg,
+// k_tile_block_sums, k_tile_block_scan): each tile knows the rank and the
+// running identifier at its first byte.  k_isect_tiles decodes a tile with
+// that prefix and tests each identifier of rank below na against the sorted
+// array b: the wavefront's smallest and largest identifiers bound a window
+// of b (a 32-way search per bound), the window goes to LDS when it fits,
+// and each identifier takes a binary search in it.  The first run counts
+// each tile's matches into a second row of slots; the same block scans turn
+// those into each tile's first output position; the second run decodes and
+// tests the tile again and stores its matches there, in list order.
+// k_isect_status gives the status that decoding in pieces of `piece`
+// integers gives (reading R15), from the stream's totals.
+constexpr u32 kIsectWin = kStageWords;   // entries of b a wavefront holds in LDS
 
-// Identifiers of this piece to consider: those decoded (cursor difference)
-// up to the list's count.
-__device__ __forceinline__ u64 isect_count(const IsectArgs &a) {
-    const u64 before = a.cin[1], m = a.cout[1] - before;
-    const u64 left = a.na > before ? a.na - before : 0;
-    return m < left ? m : left;
+// The wavefront's identifiers, as the tile decode hands them over: the
+// candidate of every byte and, per segment, the lane's code starts of rank
+// below n.
+template <int SEGS>
+struct IsectCons {
+    u32 u[SEGS][16];
+    u32 m[SEGS];
+    __device__ __forceinline__ void take(int s, const u32 (&v)[16], u32 emit, u64 gbase, u64 n,
+                                         u32 segcnt) {
+        u32 e = emit;
+        if (gbase + segcnt > n) {
+            // the codes of rank n and above are not the list's
+            const u32 c = (u32)__builtin_popcount(emit);
+            const u64 r0 = gbase + (wave_scan(c) - c);   // rank of the lane's first code
+            const u32 keep = r0 >= n ? 0u : (n - r0 < c ? (u32)(n - r0) : c);
+            while ((u32)__builtin_popcount(e) > keep) e &= ~(0x80000000u >> __builtin_clz(e));
+        }
+        m[s] = e;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) u[s][j] = v[j];
+    }
+};
+
+__device__ __forceinline__ u32 wave_min(u32 x) {
+#pragma unroll
+    for (int o = 32; o; o >>= 1) {
+        const u32 y = (u32)__shfl_xor((int)x, o);
+        x = y < x ? y : x;
+    }
+    return first_lane(x);
+}
+__device__ __forceinline__ u32 wave_max(u32 x) {
+#pragma unroll
+    for (int o = 32; o; o >>= 1) {
+        const u32 y = (u32)__shfl_xor((int)x, o);
+        x = y > x ? y : x;
+    }
+    return first_lane(x);
 }
 
-__global__ __launch_bounds__(kIsectBlock) void k_isect_mark(IsectArgs a) {
-    __shared__ u32 wsum[kIsectBlock / kWave];
-    const u32 tid = threadIdx.x, ln = lane_id(), wib = tid >> 6;
-    if (blockIdx.x == 0 && tid == 0) {
-        // fold the previous piece's matches and this piece's status
-        *a.d_count += *a.pending;
-        *a.pending = 0;
-        if (*a.piece_status > *a.d_status) *a.d_status = *a.piece_status;
-    }
-    const u64 m = isect_count(a);
-    const u64 i0 = ((u64)blockIdx.x * kIsectBlock + tid) * kIsectPer;
-    u32 cnt = 0;
-    if (i0 < m) {
-        const u32 x0 = a.piece[i0];
-        u64 lo = 0, hi = a.nb;   // first b[j] >= x0
-        while (lo < hi) {
-            const u64 mid = (lo + hi) >> 1;
-            if (a.b[mid] < x0)
-                lo = mid + 1;
-            else
-                hi = mid;
+// first = the first index with b[i] >= lo, last = the first index with
+// b[i] > hi (b sorted ascending), by lanes 0..31 and 32..63 at once: each
+// round, lane l of a half probes the l-th of up to 32 evenly spaced entries
+// of the range where its answer lies; the probes below the answer form a
+// prefix, counted by a ballot, and the range shrinks to the gap between the
+// last of them and the next probe.
+__device__ __forceinline__ void wave_bounds(const u32 *b, u64 nb, u32 lo, u32 hi, u64 &first,
+                                            u64 &last) {
+    const u32 ln = lane_id(), half = ln >> 5, l = ln & 31u;
+    const u32 x = half ? hi : lo;
+    u64 a0 = 0, a1 = nb, c0 = 0, c1 = nb;   // answers in [a0, a1] and [c0, c1]
+    while (a0 < a1 || c0 < c1) {
+        const u64 sa = (a1 - a0 + 31) >> 5, sc = (c1 - c0 + 31) >> 5;
+        const u64 r0 = half ? c0 : a0, r1 = half ? c1 : a1, st = half ? sc : sa;
+        const u64 p = r0 + (u64)l * st;
+        bool below = false;
+        if (p < r1) {
+            const u32 v = b[p];
+            below = half ? v <= x : v < x;
         }
-        u64 j = lo;
-        for (u32 e = 0; e < kIsectPer; ++e) {
-            const u64 i = i0 + e;
-            if (i >= m) break;
-            const u32 x = a.piece[i];
-            while (j < a.nb && a.b[j] < x) ++j;
-            const u8 f = (j < a.nb && a.b[j] == x) ? 1 : 0;
-            a.flags[i] = f;
-            cnt += f;
+        const u64 bm = ballot(below);
+        const u64 ka = (u64)__builtin_popcount((u32)bm), kc = (u64)__builtin_popcount((u32)(bm >> 32));
+        if (a0 < a1) {
+            const u64 nhi = a0 + ka * sa;
+            a1 = nhi < a1 ? nhi : a1;
+            a0 = ka ? a0 + (ka - 1) * sa + 1 : a0;
+        }
+        if (c0 < c1) {
+            const u64 nhi = c0 + kc * sc;
+            c1 = nhi < c1 ? nhi : c1;
+            c0 = kc ? c0 + (kc - 1) * sc + 1 : c0;
         }
     }
-    const u32 ws = wave_sum(cnt);
-    if (ln == 0) wsum[wib] = ws;
-    __syncthreads();
-    if (tid == 0) {
-        u32 t = 0;
-        for (u32 k = 0; k < kIsectBlock / kWave; ++k) t += wsum[k];
-        a.wg_counts[blockIdx.x] = t;
+    first = a0;
+    last = c0;
+}
+
+// Match masks of the wavefront's identifiers against win[0, W) (sorted,
+// W >= 1): for each identifier the number of entries below it by steps of
+// top, top/2, ..., 1 (top the highest power of two <= W), then one compare.
+template <int SEGS, class P>
+__device__ __forceinline__ void match_window(P win, u32 W, u32 top, const IsectCons<SEGS> &c,
+                                             u32 (&mt)[SEGS]) {
+    u32 pos[SEGS][16];
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) pos[s][j] = 0;
+    for (u32 step = top; step; step >>= 1) {
+#pragma unroll
+        for (int s = 0; s < SEGS; ++s)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const u32 q = pos[s][j] + step;
+                const u32 v = win[(q <= W ? q : W) - 1];
+                pos[s][j] = (q <= W && v < c.u[s][j]) ? q : pos[s][j];
+            }
+    }
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        u32 f = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const u32 v = win[pos[s][j] < W ? pos[s][j] : W - 1];
+            f |= (pos[s][j] < W && v == c.u[s][j]) ? (1u << j) : 0u;
+        }
+        mt[s] = f & c.m[s];
     }
 }
 
-// Pieces of more than kIsectDirect workgroups: the workgroups' counts
-// become exclusive prefixes in place (one workgroup) and their total goes to
-// pending, before k_isect_write.
-constexpr u32 kIsectDirect = kIsectBlock;
+template <bool WRITE>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_isect_tiles(IsectArgs a) {
+    constexpr int SEGS = kIsectSegs;
+    extern __shared__ __align__(16) u32 lds[];
+    __shared__ WgShared sh;
+    __shared__ u32 wmatch[kMaxWaves];
+    const u32 tid = threadIdx.x, ln = lane_id();
+    const u32 wib = tid >> 6;
+    const u32 wpb = blockDim.x >> 6;
+    u32 *stage = lds + wib * kStageWords;
+    const u32 tile = blockIdx.x;
+    const u64 tb = (u64)wpb * SEGS * kSegBytes;
+    TileIn t{};
+    t.base = a.s.base;
+    t.vstart = a.s.vstart;
+    t.vend = a.s.vend;
+    t.tv = (u64)tile * tb;
+    t.n = a.na;
+    t.known_c = a.s.desc[tile].c & kCountMask;
+    t.known_s = (u32)a.s.desc[tile].s;
+    t.known_mal = false;
+    IsectCons<SEGS> c;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) c.m[s] = 0;
+    const bool interior = tile > 0 && t.tv + tb + 4 <= t.vend;
+    TileOut r;
+    if (interior)
+        r = run_tile<1, kConsume, SEGS, false>(t, stage, sh, wib, wpb, &c);
+    else
+        r = run_tile<1, kConsume, SEGS, true>(t, stage, sh, wib, wpb, &c);
 
-__global__ __launch_bounds__(kScanBlock) void k_isect_scan(IsectArgs a, u32 groups) {
-    __shared__ u32 wc[kScanBlock / kWave];
-    const u32 tid = threadIdx.x, ln = lane_id(), wib = tid >> 6;
-    u64 carry = 0;
-    for (u32 b0 = 0; b0 < groups; b0 += kScanBlock * kScanPer) {
-        const u32 i0 = b0 + tid * kScanPer;
-        u32 c[kScanPer], lc = 0;
+    u32 mn = ~0u, mx = 0u;
+    bool any = false;
 #pragma unroll
-        for (int k = 0; k < kScanPer; ++k) c[k] = a.wg_counts[i0 + k < groups ? i0 + k : groups - 1];
+    for (int s = 0; s < SEGS; ++s)
 #pragma unroll
-        for (int k = 0; k < kScanPer; ++k) {
-            c[k] = i0 + k < groups ? c[k] : 0u;   // all loads issued first (groups >= 1)
-            lc += c[k];
-        }
-        const u32 ci = wave_scan(lc);   // at most 512 x 1024 matches per wavefront
-        if (ln == kWave - 1) wc[wib] = ci;
-        __syncthreads();
-        u64 pre = carry, tot = carry;
-        for (u32 k = 0; k < kScanBlock / kWave; ++k) {
-            if (k < wib) pre += wc[k];
-            tot += wc[k];
-        }
-        pre += ci - lc;
+        for (int j = 0; j < 16; ++j)
+            if ((c.m[s] >> j) & 1u) {
+                const u32 v = c.u[s][j];
+                mn = v < mn ? v : mn;
+                mx = v > mx ? v : mx;
+                any = true;
+            }
+    u32 mt[SEGS];
 #pragma unroll
-        for (int k = 0; k < kScanPer; ++k) {
-            if (i0 + k < groups) a.wg_counts[i0 + k] = (u32)pre;   // a piece has < 2^26 matches
-            pre += c[k];
-        }
-        carry = tot;
-        __syncthreads();
-    }
-    if (tid == 0) *a.pending = carry;
-}
-
-__global__ __launch_bounds__(kIsectBlock) void k_isect_write(IsectArgs a, bool scanned) {
-    __shared__ u32 wsum[kIsectBlock / kWave];
-    __shared__ u64 pre_s;
-    const u32 tid = threadIdx.x, ln = lane_id(), wib = tid >> 6;
-    if (scanned) {
-        if (tid == 0) pre_s = a.wg_counts[blockIdx.x];
-    } else {
-        // at most kIsectDirect workgroups: one count per thread
-        const u32 c = tid < gridDim.x ? a.wg_counts[tid] : 0u;
-        const u32 before = wave_sum(tid < blockIdx.x ? c : 0u), all = wave_sum(c);
-        if (ln == 0) wsum[wib] = before;
-        __syncthreads();
-        if (tid == 0) {
-            u64 pre = 0;
-            for (u32 k = 0; k < kIsectBlock / kWave; ++k) pre += wsum[k];
-            pre_s = pre;
-        }
-        __syncthreads();   // wsum is rewritten below
-        if (blockIdx.x == 0) {
-            if (ln == 0) wsum[wib] = all;
-            __syncthreads();
-            if (tid == 0) {
-                u64 tot = 0;
-                for (u32 k = 0; k < kIsectBlock / kWave; ++k) tot += wsum[k];
-                *a.pending = tot;
+    for (int s = 0; s < SEGS; ++s) mt[s] = 0;
+    if (ballot(any) != 0 && a.nb > 0) {
+        mn = wave_min(mn);
+        mx = wave_max(mx);
+        u64 first, last;
+        wave_bounds(a.b, a.nb, mn, mx, first, last);
+        const u32 W = (u32)(last - first);
+        if (W > 0) {
+            const u32 top = 0x80000000u >> __builtin_clz(W);
+            if (W <= kIsectWin) {
+                for (u32 i = ln; i < W; i += kWave) stage[i] = a.b[first + i];
+                wave_lds_sync();
+                match_window<SEGS>(stage, W, top, c, mt);
+            } else {
+                match_window<SEGS>(a.b + first, W, top, c, mt);
             }
         }
-        __syncthreads();
     }
-    const u64 m = isect_count(a);
-    const u64 i0 = ((u64)blockIdx.x * kIsectBlock + tid) * kIsectPer;
-    u32 fl = 0, cnt = 0;
-    for (u32 e = 0; e < kIsectPer; ++e) {
-        if (i0 + e < m && a.flags[i0 + e]) {
-            fl |= 1u << e;
-            ++cnt;
-        }
-    }
-    const u32 inc = wave_scan(cnt);
-    __syncthreads();   // wsum is reused
-    if (ln == kWave - 1) wsum[wib] = inc;
+    u32 cnt = 0;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) cnt += (u32)__builtin_popcount(mt[s]);
+    const u32 wcount = wave_sum(cnt);
+    if (ln == 0) wmatch[wib] = wcount;
     __syncthreads();
-    u64 base = *a.d_count + pre_s + inc - cnt;
-    for (u32 k = 0; k < wib; ++k) base += wsum[k];
-    for (u32 e = 0; e < kIsectPer; ++e) {
-        if ((fl >> e) & 1u) {
-            if (base < a.out_cap) a.out[base] = a.piece[i0 + e];
-            ++base;
+    if (!WRITE) {
+        if (tid == 0) {
+            u64 tot = 0;
+            for (u32 k = 0; k < wpb; ++k) tot += wmatch[k];
+            // the tile's own malformed flag rides in bit 37, as in the tile slots
+            a.mdesc[tile].c = tot | ((u64)(r.mal ? 1u : 0u) << 37);
+            a.mdesc[tile].s = 0;
+        }
+        return;
+    }
+    u64 base = a.mdesc[tile].c & kCountMask;   // the tile's first output position
+    for (u32 k = 0; k < wib; ++k) base += wmatch[k];
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 cs = (u32)__builtin_popcount(mt[s]);
+        const u32 inc = wave_scan(cs);
+        u64 pos = base + (inc - cs);
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if ((mt[s] >> j) & 1u) {
+                if (pos < a.out_cap) a.out[pos] = c.u[s][j];
+                ++pos;
+            }
+        base += read_lane(inc, 63);
+    }
+    if (tile == gridDim.x - 1 && wib == wpb - 1 && ln == 0) *a.d_count = base;
+}
+
+// The status of the list decoded in pieces of k = piece integers (reading
+// R15), from the stream's totals: C terminators, the first run of five
+// continuation bytes (at byte q0, if any) and the last byte.  A piece starts
+// at the end c_j of code j = p k and looks at bytes [c_j, c_j + 5k); it fails
+// as malformed once that window holds the whole run, i.e. for the first p
+// with c_(pk) >= q0 + 5 - 5k, and that is p = T / k + 1 for T the
+// terminators before byte q0 + 4 - 5k (p = 0 when that byte is before the
+// stream).  Without a run: truncated when the last byte continues and the
+// piece holding the last code (p = C / k) is among the P = ceil(na / k)
+// pieces; else the pieces decode min(P k, C) codes, too few for na
+// (truncated) or leaving codes or bytes behind (count).  One workgroup; the
+// byte searches run only for a malformed stream.
+constexpr u32 kStatusBlock = 256;
+__global__ __launch_bounds__(kStatusBlock) void k_isect_status(IsectArgs a, u32 tb) {
+    __shared__ u64 first_tile, q0_sh, t_sh;
+    const u32 tid = threadIdx.x;
+    const u64 C = *a.total, na = a.na, k = a.piece, P = (na + k - 1) / k;
+    const u64 vs = a.s.vstart, ve = a.s.vend;
+    const bool lastc = a.s.base[ve - 1] >= 0x80;   // the stream is not empty
+    const bool mal = *a.scan_status == VBYTE_EMALFORMED;
+    if (!mal) {
+        if (tid == 0) {
+            int32_t st;
+            if (lastc) {
+                st = C / k < P ? VBYTE_ETRUNC : VBYTE_ECOUNT;
+            } else {
+                const u64 done = P * k < C ? P * k : C;
+                st = done < na ? VBYTE_ETRUNC : (done < C || done > na) ? VBYTE_ECOUNT : VBYTE_OK;
+            }
+            *a.d_status = st;
+        }
+        return;
+    }
+    if (tid == 0) {
+        first_tile = ~0ull;
+        q0_sh = ~0ull;
+        t_sh = 0;
+    }
+    __syncthreads();
+    // the first tile flagged in its match slot (bit 37): the tile decode flags
+    // a run at the lane that holds its first byte, so the first run starts
+    // in that tile and no run starts before it
+    const u64 ntiles = a.s.ntiles;
+    for (u64 i = tid; i < ntiles; i += kStatusBlock)
+        if ((a.mdesc[i].c >> 37) & 1u) {
+            atomicMin((unsigned long long *)&first_tile, (unsigned long long)i);
+            break;
+        }
+    __syncthreads();
+    // (should no tile be flagged, the status stays malformed and nothing is
+    // searched; the search also covers the 4 bytes before the tile)
+    const u64 tm = first_tile;
+    if (tm >= ntiles) {
+        if (tid == 0) *a.d_status = VBYTE_EMALFORMED;
+        return;
+    }
+    const u64 lo0 = tm * tb >= vs + 4 ? tm * tb - 4 : vs;
+    const u64 hi0 = (tm + 1) * tb < ve ? (tm + 1) * tb : ve;
+    for (u64 p = lo0 + tid; p < hi0 && p + 5 <= ve; p += kStatusBlock) {
+        bool run = true;
+        for (u32 j = 0; j < 5; ++j) run = run && a.s.base[p + j] >= 0x80;
+        if (run) {
+            atomicMin((unsigned long long *)&q0_sh, (unsigned long long)p);
+            break;
         }
     }
-}
-
-// After the last piece: fold the last matches; the status is the worst
-// piece status, else ETRUNC (fewer codes than na) or ECOUNT (bytes left).
-__global__ void k_isect_finish(IsectArgs a, const u64 *cursor, u64 nbytes) {
-    *a.d_count += *a.pending;
-    *a.pending = 0;
-    int32_t st = *a.d_status;
-    if (st == VBYTE_OK) {
-        if (cursor[1] < a.na)
-            st = VBYTE_ETRUNC;
-        else if (cursor[0] < nbytes || cursor[1] > a.na)
-            st = VBYTE_ECOUNT;
+    __syncthreads();
+    if (q0_sh >= ve) {
+        if (tid == 0) *a.d_status = VBYTE_EMALFORMED;
+        return;
     }
-    *a.d_status = st;
-}
-
-__global__ void k_isect_init(IsectArgs a, u64 *cursor, u64 prev) {
-    cursor[0] = 0;
-    cursor[1] = 0;
-    cursor[2] = prev;
-    *a.d_count = 0;
-    *a.pending = 0;
-    *a.d_status = VBYTE_OK;
+    const u64 q0 = q0_sh - vs;   // stream-relative
+    const i64 X = (i64)q0 + 5 - 5 * (i64)k;
+    u64 pm = 0;
+    if (X > 0) {
+        // terminators in stream bytes [0, X - 1): the tile slot's prefix and
+        // the tile's bytes before X - 1
+        const u64 ya = vs + (u64)X - 1, ty = ya / tb;
+        const u64 from = ty * tb > vs ? ty * tb : vs;
+        u32 cnt = 0;
+        for (u64 p = from + tid; p < ya; p += kStatusBlock) cnt += a.s.base[p] < 0x80 ? 1u : 0u;
+        atomicAdd((unsigned long long *)&t_sh, (unsigned long long)cnt);
+        __syncthreads();
+        const u64 T = (a.s.desc[ty].c & kCountMask) + t_sh;
+        pm = T / k + 1;
+    }
+    if (tid == 0) *a.d_status = pm < P ? VBYTE_EMALFORMED : VBYTE_ECOUNT;
 }
 
 // ------------------------------------------------------------ batched lists
@@ -3595,29 +3749,38 @@ hipError_t launch_stream(const StreamArgs &a, int delta, int count_only, int seg
     }
 }
 
-hipError_t launch_isect_init(const IsectArgs &a, uint64_t *cursor, uint64_t prev, hipStream_t s) {
-    k_isect_init<<<1, 1, 0, s>>>(a, cursor, prev);
-    return hipGetLastError();
-}
-
-hipError_t launch_isect_piece(const IsectArgs &a, uint64_t piece, hipStream_t s) {
-    const u32 blocks = (u32)((piece + kIsectSpan - 1) / kIsectSpan);
-    k_isect_mark<<<blocks, kIsectBlock, 0, s>>>(a);
+hipError_t launch_isect(const IsectArgs &a, hipStream_t s) {
+    constexpr int SEGS = kIsectSegs, wpb = kIsectWaves;
+    const u32 ntiles = a.s.ntiles;   // >= 1
+    const u32 nblocks = (u32)((ntiles + kScanSpan - 1) / kScanSpan);
+    const u32 tb = wpb * SEGS * kSegBytes;
+    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
+    // the stream's tile slots: aggregates, then exclusive prefixes
+    StreamArgs sa = a.s;
+    sa.d_status = a.scan_status;
+    sa.d_count = a.total;
+    k_tile_agg<1, SEGS><<<ntiles, wpb * kWave, 0, s>>>(sa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const bool scanned = blocks > kIsectDirect;
-    if (scanned) {
-        k_isect_scan<<<1, kScanBlock, 0, s>>>(a, blocks);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    k_isect_write<<<blocks, kIsectBlock, 0, s>>>(a, scanned);
-    return hipGetLastError();
-}
-
-hipError_t launch_isect_finish(const IsectArgs &a, const uint64_t *cursor, uint64_t nbytes,
-                               hipStream_t s) {
-    k_isect_finish<<<1, 1, 0, s>>>(a, cursor, nbytes);
+    k_tile_block_sums<<<nblocks, kScanBlock, 0, s>>>(sa, sa.desc + ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_tile_block_scan<<<nblocks, kScanBlock, 0, s>>>(sa, sa.desc + ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_isect_tiles<false><<<ntiles, wpb * kWave, lds, s>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_isect_status<<<1, kStatusBlock, 0, s>>>(a, tb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the match counts through the same scans (their status goes to a spare word)
+    StreamArgs ma = sa;
+    ma.desc = a.mdesc;
+    ma.prev = 0;
+    ma.d_status = a.scan_status + 1;
+    ma.d_count = nullptr;
+    k_tile_block_sums<<<nblocks, kScanBlock, 0, s>>>(ma, ma.desc + ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_tile_block_scan<<<nblocks, kScanBlock, 0, s>>>(ma, ma.desc + ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_isect_tiles<true><<<ntiles, wpb * kWave, lds, s>>>(a);
     return hipGetLastError();
 }
 

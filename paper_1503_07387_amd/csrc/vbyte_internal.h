@@ -134,22 +134,23 @@ struct Stream4Args {
 };
 
 // Intersection consumer of resumable pieces (vbyte_intersect_async).
+// List intersection fused with the decode (vbyte_intersect_async).
 struct IsectArgs {
-    const uint32_t *piece;        // the piece buffer
-    const uint64_t *cin, *cout;   // cursors before and after the piece
-    const int32_t *piece_status;  // status of the piece decode
-    uint64_t na;                  // identifiers in the long list
-    const uint32_t *b;            // sorted short list
+    StreamArgs s;           // the list as one differential stream; s.desc: its tile slots
+    Desc *mdesc;            // per tile: matches (bit 37: the tile's bytes end a run of five
+                            // continuation bytes), then the tile's first output position
+    uint64_t na;            // identifiers in the list
+    uint64_t piece;         // piece size whose status the call reports
+    const uint32_t *b;      // sorted short list
     uint64_t nb;
-    uint8_t *flags;               // one per piece element
-    uint32_t *wg_counts;          // matches per workgroup of the piece
     uint32_t *out;
     uint64_t out_cap;
-    uint64_t *d_count;            // matches so far
-    uint64_t *pending;            // matches of the last piece, not yet in d_count
+    uint64_t *d_count;
     int32_t *d_status;
+    uint64_t *total;        // terminators in the stream (from the stream's scan)
+    int32_t *scan_status;   // the stream scan's status, and a spare word after it
 };
-constexpr uint32_t kIsectElemsPerBlock = 1024;   // piece elements per consumer workgroup
+constexpr int kIsectSegs = 2, kIsectWaves = 8;   // the intersection's tiling
 
 // One list of a batched launch, resolved on the device from either CSR
 // offsets or gather rows.
@@ -230,10 +231,7 @@ hipError_t launch64(const Stream64Args &a, int delta, int segs, int wpb, hipStre
 // Blocks-of-four decode: group and unit summaries, a one-workgroup scan
 // (status), decode; segs 1 or 2.
 hipError_t launch4(const Stream4Args &a, int segs, int wpb, hipStream_t s);
-hipError_t launch_isect_init(const IsectArgs &a, uint64_t *cursor, uint64_t prev, hipStream_t s);
-hipError_t launch_isect_piece(const IsectArgs &a, uint64_t piece, hipStream_t s);
-hipError_t launch_isect_finish(const IsectArgs &a, const uint64_t *cursor, uint64_t nbytes,
-                               hipStream_t s);
+hipError_t launch_isect(const IsectArgs &a, hipStream_t s);
 hipError_t launch_encode(const EncArgs &a, hipStream_t s);
 hipError_t launch_encode_bounds(const EncArgs &a, const int64_t *vals_off, int64_t *byte_off,
                                 uint64_t nb, hipStream_t s);

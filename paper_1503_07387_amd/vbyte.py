@@ -322,10 +322,12 @@ def intersect(a, na, b_ids, *, prev=0, piece=1 << 16, out=None, count=None, stat
               stream=None, check=True):
     """Identifiers of the differential list ``a`` (VByte bytes, ``na``
     identifiers from ``prev``) that occur in the sorted ``b_ids`` (int32
-    tensor of uint32 values), in list order, by decoding ``a`` in pieces of
-    ``piece`` integers and testing each piece as it is decoded
-    (vbyte_intersect_async).  Returns (matches tensor, count tensor); with
-    ``check`` the call waits and raises VByteError on a data error."""
+    tensor of uint32 values), in list order (vbyte_intersect_async: each
+    tile of ``a`` is decoded and tested in registers; the status is the one
+    that decoding in pieces of ``piece`` integers gives).  Returns (matches
+    tensor, count tensor); with ``check`` the call waits and raises
+    VByteError on a data error, after which matches and count are
+    unspecified."""
     _dev_u8(a)
     if b_ids.dtype != torch.int32 or not b_ids.is_cuda or not b_ids.is_contiguous():
         raise ValueError("b_ids must be a contiguous int32 CUDA tensor (uint32 bits)")

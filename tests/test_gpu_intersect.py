@@ -1,8 +1,9 @@
-"""GPU parity of the list intersection by a consumer of resumable pieces
-(vbyte_intersect_async, reading R15) with the oracle's piece-by-piece
-intersection: matches in list order, their count, and the status, over
-piece sizes, list densities, duplicates, a capacity below the match count,
-and the error cases."""
+"""GPU parity of the list intersection (vbyte_intersect_async, reading R15:
+decode and consumer fused per tile, the status of decoding in pieces) with
+the oracle's piece-by-piece intersection: matches in list order, their
+count, and the status, over piece sizes, list densities, duplicates,
+identifiers that wrap mod 2^32 (windows of b too wide for LDS), a capacity
+below the match count, and the error cases, fixed and drawn at random."""
 import numpy as np
 import pytest
 import torch
@@ -110,3 +111,87 @@ def test_long_list_against_whole_decode():
     want = ids[np.isin(ids, b)]
     assert s1 == s2 == vbyte.OK and c1 == c2 == want.size
     assert np.array_equal(g1[:c1], want) and np.array_equal(g2[:c2], want)
+
+
+@pytest.mark.parametrize("nb", [300, 1152, 1153, 40_000])
+def test_wrapping_identifiers(nb):
+    """Gaps up to 2^30: the identifiers wrap mod 2^32 every few codes, so a
+    wavefront's identifiers span the whole range and its window of b is all
+    of b (held in LDS up to 1152 entries, searched in memory above)."""
+    rng = np.random.default_rng(nb)
+    g = rng.integers(1, 1 << 30, size=150_000, dtype=np.uint64)
+    ids = ((np.cumsum(g) + 7) & 0xFFFFFFFF).astype(np.uint32)
+    pick = rng.choice(ids, size=nb // 2)
+    b = np.sort(np.concatenate([pick, rng.integers(0, 1 << 32, size=nb - nb // 2,
+                                                    dtype=np.uint64).astype(np.uint32)]))
+    a = oracle.encode_delta(ids, 7)
+    st, cnt, got = run(a, ids.size, b, 4096, prev=7)
+    sto, want = oracle.intersect_pieces(a, ids.size, b, 4096, 7)
+    assert st == sto == vbyte.OK
+    assert cnt == want.size and np.array_equal(got[:cnt], want)
+
+
+def test_dense_short_list():
+    """b denser than the list: windows of about 2000 entries (searched in
+    memory) next to windows that fit LDS."""
+    ids, b = lists(21, 300_000, 250_000, 400_000)
+    a = oracle.encode_delta(ids, 0)
+    st, cnt, got = run(a, ids.size, b, 1 << 16)
+    sto, want = oracle.intersect_pieces(a, ids.size, b, 1 << 16)
+    assert st == sto == vbyte.OK
+    assert cnt == want.size and np.array_equal(got[:cnt], want)
+
+
+def test_random_statuses():
+    """Short lists with runs of continuation bytes, cut tails, trailing
+    continuation bytes and counts off by a few, over piece sizes 1 .. 64:
+    the status of decoding in pieces, from the stream's totals."""
+    rng = np.random.default_rng(77)
+    ids = np.arange(3, 3 + 40, dtype=np.uint32)
+    b = ids[::3].copy()
+    seen = set()
+    for it in range(300):
+        n = int(rng.integers(0, 40))
+        L = rng.integers(1, 6, size=n)
+        vals = np.array([int(rng.integers(1 << (7 * (l - 1)) if l > 1 else 0,
+                                          min(1 << (7 * l), 1 << 32))) for l in L],
+                        dtype=np.uint64).astype(np.uint32)
+        buf = oracle.encode(vals).copy()
+        r = rng.random()
+        if r < 0.3 and buf.size:
+            q, ln = int(rng.integers(0, buf.size)), int(rng.integers(1, 8))
+            buf[q:q + ln] = 0x80 | rng.integers(0, 128, size=min(ln, buf.size - q)).astype(np.uint8)
+        elif r < 0.45 and buf.size:
+            buf = buf[:int(rng.integers(0, buf.size))]
+        elif r < 0.55:
+            buf = np.concatenate([buf, (0x80 | rng.integers(0, 128, size=int(rng.integers(1, 7))))
+                                  .astype(np.uint8)])
+        na = max(0, n + int(rng.integers(-3, 4)))
+        piece = int(rng.choice([1, 2, 3, 4, 5, 7, 16, 64]))
+        st, cnt, got = run(buf, na, b, piece)
+        sto, want = oracle.intersect_pieces(buf, na, b, piece)
+        assert st == sto, (it, list(buf), na, piece, st, sto)
+        if st == vbyte.OK:
+            assert cnt == want.size and np.array_equal(got[:cnt], want)
+        seen.add(st)
+    assert seen == {vbyte.OK, vbyte.ECOUNT, vbyte.ETRUNC, vbyte.EMALFORMED}
+
+
+def test_runs_far_into_long_lists():
+    """A run of five continuation bytes deep in a list of many tiles, near
+    tile edges, with na such that the last piece's window does or does not
+    reach the run, for several piece sizes."""
+    ids = np.cumsum(np.random.default_rng(4).integers(1, 300, size=100_000)).astype(np.uint32)
+    a = oracle.encode_delta(ids, 0)
+    seen = set()
+    for pos in (16384 * 5 - 3, 16384 * 9 + 1, a.size - 6):
+        bad = a.copy()
+        bad[pos:pos + 5] = 0x81
+        before = int((bad[:pos] < 0x80).sum())   # codes that end before the run
+        for na in (ids.size, before, before - 37, before - 3000):
+            for piece in (64, 1000, 50_000):
+                st, _, _ = run(bad, na, ids[::7], piece)
+                sto, _ = oracle.intersect_pieces(bad, na, ids[::7], piece)
+                assert st == sto, (pos, na, piece, st, sto)
+                seen.add(st)
+    assert seen == {vbyte.EMALFORMED, vbyte.ECOUNT}
