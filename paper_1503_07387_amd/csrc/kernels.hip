@@ -2764,7 +2764,8 @@ hipError_t launch4_t(const Stream4Args &a, int wpb, hipStream_t s) {
 // that prefix and tests each identifier of rank below na against the sorted
 // array b: the wavefront's smallest and largest identifiers bound a window
 // of b (a 32-way search per bound), the window goes to LDS when it fits,
-// and each identifier takes a binary search in it.  The first run counts
+// and each lane walks the entries between its smallest and largest
+// identifiers, comparing each with all of its identifiers.  The first run counts
 // each tile's matches into a second row of slots; the same block scans turn
 // those into each tile's first output position; the second run decodes and
 // tests the tile again and stores its matches there, in list order.
@@ -2849,36 +2850,59 @@ __device__ __forceinline__ void wave_bounds(const u32 *b, u64 nb, u32 lo, u32 hi
     last = c0;
 }
 
-// Match masks of the wavefront's identifiers against win[0, W) (sorted,
-// W >= 1): for each identifier the number of entries below it by steps of
-// top, top/2, ..., 1 (top the highest power of two <= W), then one compare.
+// Entries of win[0, W) (sorted, W >= 1) below x, by steps of top, top/2,
+// ..., 1 (top the highest power of two <= W).
+template <class P>
+__device__ __forceinline__ u32 count_below(P win, u32 W, u32 top, u32 x) {
+    u32 pos = 0;
+    for (u32 step = top; step; step >>= 1) {
+        const u32 q = pos + step;
+        const u32 v = win[(q <= W ? q : W) - 1];
+        pos = (q <= W && v < x) ? q : pos;
+    }
+    return pos;
+}
+
+// Match masks of the wavefront's identifiers against win[0, W).  A lane
+// walks the entries between the smallest and the largest of its valid
+// identifiers in a segment (lo[s], hi[s]) and compares each with all 16 of
+// its identifiers; with sorted identifiers that range holds a few entries.
+// After kMergeRounds entries the lanes that still have some (identifiers
+// that wrap mod 2^32, or a short list much denser than the list) test each
+// identifier by a binary search instead.
+constexpr u32 kMergeRounds = 16;
 template <int SEGS, class P>
 __device__ __forceinline__ void match_window(P win, u32 W, u32 top, const IsectCons<SEGS> &c,
+                                             const u32 (&lo)[SEGS], const u32 (&hi)[SEGS],
                                              u32 (&mt)[SEGS]) {
-    u32 pos[SEGS][16];
-#pragma unroll
-    for (int s = 0; s < SEGS; ++s)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) pos[s][j] = 0;
-    for (u32 step = top; step; step >>= 1) {
-#pragma unroll
-        for (int s = 0; s < SEGS; ++s)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const u32 q = pos[s][j] + step;
-                const u32 v = win[(q <= W ? q : W) - 1];
-                pos[s][j] = (q <= W && v < c.u[s][j]) ? q : pos[s][j];
-            }
-    }
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) {
+        const u32 m = c.m[s];
+        u32 pos = count_below(win, W, top, lo[s]);
         u32 f = 0;
+        bool act = m != 0;
+        for (u32 it = 0;; ++it) {
+            u32 x = 0;
+            if (act) {
+                x = win[pos < W ? pos : W - 1];
+                act = pos < W && x <= hi[s];
+            }
+            if (ballot(act) == 0 || it == kMergeRounds) break;
+            if (act) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const u32 v = win[pos[s][j] < W ? pos[s][j] : W - 1];
-            f |= (pos[s][j] < W && v == c.u[s][j]) ? (1u << j) : 0u;
+                for (int j = 0; j < 16; ++j) f |= (c.u[s][j] == x) ? (1u << j) : 0u;
+                ++pos;
+            }
         }
-        mt[s] = f & c.m[s];
+        if (ballot(act) != 0 && act) {
+            f = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const u32 q = count_below(win, W, top, c.u[s][j]);
+                f |= (q < W && win[q < W ? q : W - 1] == c.u[s][j]) ? (1u << j) : 0u;
+            }
+        }
+        mt[s] = f & m;
     }
 }
 
@@ -2913,18 +2937,24 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
     else
         r = run_tile<1, kConsume, SEGS, true>(t, stage, sh, wib, wpb, &c);
 
+    // each segment's smallest and largest valid identifier of the lane
+    u32 lo[SEGS], hi[SEGS];
     u32 mn = ~0u, mx = 0u;
     bool any = false;
 #pragma unroll
-    for (int s = 0; s < SEGS; ++s)
+    for (int s = 0; s < SEGS; ++s) {
+        lo[s] = ~0u;
+        hi[s] = 0u;
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if ((c.m[s] >> j) & 1u) {
-                const u32 v = c.u[s][j];
-                mn = v < mn ? v : mn;
-                mx = v > mx ? v : mx;
-                any = true;
-            }
+        for (int j = 0; j < 16; ++j) {
+            const bool v = (c.m[s] >> j) & 1u;
+            lo[s] = v && c.u[s][j] < lo[s] ? c.u[s][j] : lo[s];
+            hi[s] = v && c.u[s][j] > hi[s] ? c.u[s][j] : hi[s];
+        }
+        mn = lo[s] < mn ? lo[s] : mn;
+        mx = hi[s] > mx ? hi[s] : mx;
+        any = any || c.m[s] != 0;
+    }
     u32 mt[SEGS];
 #pragma unroll
     for (int s = 0; s < SEGS; ++s) mt[s] = 0;
@@ -2939,9 +2969,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
             if (W <= kIsectWin) {
                 for (u32 i = ln; i < W; i += kWave) stage[i] = a.b[first + i];
                 wave_lds_sync();
-                match_window<SEGS>(stage, W, top, c, mt);
+                match_window<SEGS>(stage, W, top, c, lo, hi, mt);
             } else {
-                match_window<SEGS>(a.b + first, W, top, c, mt);
+                match_window<SEGS>(a.b + first, W, top, c, lo, hi, mt);
             }
         }
     }
