@@ -296,11 +296,13 @@ vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count,
  *     in vbyte_decode_delta_m1 with its own prev).
  *   d_list_status: device int32[nlists], required; receives each list's
  *     status under the strict semantics above.
- * A small prep kernel classifies the lists and builds a work table; one
- * persistent launch then decodes every list: lists larger than
- * small_list_bytes (vbyte_set_tuning) are split into tiles chained by a
- * per-list look-back scan and are queued first, smaller lists take one
- * wavefront each.  Asynchronous on `stream`. */
+ * A small prep kernel classifies the lists and builds a work table.  Lists
+ * larger than small_list_bytes (vbyte_set_tuning) are cut into tiles and
+ * decoded in two passes with no look-back, as a single stream: each
+ * wavefront's count and byte sum, one scan over all tiles, then each
+ * wavefront decodes with its prefix within its list.  A persistent launch
+ * then decodes the smaller lists, one wavefront each.  Asynchronous on
+ * `stream`. */
 vbyte_status vbyte_decode_batch(const uint8_t *bytes, size_t nbytes, const int64_t *byte_off,
                                 uint32_t *out, size_t nout, const int64_t *out_off, size_t nlists,
                                 const uint32_t *prevs, int delta, int32_t *d_list_status,
@@ -497,7 +499,7 @@ vbyte_status vbyte_set_flow_grid(int grid);
  *     {4, 8} x tiles_per_chunk {-1, 0, 2, 4, 8, 16}.
  *   vbyte_autotune_batch: vbyte_decode_batch of the given lists (prevs 0);
  *     d_list_status is device int32[nlists].  Candidates: segs_per_wave
- *     {2, 4} x waves_per_block {4, 8} x small_list_bytes {4, 16, 64, 256} KiB.
+ *     {2, 4} x waves_per_block {4, 8} x small_list_bytes {1, 4, 16, 64} KiB.
  *   points, max_points: optional host array that receives each candidate
  *     and its mean time; *npoints (optional) the number written.
  * If the workload does not decode (a data status other than VBYTE_OK) that

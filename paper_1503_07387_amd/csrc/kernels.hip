@@ -1154,6 +1154,41 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
 // slots hold plain values with bits 63:38 clear, which no tagged descriptor
 // has, so a later look-back launch on the same workspace never accepts
 // them.
+// One wavefront's share of a tile aggregate: SEGS segments from byte wv of
+// the aligned base (valid bytes [vstart, vend); EDGE: guarded loads), their
+// continuation bytes, byte sum and whether a run of five continuation bytes
+// ends in them, all wavefront-uniform.
+template <int D, int SEGS, bool EDGE>
+__device__ __forceinline__ void wave_agg(const u8 *base, u64 vstart, u64 vend, u64 wv, u32 &cont,
+                                         u32 &sum, bool &mal) {
+    const u32 ln = lane_id();
+    u32 w[SEGS][4];
+    u32 hb, hbv, valid;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
+        if (EDGE)
+            load16_guarded(base, v, vstart, vend, w[s], valid);
+        else
+            load16(base + v, w[s]);
+    }
+    if (EDGE)
+        load4_guarded(base, (i64)wv - 4, vstart, vend, hb, hbv);
+    else
+        hb = *(const u32 *)(base + wv - 4);
+    cont = 0;
+    sum = 0;
+    bool m = false;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const u32 below = from_lane_below(w[s][3], s == 0 ? hb : read_lane(w[s - 1][3], 63));
+        seg_bytes<D != 0>(w[s], below, cont, sum, m);
+    }
+    cont = wave_sum(cont);
+    if (D) sum = wave_sum(sum);
+    mal = ballot(m) != 0;
+}
+
 template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k_tile_agg(StreamArgs a) {
     __shared__ u32 wc[kMaxWaves], ws[kMaxWaves], wm[kMaxWaves];
@@ -1167,30 +1202,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_tile_agg(StreamArgs a) {
     const u64 wv = tv + (u64)wib * (SEGS * kSegBytes);
     // interior: the tile and the 4 bytes before it lie inside the stream
     const bool interior = tile > 0 && tv + tb <= a.vend;
-    u32 w[SEGS][4];
-    u32 hb, hbv, valid;
-#pragma unroll
-    for (int s = 0; s < SEGS; ++s) {
-        const u64 v = wv + (u64)s * kSegBytes + 16u * ln;
-        if (interior)
-            load16(a.base + v, w[s]);
-        else
-            load16_guarded(a.base, v, a.vstart, a.vend, w[s], valid);
-    }
+    u32 cont, sum;
+    bool wmal;
     if (interior)
-        hb = *(const u32 *)(a.base + wv - 4);
+        wave_agg<D, SEGS, false>(a.base, a.vstart, a.vend, wv, cont, sum, wmal);
     else
-        load4_guarded(a.base, (i64)wv - 4, a.vstart, a.vend, hb, hbv);
-    u32 cont = 0, sum = 0;
-    bool mal = false;
-#pragma unroll
-    for (int s = 0; s < SEGS; ++s) {
-        const u32 below = from_lane_below(w[s][3], s == 0 ? hb : read_lane(w[s - 1][3], 63));
-        seg_bytes<D != 0>(w[s], below, cont, sum, mal);
-    }
-    cont = wave_sum(cont);
-    if (D) sum = wave_sum(sum);
-    const bool wmal = ballot(mal) != 0;
+        wave_agg<D, SEGS, true>(a.base, a.vstart, a.vend, wv, cont, sum, wmal);
     if (ln == 0) {
         wc[wib] = cont;
         ws[wib] = sum;
@@ -3127,9 +3144,9 @@ __device__ __forceinline__ bool list_ok(const ListArgs &a, const ListDesc &d) {
 
 // Prep: classify every list (empty / small / large) and build the work
 // table with a decoupled look-back scan over blocks of kPrepBlock lists.
-// Large lists get one item per span of up to kSpanTiles workgroup tiles, at
-// [0, L); small lists get one slot each, counted down from max_items - 1 (so
-// a slot needs no knowledge of L).
+// Large lists get one item per tile of tb bytes, (list, tile), at [0, L), a
+// list's tiles consecutive; small lists get one slot each, counted down from
+// max_items - 1 (so a slot needs no knowledge of L).
 __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u64 tb) {
     __shared__ u32 sh_c[kPrepBlock / kWave], sh_s[kPrepBlock / kWave];
     __shared__ u32 sh_epoch;
@@ -3160,8 +3177,8 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
             nsmall = 1;
         } else {
             const u64 vs = (u64)(uintptr_t)(a.bytes + d.bb) & 15u;
-            const u64 tiles = (vs + (u64)(d.be - d.bb) + tb - 1) / tb;
-            nlarge = (u32)((tiles + kSpanTiles - 1) / kSpanTiles);
+            nlarge = (u32)((vs + (u64)(d.be - d.bb) + tb - 1) / tb);
+            a.list_status[i] = VBYTE_OK;   // raised by the tile kernels (atomic max)
         }
     }
     const u32 cl = wave_scan(nlarge), cs = wave_scan(nsmall);
@@ -3197,7 +3214,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
             sh_exs = ex.s;
             if (blk == nblocks - 1) {
                 const u64 L = ex.c + bl, S = (u64)ex.s + bs;
-                const bool fits = L + S <= a.max_items;
+                const bool fits = L + S <= a.max_items && L <= a.max_large;
                 const bool stalled = launch_stalled(a.hdr + kStallWord, epoch);
                 astore(&a.totals[0], fits && !stalled ? L : 0);
                 astore(&a.totals[1], fits && !stalled ? S : 0);
@@ -3215,6 +3232,99 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
     }
     if (nsmall) {
         if (sslot < a.max_items) a.items[a.max_items - 1 - sslot] = make_int2((int)i, 0);
+    }
+}
+
+// Large lists of a batch: each list is cut into tiles of wpb x SEGS KiB (the
+// prep's work items, items[k] = (list, tile)) and each wavefront of a tile
+// takes SEGS KiB of it.  Two passes with no look-back and no queue, as for
+// a single stream: k_list_agg stores each wavefront's terminator count and
+// byte sum in its slot (slot k wpb + w for wavefront w of item k), the block
+// scans turn the slots into exclusive prefixes over all items, and
+// k_list_known decodes each wavefront alone with its prefix within its
+// list, the slot's prefix minus that of the list's first slot (a list's
+// items are consecutive).  A run of five continuation bytes raises its
+// list's status to malformed (atomic max); the wavefront holding a list's
+// last byte raises it to the list's truncation or count status the same
+// way, so the list ends with the larger code.  Both kernels loop over the
+// items with a grid stride.
+__device__ __forceinline__ void list_geometry(const ListArgs &a, const ListDesc &d, const u8 *&base,
+                                              u64 &vstart, u64 &vend) {
+    const u8 *p0 = a.bytes + d.bb;
+    base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
+    vstart = (u64)(p0 - base);
+    vend = vstart + (u64)(d.be - d.bb);
+}
+
+template <int D, int SEGS>
+__global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u32 wpb = blockDim.x >> 6;
+    const u64 ub = (u64)SEGS * kSegBytes, tb = (u64)wpb * ub;
+    const u64 L = aload(&a.totals[0]);
+    // every slot up to max_large gets written (zero past the items), so the
+    // scan can run over a size fixed at launch
+    for (u64 k = blockIdx.x; k < a.max_large; k += gridDim.x) {
+        u64 terms = 0;
+        u32 cont = 0, sum = 0;
+        if (k < L) {
+            const int2 e = a.items[k];
+            const u64 li = (u64)e.x, ti = (u64)e.y;
+            const ListDesc d = list_desc(a, li);
+            const u8 *base;
+            u64 vstart, vend;
+            list_geometry(a, d, base, vstart, vend);
+            const u64 wv = ti * tb + (u64)wib * ub;
+            if (wv < vend) {
+                bool mal;
+                if (wv >= vstart + 4 && wv + ub <= vend)
+                    wave_agg<D, SEGS, false>(base, vstart, vend, wv, cont, sum, mal);
+                else
+                    wave_agg<D, SEGS, true>(base, vstart, vend, wv, cont, sum, mal);
+                const u64 lo = wv > vstart ? wv : vstart, hi = wv + ub < vend ? wv + ub : vend;
+                terms = hi - lo - cont;
+                if (mal && ln == 0) atomicMax(&a.list_status[li], (int32_t)VBYTE_EMALFORMED);
+            }
+        }
+        if (ln == 0) {
+            Desc *slot = a.desc + k * wpb + wib;
+            slot->c = terms;
+            slot->s = sum;
+        }
+    }
+}
+
+template <int D, int SEGS>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4 : 8))) void k_list_known(ListArgs a) {
+    extern __shared__ __align__(16) u32 lds[];
+    __shared__ WgShared sh;   // not used by wavefronts that decode alone
+    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u32 wpb = blockDim.x >> 6;
+    u32 *stage = lds + wib * kStageWords;
+    const u64 ub = (u64)SEGS * kSegBytes, tb = (u64)wpb * ub;
+    u64 L = aload(&a.totals[0]);
+    L = L < a.max_large ? L : a.max_large;
+    for (u64 k = blockIdx.x; k < L; k += gridDim.x) {
+        const int2 e = a.items[k];
+        const u64 li = (u64)e.x, ti = (u64)e.y;
+        const ListDesc d = list_desc(a, li);
+        TileIn t{};
+        list_geometry(a, d, t.base, t.vstart, t.vend);
+        const u64 wv = ti * tb + (u64)wib * ub;
+        if (wv >= t.vend) continue;
+        const Desc sq = a.desc[k * wpb + wib], s0 = a.desc[(k - ti) * wpb];
+        t.tv = ti * tb;
+        t.out = a.out + d.ob;
+        t.n = (u64)d.n;
+        t.known_c = (sq.c & kCountMask) - (s0.c & kCountMask);
+        t.known_s = (a.prevs ? a.prevs[li] : 0u) + ((u32)sq.s - (u32)s0.s);
+        TileOut r;
+        if (wv >= t.vstart + 4 && wv + ub + 4 <= t.vend)
+            r = run_tile<D, kKnownW, SEGS, false>(t, stage, sh, wib, wpb);
+        else
+            r = run_tile<D, kKnownW, SEGS, true>(t, stage, sh, wib, wpb);
+        if (wv + ub >= t.vend && ln == 0)
+            atomicMax(&a.list_status[li], final_status(false, t.base[t.vend - 1], r.total, t.n));
     }
 }
 
@@ -3280,12 +3390,10 @@ __device__ __forceinline__ u32 pick_next(u32 *counter, u32 *slot) {
     return first_lane(*slot);
 }
 
-// Persistent batched decode.  Workgroups first take spans of large-list
-// tiles from one queue (in list order, so a tile's predecessors were taken
-// earlier by running workgroups), then chunks of small lists from a second
-// queue (each wavefront pulls lists of the chunk through an LDS counter).
-// Both queue words are reset by their last taker; each queue costs one
-// device-wide atomic per span or chunk, not per tile or list.
+// Persistent decode of the small lists of a batch: workgroups take chunks of
+// small lists from a queue (each wavefront pulls lists of the chunk through
+// an LDS counter).  The queue word is reset by its last taker; the queue
+// costs one device-wide atomic per chunk, not per list.
 template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     extern __shared__ __align__(16) u32 lds[];
@@ -3294,68 +3402,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     __shared__ u32 sh_pick[kMaxWaves];
     const u32 tid = threadIdx.x;
     const u32 wib = tid >> 6;
-    const u32 wpb = blockDim.x >> 6;
     u32 *stage = lds + wib * kStageWords;
-    if (tid == 0) sh.epoch = (u32)aload(a.hdr);
-    __syncthreads();
-    const u32 epoch = sh.epoch;
-    const u64 L = aload(&a.totals[0]);
     const u64 S = aload(&a.totals[1]);
     const u64 fail_code = aload(&a.totals[2]);   // 1: the work table was too small; 2: prep stalled
     const bool failed = fail_code != 0;
     const u64 G = gridDim.x;
-    const u64 tb = (u64)wpb * SEGS * kSegBytes;
-    u64 *qlarge = a.hdr + 1;
     u64 *qsmall = a.hdr + 2;
-
-    for (;;) {
-        if (tid == 0) {
-            const u64 k = aadd(qlarge, 1);
-            if (k == L + G - 1) {      // last taker: every workgroup has read the epoch
-                astore(qlarge, 0);
-                astore(a.hdr, (u64)epoch + 1);
-            }
-            sh.item = k;
-        }
-        __syncthreads();
-        const u64 k = sh.item;
-        __syncthreads();
-        if (k >= L) break;
-        const int2 e = a.items[k];
-        const u64 li = (u64)e.x;
-        const u32 sp = (u32)e.y;
-        const ListDesc d = list_desc(a, li);
-        const u8 *p0 = a.bytes + d.bb;
-        TileIn t{};
-        t.base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
-        t.vstart = (u64)(p0 - t.base);
-        t.vend = t.vstart + (u64)(d.be - d.bb);
-        t.out = a.out + d.ob;
-        t.n = (u64)d.n;
-        t.prev = a.prevs ? a.prevs[li] : 0u;
-        t.desc = a.desc;
-        t.dfirst = (i64)(k - sp) * kSpanTiles;
-        t.tag = make_tag(epoch);
-        t.spin_limit = a.spin_limit;
-        t.stall = a.hdr + kStallWord;
-        const u64 tiles = (t.vend + tb - 1) / tb;
-        const u64 t0 = (u64)sp * kSpanTiles;
-        const u64 t1 = t0 + kSpanTiles < tiles ? t0 + kSpanTiles : tiles;
-        for (u64 ti = t0; ti < t1; ++ti) {
-            t.tv = ti * tb;
-            t.didx = t.dfirst + (i64)ti;
-            const bool interior = ti > 0 && t.tv + tb + 4 <= t.vend;
-            const TileOut r = interior ? run_tile<D, kFull, SEGS, false>(t, stage, sh, wib, wpb)
-                                       : run_tile<D, kFull, SEGS, true>(t, stage, sh, wib, wpb);
-            if (ti == tiles - 1 && tid == 0)
-                a.list_status[li] = launch_stalled(t.stall, epoch)
-                                        ? VBYTE_ESTALLED
-                                        : final_status(r.mal, t.base[t.vend - 1], r.total, t.n);
-            if (r.stalled && tid == 0)
-                __hip_atomic_store(&a.list_status[li], (int32_t)VBYTE_ESTALLED, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
 
     // Chunks of up to kSmallChunk lists, smaller when there are few small
     // lists, so that there are about 2 chunks per workgroup and every
@@ -3749,12 +3801,46 @@ hipError_t launch_stream_s(const StreamArgs &a, int delta, int count_only, int w
     return launch_stream_t<0, false, SEGS>(a, wpb, s);
 }
 
+template <int D, int SEGS>
+hipError_t launch_large_lists_t(const ListArgs &a, int wpb, u32 grid, hipStream_t s) {
+    k_list_agg<D, SEGS><<<grid, wpb * kWave, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the slots through the block scans of the two-pass decode (the status
+    // they write goes to a spare header word)
+    StreamArgs sa{};
+    sa.base = (const u8 *)a.hdr;
+    sa.vstart = 0;
+    sa.vend = 1;
+    sa.ntiles = (u32)(a.max_large * (u64)wpb);
+    sa.desc = a.desc;
+    sa.d_status = (int32_t *)(a.totals + 3);
+    sa.d_count = nullptr;
+    const u32 nblocks = (u32)((sa.ntiles + kScanSpan - 1) / kScanSpan);
+    k_tile_block_sums<<<nblocks, kScanBlock, 0, s>>>(sa, sa.desc + sa.ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_tile_block_scan<<<nblocks, kScanBlock, 0, s>>>(sa, sa.desc + sa.ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
+    k_list_known<D, SEGS><<<grid, wpb * kWave, lds, s>>>(a);
+    return hipGetLastError();
+}
+
 template <int SEGS>
 hipError_t launch_batch_s(const ListArgs &a, int wpb, int grid_blocks, hipStream_t s) {
     const u32 nblocks = (u32)((a.nlists + kPrepBlock - 1) / kPrepBlock);
     if (nblocks) {
         k_prep<<<nblocks, kPrepBlock, 0, s>>>(a, nblocks, (u64)wpb * SEGS * kSegBytes);
         hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (a.max_large) {
+        // the tile kernels loop over the items: 4x the persistent grid
+        const u64 want = (u64)grid_blocks * 4;
+        const u32 grid = (u32)(a.max_large < want ? a.max_large : want);
+        hipError_t e = a.delta == 2 ? launch_large_lists_t<2, SEGS>(a, wpb, grid, s)
+                       : a.delta    ? launch_large_lists_t<1, SEGS>(a, wpb, grid, s)
+                                    : launch_large_lists_t<0, SEGS>(a, wpb, grid, s);
         if (e != hipSuccess) return e;
     }
     const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);

@@ -7,7 +7,7 @@
 // wavefront {2, 4} x wavefronts per workgroup {4, 8} x single-stream kernel
 // {-1 (two passes), 0 (look-back per tile), chunks of 2, 4, 8, 16
 // tiles} for a single stream; for the batched form {2, 4} x
-// {4, 8} x small-list threshold {4, 16, 64, 256} KiB.  The
+// {4, 8} x small-list threshold {1, 4, 16, 64} KiB.  The
 // tuning is process-wide, so no other decode should run meanwhile.
 
 #include <hip/hip_runtime.h>
@@ -141,7 +141,7 @@ vbyte_status vbyte_autotune_batch(const uint8_t *bytes, size_t nbytes, const int
     int nc = 0;
     for (int segs : {2, 4})
         for (int wpb : {4, 8})
-            for (int64_t small : {4096, 16384, 65536, 262144})
+            for (int64_t small : {1024, 4096, 16384, 65536})
                 cands[nc++] = Cand{segs, wpb, small, vbyte_get_chunk_tiles()};
     auto call = [&]() {
         return vbyte_decode_batch(bytes, nbytes, byte_off, out, nout, out_off, nlists, nullptr,

@@ -167,9 +167,10 @@ struct ListArgs {
     uint64_t nlists;
     int delta;
     uint64_t small_bytes;      // lists of at most this many bytes take one wavefront
-    uint64_t max_items;        // capacity of the work table / descriptor array
-    uint64_t *hdr;             // persistent-queue header (ticket word)
-    Desc *desc;                // kSpanTiles per large span
+    uint64_t max_items;        // capacity of the work table
+    uint64_t max_large;        // capacity for large-list tiles (items [0, L), L <= max_large)
+    uint64_t *hdr;             // header: epoch, small-list queue word, prep ticket
+    Desc *desc;                // wpb slots per large-list tile, then the scan's block totals
     Desc *prep_desc;           // one per prep block
     int2 *items;               // work table: (list, tile) per item
     uint64_t *totals;          // [0] large spans L, [1] small lists S, [2] 1 if the table
@@ -270,7 +271,6 @@ inline uint64_t stream_tiles(uint64_t vstart, uint64_t nbytes, int segs, int wpb
 }
 
 constexpr int kPrepBlock = 256;           // lists per prep workgroup
-constexpr int kSpanTiles = 1;             // large-list tiles per batched work item
 constexpr int kSmallChunk = 64;           // small lists per batched work item
 constexpr int kBatchWavesPerCu = 16;      // resident wavefronts per CU of the persistent batched decode
 
