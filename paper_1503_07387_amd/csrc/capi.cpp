@@ -401,8 +401,9 @@ vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan) {
     off += two_pass_slots(a.max_large * (uint64_t)wpb) * sizeof(Desc);
     plan->prep_off = off;
     off += (size_t)nblocks * sizeof(Desc);
+    off = (off + 63) & ~(size_t)63;
     plan->items_off = off;
-    off += a.max_items * sizeof(int2);
+    off += a.max_items * sizeof(BatchItem);
     plan->bytes = off;
     plan->segs = segs;
     plan->wpb = wpb;
@@ -421,7 +422,7 @@ void batch_bind(ListArgs &a, const BatchPlan &plan, uint8_t *ws) {
     a.totals = (uint64_t *)(ws + kTotalsOff);
     a.desc = (Desc *)(ws + plan.desc_off);
     a.prep_desc = (Desc *)(ws + plan.prep_off);
-    a.items = (int2 *)(ws + plan.items_off);
+    a.items = (BatchItem *)(ws + plan.items_off);
 }
 
 vbyte_status hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }

@@ -3226,12 +3226,14 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
     __syncthreads();
     const u64 lstart = sh_exc + wl + (cl - nlarge);
     const u64 sslot = (u64)sh_exs + ws + (cs - nsmall);
-    for (u32 k = 0; k < nlarge; ++k) {
-        const u64 it = lstart + k;
-        if (it < a.max_items) a.items[it] = make_int2((int)i, (int)k);
-    }
-    if (nsmall) {
-        if (sslot < a.max_items) a.items[a.max_items - 1 - sslot] = make_int2((int)i, 0);
+    if (nlarge || nsmall) {
+        const ListDesc d = list_desc(a, i);
+        BatchItem it{d.bb, d.be, d.ob, d.n, (u32)i, 0u, a.prevs ? a.prevs[i] : 0u, 0u};
+        for (u32 k = 0; k < nlarge; ++k) {
+            it.ti = k;
+            if (lstart + k < a.max_items) a.items[lstart + k] = it;
+        }
+        if (nsmall && sslot < a.max_items) a.items[a.max_items - 1 - sslot] = it;
     }
 }
 
@@ -3248,7 +3250,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
 // last byte raises it to the list's truncation or count status the same
 // way, so the list ends with the larger code.  Both kernels loop over the
 // items with a grid stride.
-__device__ __forceinline__ void list_geometry(const ListArgs &a, const ListDesc &d, const u8 *&base,
+__device__ __forceinline__ void list_geometry(const ListArgs &a, const BatchItem &d, const u8 *&base,
                                               u64 &vstart, u64 &vend) {
     const u8 *p0 = a.bytes + d.bb;
     base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
@@ -3264,13 +3266,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
     const u64 L = aload(&a.totals[0]);
     // every slot up to max_large gets written (zero past the items), so the
     // scan can run over a size fixed at launch
+    // each iteration loads the next iteration's item first
+    BatchItem cur{};
+    if (blockIdx.x < L) cur = a.items[blockIdx.x];
     for (u64 k = blockIdx.x; k < a.max_large; k += gridDim.x) {
+        BatchItem nxt{};
+        if (k + gridDim.x < L) nxt = a.items[k + gridDim.x];
         u64 terms = 0;
         u32 cont = 0, sum = 0;
         if (k < L) {
-            const int2 e = a.items[k];
-            const u64 li = (u64)e.x, ti = (u64)e.y;
-            const ListDesc d = list_desc(a, li);
+            const BatchItem &d = cur;
+            const u64 li = d.li, ti = d.ti;
             const u8 *base;
             u64 vstart, vend;
             list_geometry(a, d, base, vstart, vend);
@@ -3291,6 +3297,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
             slot->c = terms;
             slot->s = sum;
         }
+        cur = nxt;
     }
 }
 
@@ -3304,10 +3311,14 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
     const u64 ub = (u64)SEGS * kSegBytes, tb = (u64)wpb * ub;
     u64 L = aload(&a.totals[0]);
     L = L < a.max_large ? L : a.max_large;
+    BatchItem cur{};
+    if (blockIdx.x < L) cur = a.items[blockIdx.x];
     for (u64 k = blockIdx.x; k < L; k += gridDim.x) {
-        const int2 e = a.items[k];
-        const u64 li = (u64)e.x, ti = (u64)e.y;
-        const ListDesc d = list_desc(a, li);
+        BatchItem nxt{};
+        if (k + gridDim.x < L) nxt = a.items[k + gridDim.x];
+        const BatchItem d = cur;
+        cur = nxt;
+        const u64 li = d.li, ti = d.ti;
         TileIn t{};
         list_geometry(a, d, t.base, t.vstart, t.vend);
         const u64 wv = ti * tb + (u64)wib * ub;
@@ -3317,7 +3328,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
         t.out = a.out + d.ob;
         t.n = (u64)d.n;
         t.known_c = (sq.c & kCountMask) - (s0.c & kCountMask);
-        t.known_s = (a.prevs ? a.prevs[li] : 0u) + ((u32)sq.s - (u32)s0.s);
+        t.known_s = d.prev + ((u32)sq.s - (u32)s0.s);
         TileOut r;
         if (wv >= t.vstart + 4 && wv + ub + 4 <= t.vend)
             r = run_tile<D, kKnownW, SEGS, false>(t, stage, sh, wib, wpb);
@@ -3331,17 +3342,18 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
 // Small list: one wavefront walks its segments in order, carrying the rank
 // and the running sum, with no look-back.
 template <int D>
-__device__ __forceinline__ void run_small(const ListArgs &a, u64 li, const ListDesc &d, u32 *rows) {
+__device__ __forceinline__ void run_small(const ListArgs &a, const BatchItem &d, u32 *rows) {
     constexpr bool DELTA = D != 0, RANK = D == 2;
     const u32 ln = lane_id();
     const u8 *p0 = a.bytes + d.bb;
     const u8 *base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
     const u64 vstart = (u64)(p0 - base);
     const u64 vend = vstart + (u64)(d.be - d.bb);
+    const u8 last = base[vend - 1];   // for the status, loaded with the first segment
     u32 *out = a.out + d.ob;
     const u64 n = (u64)d.n;
     u64 rank = 0;
-    u32 run = a.prevs ? a.prevs[li] : 0u;
+    u32 run = d.prev;
     bool mal = false;
     u32 pw = 0, pv = 0;   // lane 63's last dword and validity of the previous segment
     for (u64 tv = 0; tv < vend; tv += kSegBytes) {
@@ -3378,7 +3390,7 @@ __device__ __forceinline__ void run_small(const ListArgs &a, u64 li, const ListD
     }
     const bool anymal = ballot(mal) != 0;
     // every lane stores the same (uniform) status word
-    a.list_status[li] = final_status(anymal, base[vend - 1], rank, n);
+    a.list_status[d.li] = final_status(anymal, last, rank, n);
 }
 
 // Wavefront-uniform fetch-and-increment of an LDS counter: lane 0 performs
@@ -3429,13 +3441,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
         if (c >= nchunks) break;
         const u64 lo = c * chunk;
         const u64 hi = lo + chunk < S ? lo + chunk : S;
-        // each wavefront pulls lists of the chunk through the LDS counter
+        // each wavefront pulls lists of the chunk through the LDS counter,
+        // one list ahead: the next list's item loads while this one decodes
         u32 j = pick_next(&sh_next, &sh_pick[wib]);
         while (lo + j < hi) {
-            const u64 slot = lo + j;
-            const int2 e = a.items[a.max_items - 1 - slot];
-            const u64 li = (u64)e.x;
-            run_small<D>(a, li, list_desc(a, li), stage);
+            const BatchItem cur = a.items[a.max_items - 1 - (lo + j)];
+            run_small<D>(a, cur, stage);
             j = pick_next(&sh_next, &sh_pick[wib]);
         }
         __syncthreads();
@@ -3801,10 +3812,43 @@ hipError_t launch_stream_s(const StreamArgs &a, int delta, int count_only, int w
     return launch_stream_t<0, false, SEGS>(a, wpb, s);
 }
 
+// Workgroups of `kernel` resident at once on the device: the tile kernels of
+// the batch loop over their items, so a grid larger than that would run in
+// rounds, each block's items one after another.
+template <class K>
+hipError_t resident_grid(K kernel, int wpb, size_t lds, std::atomic<int> (&cache)[9], u32 &grid) {
+    int b = cache[wpb].load(std::memory_order_relaxed);
+    if (b <= 0) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, wpb * kWave, lds);
+        if (e != hipSuccess) return e;
+        b = b > 0 ? b : 1;
+        cache[wpb].store(b, std::memory_order_relaxed);
+    }
+    static std::atomic<int> cus{0};
+    int c = cus.load(std::memory_order_relaxed);
+    if (c <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        cus.store(c, std::memory_order_relaxed);
+    }
+    grid = (u32)(c * b);
+    return hipSuccess;
+}
+
 template <int D, int SEGS>
-hipError_t launch_large_lists_t(const ListArgs &a, int wpb, u32 grid, hipStream_t s) {
-    k_list_agg<D, SEGS><<<grid, wpb * kWave, 0, s>>>(a);
-    hipError_t e = hipGetLastError();
+hipError_t launch_large_lists_t(const ListArgs &a, int wpb, hipStream_t s) {
+    static std::atomic<int> occ_agg[9], occ_known[9];   // per wpb (zero-initialised statics)
+    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
+    u32 ga = 0, gk = 0;
+    hipError_t e = resident_grid(k_list_agg<D, SEGS>, wpb, 0, occ_agg, ga);
+    if (e != hipSuccess) return e;
+    if ((e = resident_grid(k_list_known<D, SEGS>, wpb, lds, occ_known, gk)) != hipSuccess) return e;
+    ga = (u64)ga < a.max_large ? ga : (u32)a.max_large;
+    gk = (u64)gk < a.max_large ? gk : (u32)a.max_large;
+    k_list_agg<D, SEGS><<<ga, wpb * kWave, 0, s>>>(a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the slots through the block scans of the two-pass decode (the status
     // they write goes to a spare header word)
@@ -3821,8 +3865,7 @@ hipError_t launch_large_lists_t(const ListArgs &a, int wpb, u32 grid, hipStream_
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_tile_block_scan<<<nblocks, kScanBlock, 0, s>>>(sa, sa.desc + sa.ntiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
-    k_list_known<D, SEGS><<<grid, wpb * kWave, lds, s>>>(a);
+    k_list_known<D, SEGS><<<gk, wpb * kWave, lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -3835,21 +3878,28 @@ hipError_t launch_batch_s(const ListArgs &a, int wpb, int grid_blocks, hipStream
         if (e != hipSuccess) return e;
     }
     if (a.max_large) {
-        // the tile kernels loop over the items: 4x the persistent grid
-        const u64 want = (u64)grid_blocks * 4;
-        const u32 grid = (u32)(a.max_large < want ? a.max_large : want);
-        hipError_t e = a.delta == 2 ? launch_large_lists_t<2, SEGS>(a, wpb, grid, s)
-                       : a.delta    ? launch_large_lists_t<1, SEGS>(a, wpb, grid, s)
-                                    : launch_large_lists_t<0, SEGS>(a, wpb, grid, s);
+        hipError_t e = a.delta == 2 ? launch_large_lists_t<2, SEGS>(a, wpb, s)
+                       : a.delta    ? launch_large_lists_t<1, SEGS>(a, wpb, s)
+                                    : launch_large_lists_t<0, SEGS>(a, wpb, s);
         if (e != hipSuccess) return e;
     }
+    // the small lists: as many workgroups as are resident at once (the
+    // decode of a small list waits on memory more than it computes)
+    (void)grid_blocks;
     const size_t lds = (size_t)wpb * kStageWords * sizeof(u32);
-    if (a.delta == 2)
-        k_batch<2, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
-    else if (a.delta)
-        k_batch<1, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
-    else
-        k_batch<0, SEGS><<<grid_blocks, wpb * kWave, lds, s>>>(a);
+    static std::atomic<int> occ_small[3][9];
+    u32 grid = 0;
+    hipError_t e;
+    if (a.delta == 2) {
+        if ((e = resident_grid(k_batch<2, SEGS>, wpb, lds, occ_small[2], grid)) != hipSuccess) return e;
+        k_batch<2, SEGS><<<grid, wpb * kWave, lds, s>>>(a);
+    } else if (a.delta) {
+        if ((e = resident_grid(k_batch<1, SEGS>, wpb, lds, occ_small[1], grid)) != hipSuccess) return e;
+        k_batch<1, SEGS><<<grid, wpb * kWave, lds, s>>>(a);
+    } else {
+        if ((e = resident_grid(k_batch<0, SEGS>, wpb, lds, occ_small[0], grid)) != hipSuccess) return e;
+        k_batch<0, SEGS><<<grid, wpb * kWave, lds, s>>>(a);
+    }
     return hipGetLastError();
 }
 

@@ -154,6 +154,14 @@ constexpr int kIsectSegs = 2, kIsectWaves = 8;   // the intersection's tiling
 
 // One list of a batched launch, resolved on the device from either CSR
 // offsets or gather rows.
+// A work item of the batched decode: the list's byte and output ranges,
+// its start value, its index and the item's tile within it.
+struct BatchItem {
+    int64_t bb, be, ob, n;
+    uint32_t li, ti, prev, pad;
+};
+static_assert(sizeof(BatchItem) == 48, "work item is 48 bytes");
+
 struct ListArgs {
     const uint8_t *bytes;
     uint64_t nbytes;           // size of `bytes`; every list must lie inside
@@ -172,7 +180,7 @@ struct ListArgs {
     uint64_t *hdr;             // header: epoch, small-list queue word, prep ticket
     Desc *desc;                // wpb slots per large-list tile, then the scan's block totals
     Desc *prep_desc;           // one per prep block
-    int2 *items;               // work table: (list, tile) per item
+    BatchItem *items;          // work table: one self-contained item per large-list tile or small list
     uint64_t *totals;          // [0] large spans L, [1] small lists S, [2] 1 if the table
                                // overflowed (written by the prep kernel)
     uint32_t wpb;              // wavefronts per workgroup (small lists per work item)
