@@ -1316,12 +1316,22 @@ __device__ __forceinline__ void scan_span(const StreamArgs &a, u64 i_begin, u64 
 constexpr u64 kScanSpan = kTwoPassScanSpan;   // tile slots per scan workgroup
 static_assert(kScanSpan == 2 * kScanBlock, "two slots per thread");
 
+// Slots of a block scan: ntiles, or the count an earlier kernel wrote (at
+// most ntiles, which sized the grid).
+__device__ __forceinline__ u64 scan_slots(const StreamArgs &a) {
+    if (!a.d_nslots) return a.ntiles;
+    const u64 n = *a.d_nslots;
+    return n < a.ntiles ? n : a.ntiles;
+}
+
 __global__ __launch_bounds__(kScanBlock) void k_tile_block_sums(StreamArgs a, Desc *bsum) {
     __shared__ u64 bc[kScanBlock / kWave];
     __shared__ u32 bs[kScanBlock / kWave], bm[kScanBlock / kWave];
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
+    const u64 nt = scan_slots(a);
     const u64 i0 = (u64)blockIdx.x * kScanSpan;
-    const u64 i1 = i0 + kScanSpan < a.ntiles ? i0 + kScanSpan : a.ntiles;
+    if (i0 >= nt) return;   // past the slots written this launch
+    const u64 i1 = i0 + kScanSpan < nt ? i0 + kScanSpan : nt;
     u64 c = 0;
     u32 sm = 0;
     bool m = false;
@@ -1357,7 +1367,9 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_block_scan(StreamArgs a, co
     __shared__ u64 pc_sh;
     __shared__ u32 ps_sh, pm_sh, all_m_sh;
     const u32 tid = threadIdx.x, ln = lane_id();
-    const u32 b = blockIdx.x, nb = gridDim.x;
+    const u64 nt = scan_slots(a);
+    const u32 b = blockIdx.x, nb = (u32)((nt + kScanSpan - 1) / kScanSpan);
+    if (b >= nb) return;   // past the slots written this launch
     const u8 lastb = a.base[a.vend - 1];
     if (tid < kWave) {
         // the carry: totals of the blocks before this one (and the
@@ -1392,7 +1404,7 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_block_scan(StreamArgs a, co
     u32 carry_s = ps_sh;
     bool carry_m = pm_sh != 0;
     const u64 i0 = (u64)b * kScanSpan;
-    const u64 i1 = i0 + kScanSpan < a.ntiles ? i0 + kScanSpan : a.ntiles;
+    const u64 i1 = i0 + kScanSpan < nt ? i0 + kScanSpan : nt;
     scan_span(a, i0, i1, carry_c, carry_s, carry_m);
     if (b == nb - 1 && tid == 0) {
         *a.d_status = final_status(all_m_sh != 0, lastb, carry_c, a.n);
@@ -3217,6 +3229,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
                 const bool fits = L + S <= a.max_items && L <= a.max_large;
                 const bool stalled = launch_stalled(a.hdr + kStallWord, epoch);
                 astore(&a.totals[0], fits && !stalled ? L : 0);
+                astore(&a.totals[3], fits && !stalled ? L * a.wpb : 0);
                 astore(&a.totals[1], fits && !stalled ? S : 0);
                 astore(&a.totals[2], stalled ? 2 : fits ? 0 : 1);
                 astore(a.hdr, (u64)epoch + 1);   // every block has published
@@ -3263,13 +3276,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
     const u32 wpb = blockDim.x >> 6;
     const u64 ub = (u64)SEGS * kSegBytes, tb = (u64)wpb * ub;
-    const u64 L = aload(&a.totals[0]);
-    // every slot up to max_large gets written (zero past the items), so the
-    // scan can run over a size fixed at launch
+    u64 L = aload(&a.totals[0]);
+    L = L < a.max_large ? L : a.max_large;
     // each iteration loads the next iteration's item first
     BatchItem cur{};
     if (blockIdx.x < L) cur = a.items[blockIdx.x];
-    for (u64 k = blockIdx.x; k < a.max_large; k += gridDim.x) {
+    for (u64 k = blockIdx.x; k < L; k += gridDim.x) {
         BatchItem nxt{};
         if (k + gridDim.x < L) nxt = a.items[k + gridDim.x];
         u64 terms = 0;
@@ -3858,8 +3870,9 @@ hipError_t launch_large_lists_t(const ListArgs &a, int wpb, hipStream_t s) {
     sa.vend = 1;
     sa.ntiles = (u32)(a.max_large * (u64)wpb);
     sa.desc = a.desc;
-    sa.d_status = (int32_t *)(a.totals + 3);
+    sa.d_status = (int32_t *)(a.totals + 4);
     sa.d_count = nullptr;
+    sa.d_nslots = a.totals + 3;   // L x wpb, written by the prep
     const u32 nblocks = (u32)((sa.ntiles + kScanSpan - 1) / kScanSpan);
     k_tile_block_sums<<<nblocks, kScanBlock, 0, s>>>(sa, sa.desc + sa.ntiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;

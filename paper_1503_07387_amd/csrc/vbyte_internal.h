@@ -81,6 +81,9 @@ struct StreamArgs {
     uint64_t window;
     uint64_t *scratch;
     uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
+    // Block scans only: the number of slots, read on the device when set
+    // (written by an earlier kernel), else ntiles, which then bounds it.
+    const uint64_t *d_nslots = nullptr;
 };
 
 // Single-stream decode in one persistent launch of `grid` workgroups that
@@ -181,8 +184,9 @@ struct ListArgs {
     Desc *desc;                // wpb slots per large-list tile, then the scan's block totals
     Desc *prep_desc;           // one per prep block
     BatchItem *items;          // work table: one self-contained item per large-list tile or small list
-    uint64_t *totals;          // [0] large spans L, [1] small lists S, [2] 1 if the table
-                               // overflowed (written by the prep kernel)
+    uint64_t *totals;          // [0] large-list tiles L, [1] small lists S, [2] 1 if the
+                               // table overflowed, 2 if the prep stalled, [3] L x wpb slots
+                               // (written by the prep kernel); [4] a spare status word
     uint32_t wpb;              // wavefronts per workgroup (small lists per work item)
     uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
 };
