@@ -3405,6 +3405,118 @@ __device__ __forceinline__ void run_small(const ListArgs &a, const BatchItem &d,
     a.list_status[d.li] = final_status(anymal, last, rank, n);
 }
 
+// Several small lists in one wavefront: list q of the pack (q < m) takes the
+// c_q lanes from lane s_q = (c_0 + ... + c_(q-1)), one aligned 16-byte chunk
+// of its bytes per lane (c_q = ceil((vstart + bytes) / 16) <= 64), so a lane
+// never holds two lists.  The halos stop at the list's first and last lanes;
+// the count and sum scans run over the whole wavefront and each lane takes
+// off the value at its list's first lane; the integers are compacted in LDS
+// in wavefront order and each list's run is copied to its output.  Lane q
+// brings list q's item (`it`, `need` = c_q, `incl` = s_q + c_q).
+__device__ __forceinline__ u32 lane_u32(u32 v, u32 l) {
+    return (u32)__builtin_amdgcn_ds_bpermute((int)(l << 2), (int)v);
+}
+__device__ __forceinline__ u64 lane_u64(u64 v, u32 l) {
+    return ((u64)lane_u32((u32)(v >> 32), l) << 32) | lane_u32((u32)v, l);
+}
+__device__ __forceinline__ u32 wave_scan_max(u32 x) {   // x >= 0: 0 is the identity
+    x = max(x, dpp_zero<0x111>(x));
+    x = max(x, dpp_zero<0x112>(x));
+    x = max(x, dpp_zero<0x114>(x));
+    x = max(x, dpp_zero<0x118>(x));
+    x = max(x, dpp_zero<0x142, 0xA>(x));
+    x = max(x, dpp_zero<0x143, 0xC>(x));
+    return x;
+}
+
+template <int D>
+__device__ __forceinline__ void run_packed(const ListArgs &a, const BatchItem &it, u32 need, u32 incl,
+                                           u32 m, u32 *stage) {
+    constexpr bool DELTA = D != 0, RANK = D == 2;
+    const u32 ln = lane_id();
+    // lane -> list of the pack: list q marks its first lane, a max scan spreads it
+    stage[ln] = 0;
+    wave_lds_sync();
+    if (ln < m) stage[incl - need] = ln + 1;
+    wave_lds_sync();
+    const u32 q1 = wave_scan_max(stage[ln]);   // 1 + the lane's list, 0 past the pack
+    wave_lds_sync();
+    const u32 q = q1 ? q1 - 1 : 0;
+    const u32 used = read_lane(incl, m - 1);   // lanes the pack takes
+    const bool in = ln < used;
+    // the list's fields from lane q
+    const u64 bb = lane_u64((u64)it.bb, q), be = lane_u64((u64)it.be, q);
+    const u32 prev = lane_u32(it.prev, q);
+    const u32 s0 = lane_u32(incl - need, q), cq = lane_u32(need, q);
+    const u32 o = ln - s0;   // the lane's chunk within its list
+    const u8 *p0 = a.bytes + bb;
+    const u8 *base = (const u8 *)((uintptr_t)p0 & ~(uintptr_t)15);
+    const u64 vstart = (u64)(p0 - base);
+    const u64 vend = vstart + (be - bb);
+    u32 w[4] = {0, 0, 0, 0}, valid = 0;
+    if (in) load16_guarded(base, 16u * o, vstart, vend, w, valid);
+    const bool first = o == 0, last = o + 1 == cq;
+    // cross-lane reads in uniform control flow, then the list edges applied
+    u32 below = from_lane_below(w[3], 0u);
+    const u32 bv = from_lane_below(valid, 0u);
+    const bool below_ok = !first && ((bv >> 15) & 1u) != 0;
+    if (first) below = 0;
+    u32 ab = from_lane_above(w[0], 0u);
+    u32 abv = from_lane_above(valid, 0u) & 0xFu;
+    if (last || !in) {
+        ab = 0;
+        abv = 0;
+    }
+    const SegMask mk = seg_mask<true>(w, valid, below, below_ok, ab, abv);
+    // the list's last byte, from the lane that holds it
+    u32 lastb = 0;
+    if (in && last) {
+        const u32 k = (u32)(vend - 1 - 16u * o);   // 0..15
+        const u32 word = k < 4 ? w[0] : k < 8 ? w[1] : k < 12 ? w[2] : w[3];
+        lastb = (word >> (8 * (k & 3))) & 0xFFu;
+    }
+    const u32 cnt = (u32)__builtin_popcount(mk.emit);
+    const u32 ci = wave_scan(cnt);
+    const u32 cx = ci - cnt;                  // codes of the wavefront before the lane
+    const u32 cbase = lane_u32(cx, s0);       // ... before the list's first lane
+    u32 r[16];
+    if (DELTA) {
+        const u32 ls = horner<true>(w, ab, mk.emit, r);
+        const u32 si = wave_scan(ls);
+        const u32 sx = si - ls;
+        const u32 add = prev + (sx - lane_u32(sx, s0)) + ls;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) r[j] += add;
+    } else {
+        horner<false>(w, ab, mk.emit, r);
+    }
+    // compact the integers in wavefront order (rank term for differences
+    // minus one: the code's rank within its list)
+    u32 pos = cx;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if ((mk.emit >> j) & 1u) {
+            stage[pos] = RANK ? r[j] + (pos - cbase) : r[j];
+            ++pos;
+        }
+    wave_lds_sync();
+    const u64 malm = ballot(mk.mal);
+    for (u32 k = 0; k < m; ++k) {
+        const u32 ks = read_lane(incl - need, k), kc = read_lane(need, k);
+        const u32 from = read_lane(cx, ks), to = read_lane(ci, ks + kc - 1);
+        const u64 n = ((u64)read_lane((u32)((u64)it.n >> 32), k) << 32) | read_lane((u32)it.n, k);
+        const u64 ob = ((u64)read_lane((u32)((u64)it.ob >> 32), k) << 32) | read_lane((u32)it.ob, k);
+        const u32 total = to - from;
+        const u32 lim = (u64)total < n ? total : (u32)n;
+        for (u32 i = ln; i < lim; i += kWave) a.out[ob + i] = stage[from + i];
+        const u64 lm = (kc >= 64 ? ~0ull : ((1ull << kc) - 1)) << ks;
+        if (ln == 0)
+            a.list_status[read_lane(it.li, k)] =
+                final_status((malm & lm) != 0, (u8)read_lane(lastb, ks + kc - 1), total, n);
+    }
+    wave_lds_sync();
+}
+
 // Wavefront-uniform fetch-and-increment of an LDS counter: lane 0 performs
 // the atomic and leaves the old value in the wavefront's LDS slot, which all
 // lanes then read (through memory, so the result is uniform by construction).
@@ -3421,9 +3533,6 @@ __device__ __forceinline__ u32 pick_next(u32 *counter, u32 *slot) {
 template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     extern __shared__ __align__(16) u32 lds[];
-    __shared__ WgShared sh;
-    __shared__ u32 sh_next;
-    __shared__ u32 sh_pick[kMaxWaves];
     const u32 tid = threadIdx.x;
     const u32 wib = tid >> 6;
     u32 *stage = lds + wib * kStageWords;
@@ -3431,37 +3540,37 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     const u64 fail_code = aload(&a.totals[2]);   // 1: the work table was too small; 2: prep stalled
     const bool failed = fail_code != 0;
     const u64 G = gridDim.x;
-    u64 *qsmall = a.hdr + 2;
 
-    // Chunks of up to kSmallChunk lists, smaller when there are few small
-    // lists, so that there are about 2 chunks per workgroup and every
-    // workgroup gets some; one device-wide atomic (about 12 ns, serialised
-    // on the queue word) per chunk.
-    u64 chunk = S / (G * 2);
-    chunk = chunk < 1 ? 1 : (chunk > (u64)kSmallChunk ? (u64)kSmallChunk : chunk);
-    const u64 nchunks = (S + chunk - 1) / chunk;
-    for (;;) {
-        if (tid == 0) {
-            const u64 c = aadd(qsmall, 1);
-            if (c == nchunks + G - 1) astore(qsmall, 0);
-            sh.item = c;
-            sh_next = 0;
+    // Wavefront w of the W in the grid takes the consecutive small lists
+    // [w S / W, (w + 1) S / W) (no queue: the lists need no ordering).  It
+    // packs the next lists that fit in 64 lanes (16 bytes each) into one
+    // pass; a list of more than 64 lanes decodes alone, segment by segment.
+    const u32 ln = lane_id();
+    const u64 W = G * (blockDim.x >> 6);
+    const u64 wid = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
+    {
+        const u64 lo = wid * S / W;
+        const u64 hi = (wid + 1) * S / W;
+        for (u64 p = lo; p < hi;) {
+            BatchItem it{};
+            u32 need = 65;   // lanes of the list at lane t (65: none, never fits)
+            if (p + ln < hi) {
+                it = a.items[a.max_items - 1 - (p + ln)];
+                const u64 vs = (u64)(uintptr_t)(a.bytes + it.bb) & 15u;
+                const u64 l = (vs + (u64)(it.be - it.bb) + 15) >> 4;
+                need = l < 65 ? (u32)l : 65u;
+            }
+            if (read_lane(need, 0) > 64) {
+                const BatchItem d = a.items[a.max_items - 1 - p];
+                run_small<D>(a, d, stage);
+                ++p;
+                continue;
+            }
+            const u32 incl = wave_scan(need);
+            const u32 m = (u32)__builtin_popcountll(ballot(incl <= 64 && p + ln < hi));
+            run_packed<D>(a, it, need, incl, m, stage);
+            p += m;
         }
-        __syncthreads();
-        const u64 c = sh.item;
-        __syncthreads();
-        if (c >= nchunks) break;
-        const u64 lo = c * chunk;
-        const u64 hi = lo + chunk < S ? lo + chunk : S;
-        // each wavefront pulls lists of the chunk through the LDS counter,
-        // one list ahead: the next list's item loads while this one decodes
-        u32 j = pick_next(&sh_next, &sh_pick[wib]);
-        while (lo + j < hi) {
-            const BatchItem cur = a.items[a.max_items - 1 - (lo + j)];
-            run_small<D>(a, cur, stage);
-            j = pick_next(&sh_next, &sh_pick[wib]);
-        }
-        __syncthreads();
     }
     if (failed) {
         const u64 nthreads = (u64)gridDim.x * blockDim.x;
