@@ -262,45 +262,41 @@ __device__ __forceinline__ void load16(const u8 *p, u32 (&w)[4]) {
     w[3] = q.w;
 }
 
-// Bytes [v, v+16) of the aligned base; only bytes in [lo, hi) are read, the
-// others are zero and marked invalid.
+// 0xFF in each byte k of the result whose bit k of m (0..3) is set.
+__device__ __forceinline__ u32 byte_mask4(u32 m) {
+    return ((m & 1u) * 0xFFu) | ((m & 2u) * 0x7F80u) | ((m & 4u) * 0x3FC000u) | ((m & 8u) * 0x1FE00000u);
+}
+
+// Bytes [v, v+16) of the aligned base: those in [lo, hi) are marked valid,
+// the others read as zero.  A chunk that holds a byte of [lo, hi) is loaded
+// with one 16-byte load (an aligned chunk never crosses a page, so it is
+// mapped whenever one of its bytes is) and its other bytes are cleared
+// before any use; a chunk with none is not loaded.
 __device__ __forceinline__ void load16_guarded(const u8 *base, u64 v, u64 lo, u64 hi, u32 (&w)[4],
                                                u32 &valid) {
     w[0] = w[1] = w[2] = w[3] = 0;
     valid = 0;
-    if (v >= lo && v + 16 <= hi) {
-        load16(base + v, w);
-        valid = 0xFFFFu;
-        return;
-    }
+    if (v + 16 <= lo || v >= hi) return;
+    load16(base + v, w);
+    const u32 a = v < lo ? (u32)(lo - v) : 0u;         // first byte in range, 0..15
+    const u32 e = v + 16 > hi ? (u32)(hi - v) : 16u;   // one past the last, 1..16
+    valid = (0xFFFFu >> (16u - e)) & (0xFFFFu << a) & 0xFFFFu;
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
-        const u64 p = v + b;
-        if (p >= lo && p < hi) {
-            w[b >> 2] |= (u32)base[p] << (8 * (b & 3));
-            valid |= 1u << b;
-        }
-    }
+    for (int k = 0; k < 4; ++k) w[k] &= byte_mask4((valid >> (4 * k)) & 0xFu);
 }
 
-// 4 bytes [v, v+4) (v a multiple of 4) with validity bits at 0..3.
+// 4 bytes [v, v+4) (v a multiple of 4) with validity bits at 0..3, loaded
+// as one dword when it holds a byte of [lo, hi) (same reasoning as above).
 __device__ __forceinline__ void load4_guarded(const u8 *base, i64 v, u64 lo, u64 hi, u32 &w,
                                               u32 &valid4) {
     w = 0;
     valid4 = 0;
-    if (v >= (i64)lo && (u64)v + 4 <= hi) {
-        w = *(const u32 *)(base + v);
-        valid4 = 0xFu;
-        return;
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const i64 p = v + b;
-        if (p >= (i64)lo && (u64)p < hi) {
-            w |= (u32)base[p] << (8 * b);
-            valid4 |= 1u << b;
-        }
-    }
+    if (v + 4 <= (i64)lo || v >= (i64)hi) return;
+    w = *(const u32 *)(base + v);
+    const u32 a = v < (i64)lo ? (u32)((i64)lo - v) : 0u;         // 0..3
+    const u32 e = (u64)v + 4 > hi ? (u32)((i64)hi - v) : 4u;     // 1..4
+    valid4 = (0xFu >> (4u - e)) & (0xFu << a) & 0xFu;
+    w &= byte_mask4(valid4);
 }
 
 // Top bit of each byte (bit 7 of byte k -> bit k), by dot products of the
