@@ -636,7 +636,7 @@ def bench_serving(torch, vbyte, serve, workloads, idx, nq=10000, warm=1000):
 def summarize_trace(trace_csv, stats_csv, out_md, command_line, kinds=HEADLINE_KINDS):
     """Turn a rocprofv3 --kernel-trace --stats run of bench.py (with a fixed
     --tuning, so that every decode call runs the same kernels) into the
-    per-stream duration table of profiles/decode_delta_64Mi_kernel_trace.md:
+    per-call duration table of profiles/decode_plain_1Gi_mix_kernel_trace.md:
     per decode call, the sum of its kernels' durations and its span from
     the first kernel's start to the last kernel's end (what the HIP events
     around the call in bench.py measure), and per kernel."""
