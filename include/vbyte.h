@@ -300,8 +300,9 @@ vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count,
  * larger than small_list_bytes (vbyte_set_tuning) are cut into tiles and
  * decoded in two passes with no look-back, as a single stream: each
  * wavefront's count and byte sum, one scan over all tiles, then each
- * wavefront decodes with its prefix within its list.  A persistent launch
- * then decodes the smaller lists, one wavefront each.  Asynchronous on
+ * wavefront decodes with its prefix within its list.  A last launch decodes
+ * the smaller lists, several to a wavefront (each on its own lanes) when
+ * they fit in 64 x 16 bytes, else one wavefront each.  Asynchronous on
  * `stream`. */
 vbyte_status vbyte_decode_batch(const uint8_t *bytes, size_t nbytes, const int64_t *byte_off,
                                 uint32_t *out, size_t nout, const int64_t *out_off, size_t nlists,

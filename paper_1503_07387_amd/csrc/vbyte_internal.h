@@ -180,7 +180,7 @@ struct ListArgs {
     uint64_t small_bytes;      // lists of at most this many bytes take one wavefront
     uint64_t max_items;        // capacity of the work table
     uint64_t max_large;        // capacity for large-list tiles (items [0, L), L <= max_large)
-    uint64_t *hdr;             // header: epoch, small-list queue word, prep ticket
+    uint64_t *hdr;             // header: epoch (word 0), prep ticket (3), stall word (4)
     Desc *desc;                // wpb slots per large-list tile, then the scan's block totals
     Desc *prep_desc;           // one per prep block
     BatchItem *items;          // work table: one self-contained item per large-list tile or small list
