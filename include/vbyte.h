@@ -445,10 +445,15 @@ vbyte_status vbyte_encode_batch(const uint32_t *values, size_t n, const int64_t 
 size_t vbyte_workspace_size(size_t nbytes);
 
 /* Tuning knobs of the decode kernels (0 keeps a value unchanged):
- * segs_per_wave: 1 KiB segments one wavefront decodes per tile (1..4);
+ * segs_per_wave: 1 KiB segments one wavefront decodes per tile (1, 2, 4);
  * waves_per_block: wavefronts per workgroup (1..8);
- * small_list_bytes: lists up to this size take one wavefront each in the
- * batched forms.  Returns VBYTE_EINVAL for an unsupported value. */
+ * small_list_bytes: lists up to this size take the small-list path in the
+ * batched forms.  Returns VBYTE_EINVAL for an unsupported value.
+ * The process-wide defaults (2, 8, 16384, the two-pass schedule, a spin
+ * limit of 2^20) can also be set from the environment when the library is
+ * loaded: VBYTE_SEGS_PER_WAVE, VBYTE_WAVES_PER_BLOCK, VBYTE_SMALL_LIST_BYTES,
+ * VBYTE_SCHEDULE (as vbyte_set_chunk_tiles) and VBYTE_SPIN_LIMIT; values
+ * out of range are ignored. */
 vbyte_status vbyte_set_tuning(int segs_per_wave, int waves_per_block, int64_t small_list_bytes);
 void vbyte_get_tuning(int *segs_per_wave, int *waves_per_block, int64_t *small_list_bytes);
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <cstdlib>
 #include <mutex>
 #include <utility>
 
@@ -32,6 +33,31 @@ std::atomic<int> g_chunk{-1};  // single stream: -1 = two passes, four launches,
                                // 0 = per-tile look-back, k = chunks of k tiles
 std::atomic<int> g_flow_grid{0};   // workgroups of the one-launch decode (0: per CU count)
 std::atomic<uint32_t> g_spin_limit{kDefaultSpinLimit};
+
+// Process-wide defaults from the environment, read once when the library is
+// loaded: VBYTE_SEGS_PER_WAVE (1, 2, 4), VBYTE_WAVES_PER_BLOCK (1..8),
+// VBYTE_SMALL_LIST_BYTES (>= 1), VBYTE_SCHEDULE (-2..64, as
+// vbyte_set_chunk_tiles), VBYTE_SPIN_LIMIT (>= 1).  A value that is not a
+// whole number in range is ignored.
+bool env_int(const char *name, long long lo, long long hi, long long *v) {
+    const char *t = std::getenv(name);
+    if (!t || !*t) return false;
+    char *end = nullptr;
+    const long long x = std::strtoll(t, &end, 10);
+    if (*end != '\0' || x < lo || x > hi) return false;
+    *v = x;
+    return true;
+}
+struct EnvDefaults {
+    EnvDefaults() {
+        long long v = 0;
+        if (env_int("VBYTE_SEGS_PER_WAVE", 1, 4, &v) && v != 3) g_segs.store((int)v);
+        if (env_int("VBYTE_WAVES_PER_BLOCK", 1, 8, &v)) g_wpb.store((int)v);
+        if (env_int("VBYTE_SMALL_LIST_BYTES", 1, 1ll << 40, &v)) g_small.store((int64_t)v);
+        if (env_int("VBYTE_SCHEDULE", kScheduleFlow, 64, &v)) g_chunk.store((int)v);
+        if (env_int("VBYTE_SPIN_LIMIT", 1, 0xFFFFFFFFll, &v)) g_spin_limit.store((uint32_t)v);
+    }
+} g_env_defaults;
 
 vbyte_status hip_fail(hipError_t e, const char *what) {
     std::snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));

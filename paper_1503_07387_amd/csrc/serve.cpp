@@ -25,6 +25,7 @@
 // single-stream launch per list (the baseline the batched form is compared
 // against).
 
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -119,6 +120,14 @@ struct vbyte_server {
     uint32_t *pool = nullptr;
     uint64_t pool_elems = 0;
     std::vector<Slot> slots;
+};
+
+// A roctx range for the lifetime of the object (ends on every return path).
+struct RoctxRange {
+    explicit RoctxRange(const char *what) { roctxRangePushA(what); }
+    ~RoctxRange() { roctxRangePop(); }
+    RoctxRange(const RoctxRange &) = delete;
+    RoctxRange &operator=(const RoctxRange &) = delete;
 };
 
 static vbyte_status hip_err(hipError_t e) { return e == hipSuccess ? VBYTE_OK : VBYTE_EHIP; }
@@ -236,6 +245,9 @@ vbyte_status vbyte_server_run(vbyte_server *s, size_t nreq, const double *arriva
 
     const Clock::time_point t0 = Clock::now();
     auto now_s = [&]() { return std::chrono::duration<double>(Clock::now() - t0).count(); };
+    // roctx ranges (visible with rocprofv3 --marker-trace): the whole run,
+    // each batch's admission and launches; a mark per finished group
+    const RoctxRange run_range("vbyte_server_run");
 
     while (completed < nreq) {
         bool progressed = false;
@@ -256,6 +268,7 @@ vbyte_status vbyte_server_run(vbyte_server *s, size_t nreq, const double *arriva
                 const double t = now_s();
                 for (size_t k = sl.gend[g]; k < sl.gend[g + 1]; ++k) latency_s[sl.reqs[k]] = t - arrival_s[sl.reqs[k]];
                 sl.gseen[g] = 1;
+                roctxMarkA("vbyte serve: group done");
                 progressed = true;
             }
             hipError_t q = hipEventQuery(sl.done);
@@ -305,6 +318,7 @@ vbyte_status vbyte_server_run(vbyte_server *s, size_t nreq, const double *arriva
                 pending.pop_front();
             }
             if (batch.empty()) break;
+            const RoctxRange batch_range("vbyte serve: batch admission and launches");
             vbyte_status es = ensure_rows(sl, rows);
             if (es != VBYTE_OK) return es;
             // groups: the batch's requests by output size, smallest first

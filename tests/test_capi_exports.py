@@ -116,3 +116,26 @@ def test_workspace_size_covers_every_single_stream_form():
             prev = ws
     finally:
         lib.vbyte_set_tuning(segs.value, wpb.value, small.value)
+
+
+def test_tuning_defaults_from_the_environment():
+    """VBYTE_* variables set the process-wide defaults when the library is
+    loaded (no GPU call involved); out-of-range values are ignored."""
+    import subprocess
+    import sys
+    code = ("import ctypes, sys; sys.path.insert(0, %r); from paper_1503_07387_amd import vbyte; "
+            "L = vbyte.load(); s, w, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64(); "
+            "L.vbyte_get_tuning(ctypes.byref(s), ctypes.byref(w), ctypes.byref(m)); "
+            "print(s.value, w.value, m.value, L.vbyte_get_chunk_tiles())") % ROOT
+    def run(env):
+        e = dict(os.environ)
+        e.update(env)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=e, timeout=120)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return [int(t) for t in r.stdout.split()]
+    base = run({})
+    assert base == [2, 8, 16384, -1]
+    assert run({"VBYTE_SEGS_PER_WAVE": "4", "VBYTE_WAVES_PER_BLOCK": "4",
+                "VBYTE_SMALL_LIST_BYTES": "2048", "VBYTE_SCHEDULE": "-2"}) == [4, 4, 2048, -2]
+    assert run({"VBYTE_SEGS_PER_WAVE": "3", "VBYTE_WAVES_PER_BLOCK": "9",
+                "VBYTE_SMALL_LIST_BYTES": "x", "VBYTE_SCHEDULE": "65"}) == base
