@@ -135,19 +135,19 @@ def test_config3_alone_equals_in_mix(config3):
 
 
 def test_small_request_does_not_wait_for_the_largest_in_its_batch():
-    """Two requests admitted together into one batch: one asks for three
+    """Two requests admitted together into one batch: one asks for four
     32Mi-integer lists, the other for two 100-integer lists.  The small
     request completes when its own lists are decoded (the batch's requests
     are decoded in groups, smallest first, each followed by an event), well
     before the batch ends; both results equal the oracle's."""
     rng = np.random.default_rng(77)
-    lens = np.array([1 << 25, 1 << 25, 1 << 25, 100, 100, 5], np.int64)
+    lens = np.array([1 << 25, 1 << 25, 1 << 25, 1 << 25, 100, 100, 5], np.int64)
     gaps = [rng.geometric(1 / 50, int(n)).astype(np.uint32) for n in lens]
     enc = [oracle.encode(g) for g in gaps]
     byte_off = np.concatenate([[0], np.cumsum([e.size for e in enc])]).astype(np.int64)
     b = np.concatenate(enc)
     idx = {"bytes": b, "byte_off": byte_off, "counts": lens, "dev": torch.from_numpy(b).cuda()}
-    terms = [np.array([0, 1, 2], np.int64), np.array([3, 4], np.int64)]
+    terms = [np.array([0, 1, 2, 3], np.int64), np.array([4, 5], np.int64)]
     srv = serve.Server(idx["dev"], byte_off, lens, pool_bytes=1 << 30, nstreams=1,
                        max_batch_requests=8)
     want = [expected(idx, terms[r]) for r in range(2)]
