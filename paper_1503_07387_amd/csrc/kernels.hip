@@ -3235,14 +3235,31 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
     __syncthreads();
     const u64 lstart = sh_exc + wl + (cl - nlarge);
     const u64 sslot = (u64)sh_exs + ws + (cs - nsmall);
+    BatchItem it{};
     if (nlarge || nsmall) {
         const ListDesc d = list_desc(a, i);
-        BatchItem it{d.bb, d.be, d.ob, d.n, (u32)i, 0u, a.prevs ? a.prevs[i] : 0u, 0u};
-        for (u32 k = 0; k < nlarge; ++k) {
-            it.ti = k;
-            if (lstart + k < a.max_items) a.items[lstart + k] = it;
-        }
+        it = BatchItem{d.bb, d.be, d.ob, d.n, (u32)i, 0u, a.prevs ? a.prevs[i] : 0u, 0u};
         if (nsmall && sslot < a.max_items) a.items[a.max_items - 1 - sslot] = it;
+    }
+    // a large list's items (one per tile) are written by the whole
+    // wavefront, lane l taking tiles l, l + 64, ...: a list of many tiles
+    // would keep one lane busy long after the others
+    for (u64 big = ballot(nlarge != 0); big; big &= big - 1) {
+        const u32 j = (u32)__builtin_ctzll(big);
+        const u32 nj = read_lane(nlarge, j);
+        const u64 sj = ((u64)read_lane((u32)(lstart >> 32), j) << 32) | read_lane((u32)lstart, j);
+        BatchItem ij;
+        ij.bb = (int64_t)(((u64)read_lane((u32)((u64)it.bb >> 32), j) << 32) | read_lane((u32)it.bb, j));
+        ij.be = (int64_t)(((u64)read_lane((u32)((u64)it.be >> 32), j) << 32) | read_lane((u32)it.be, j));
+        ij.ob = (int64_t)(((u64)read_lane((u32)((u64)it.ob >> 32), j) << 32) | read_lane((u32)it.ob, j));
+        ij.n = (int64_t)(((u64)read_lane((u32)((u64)it.n >> 32), j) << 32) | read_lane((u32)it.n, j));
+        ij.li = read_lane(it.li, j);
+        ij.prev = read_lane(it.prev, j);
+        ij.pad = 0;
+        for (u32 k = ln; k < nj; k += kWave) {
+            ij.ti = k;
+            if (sj + k < a.max_items) a.items[sj + k] = ij;
+        }
     }
 }
 
