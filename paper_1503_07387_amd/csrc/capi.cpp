@@ -410,21 +410,20 @@ vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan) {
     if (((uintptr_t)a.out & 3u) != 0) return VBYTE_EINVAL;
     if (a.nlists >= (1ull << 31)) return VBYTE_EINVAL;
     const int segs = g_segs.load(), wpb = g_wpb.load();
-    const uint64_t tb = (uint64_t)segs * wpb * kSegBytes;
     a.wpb = (uint32_t)wpb;
     a.small_bytes = (uint64_t)std::max<int64_t>(g_small.load(), 0);
     // A large list holds more than small_bytes bytes and needs at most
-    // bytes/tb + 2 tiles (one work item each, wpb slots); a small list needs
-    // one item.
+    // bytes/ub + 2 pieces of ub = segs KiB (one work item and slot each); a
+    // small list needs one item.
+    const uint64_t ub = (uint64_t)segs * kSegBytes;
     const uint64_t nlarge_max = std::min<uint64_t>(a.nlists, list_bytes / (a.small_bytes + 1));
-    a.max_large = list_bytes / tb + 2 * nlarge_max;
+    a.max_large = list_bytes / ub + 2 * nlarge_max;
     a.max_items = a.max_large + a.nlists + 2;
-    if (a.max_items >= (1ull << 31) || a.max_large * (uint64_t)wpb >= (1ull << 31))
-        return VBYTE_EINVAL;
+    if (a.max_items >= (1ull << 31)) return VBYTE_EINVAL;
     const uint32_t nblocks = (uint32_t)((a.nlists + kPrepBlock - 1) / kPrepBlock);
     size_t off = kHeaderBytes;
     plan->desc_off = off;
-    off += two_pass_slots(a.max_large * (uint64_t)wpb) * sizeof(Desc);
+    off += two_pass_slots(a.max_large) * sizeof(Desc);
     plan->prep_off = off;
     off += (size_t)nblocks * sizeof(Desc);
     off = (off + 63) & ~(size_t)63;

@@ -3152,10 +3152,10 @@ __device__ __forceinline__ bool list_ok(const ListArgs &a, const ListDesc &d) {
 
 // Prep: classify every list (empty / small / large) and build the work
 // table with a decoupled look-back scan over blocks of kPrepBlock lists.
-// Large lists get one item per tile of tb bytes, (list, tile), at [0, L), a
-// list's tiles consecutive; small lists get one slot each, counted down from
+// Large lists get one item per piece of ub bytes, (list, piece), at [0, L),
+// a list's pieces consecutive; small lists get one slot each, counted down from
 // max_items - 1 (so a slot needs no knowledge of L).
-__global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u64 tb) {
+__global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u64 ub) {
     __shared__ u32 sh_c[kPrepBlock / kWave], sh_s[kPrepBlock / kWave];
     __shared__ u32 sh_epoch;
     __shared__ u64 sh_exc;
@@ -3185,7 +3185,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
             nsmall = 1;
         } else {
             const u64 vs = (u64)(uintptr_t)(a.bytes + d.bb) & 15u;
-            nlarge = (u32)((vs + (u64)(d.be - d.bb) + tb - 1) / tb);
+            nlarge = (u32)((vs + (u64)(d.be - d.bb) + ub - 1) / ub);
             a.list_status[i] = VBYTE_OK;   // raised by the tile kernels (atomic max)
         }
     }
@@ -3225,7 +3225,6 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
                 const bool fits = L + S <= a.max_items && L <= a.max_large;
                 const bool stalled = launch_stalled(a.hdr + kStallWord, epoch);
                 astore(&a.totals[0], fits && !stalled ? L : 0);
-                astore(&a.totals[3], fits && !stalled ? L * a.wpb : 0);
                 astore(&a.totals[1], fits && !stalled ? S : 0);
                 astore(&a.totals[2], stalled ? 2 : fits ? 0 : 1);
                 astore(a.hdr, (u64)epoch + 1);   // every block has published
@@ -3241,8 +3240,8 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
         it = BatchItem{d.bb, d.be, d.ob, d.n, (u32)i, 0u, a.prevs ? a.prevs[i] : 0u, 0u};
         if (nsmall && sslot < a.max_items) a.items[a.max_items - 1 - sslot] = it;
     }
-    // a large list's items (one per tile) are written by the whole
-    // wavefront, lane l taking tiles l, l + 64, ...: a list of many tiles
+    // a large list's items (one per piece) are written by the whole
+    // wavefront, lane l taking pieces l, l + 64, ...: a list of many pieces
     // would keep one lane busy long after the others
     for (u64 big = ballot(nlarge != 0); big; big &= big - 1) {
         const u32 j = (u32)__builtin_ctzll(big);
@@ -3263,19 +3262,18 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
     }
 }
 
-// Large lists of a batch: each list is cut into tiles of wpb x SEGS KiB (the
-// prep's work items, items[k] = (list, tile)) and each wavefront of a tile
-// takes SEGS KiB of it.  Two passes with no look-back and no queue, as for
-// a single stream: k_list_agg stores each wavefront's terminator count and
-// byte sum in its slot (slot k wpb + w for wavefront w of item k), the block
-// scans turn the slots into exclusive prefixes over all items, and
-// k_list_known decodes each wavefront alone with its prefix within its
-// list, the slot's prefix minus that of the list's first slot (a list's
-// items are consecutive).  A run of five continuation bytes raises its
-// list's status to malformed (atomic max); the wavefront holding a list's
-// last byte raises it to the list's truncation or count status the same
-// way, so the list ends with the larger code.  Both kernels loop over the
-// items with a grid stride.
+// Large lists of a batch: each list is cut into pieces of SEGS KiB, one per
+// wavefront (the prep's work items, items[k] = (list, piece), a list's
+// pieces consecutive).  Two passes with no look-back and no queue, as for a
+// single stream: k_list_agg stores each piece's terminator count and byte
+// sum in slot k, the block scans turn the slots into exclusive prefixes over
+// all items, and k_list_known decodes each piece alone with its prefix
+// within its list, the slot's prefix minus that of the list's first piece.
+// A run of five continuation bytes raises its list's status to malformed
+// (atomic max); the wavefront holding a list's last byte raises it to the
+// list's truncation or count status the same way, so the list ends with the
+// larger code.  Both kernels hand out items with a grid stride over
+// wavefronts.
 __device__ __forceinline__ void list_geometry(const ListArgs &a, const BatchItem &d, const u8 *&base,
                                               u64 &vstart, u64 &vend) {
     const u8 *p0 = a.bytes + d.bb;
@@ -3286,41 +3284,35 @@ __device__ __forceinline__ void list_geometry(const ListArgs &a, const BatchItem
 
 template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
-    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
-    const u32 wpb = blockDim.x >> 6;
-    const u64 ub = (u64)SEGS * kSegBytes, tb = (u64)wpb * ub;
+    const u32 ln = lane_id();
+    const u64 ub = (u64)SEGS * kSegBytes;
     u64 L = aload(&a.totals[0]);
     L = L < a.max_large ? L : a.max_large;
-    // each iteration loads the next iteration's item first
+    // wavefront w of the grid takes items w, w + W, ...; each iteration
+    // loads the next iteration's item first
+    const u64 W = (u64)gridDim.x * (blockDim.x >> 6);
+    const u64 k0 = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     BatchItem cur{};
-    if (blockIdx.x < L) cur = a.items[blockIdx.x];
-    for (u64 k = blockIdx.x; k < L; k += gridDim.x) {
+    if (k0 < L) cur = a.items[k0];
+    for (u64 k = k0; k < L; k += W) {
         BatchItem nxt{};
-        if (k + gridDim.x < L) nxt = a.items[k + gridDim.x];
-        u64 terms = 0;
-        u32 cont = 0, sum = 0;
-        if (k < L) {
-            const BatchItem &d = cur;
-            const u64 li = d.li, ti = d.ti;
-            const u8 *base;
-            u64 vstart, vend;
-            list_geometry(a, d, base, vstart, vend);
-            const u64 wv = ti * tb + (u64)wib * ub;
-            if (wv < vend) {
-                bool mal;
-                if (wv >= vstart + 4 && wv + ub <= vend)
-                    wave_agg<D, SEGS, false>(base, vstart, vend, wv, cont, sum, mal);
-                else
-                    wave_agg<D, SEGS, true>(base, vstart, vend, wv, cont, sum, mal);
-                const u64 lo = wv > vstart ? wv : vstart, hi = wv + ub < vend ? wv + ub : vend;
-                terms = hi - lo - cont;
-                if (mal && ln == 0) atomicMax(&a.list_status[li], (int32_t)VBYTE_EMALFORMED);
-            }
-        }
+        if (k + W < L) nxt = a.items[k + W];
+        const BatchItem &d = cur;
+        const u8 *base;
+        u64 vstart, vend;
+        list_geometry(a, d, base, vstart, vend);
+        const u64 wv = (u64)d.ti * ub;   // < vend: the prep makes no empty piece
+        u32 cont, sum;
+        bool mal;
+        if (wv >= vstart + 4 && wv + ub <= vend)
+            wave_agg<D, SEGS, false>(base, vstart, vend, wv, cont, sum, mal);
+        else
+            wave_agg<D, SEGS, true>(base, vstart, vend, wv, cont, sum, mal);
+        const u64 lo = wv > vstart ? wv : vstart, hi = wv + ub < vend ? wv + ub : vend;
+        if (mal && ln == 0) atomicMax(&a.list_status[d.li], (int32_t)VBYTE_EMALFORMED);
         if (ln == 0) {
-            Desc *slot = a.desc + k * wpb + wib;
-            slot->c = terms;
-            slot->s = sum;
+            a.desc[k].c = hi - lo - cont;
+            a.desc[k].s = sum;
         }
         cur = nxt;
     }
@@ -3330,37 +3322,38 @@ template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4 : 8))) void k_list_known(ListArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;   // not used by wavefronts that decode alone
-    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
-    const u32 wpb = blockDim.x >> 6;
+    const u32 wib = threadIdx.x >> 6, ln = lane_id();
     u32 *stage = lds + wib * kStageWords;
-    const u64 ub = (u64)SEGS * kSegBytes, tb = (u64)wpb * ub;
+    const u64 ub = (u64)SEGS * kSegBytes;
     u64 L = aload(&a.totals[0]);
     L = L < a.max_large ? L : a.max_large;
+    const u64 W = (u64)gridDim.x * (blockDim.x >> 6);
+    const u64 k0 = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
     BatchItem cur{};
-    if (blockIdx.x < L) cur = a.items[blockIdx.x];
-    for (u64 k = blockIdx.x; k < L; k += gridDim.x) {
+    if (k0 < L) cur = a.items[k0];
+    for (u64 k = k0; k < L; k += W) {
         BatchItem nxt{};
-        if (k + gridDim.x < L) nxt = a.items[k + gridDim.x];
+        if (k + W < L) nxt = a.items[k + W];
         const BatchItem d = cur;
         cur = nxt;
-        const u64 li = d.li, ti = d.ti;
+        const u64 ti = d.ti;
         TileIn t{};
         list_geometry(a, d, t.base, t.vstart, t.vend);
-        const u64 wv = ti * tb + (u64)wib * ub;
-        if (wv >= t.vend) continue;
-        const Desc sq = a.desc[k * wpb + wib], s0 = a.desc[(k - ti) * wpb];
-        t.tv = ti * tb;
+        const u64 wv = ti * ub;
+        const Desc sq = a.desc[k], s0 = a.desc[k - ti];
+        t.tv = wv;
         t.out = a.out + d.ob;
         t.n = (u64)d.n;
         t.known_c = (sq.c & kCountMask) - (s0.c & kCountMask);
         t.known_s = d.prev + ((u32)sq.s - (u32)s0.s);
         TileOut r;
+        // the piece is its own one-wavefront tile (wavefront index 0 of 1)
         if (wv >= t.vstart + 4 && wv + ub + 4 <= t.vend)
-            r = run_tile<D, kKnownW, SEGS, false>(t, stage, sh, wib, wpb);
+            r = run_tile<D, kKnownW, SEGS, false>(t, stage, sh, 0, 1);
         else
-            r = run_tile<D, kKnownW, SEGS, true>(t, stage, sh, wib, wpb);
+            r = run_tile<D, kKnownW, SEGS, true>(t, stage, sh, 0, 1);
         if (wv + ub >= t.vend && ln == 0)
-            atomicMax(&a.list_status[li], final_status(false, t.base[t.vend - 1], r.total, t.n));
+            atomicMax(&a.list_status[d.li], final_status(false, t.base[t.vend - 1], r.total, t.n));
     }
 }
 
@@ -3990,11 +3983,11 @@ hipError_t launch_large_lists_t(const ListArgs &a, int wpb, hipStream_t s) {
     sa.base = (const u8 *)a.hdr;
     sa.vstart = 0;
     sa.vend = 1;
-    sa.ntiles = (u32)(a.max_large * (u64)wpb);
+    sa.ntiles = (u32)a.max_large;
     sa.desc = a.desc;
     sa.d_status = (int32_t *)(a.totals + 4);
     sa.d_count = nullptr;
-    sa.d_nslots = a.totals + 3;   // L x wpb, written by the prep
+    sa.d_nslots = a.totals + 0;   // L, written by the prep
     const u32 nblocks = (u32)((sa.ntiles + kScanSpan - 1) / kScanSpan);
     k_tile_block_sums<<<nblocks, kScanBlock, 0, s>>>(sa, sa.desc + sa.ntiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -4008,7 +4001,7 @@ template <int SEGS>
 hipError_t launch_batch_s(const ListArgs &a, int wpb, int grid_blocks, hipStream_t s) {
     const u32 nblocks = (u32)((a.nlists + kPrepBlock - 1) / kPrepBlock);
     if (nblocks) {
-        k_prep<<<nblocks, kPrepBlock, 0, s>>>(a, nblocks, (u64)wpb * SEGS * kSegBytes);
+        k_prep<<<nblocks, kPrepBlock, 0, s>>>(a, nblocks, (u64)SEGS * kSegBytes);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

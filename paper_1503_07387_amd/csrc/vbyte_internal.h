@@ -179,14 +179,14 @@ struct ListArgs {
     int delta;
     uint64_t small_bytes;      // lists of at most this many bytes take one wavefront
     uint64_t max_items;        // capacity of the work table
-    uint64_t max_large;        // capacity for large-list tiles (items [0, L), L <= max_large)
+    uint64_t max_large;        // capacity for large-list pieces (items [0, L), L <= max_large)
     uint64_t *hdr;             // header: epoch (word 0), prep ticket (3), stall word (4)
-    Desc *desc;                // wpb slots per large-list tile, then the scan's block totals
+    Desc *desc;                // a slot per large-list piece, then the scan's block totals
     Desc *prep_desc;           // one per prep block
     BatchItem *items;          // work table: one self-contained item per large-list tile or small list
-    uint64_t *totals;          // [0] large-list tiles L, [1] small lists S, [2] 1 if the
-                               // table overflowed, 2 if the prep stalled, [3] L x wpb slots
-                               // (written by the prep kernel); [4] a spare status word
+    uint64_t *totals;          // [0] large-list pieces L, [1] small lists S, [2] 1 if the
+                               // table overflowed, 2 if the prep stalled (written by the
+                               // prep kernel); [4] a spare status word
     uint32_t wpb;              // wavefronts per workgroup (small lists per work item)
     uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
 };
