@@ -429,6 +429,8 @@ vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan) {
     off = (off + 63) & ~(size_t)63;
     plan->items_off = off;
     off += a.max_items * sizeof(BatchItem);
+    plan->pmap_off = off;   // 48-byte items keep it 16-byte aligned
+    off += a.max_large * sizeof(uint32_t);
     plan->bytes = off;
     plan->segs = segs;
     plan->wpb = wpb;
@@ -448,6 +450,7 @@ void batch_bind(ListArgs &a, const BatchPlan &plan, uint8_t *ws) {
     a.desc = (Desc *)(ws + plan.desc_off);
     a.prep_desc = (Desc *)(ws + plan.prep_off);
     a.items = (BatchItem *)(ws + plan.items_off);
+    a.pmap = (uint32_t *)(ws + plan.pmap_off);
 }
 
 vbyte_status hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }

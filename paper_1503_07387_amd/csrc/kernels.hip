@@ -3152,8 +3152,8 @@ __device__ __forceinline__ bool list_ok(const ListArgs &a, const ListDesc &d) {
 
 // Prep: classify every list (empty / small / large) and build the work
 // table with a decoupled look-back scan over blocks of kPrepBlock lists.
-// Large lists get one item per piece of ub bytes, (list, piece), at [0, L),
-// a list's pieces consecutive; small lists get one slot each, counted down from
+// Large lists get pieces of ub bytes, numbered [0, L), a list's pieces
+// consecutive, with the list's item at its first piece (see pmap below); small lists get one slot each, counted down from
 // max_items - 1 (so a slot needs no knowledge of L).
 __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u64 ub) {
     __shared__ u32 sh_c[kPrepBlock / kWave], sh_s[kPrepBlock / kWave];
@@ -3234,46 +3234,40 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
     __syncthreads();
     const u64 lstart = sh_exc + wl + (cl - nlarge);
     const u64 sslot = (u64)sh_exs + ws + (cs - nsmall);
-    BatchItem it{};
     if (nlarge || nsmall) {
         const ListDesc d = list_desc(a, i);
-        it = BatchItem{d.bb, d.be, d.ob, d.n, (u32)i, 0u, a.prevs ? a.prevs[i] : 0u, 0u};
+        const BatchItem it{d.bb, d.be, d.ob, d.n, (u32)i, 0u, a.prevs ? a.prevs[i] : 0u, 0u};
         if (nsmall && sslot < a.max_items) a.items[a.max_items - 1 - sslot] = it;
+        if (nlarge && lstart < a.max_large) a.items[lstart] = it;   // the head
     }
-    // a large list's items (one per piece) are written by the whole
-    // wavefront, lane l taking pieces l, l + 64, ...: a list of many pieces
-    // would keep one lane busy long after the others
+    // every piece of a large list points at its head; the map is written by
+    // the whole wavefront, lane l taking pieces l, l + 64, ..., so a list of
+    // many pieces does not keep one lane busy long after the others
     for (u64 big = ballot(nlarge != 0); big; big &= big - 1) {
         const u32 j = (u32)__builtin_ctzll(big);
         const u32 nj = read_lane(nlarge, j);
         const u64 sj = ((u64)read_lane((u32)(lstart >> 32), j) << 32) | read_lane((u32)lstart, j);
-        BatchItem ij;
-        ij.bb = (int64_t)(((u64)read_lane((u32)((u64)it.bb >> 32), j) << 32) | read_lane((u32)it.bb, j));
-        ij.be = (int64_t)(((u64)read_lane((u32)((u64)it.be >> 32), j) << 32) | read_lane((u32)it.be, j));
-        ij.ob = (int64_t)(((u64)read_lane((u32)((u64)it.ob >> 32), j) << 32) | read_lane((u32)it.ob, j));
-        ij.n = (int64_t)(((u64)read_lane((u32)((u64)it.n >> 32), j) << 32) | read_lane((u32)it.n, j));
-        ij.li = read_lane(it.li, j);
-        ij.prev = read_lane(it.prev, j);
-        ij.pad = 0;
-        for (u32 k = ln; k < nj; k += kWave) {
-            ij.ti = k;
-            if (sj + k < a.max_items) a.items[sj + k] = ij;
-        }
+        for (u32 k = ln; k < nj; k += kWave)
+            if (sj + k < a.max_large) a.pmap[sj + k] = (u32)sj;
     }
 }
 
 // Large lists of a batch: each list is cut into pieces of SEGS KiB, one per
-// wavefront (the prep's work items, items[k] = (list, piece), a list's
-// pieces consecutive).  Two passes with no look-back and no queue, as for a
-// single stream: k_list_agg stores each piece's terminator count and byte
-// sum in slot k, the block scans turn the slots into exclusive prefixes over
-// all items, and k_list_known decodes each piece alone with its prefix
-// within its list, the slot's prefix minus that of the list's first piece.
-// A run of five continuation bytes raises its list's status to malformed
-// (atomic max); the wavefront holding a list's last byte raises it to the
-// list's truncation or count status the same way, so the list ends with the
-// larger code.  Both kernels hand out items with a grid stride over
-// wavefronts.
+// wavefront.  The prep numbers the pieces of all large lists [0, L), a
+// list's pieces consecutive, stores each large list's item once, at the
+// index of its first piece (its head), and maps every piece to its head
+// (pmap[k] = head, 4 bytes a piece, so a list of many pieces costs little to
+// lay out); piece k is then the list's piece k - head.  Two passes with no
+// look-back and no queue, as for a single stream: k_list_agg stores each
+// piece's terminator count and byte sum in slot k, the block scans turn the
+// slots into exclusive prefixes over all pieces, and k_list_known decodes
+// each piece alone with its prefix within its list, the slot's prefix minus
+// that of the list's head.  A run of five continuation bytes raises its
+// list's status to malformed (atomic max); the wavefront holding a list's
+// last byte raises it to the list's truncation or count status the same
+// way, so the list ends with the larger code.  Both kernels launch one
+// wavefront per piece the table can hold (those past L return at once) and
+// keep a grid stride for grids that are capped.
 __device__ __forceinline__ void list_geometry(const ListArgs &a, const BatchItem &d, const u8 *&base,
                                               u64 &vstart, u64 &vend) {
     const u8 *p0 = a.bytes + d.bb;
@@ -3288,20 +3282,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
     const u64 ub = (u64)SEGS * kSegBytes;
     u64 L = aload(&a.totals[0]);
     L = L < a.max_large ? L : a.max_large;
-    // wavefront w of the grid takes items w, w + W, ...; each iteration
-    // loads the next iteration's item first
+    // the wavefront's index made uniform, so the table loads are scalar
     const u64 W = (u64)gridDim.x * (blockDim.x >> 6);
-    const u64 k0 = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    BatchItem cur{};
-    if (k0 < L) cur = a.items[k0];
+    const u64 k0 = (u64)blockIdx.x * (blockDim.x >> 6) + (u32)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (u64 k = k0; k < L; k += W) {
-        BatchItem nxt{};
-        if (k + W < L) nxt = a.items[k + W];
-        const BatchItem &d = cur;
+        const u32 head = a.pmap[k];
+        const BatchItem d = a.items[head];
         const u8 *base;
         u64 vstart, vend;
         list_geometry(a, d, base, vstart, vend);
-        const u64 wv = (u64)d.ti * ub;   // < vend: the prep makes no empty piece
+        const u64 wv = (k - head) * ub;   // < vend: the prep makes no empty piece
         u32 cont, sum;
         bool mal;
         if (wv >= vstart + 4 && wv + ub <= vend)
@@ -3314,7 +3304,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
             a.desc[k].c = hi - lo - cont;
             a.desc[k].s = sum;
         }
-        cur = nxt;
     }
 }
 
@@ -3322,25 +3311,20 @@ template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4 : 8))) void k_list_known(ListArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     __shared__ WgShared sh;   // not used by wavefronts that decode alone
-    const u32 wib = threadIdx.x >> 6, ln = lane_id();
+    const u32 wib = (u32)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = lane_id();
     u32 *stage = lds + wib * kStageWords;
     const u64 ub = (u64)SEGS * kSegBytes;
     u64 L = aload(&a.totals[0]);
     L = L < a.max_large ? L : a.max_large;
     const u64 W = (u64)gridDim.x * (blockDim.x >> 6);
     const u64 k0 = (u64)blockIdx.x * (blockDim.x >> 6) + wib;
-    BatchItem cur{};
-    if (k0 < L) cur = a.items[k0];
     for (u64 k = k0; k < L; k += W) {
-        BatchItem nxt{};
-        if (k + W < L) nxt = a.items[k + W];
-        const BatchItem d = cur;
-        cur = nxt;
-        const u64 ti = d.ti;
+        const u32 head = a.pmap[k];
+        const BatchItem d = a.items[head];
         TileIn t{};
         list_geometry(a, d, t.base, t.vstart, t.vend);
-        const u64 wv = ti * ub;
-        const Desc sq = a.desc[k], s0 = a.desc[k - ti];
+        const u64 wv = (k - head) * ub;
+        const Desc sq = a.desc[k], s0 = a.desc[head];
         t.tv = wv;
         t.out = a.out + d.ob;
         t.n = (u64)d.n;
@@ -3523,24 +3507,13 @@ __device__ __forceinline__ void run_packed(const ListArgs &a, const BatchItem &i
     wave_lds_sync();
 }
 
-// Wavefront-uniform fetch-and-increment of an LDS counter: lane 0 performs
-// the atomic and leaves the old value in the wavefront's LDS slot, which all
-// lanes then read (through memory, so the result is uniform by construction).
-__device__ __forceinline__ u32 pick_next(u32 *counter, u32 *slot) {
-    if (lane_id() == 0) *slot = atomicAdd(counter, 1u);
-    wave_lds_sync();
-    return first_lane(*slot);
-}
-
-// Persistent decode of the small lists of a batch: workgroups take chunks of
-// small lists from a queue (each wavefront pulls lists of the chunk through
-// an LDS counter).  The queue word is reset by its last taker; the queue
-// costs one device-wide atomic per chunk, not per list.
+// Persistent decode of the small lists of a batch: each wavefront of the
+// grid takes a fixed share of them (below).
 template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
     extern __shared__ __align__(16) u32 lds[];
     const u32 tid = threadIdx.x;
-    const u32 wib = tid >> 6;
+    const u32 wib = (u32)__builtin_amdgcn_readfirstlane(tid >> 6);
     u32 *stage = lds + wib * kStageWords;
     const u64 S = aload(&a.totals[1]);
     const u64 fail_code = aload(&a.totals[2]);   // 1: the work table was too small; 2: prep stalled
@@ -3559,7 +3532,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
         const u64 hi = (wid + 1) * S / W;
         for (u64 p = lo; p < hi;) {
             BatchItem it{};
-            u32 need = 65;   // lanes of the list at lane t (65: none, never fits)
+            u32 need = 65;
             if (p + ln < hi) {
                 it = a.items[a.max_items - 1 - (p + ln)];
                 const u64 vs = (u64)(uintptr_t)(a.bytes + it.bb) & 15u;
@@ -3972,8 +3945,12 @@ hipError_t launch_large_lists_t(const ListArgs &a, int wpb, hipStream_t s) {
     hipError_t e = resident_grid(k_list_agg<D, SEGS>, wpb, 0, occ_agg, ga);
     if (e != hipSuccess) return e;
     if ((e = resident_grid(k_list_known<D, SEGS>, wpb, lds, occ_known, gk)) != hipSuccess) return e;
-    ga = (u64)ga < a.max_large ? ga : (u32)a.max_large;
-    gk = (u64)gk < a.max_large ? gk : (u32)a.max_large;
+    // one wavefront per piece the table can hold (L is known only on the
+    // device), at least the resident grid, at most 2^20 workgroups
+    const u64 want = (a.max_large + wpb - 1) / wpb;
+    const u32 g = (u32)(want < (1u << 20) ? want : (1u << 20));
+    ga = g > ga ? g : ga;
+    gk = g > gk ? g : gk;
     k_list_agg<D, SEGS><<<ga, wpb * kWave, 0, s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -158,7 +158,7 @@ constexpr int kIsectSegs = 2, kIsectWaves = 8;   // the intersection's tiling
 // One list of a batched launch, resolved on the device from either CSR
 // offsets or gather rows.
 // A work item of the batched decode: the list's byte and output ranges,
-// its start value, its index and the item's tile within it.
+// its start value and its index (ti is unused, 0).
 struct BatchItem {
     int64_t bb, be, ob, n;
     uint32_t li, ti, prev, pad;
@@ -183,7 +183,9 @@ struct ListArgs {
     uint64_t *hdr;             // header: epoch (word 0), prep ticket (3), stall word (4)
     Desc *desc;                // a slot per large-list piece, then the scan's block totals
     Desc *prep_desc;           // one per prep block
-    BatchItem *items;          // work table: one self-contained item per large-list tile or small list
+    BatchItem *items;          // work table: a large list's item at its first piece's index,
+                               // small lists from the back
+    uint32_t *pmap;            // per large-list piece: the index of its list's first piece
     uint64_t *totals;          // [0] large-list pieces L, [1] small lists S, [2] 1 if the
                                // table overflowed, 2 if the prep stalled (written by the
                                // prep kernel); [4] a spare status word
@@ -268,7 +270,7 @@ hipError_t launch_fill_i64(int64_t *p, uint64_t n, int64_t value, hipStream_t s)
 // `a` from the current tuning and lays out the workspace; batch_bind points
 // `a` into a workspace of plan.bytes (zero-filled before its first use).
 struct BatchPlan {
-    size_t bytes, desc_off, prep_off, items_off;
+    size_t bytes, desc_off, prep_off, items_off, pmap_off;
     int segs, wpb, grid;
 };
 vbyte_status batch_plan(ListArgs &a, size_t list_bytes, BatchPlan *plan);
