@@ -297,12 +297,13 @@ vbyte_status vbyte_count(const uint8_t *bytes, size_t nbytes, uint64_t *d_count,
  *   d_list_status: device int32[nlists], required; receives each list's
  *     status under the strict semantics above.
  * A small prep kernel classifies the lists and builds a work table.  Lists
- * larger than small_list_bytes (vbyte_set_tuning) are cut into tiles and
- * decoded in two passes with no look-back, as a single stream: each
- * wavefront's count and byte sum, one scan over all tiles, then each
- * wavefront decodes with its prefix within its list.  A last launch decodes
- * the smaller lists, several to a wavefront (each on its own lanes) when
- * they fit in 64 x 16 bytes, else one wavefront each.  Asynchronous on
+ * larger than small_list_bytes (vbyte_set_tuning) are cut into pieces of
+ * segs_per_wave KiB, one wavefront each, and decoded in two passes with no
+ * look-back, as a single stream: each piece's count and byte sum, one scan
+ * over all pieces, then each piece decodes with its prefix within its list
+ * (a list of one piece skips the first pass).  A last launch decodes the
+ * smaller lists, several to a wavefront (each on its own lanes) when they
+ * fit in 64 x 16 bytes, else one wavefront each.  Asynchronous on
  * `stream`. */
 vbyte_status vbyte_decode_batch(const uint8_t *bytes, size_t nbytes, const int64_t *byte_off,
                                 uint32_t *out, size_t nout, const int64_t *out_off, size_t nlists,

@@ -816,7 +816,7 @@ __device__ __forceinline__ TileOut run_tile_regs(const TileIn &t, const TileRegs
         const Straddle st = straddle(hb, read_lane(w[0][0], 0), read_lane(w[0][1], 0));
         exc = t.known_c + st.code;
         exs = t.known_s + st.rest;
-        res = TileOut{exc + ctot, false, exs + stot};
+        res = TileOut{exc + ctot, wmal, exs + stot};
     } else {
         if (ln == 0) {
             sh.wcnt[wib] = ctot;
@@ -3262,12 +3262,13 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(ListArgs a, u32 nblocks, u6
 // piece's terminator count and byte sum in slot k, the block scans turn the
 // slots into exclusive prefixes over all pieces, and k_list_known decodes
 // each piece alone with its prefix within its list, the slot's prefix minus
-// that of the list's head.  A run of five continuation bytes raises its
-// list's status to malformed (atomic max); the wavefront holding a list's
-// last byte raises it to the list's truncation or count status the same
-// way, so the list ends with the larger code.  Both kernels launch one
-// wavefront per piece the table can hold (those past L return at once) and
-// keep a grid stride for grids that are capped.
+// that of the list's head (a list of one piece needs no slot: k_list_agg
+// skips it and k_list_known finds its malformed runs).  A run of five
+// continuation bytes raises its list's status to malformed (atomic max); the
+// wavefront holding a list's last byte raises it to the list's truncation
+// or count status the same way, so the list ends with the larger code.  Both
+// kernels launch one wavefront per piece the table can hold (those past L
+// return at once) and keep a grid stride for grids that are capped.
 __device__ __forceinline__ void list_geometry(const ListArgs &a, const BatchItem &d, const u8 *&base,
                                               u64 &vstart, u64 &vend) {
     const u8 *p0 = a.bytes + d.bb;
@@ -3292,6 +3293,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
         u64 vstart, vend;
         list_geometry(a, d, base, vstart, vend);
         const u64 wv = (k - head) * ub;   // < vend: the prep makes no empty piece
+        if (vend <= ub) {
+            // a list of one piece: its prefix is the list's start, so the
+            // decode pass needs no slot (it also finds a malformed run)
+            if (ln == 0) {
+                a.desc[k].c = 0;
+                a.desc[k].s = 0;
+            }
+            continue;
+        }
         u32 cont, sum;
         bool mal;
         if (wv >= vstart + 4 && wv + ub <= vend)
@@ -3336,6 +3346,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(D ? 4
             r = run_tile<D, kKnownW, SEGS, false>(t, stage, sh, 0, 1);
         else
             r = run_tile<D, kKnownW, SEGS, true>(t, stage, sh, 0, 1);
+        if (t.vend <= ub && r.mal && ln == 0) atomicMax(&a.list_status[d.li], (int32_t)VBYTE_EMALFORMED);
         if (wv + ub >= t.vend && ln == 0)
             atomicMax(&a.list_status[d.li], final_status(false, t.base[t.vend - 1], r.total, t.n));
     }

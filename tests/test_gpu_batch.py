@@ -124,6 +124,29 @@ def test_bad_lists_fail_alone():
     assert st[3] == vbyte.ETRUNC and st[5] == vbyte.ECOUNT
 
 
+@pytest.mark.parametrize("segs", [1, 4])
+def test_bad_one_piece_lists(segs):
+    """Lists that fit one wavefront's piece go to the piece decode with no
+    aggregation pass, which then alone finds their malformed runs (start,
+    middle and end of a list, runs that cross list boundaries) and their
+    truncation and count statuses."""
+    vbyte.set_tuning(segs, 8, 1)   # every non-empty list takes the piece path
+    rng = np.random.default_rng(60 + segs)
+    lens = list(rng.integers(1, 400 * segs, 300))
+    lists, b, byte_off, out_off = make_lists(rng, lens, (1, 2, 3))
+    bad = b.copy()
+    for i in range(0, len(lens), 7):
+        a0, e0 = int(byte_off[i]), int(byte_off[i + 1])
+        at = [a0, (a0 + e0) // 2, max(a0, e0 - 5), e0 - 2][i % 4]
+        bad[at:at + 5] = 0x80 | (i & 0x7F)
+    y, st = compare(bad, byte_off, out_off, boff=7)
+    assert (st == vbyte.EMALFORMED).sum() > 0 and (st == vbyte.OK).sum() > 0
+    oo = out_off.copy()
+    oo[1:] += np.arange(1, len(lens) + 1) % 3 - 1   # one more, same, one fewer, ...
+    oo[1:] = np.maximum.accumulate(np.maximum(oo[1:], 0))
+    compare(b, byte_off, oo, delta=True)
+
+
 def test_invalid_offsets_are_rejected_per_list():
     rng = np.random.default_rng(7)
     lens = [100, 200, 300, 400]
