@@ -3277,6 +3277,8 @@ __device__ __forceinline__ void list_geometry(const ListArgs &a, const BatchItem
     vend = vstart + (u64)(d.be - d.bb);
 }
 
+constexpr u64 kListGridCap = 1u << 16;   // workgroups of the piece kernels
+
 template <int D, int SEGS>
 __global__ __launch_bounds__(kMaxBlock) void k_list_agg(ListArgs a) {
     const u32 ln = lane_id();
@@ -3957,9 +3959,10 @@ hipError_t launch_large_lists_t(const ListArgs &a, int wpb, hipStream_t s) {
     if (e != hipSuccess) return e;
     if ((e = resident_grid(k_list_known<D, SEGS>, wpb, lds, occ_known, gk)) != hipSuccess) return e;
     // one wavefront per piece the table can hold (L is known only on the
-    // device), at least the resident grid, at most 2^20 workgroups
+    // device), at least the resident grid, at most kListGridCap workgroups
+    // (the kernels' grid stride takes the rest)
     const u64 want = (a.max_large + wpb - 1) / wpb;
-    const u32 g = (u32)(want < (1u << 20) ? want : (1u << 20));
+    const u32 g = (u32)(want < kListGridCap ? want : kListGridCap);
     ga = g > ga ? g : ga;
     gk = g > gk ? g : gk;
     k_list_agg<D, SEGS><<<ga, wpb * kWave, 0, s>>>(a);

@@ -147,6 +147,22 @@ def test_bad_one_piece_lists(segs):
     compare(b, byte_off, oo, delta=True)
 
 
+def test_more_pieces_than_the_grid_cap():
+    """More large-list pieces than the piece kernels' capped grid holds
+    (2^16 workgroups of one wavefront with 1 KiB pieces): the grid stride
+    takes the rest."""
+    vbyte.set_tuning(1, 1, 1)
+    rng = np.random.default_rng(61)
+    lens = rng.integers(700, 1400, 48000)
+    _, b, byte_off, out_off = make_lists(rng, lens, (1, 2))
+    pieces = int(((byte_off[1:] - byte_off[:-1] + 1023) // 1024).sum())   # at least
+    assert pieces > (1 << 16)
+    y, st = compare(b, byte_off, out_off, boff=3)
+    assert (st == vbyte.OK).all()
+    compare(b, byte_off, out_off, prevs=rng.integers(0, 1 << 32, lens.size, dtype=np.uint64).astype(np.uint32),
+            delta=True, boff=3)
+
+
 def test_invalid_offsets_are_rejected_per_list():
     rng = np.random.default_rng(7)
     lens = [100, 200, 300, 400]
