@@ -3581,16 +3581,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
 // before it); chunk c is aligned elements [256 c, 256 c + 256): one 128-bit
 // load per lane of a wavefront.  k_enc_len stores each chunk's byte count;
 // k_enc_bsum / k_enc_bscan turn the counts into exclusive byte offsets (the
-// last block writes the total); k_enc_write loads the chunk again, gives
-// every value its byte offset (lane scan plus the chunk offset) and builds
-// the chunk's bytes in LDS by OR-ing each code, shifted to its byte offset,
-// into the one or two dwords it touches (codes never overlap, so the ORs
-// assemble the bytes exactly); the dwords then go out as 16-byte stores,
-// with byte stores at the chunk's two edges.  k_enc_bounds gives every CSR
+// last block writes the total); k_enc_write loads the chunk again and gives
+// every value its byte offset (lane scan plus the chunk offset).  A chunk
+// whose codes are all one byte, or all one or two bytes, is stored straight
+// from registers as dwords (a lane's codes then span at least four bytes, so
+// a dword holds bytes of at most two lanes); any other chunk is built in LDS
+// by OR-ing each code, shifted to its byte offset, into the one or two dwords
+// it touches (codes never overlap, so the ORs assemble the bytes exactly) and
+// stored from there.  Dwords shared with the neighbouring chunks go out byte
+// by byte in every form.  k_enc_bounds gives every CSR
 // list boundary its byte offset: the chunk offset plus the lengths of the
 // values before it in its chunk.
 constexpr int kEncPerWave = 8;        // chunks per wavefront in k_enc_len
-constexpr int kEncWritePerWave = 4;   // chunks per wavefront in k_enc_write
+constexpr int kEncWritePerWave = 1;   // chunks per wavefront in k_enc_write
 
 __device__ __forceinline__ u32 code_len(u32 x) {
     return 1u + (x >= (1u << 7)) + (x >= (1u << 14)) + (x >= (1u << 21)) + (x >= (1u << 28));
@@ -3729,6 +3732,76 @@ __global__ __launch_bounds__(kScanBlock) void k_enc_bscan(EncArgs a) {
 __device__ __forceinline__ void enc_write_chunk(const EncArgs &a, u32 *st, const u32 (&v)[4],
                                                 u32 valid, u64 base) {
     const u32 ln = lane_id();
+    if (ballot(valid != 0xFu || (v[0] | v[1] | v[2] | v[3]) >= 128u) == 0) {
+        // Every code of the chunk is one byte: its 256 bytes are the values
+        // in order, lane l's four at base + 4 l.  Dword j of the dword-aligned
+        // window holds lane j's bytes shifted up by the window's offset m
+        // and lane j - 1's top m bytes; the first and last dwords also hold
+        // bytes of the neighbouring chunks, so their own bytes go out one by
+        // one.  No LDS.
+        const u32 m = (u32)(((uintptr_t)a.bytes + base) & 3u);
+        const u32 p = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+        const u32 below = from_lane_below(p, 0u);
+        const u32 dw = m ? (p << (8u * m)) | (below >> (32u - 8u * m)) : p;
+        const u64 g0 = base - m + 4u * ln;   // byte index of the lane's dword
+        if ((ln > 0 || m == 0) && g0 + 4 <= a.capacity) {
+            *(u32 *)(a.bytes + g0) = dw;
+        } else {
+            for (u32 t = ln == 0 ? m : 0u; t < 4; ++t)
+                if (g0 + t < a.capacity) a.bytes[g0 + t] = (u8)(dw >> (8 * t));
+        }
+        if (ln == 63 && m) {   // lane 63's top m bytes start the dword after
+            const u32 top = p >> (32u - 8u * m);
+            for (u32 t = 0; t < m; ++t)
+                if (g0 + 4 + t < a.capacity) a.bytes[g0 + 4 + t] = (u8)(top >> (8 * t));
+        }
+        return;
+    }
+    if (ballot(valid != 0xFu || (v[0] | v[1] | v[2] | v[3]) >= 16384u) == 0) {
+        // Every code is one or two bytes, so a lane's codes take 4..8 bytes
+        // and a dword of the window holds bytes of at most two lanes.  Dword
+        // j is written by the lane that holds its first byte of the chunk:
+        // its own bytes there, ORed with the first dword of the lane above
+        // when that lane starts inside it.  The window's first and last
+        // dwords, shared with the neighbouring chunks, go out byte by byte.
+        const u32 m = (u32)(((uintptr_t)a.bytes + base) & 3u);
+        u64 pk = 0;
+        u32 nb = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u32 x = v[k];
+            const u32 two = x >= 128u ? 1u : 0u;
+            const u32 c = two ? ((x & 0x7Fu) | 0x80u | ((x >> 7) << 8)) : x;
+            pk |= (u64)c << (8 * nb);
+            nb += 1 + two;
+        }
+        const u32 incl = wave_scan(nb);
+        const u32 endb = m + read_lane(incl, 63);   // one past the chunk's last window byte
+        const u32 off = m + incl - nb;              // the lane's first window byte
+        const u32 sh = off & 3u, w = off >> 2, e = (off + nb - 1) >> 2;
+        const u64 lo = pk << (8 * sh);
+        const u32 q[3] = {(u32)lo, (u32)(lo >> 32), sh ? (u32)(pk >> (64 - 8 * sh)) : 0u};
+        const u32 up = from_lane_above((u32)lo, 0u);   // the lane above's first dword
+        const u32 nxt = ((off + nb) & 3u) && ln < 63 ? up : 0u;
+        const u32 first = ln == 0 ? 0u : (off + 3) >> 2;
+        const u64 gw = base - m;   // byte index of window byte 0
+#pragma unroll
+        for (u32 j = 0; j < 3; ++j) {
+            const u32 idx = w + j;
+            if (idx < first || idx > e) continue;
+            const u32 val = q[j] | (idx == e ? nxt : 0u);
+            const u64 g = gw + 4ull * idx;
+            const u32 b0 = 4 * idx < m ? m - 4 * idx : 0u;
+            const u32 b1 = 4 * idx + 4 > endb ? endb - 4 * idx : 4u;
+            if (b0 == 0 && b1 == 4 && g + 4 <= a.capacity) {
+                *(u32 *)(a.bytes + g) = val;
+            } else {
+                for (u32 t = b0; t < b1; ++t)
+                    if (g + t < a.capacity) a.bytes[g + t] = (u8)(val >> (8 * t));
+            }
+        }
+        return;
+    }
     u32 len[4], lsum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {

@@ -64,6 +64,35 @@ def test_capacity_below_size():
         assert (h[cap:] == 0xAB).all(), "write past capacity"
 
 
+@pytest.mark.parametrize("kind", ["one_byte", "one_or_two"])
+def test_short_code_chunks_at_every_output_offset(kind):
+    """Chunks whose codes are all one byte, or all one or two bytes, are
+    stored with no LDS staging: every misalignment of the output, a
+    two-byte code in an otherwise one-byte chunk, a chunk with a five-byte
+    code, and capacities that cut a chunk (nothing written past them)."""
+    rng = np.random.default_rng(9 if kind == "one_byte" else 10)
+    n = 256 * 40 + 77
+    if kind == "one_byte":
+        x = rng.integers(0, 128, n).astype(np.uint32)
+        x[256 * 7 + 100] = 200
+        x[256 * 20:256 * 21] = 5000
+    else:
+        x = np.where(rng.random(n) < 0.5, rng.integers(0, 128, n), rng.integers(128, 16384, n)).astype(np.uint32)
+        x[256 * 9 + 31] = 1 << 30
+    ref = oracle.encode(x)
+    for shift in range(4):
+        for cap in (ref.size, ref.size - 1, 256 * 3 + 1, 256 * 11 + 2, 3):
+            buf = torch.full((ref.size + 64,), 0xAB, dtype=torch.uint8, device="cuda")
+            nbytes = torch.empty(1, dtype=torch.int64, device="cuda")
+            vbyte.encode(on_gpu(x, shift), out=buf[shift:shift + cap], nbytes=nbytes, trim=False)
+            torch.cuda.synchronize()
+            h = buf.cpu().numpy()
+            assert int(nbytes.item()) == ref.size
+            assert (h[:shift] == 0xAB).all()
+            assert np.array_equal(h[shift:shift + cap], ref[:cap]), (shift, cap)
+            assert (h[shift + cap:] == 0xAB).all(), "write past capacity"
+
+
 @pytest.mark.parametrize("mean", [8, 300])
 def test_full_gap_streams(mean):
     g = workloads.geometric_gaps(mean=mean)
