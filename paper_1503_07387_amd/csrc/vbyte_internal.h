@@ -157,8 +157,8 @@ constexpr int kIsectSegs = 2, kIsectWaves = 8;   // the intersection's tiling
 
 // One list of a batched launch, resolved on the device from either CSR
 // offsets or gather rows.
-// A work item of the batched decode: the list's byte and output ranges,
-// its start value and its index (ti is unused, 0).
+// A list item of the batched decode: the list's byte and output ranges, its
+// start value and its index (ti is unused, 0; the size stays 48 bytes).
 struct BatchItem {
     int64_t bb, be, ob, n;
     uint32_t li, ti, prev, pad;
@@ -177,7 +177,7 @@ struct ListArgs {
     int32_t *list_status;
     uint64_t nlists;
     int delta;
-    uint64_t small_bytes;      // lists of at most this many bytes take one wavefront
+    uint64_t small_bytes;      // lists of at most this many bytes go to the small-list kernel
     uint64_t max_items;        // capacity of the work table
     uint64_t max_large;        // capacity for large-list pieces (items [0, L), L <= max_large)
     uint64_t *hdr;             // header: epoch (word 0), prep ticket (3), stall word (4)
@@ -189,7 +189,7 @@ struct ListArgs {
     uint64_t *totals;          // [0] large-list pieces L, [1] small lists S, [2] 1 if the
                                // table overflowed, 2 if the prep stalled (written by the
                                // prep kernel); [4] a spare status word
-    uint32_t wpb;              // wavefronts per workgroup (small lists per work item)
+    uint32_t wpb;              // wavefronts per workgroup of the list kernels
     uint32_t spin_limit = kDefaultSpinLimit;   // look-back round trips before giving up
 };
 
