@@ -3545,7 +3545,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
         const u64 hi = (wid + 1) * S / W;
         for (u64 p = lo; p < hi;) {
             BatchItem it{};
-            u32 need = 65;
+            u32 need = 65;   // lanes of the list at lane t (65: none, never fits)
             if (p + ln < hi) {
                 it = a.items[a.max_items - 1 - (p + ln)];
                 const u64 vs = (u64)(uintptr_t)(a.bytes + it.bb) & 15u;
