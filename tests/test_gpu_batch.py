@@ -147,6 +147,36 @@ def test_bad_one_piece_lists(segs):
     compare(b, byte_off, oo, delta=True)
 
 
+@pytest.mark.parametrize("segs", [1, 2, 4])
+def test_lists_around_one_piece(segs):
+    """Lists whose bytes (with their start misalignment) end just below, at
+    and just above one piece of segs KiB and of two pieces: the one-piece
+    lists skip the aggregation pass, the others do not.  One-byte codes, so
+    n equals the byte count."""
+    vbyte.set_tuning(segs, 4, 1)
+    ub = segs * 1024
+    rng = np.random.default_rng(70 + segs)
+    sizes = [ub + d for d in range(-24, 25)] + [2 * ub + d for d in range(-20, 21, 4)]
+    lens = list(rng.permutation(np.array(sizes * 2)))
+    lists, b, byte_off, out_off = make_lists(rng, lens, (1,))
+    prevs = rng.integers(0, 1 << 32, len(lens), dtype=np.uint64).astype(np.uint32)
+    for boff in (0, 9):
+        y, st = compare(b, byte_off, out_off, boff=boff)
+        assert (st == vbyte.OK).all()
+        compare(b, byte_off, out_off, prevs=prevs, delta=True, boff=boff)
+    # differences minus one: strictly increasing lists
+    inc = [np.cumsum(rng.integers(1, 100, int(k)), dtype=np.uint64).astype(np.uint32) for k in lens]
+    enc = [oracle.encode_delta_m1(x, 0) for x in inc]
+    bo = np.zeros(len(lens) + 1, np.int64)
+    bo[1:] = np.cumsum([e.size for e in enc])
+    data = torch.from_numpy(np.concatenate(enc)).to(dev())
+    out, st = vbyte.decode_batch(data, torch.from_numpy(bo).to(dev()), torch.from_numpy(out_off).to(dev()),
+                                 delta=True, minus_one=True)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == vbyte.OK).all()
+    assert np.array_equal(u32(out), np.concatenate(inc))
+
+
 def test_more_pieces_than_the_grid_cap():
     """More large-list pieces than the piece kernels' capped grid holds
     (2^16 workgroups of one wavefront with 1 KiB pieces): the grid stride
