@@ -65,11 +65,12 @@ vbyte_status hip_fail(hipError_t e, const char *what) {
 }
 
 // Workspace layout (bytes):
-//   [0, 32)     epoch word, the two batched queue words, the tile ticket
+//   [0, 40)     epoch word (0), ticket word (3), stall word (4)
 //   [64, 68)    status slot used by the synchronous calls
-//   [128, 152)  batch totals (3 x uint64)
+//   [128, 168)  batch totals (5 x uint64)
 //   [192, 208)  resumable piece: offset of the code of rank k, code count
-//   [256, ...)  descriptors, then batch tables
+//   [256, 512)  completion counters of the one-launch decode
+//   [512, ...)  descriptors, then batch tables
 constexpr size_t kStatusOff = 64;
 constexpr size_t kTotalsOff = 128;
 constexpr size_t kPieceOff = 192;   // resumable pieces: rank-n offset and code count
