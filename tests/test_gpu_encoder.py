@@ -93,6 +93,18 @@ def test_short_code_chunks_at_every_output_offset(kind):
             assert (h[shift + cap:] == 0xAB).all(), "write past capacity"
 
 
+@pytest.mark.parametrize("gap_hi", [100, 10000])
+def test_short_differences_minus_one(gap_hi):
+    """Differences minus one of increasing values whose gaps code in one
+    byte (gaps < 129) or in one or two bytes: the chunks take the register
+    paths, at every alignment of the values."""
+    rng = np.random.default_rng(gap_hi)
+    x = np.cumsum(rng.integers(1, gap_hi, 256 * 30 + 41), dtype=np.uint64).astype(np.uint32)
+    for e0 in (0, 1, 2, 3):
+        got = vbyte.encode(on_gpu(x, e0), minus_one=True, prev=int(x[0]) - 1).cpu().numpy()
+        assert np.array_equal(got, oracle.encode_delta_m1(x, int(x[0]) - 1)), e0
+
+
 @pytest.mark.parametrize("mean", [8, 300])
 def test_full_gap_streams(mean):
     g = workloads.geometric_gaps(mean=mean)
