@@ -814,16 +814,16 @@ static vbyte_status encode_common(const uint32_t *values, size_t n, uint32_t pre
     a.capacity = capacity;
     a.d_nbytes = d_nbytes;
     a.nchunks = (a.e0 + n + kEncChunk - 1) / kEncChunk;
-    const uint64_t nsb = (a.nchunks + 8 * 1024 - 1) / (8 * 1024);
-    // workspace: chunk counts (4 B), chunk offsets (8 B), scan block totals (8 B)
+    const uint64_t ngs = (a.nchunks + kEncLenChunks - 1) / kEncLenChunks;
+    // workspace: chunk counts (4 B), chunk offsets (8 B), length-workgroup totals (4 B)
     const size_t off_pre = kHeaderBytes + ((a.nchunks * 4 + 15) & ~(uint64_t)15);
-    const size_t off_bsum = off_pre + a.nchunks * 8;
+    const size_t off_gsum = off_pre + a.nchunks * 8;
     Workspace *w = nullptr;
-    vbyte_status st = get_ws(s, off_bsum + nsb * 8, 0, &w);
+    vbyte_status st = get_ws(s, off_gsum + ngs * 4, 0, &w);
     if (st != VBYTE_OK) return st;
     a.csum = (uint32_t *)(ws_base(w) + kHeaderBytes);
     a.cpre = (uint64_t *)(ws_base(w) + off_pre);
-    a.bsum = (uint64_t *)(ws_base(w) + off_bsum);
+    a.gsum = (uint32_t *)(ws_base(w) + off_gsum);
     hipError_t e = launch_encode(a, s);
     if (e != hipSuccess) return hip_fail(e, "encode launch");
     if (nbounds) {

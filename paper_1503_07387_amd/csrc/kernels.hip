@@ -3579,9 +3579,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_batch(ListArgs a) {
 // Two passes over the values with no look-back.  The values are addressed
 // from the 16-byte-aligned element at or below values[0] (e0 elements
 // before it); chunk c is aligned elements [256 c, 256 c + 256): one 128-bit
-// load per lane of a wavefront.  k_enc_len stores each chunk's byte count;
-// k_enc_bsum / k_enc_bscan turn the counts into exclusive byte offsets (the
-// last block writes the total); k_enc_write loads the chunk again and gives
+// load per lane of a wavefront.  k_enc_len stores each chunk's byte count
+// and each of its workgroups' totals; k_enc_bscan turns the counts into
+// exclusive byte offsets (a scan workgroup's carry is the sum of the length
+// workgroups' totals before it; the last block writes the total);
+// k_enc_write loads the chunk again and gives
 // every value its byte offset (lane scan plus the chunk offset).  A chunk
 // whose codes are all one byte, or all one or two bytes, is stored straight
 // from registers as dwords (a lane's codes then span at least four bytes, so
@@ -3656,15 +3658,22 @@ __device__ __forceinline__ u32 enc_load(const EncArgs &a, u64 c, u32 (&v)[4]) {
     return valid;
 }
 
-// A wavefront takes kEncPerWave consecutive chunks, all loads issued first.
-__global__ __launch_bounds__(256) void k_enc_len(EncArgs a) {
-    const u32 ln = lane_id();
-    const u64 c0 = ((u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * kEncPerWave;
+// A wavefront takes kEncPerWave consecutive chunks, all loads issued first;
+// a workgroup (kEncLenWaves wavefronts, kEncLenChunks chunks) also stores
+// its chunks' total for the scan.
+constexpr u32 kEncLenWaves = kEncLenChunks / kEncPerWave;
+static_assert(kEncLenWaves * kEncPerWave == kEncLenChunks, "a length workgroup's chunks");
+
+__global__ __launch_bounds__(kEncLenWaves * kWave) void k_enc_len(EncArgs a) {
+    __shared__ u32 wt[kEncLenWaves];
+    const u32 ln = lane_id(), wib = threadIdx.x >> 6;
+    const u64 c0 = ((u64)blockIdx.x * kEncLenWaves + wib) * kEncPerWave;
     u32 v[kEncPerWave][4], valid[kEncPerWave];
 #pragma unroll
     for (int q = 0; q < kEncPerWave; ++q)
         valid[q] = c0 + q < a.nchunks ? enc_load(a, c0 + q, v[q]) : 0u;
     u32 mine = 0;   // lane q ends up with chunk q's count
+    u32 tot = 0;
 #pragma unroll
     for (int q = 0; q < kEncPerWave; ++q) {
         u32 len = 0;
@@ -3672,38 +3681,36 @@ __global__ __launch_bounds__(256) void k_enc_len(EncArgs a) {
         for (int k = 0; k < 4; ++k) len += (valid[q] >> k) & 1u ? code_len(v[q][k]) : 0u;
         len = wave_sum(len);
         mine = ln == (u32)q ? len : mine;
+        tot += len;
     }
     if (ln < (u32)kEncPerWave && c0 + ln < a.nchunks) a.csum[c0 + ln] = mine;
+    if (ln == 0) wt[wib] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 t = 0;   // at most kEncLenChunks x 1280
+        for (u32 k = 0; k < kEncLenWaves; ++k) t += wt[k];
+        a.gsum[blockIdx.x] = t;
+    }
 }
 
 constexpr u64 kEncScanSpan = 8 * kScanBlock;   // chunk counts per scan workgroup (8 per thread)
+static_assert(kEncScanSpan % kEncLenChunks == 0, "a scan block holds whole length workgroups");
 
-__global__ __launch_bounds__(kScanBlock) void k_enc_bsum(EncArgs a) {
-    __shared__ u64 ws[kScanBlock / kWave];
-    const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
-    const u64 i0 = (u64)blockIdx.x * kEncScanSpan;
-    u64 sum = 0;
-    for (u64 i = i0 + tid; i < i0 + kEncScanSpan && i < a.nchunks; i += kScanBlock) sum += a.csum[i];
-    const u32 w = wave_sum((u32)sum);   // at most 8 x 1280 per lane
-    if (ln == 0) ws[wib] = w;
-    __syncthreads();
-    if (tid == 0) {
-        u64 t = 0;
-        for (u32 k = 0; k < kScanBlock / kWave; ++k) t += ws[k];
-        a.bsum[blockIdx.x] = t;
-    }
-}
-
+// Scan workgroup b: its carry is the sum of the length workgroups' totals
+// before its first chunk (every thread adds a strided share), then each
+// thread scans 8 consecutive chunk counts.
 __global__ __launch_bounds__(kScanBlock) void k_enc_bscan(EncArgs a) {
-    __shared__ u64 carry_sh, wtot[kScanBlock / kWave];
+    __shared__ u64 carry_sh, part[kScanBlock / kWave];
+    __shared__ u32 wtot[kScanBlock / kWave];
     const u32 tid = threadIdx.x, wib = tid >> 6, ln = lane_id();
     const u32 b = blockIdx.x, nb = gridDim.x;
-    if (tid < kWave) {
+    {
+        const u64 ng = (u64)b * (kEncScanSpan / kEncLenChunks);
         u64 c = 0;
-        for (u32 k = ln; k < b; k += kWave) c += a.bsum[k];
+        for (u64 k = tid; k < ng; k += kScanBlock) c += a.gsum[k];
         // 64-bit lane sums as 24 low bits and the rest
         const u32 lo = wave_sum((u32)c & 0xFFFFFFu), hi = wave_sum((u32)(c >> 24));
-        if (tid == 0) carry_sh = ((u64)hi << 24) + lo;
+        if (ln == 0) part[wib] = ((u64)hi << 24) + lo;
     }
     // thread t holds the 8 consecutive counts 8 t .. 8 t + 7 of the block
     const u64 i0 = (u64)b * kEncScanSpan + 8u * tid;
@@ -3715,6 +3722,12 @@ __global__ __launch_bounds__(kScanBlock) void k_enc_bscan(EncArgs a) {
     }
     const u32 incl = wave_scan(lsum);   // a wavefront's 512 counts fit 32 bits
     if (ln == 63) wtot[wib] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        u64 t = 0;
+        for (u32 k = 0; k < kScanBlock / kWave; ++k) t += part[k];
+        carry_sh = t;
+    }
     __syncthreads();
     u64 off = carry_sh;
     for (u32 k = 0; k < wib; ++k) off += wtot[k];
@@ -4199,15 +4212,11 @@ hipError_t launch_batch(const ListArgs &a, int segs, int wpb, int grid_blocks, h
 
 hipError_t launch_encode(const EncArgs &a, hipStream_t s) {
     const u32 wpb = 4;
-    const u64 per_block = (u64)wpb * kEncPerWave;
-    const u64 blocks = (a.nchunks + per_block - 1) / per_block;
-    k_enc_len<<<(unsigned)blocks, wpb * kWave, 0, s>>>(a);
+    const u64 blocks = (a.nchunks + kEncLenChunks - 1) / kEncLenChunks;
+    k_enc_len<<<(unsigned)blocks, kEncLenWaves * kWave, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const u64 nsb = (a.nchunks + kEncScanSpan - 1) / kEncScanSpan;
-    k_enc_bsum<<<(unsigned)nsb, kScanBlock, 0, s>>>(a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
     k_enc_bscan<<<(unsigned)nsb, kScanBlock, 0, s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

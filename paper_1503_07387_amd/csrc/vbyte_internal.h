@@ -196,6 +196,7 @@ struct ListArgs {
 // Encoder (k_enc_*): values addressed from the 16-byte-aligned element at
 // or below values[0]; chunks of kEncChunk aligned elements.
 constexpr uint64_t kEncChunk = 256;
+constexpr uint64_t kEncLenChunks = 32;   // chunks per workgroup of the length pass
 constexpr uint32_t kEncStageWords = (kEncChunk * 5 + 16 + 3) / 4 + 8;   // a chunk's bytes, 16-byte shifted, zeroed in 16-byte units
 struct EncArgs {
     const uint32_t *vbase;   // 16-byte aligned, <= values
@@ -209,7 +210,7 @@ struct EncArgs {
     uint64_t nchunks;        // ceil((e0 + n) / kEncChunk)
     uint32_t *csum;          // per chunk: bytes of its codes
     uint64_t *cpre;          // per chunk: exclusive byte offset
-    uint64_t *bsum;          // per scan block of 8192 chunks: bytes
+    uint32_t *gsum;          // per k_enc_len workgroup (kEncLenChunks chunks): bytes
 };
 
 // Launchers (kernels.hip).
